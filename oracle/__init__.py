@@ -1,0 +1,181 @@
+"""CPU oracle for the linear-work R-MAT sampler (arXiv 1905.03525).
+
+TEST INFRASTRUCTURE ONLY.  The product library never imports, links or calls
+this package; only the test suite, the smoke check and the CPU-baseline leg of
+the benchmark do.  It shares no code with the HIP implementation.
+
+The arithmetic lives in ``rmat_oracle.c`` (plain C, compiled with gcc); this
+module compiles it on demand and exposes it through ctypes with numpy arrays.
+The header comment of ``rmat_oracle.c`` lists the passages of the paper each
+step follows and the readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rmat_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FIXED = 0
+VARIABLE = 1
+
+_ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EINTERNAL", -4: "ERANGE"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed: {_ERRORS.get(code, code)}")
+        self.code = code
+        self.name = _ERRORS.get(code, str(code))
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (no fused multiply-add: the canonical
+    products must round after every multiplication)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-pthread", "-Wall", "-Wno-unused-function",
+            _SRC, "-o", tmp, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_canonical_product.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        L.orc_canonical_product.restype = ctypes.c_double
+        L.orc_table_new.restype = ctypes.c_void_p
+        L.orc_table_delete.argtypes = [ctypes.c_void_p]
+        L.orc_build_table.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+        L.orc_build_table.restype = ctypes.c_int
+        L.orc_table_info.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_table_arrays.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 8
+        L.orc_generate.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+        L.orc_generate.restype = ctypes.c_int
+        L.orc_generate_reduce.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.orc_generate_reduce.restype = ctypes.c_int
+        L.orc_edge_mix.argtypes = [ctypes.c_uint64] * 3
+        L.orc_edge_mix.restype = ctypes.c_uint64
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 (Salmon et al., SC'11): 4 output words for one counter."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def canonical_product(q, counts) -> float:
+    """Probability of a path with the given letter counts (reading R3)."""
+    qa = (ctypes.c_double * 4)(*[float(v) for v in q])
+    ca = (ctypes.c_int * 4)(*[int(v) for v in counts])
+    return float(lib().orc_canonical_product(qa, ca))
+
+
+def edge_mix(e: int, src: int, dst: int) -> int:
+    return int(lib().orc_edge_mix(e, src, dst))
+
+
+@dataclass
+class Table:
+    """An oracle table: items in tree order, then the alias buckets."""
+    k: int
+    mode: int
+    cap: int
+    bucket_bits: int
+    n_items: int
+    n_buckets: int
+    capacity: int
+    length: np.ndarray   # uint8, per item (padding items: 0)
+    code: np.ndarray     # uint64, base-4 path code, root-most letter first
+    row: np.ndarray      # uint32, row bits of the path (root-most = MSB)
+    col: np.ndarray      # uint32
+    p: np.ndarray        # float64, canonical product
+    w: np.ndarray        # int64, fixed-point weight (sum = 2^32)
+    thr: np.ndarray      # uint32, per bucket
+    alias: np.ndarray    # uint32, per bucket
+    handle: "ctypes.c_void_p" = None
+
+    def __del__(self):
+        if self.handle is not None and _lib is not None:
+            _lib.orc_table_delete(self.handle)
+            self.handle = None
+
+    @property
+    def expected_len(self) -> float:
+        """Mean path length under the quantised law, sum(w L) / 2^32."""
+        return float(np.sum(self.w.astype(np.float64) * self.length) / 2.0**32)
+
+
+def build_table(a, b, c, d, k, bound, mode) -> Table:
+    L = lib()
+    h = L.orc_table_new()
+    rc = L.orc_build_table(a, b, c, d, int(k), int(bound), int(mode), h)
+    if rc != 0:
+        L.orc_table_delete(h)
+        raise OracleError(rc, "build_table")
+    info = np.zeros(7, dtype=np.uint64)
+    L.orc_table_info(h, _ptr(info))
+    nb = int(info[5])
+    arrs = dict(
+        length=np.zeros(nb, np.uint8), code=np.zeros(nb, np.uint64), row=np.zeros(nb, np.uint32),
+        col=np.zeros(nb, np.uint32), p=np.zeros(nb, np.float64), w=np.zeros(nb, np.int64),
+        thr=np.zeros(nb, np.uint32), alias=np.zeros(nb, np.uint32))
+    L.orc_table_arrays(h, *[_ptr(arrs[n]) for n in ("length", "code", "row", "col", "p", "w", "thr", "alias")])
+    return Table(k=int(info[0]), mode=int(info[1]), cap=int(info[2]), bucket_bits=int(info[3]),
+                 n_items=int(info[4]), n_buckets=nb, capacity=int(info[6]), handle=h, **arrs)
+
+
+def generate(t: Table, seed: int, edge_begin: int, m: int, threads: int = 1,
+             width: int | None = None, samples: bool = False):
+    """Edges [edge_begin, edge_begin + m) as (src, dst[, samples per edge])."""
+    if width is None:
+        width = 4 if t.k <= 32 else 8
+    dt = np.uint32 if width == 4 else np.uint64
+    src = np.zeros(m, dt)
+    dst = np.zeros(m, dt)
+    ns = np.zeros(m, np.uint32) if samples else None
+    rc = lib().orc_generate(t.handle, seed, edge_begin, m, _ptr(src), _ptr(dst), width,
+                            _ptr(ns) if samples else None, int(threads))
+    if rc != 0:
+        raise OracleError(rc, "generate")
+    return (src, dst, ns) if samples else (src, dst)
+
+
+def generate_reduce(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int = 16,
+                    threads: int = 1):
+    """Histogram of src >> (k - hist_bits) and XOR of edge_mix over the chunk."""
+    hist = np.zeros(1 << hist_bits, np.uint64)
+    x = np.zeros(1, np.uint64)
+    rc = lib().orc_generate_reduce(t.handle, seed, edge_begin, m, hist_bits, _ptr(hist), _ptr(x), int(threads))
+    if rc != 0:
+        raise OracleError(rc, "generate_reduce")
+    return hist, int(x[0])

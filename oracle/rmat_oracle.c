@@ -1,0 +1,629 @@
+/*
+ * rmat_oracle.c -- plain, slow, CPU reference for the linear-work R-MAT sampler.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may use it.  It shares no code, header, table or
+ * constant generator with the HIP implementation.
+ *
+ * What it computes follows Huebschle-Schneider & Sanders, "Linear Work
+ * Generation of R-MAT Graphs" (arXiv 1905.03525):
+ *
+ *   - Sec. 1: the R-MAT process.  An edge of a graph with n = 2^k nodes is k
+ *     independent quadrant choices a (row 0, col 0), b (row 0, col 1),
+ *     c (row 1, col 0), d (row 1, col 1); one row bit and one column bit per
+ *     level.
+ *   - Sec. 2, the max-priority-queue fragment: a table of quadrant paths is
+ *     grown by repeatedly expanding the most probable path into its four
+ *     one-letter extensions; a path's probability is the product of its
+ *     letters.  The fixed-length variant takes all paths of one length.
+ *   - Sec. 2: the table is turned into a Walker alias structure [Walker 1977]
+ *     for constant-time sampling.
+ *   - Sec. 2, the sampling loop: sampled paths are appended to the row and
+ *     column bit strings until k bits are known; the first k bits form the
+ *     edge.
+ *
+ * Readings taken where the paper is silent (each is listed in the design
+ * notes, with the reason):
+ *   R1 letter -> bits: a=(0,0) b=(0,1) c=(1,0) d=(1,1); the row is the source.
+ *   R2 variable table size: expand while |entries| + 3 < bound, so the table
+ *      has 1 + 3t entries, t = ceil((bound - 4) / 3).  This reproduces every
+ *      table size on the x-axis of Fig. 1 (253, 511, 1021, ...).
+ *   R3 ties in deleteMax: order by probability descending, then depth
+ *      ascending, then the path read as base-4 digits (a<b<c<d) ascending.
+ *      A path's probability is the canonical product: 1.0 times a (n_a
+ *      times), then b, then c, then d, each product rounded to nearest double.
+ *   R4 depth cap min(15, k): a path of that length is never expanded.  With
+ *      it the table's mean path length matches the "13.9 bits" (2^13 entries)
+ *      and "15 bits" (2^21 entries) of Sec. 4 for a=.9, b=c=.025, d=.05.
+ *   R5 fixed length: l = floor(log4 bound), 1 <= l <= depth cap.
+ *   R6 items are the leaves sorted in tree order (left-aligned code); the
+ *      alias table has 2^ceil(log2 |A|) buckets; padding items weigh 0.
+ *   R7 weights w_j: p_j * 2^32 rounded by largest remainders (floors, then
+ *      one more unit to each of the items with the largest fractional parts,
+ *      ties to the lower index) so that they sum to exactly 2^32.
+ *   R8 alias table: the deterministic sweep in build_alias() below; bucket i
+ *      holds threshold T_i and alias A_i, bucket capacity C = 2^(32 - b).
+ *   R9 randomness: Philox4x32-10 [Salmon, Moraes, Dror, Shaw, SC'11] with
+ *      key (seed_lo, seed_hi) and counter (e_lo, e_hi, j, 0); sample s of
+ *      edge e uses output word s mod 4 of counter j = s / 4.
+ *  R10 a sample x picks bucket x >> (32 - b); with f = x mod C the item is
+ *      the bucket's own item if f < T, else its alias.
+ *  R11 the first (root-most) letter of the stream is the most significant
+ *      bit of the k-bit row and column ids.
+ *  R12 letters left over after the k-th are discarded (each edge has its own
+ *      counter stream), instead of being carried over to the next edge.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EINTERNAL (-3)
+#define ORC_ERANGE (-4)
+
+#define ORC_FIXED 0
+#define ORC_VARIABLE 1
+#define ORC_MAX_CAP 15
+
+/* ------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon et al., SC'11, Sec. 3: the Philox S-box with
+ * multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key increments 0x9E3779B9 /
+ * 0xBB67AE85; ten rounds, the key bumped between rounds).
+ * ---------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------
+ * Path probabilities (Sec. 2: a path's probability is the product of its
+ * letters; reading R3 fixes the multiplication order).
+ * ---------------------------------------------------------------------- */
+double orc_canonical_product(const double q[4], const int counts[4]) {
+  double p = 1.0;
+  for (int letter = 0; letter < 4; ++letter)
+    for (int i = 0; i < counts[letter]; ++i) p = p * q[letter];
+  return p;
+}
+
+typedef struct {
+  double p;
+  uint64_t code; /* base-4 digits, root-most letter most significant */
+  int depth;
+  int counts[4];
+} node_t;
+
+/* Total order of reading R3: does u come before v? */
+static int node_before(const node_t* u, const node_t* v) {
+  if (u->p != v->p) return u->p > v->p;
+  if (u->depth != v->depth) return u->depth < v->depth;
+  return u->code < v->code;
+}
+
+/* Binary max-heap under node_before: the max-priority queue of Sec. 2. */
+typedef struct {
+  node_t* a;
+  size_t n, cap;
+} heap_t;
+
+static int heap_push(heap_t* h, node_t v) {
+  if (h->n == h->cap) {
+    size_t nc = h->cap ? 2 * h->cap : 1024;
+    node_t* na = (node_t*)realloc(h->a, nc * sizeof(node_t));
+    if (!na) return ORC_ENOMEM;
+    h->a = na;
+    h->cap = nc;
+  }
+  size_t i = h->n++;
+  h->a[i] = v;
+  while (i > 0) {
+    size_t parent = (i - 1) / 2;
+    if (!node_before(&h->a[i], &h->a[parent])) break;
+    node_t t = h->a[i]; h->a[i] = h->a[parent]; h->a[parent] = t;
+    i = parent;
+  }
+  return ORC_OK;
+}
+
+static node_t heap_pop(heap_t* h) {
+  node_t top = h->a[0];
+  h->a[0] = h->a[--h->n];
+  size_t i = 0;
+  for (;;) {
+    size_t l = 2 * i + 1, r = l + 1, best = i;
+    if (l < h->n && node_before(&h->a[l], &h->a[best])) best = l;
+    if (r < h->n && node_before(&h->a[r], &h->a[best])) best = r;
+    if (best == i) break;
+    node_t t = h->a[i]; h->a[i] = h->a[best]; h->a[best] = t;
+    i = best;
+  }
+  return top;
+}
+
+/* ------------------------------------------------------------------------
+ * The table.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int k, mode, cap, bucket_bits;
+  uint64_t bound, n_items, n_buckets, capacity; /* capacity = C = 2^(32-b) */
+  double q[4];
+  /* per item (n_buckets entries; items >= n_items are padding) */
+  uint8_t* len;
+  uint64_t* code;
+  uint32_t* row;   /* row bits of the path, root-most letter is the MSB */
+  uint32_t* col;
+  double* p;
+  int64_t* w;
+  /* per bucket */
+  uint32_t* thr;   /* T_i, equal to C for a full bucket */
+  uint32_t* alias; /* A_i, equal to i for a full bucket */
+} orc_table;
+
+static int cmp_u64(const void* x, const void* y) {
+  uint64_t a = *(const uint64_t*)x, b = *(const uint64_t*)y;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+void orc_free_table(orc_table* t) {
+  if (!t) return;
+  free(t->len); free(t->code); free(t->row); free(t->col);
+  free(t->p); free(t->w); free(t->thr); free(t->alias);
+  memset(t, 0, sizeof(*t));
+}
+
+/* Validation of the inputs (Sec. 1: a+b+c+d = 1; readings R2, R5). */
+static int validate(const double q[4], int k, uint64_t bound, int mode) {
+  double s = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    if (!(q[i] >= 0.0) || isnan(q[i]) || isinf(q[i])) return ORC_EINVAL;
+    s += q[i];
+  }
+  if (fabs(s - 1.0) > 1e-9) return ORC_EINVAL;
+  if (k < 1 || k > 64) return ORC_EINVAL;
+  if (bound > (1ull << 24)) return ORC_EINVAL;
+  if (mode == ORC_VARIABLE) {
+    if (bound < 5) return ORC_EINVAL;
+  } else if (mode == ORC_FIXED) {
+    if (bound < 4) return ORC_EINVAL;
+  } else {
+    return ORC_EINVAL;
+  }
+  return ORC_OK;
+}
+
+/* Enumerate the leaves.  Fixed: all 4^l paths (Sec. 2, first strategy).
+ * Variable: the priority-queue expansion of Sec. 2 with readings R2-R4.
+ * Output: codes and depths of the leaves in tree order. */
+static int enumerate_leaves(orc_table* t, uint64_t** out_lac_sorted) {
+  int cap = t->k < ORC_MAX_CAP ? t->k : ORC_MAX_CAP;
+  t->cap = cap;
+  size_t n = 0;
+  node_t* leaves = NULL;
+  if (t->mode == ORC_FIXED) {
+    int ell = 0;
+    while (ell < 30 && (1ull << (2 * (ell + 1))) <= t->bound) ++ell;
+    if (ell < 1 || ell > cap) return ORC_EINVAL;
+    n = (size_t)1 << (2 * ell);
+    leaves = (node_t*)calloc(n, sizeof(node_t));
+    if (!leaves) return ORC_ENOMEM;
+    for (size_t code = 0; code < n; ++code) {
+      node_t v;
+      memset(&v, 0, sizeof(v));
+      v.code = code;
+      v.depth = ell;
+      for (int pos = 0; pos < ell; ++pos) v.counts[(code >> (2 * pos)) & 3]++;
+      v.p = orc_canonical_product(t->q, v.counts);
+      leaves[code] = v;
+    }
+  } else {
+    heap_t q = {0, 0, 0};
+    size_t n_final = 0, cap_final = 0;
+    node_t* final_leaves = NULL; /* entries at the depth cap: never expanded */
+    node_t root;
+    memset(&root, 0, sizeof(root));
+    root.p = 1.0;
+    if (heap_push(&q, root)) return ORC_ENOMEM;
+    while (q.n > 0 && (uint64_t)(q.n + n_final) + 3 < t->bound) {
+      node_t v = heap_pop(&q);
+      for (int letter = 0; letter < 4; ++letter) {
+        node_t c = v;
+        c.code = v.code * 4 + (uint64_t)letter;
+        c.depth = v.depth + 1;
+        c.counts[letter]++;
+        c.p = orc_canonical_product(t->q, c.counts);
+        if (c.depth < cap) {
+          if (heap_push(&q, c)) { free(q.a); free(final_leaves); return ORC_ENOMEM; }
+        } else {
+          if (n_final == cap_final) {
+            cap_final = cap_final ? 2 * cap_final : 1024;
+            node_t* nf = (node_t*)realloc(final_leaves, cap_final * sizeof(node_t));
+            if (!nf) { free(q.a); free(final_leaves); return ORC_ENOMEM; }
+            final_leaves = nf;
+          }
+          final_leaves[n_final++] = c;
+        }
+      }
+    }
+    n = q.n + n_final;
+    leaves = (node_t*)malloc(n * sizeof(node_t));
+    if (!leaves) { free(q.a); free(final_leaves); return ORC_ENOMEM; }
+    if (q.n) memcpy(leaves, q.a, q.n * sizeof(node_t));
+    if (n_final) memcpy(leaves + q.n, final_leaves, n_final * sizeof(node_t));
+    free(q.a);
+    free(final_leaves);
+  }
+  /* Tree order = order of left-aligned codes.  Key: lac << 32 | index. */
+  uint64_t* key = (uint64_t*)malloc(n * sizeof(uint64_t));
+  if (!key) { free(leaves); return ORC_ENOMEM; }
+  for (size_t i = 0; i < n; ++i) {
+    uint64_t lac = leaves[i].code << (2 * (ORC_MAX_CAP - leaves[i].depth));
+    key[i] = (lac << 25) | (uint64_t)i; /* lac < 2^30, i < 2^25 */
+  }
+  qsort(key, n, sizeof(uint64_t), cmp_u64);
+  uint64_t nb = 1;
+  int b = 0;
+  while (nb < n) { nb <<= 1; ++b; }
+  t->n_items = n;
+  t->n_buckets = nb;
+  t->bucket_bits = b;
+  t->capacity = 1ull << (32 - b);
+  t->len = (uint8_t*)calloc(nb, 1);
+  t->code = (uint64_t*)calloc(nb, sizeof(uint64_t));
+  t->row = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  t->col = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  t->p = (double*)calloc(nb, sizeof(double));
+  t->w = (int64_t*)calloc(nb, sizeof(int64_t));
+  t->thr = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  t->alias = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  if (!t->len || !t->code || !t->row || !t->col || !t->p || !t->w || !t->thr ||
+      !t->alias) {
+    free(key); free(leaves);
+    return ORC_ENOMEM;
+  }
+  for (size_t j = 0; j < n; ++j) {
+    const node_t* v = &leaves[key[j] & ((1ull << 25) - 1)];
+    t->len[j] = (uint8_t)v->depth;
+    t->code[j] = v->code;
+    t->p[j] = v->p;
+    uint32_t r = 0, c = 0;
+    for (int pos = v->depth - 1; pos >= 0; --pos) {
+      unsigned digit = (unsigned)(v->code >> (2 * pos)) & 3u;
+      r = (r << 1) | (digit >> 1);
+      c = (c << 1) | (digit & 1u);
+    }
+    t->row[j] = r;
+    t->col[j] = c;
+  }
+  free(key);
+  free(leaves);
+  (void)out_lac_sorted;
+  return ORC_OK;
+}
+
+/* Reading R7: fixed-point weights summing to exactly 2^32, by largest
+ * remainders.  x_j = p_j * 2^32 (exact scaling); every item gets floor(x_j);
+ * the R = 2^32 - sum(floor(x_j)) units left over go one each to the R items
+ * with the largest fractional parts x_j - floor(x_j), ties to the lower
+ * index.  Every weight is within one unit of x_j. */
+typedef struct {
+  double frac;
+  uint64_t index;
+} frac_t;
+
+static int cmp_frac(const void* x, const void* y) {
+  const frac_t* a = (const frac_t*)x;
+  const frac_t* b = (const frac_t*)y;
+  if (a->frac != b->frac) return a->frac > b->frac ? -1 : 1;
+  return a->index < b->index ? -1 : (a->index > b->index ? 1 : 0);
+}
+
+static int quantise(orc_table* t) {
+  const double scale = 4294967296.0;
+  const uint64_t n = t->n_items;
+  frac_t* fr = (frac_t*)malloc(n * sizeof(frac_t));
+  if (!fr) return ORC_ENOMEM;
+  int64_t sum = 0;
+  for (uint64_t j = 0; j < n; ++j) {
+    double x = t->p[j] * scale;
+    double fl = floor(x);
+    t->w[j] = (int64_t)fl;
+    sum += t->w[j];
+    fr[j].frac = x - fl;
+    fr[j].index = j;
+  }
+  int64_t residual = (int64_t)(1ull << 32) - sum;
+  if (residual < 0 || (uint64_t)residual > n) { free(fr); return ORC_EINTERNAL; }
+  qsort(fr, n, sizeof(frac_t), cmp_frac);
+  for (int64_t r = 0; r < residual; ++r) t->w[fr[r].index] += 1;
+  free(fr);
+  return ORC_OK;
+}
+
+/* Reading R8: Walker's alias structure [Walker 1977] built by one sweep.
+ * Lights (w < C) and heavies (w >= C) are each taken in ascending index
+ * order.  The current heavy pays for each light's deficit; once the heavy's
+ * remaining mass r drops below C, its own bucket gets threshold r and the
+ * next heavy as alias, and the next heavy becomes current.  Every heavy left
+ * at the end holds exactly C and aliases itself. */
+static int build_alias(orc_table* t) {
+  const uint64_t nb = t->n_buckets;
+  const int64_t C = (int64_t)t->capacity;
+  uint32_t* lights = (uint32_t*)malloc(nb * sizeof(uint32_t));
+  uint32_t* heavies = (uint32_t*)malloc(nb * sizeof(uint32_t));
+  if (!lights || !heavies) { free(lights); free(heavies); return ORC_ENOMEM; }
+  uint64_t nl = 0, nh = 0;
+  for (uint64_t i = 0; i < nb; ++i) {
+    if (t->w[i] < C) lights[nl++] = (uint32_t)i;
+    else heavies[nh++] = (uint32_t)i;
+  }
+  int rc = ORC_OK;
+  if (nh == 0) { rc = ORC_EINTERNAL; goto done; }
+  uint64_t h = 0;
+  uint32_t j = heavies[0];
+  int64_t r = t->w[j];
+  for (uint64_t li = 0; li < nl; ++li) {
+    uint32_t i = lights[li];
+    t->thr[i] = (uint32_t)t->w[i];
+    t->alias[i] = j;
+    r -= C - t->w[i];
+    while (r < C) {
+      if (++h >= nh) { rc = ORC_EINTERNAL; goto done; }
+      uint32_t jn = heavies[h];
+      t->thr[j] = (uint32_t)r;
+      t->alias[j] = jn;
+      r = t->w[jn] - (C - r);
+      j = jn;
+    }
+  }
+  if (r != C) { rc = ORC_EINTERNAL; goto done; }
+  t->thr[j] = (uint32_t)C;
+  t->alias[j] = j;
+  for (uint64_t hh = h + 1; hh < nh; ++hh) {
+    uint32_t jj = heavies[hh];
+    if (t->w[jj] != C) { rc = ORC_EINTERNAL; goto done; }
+    t->thr[jj] = (uint32_t)C;
+    t->alias[jj] = jj;
+  }
+done:
+  free(lights);
+  free(heavies);
+  return rc;
+}
+
+int orc_build_table(double a, double b, double c, double d, int k,
+                    uint64_t bound, int mode, orc_table* out) {
+  memset(out, 0, sizeof(*out));
+  double q[4] = {a, b, c, d};
+  int rc = validate(q, k, bound, mode);
+  if (rc) return rc;
+  out->k = k;
+  out->mode = mode;
+  out->bound = bound;
+  memcpy(out->q, q, sizeof(q));
+  if ((rc = enumerate_leaves(out, NULL)) != ORC_OK) { orc_free_table(out); return rc; }
+  if ((rc = quantise(out)) != ORC_OK) { orc_free_table(out); return rc; }
+  if ((rc = build_alias(out)) != ORC_OK) { orc_free_table(out); return rc; }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Sampling (Sec. 2, the sampling loop, with readings R9-R12).
+ * ---------------------------------------------------------------------- */
+static void sample_edge(const orc_table* t, uint64_t seed, uint64_t e,
+                        uint64_t* src, uint64_t* dst, uint32_t* n_samples) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const int k = t->k;
+  const int shift = 32 - t->bucket_bits;
+  const uint32_t fmask = (uint32_t)(t->capacity - 1);
+  uint64_t row = 0, col = 0;
+  int filled = 0;
+  uint32_t s = 0, words[4] = {0, 0, 0, 0};
+  while (filled < k) {
+    if ((s & 3u) == 0) {
+      const uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), s >> 2, 0u};
+      orc_philox4x32_10(ctr, key, words);
+    }
+    uint32_t x = words[s & 3u];
+    ++s;
+    uint32_t bucket = x >> shift;
+    uint32_t f = x & fmask;
+    uint32_t item = (f < t->thr[bucket]) ? bucket : t->alias[bucket];
+    int L = t->len[item];
+    int take = (L < k - filled) ? L : (k - filled);
+    row = (row << take) | (uint64_t)(t->row[item] >> (L - take));
+    col = (col << take) | (uint64_t)(t->col[item] >> (L - take));
+    filled += take;
+  }
+  *src = row;
+  *dst = col;
+  if (n_samples) *n_samples = s;
+}
+
+/* MurmurHash3's 64-bit finaliser (A. Appleby, public domain). */
+static uint64_t fmix64(uint64_t z) {
+  z ^= z >> 33;
+  z *= 0xFF51AFD7ED558CCDull;
+  z ^= z >> 33;
+  z *= 0xC4CEB9FE1A85EC53ull;
+  z ^= z >> 33;
+  return z;
+}
+
+/* Per-edge checksum term of the chunk reduction. */
+uint64_t orc_edge_mix(uint64_t e, uint64_t src, uint64_t dst) {
+  uint64_t rot = (dst << 32) | (dst >> 32);
+  return fmix64(e ^ fmix64(src ^ rot));
+}
+
+typedef struct {
+  const orc_table* t;
+  uint64_t seed, edge_begin, lo, hi;
+  void* src;
+  void* dst;
+  int width; /* bytes per id: 4 or 8 */
+  uint32_t* n_samples;
+  /* reduction outputs */
+  int hist_bits;
+  uint64_t* hist;
+  uint64_t xor_acc;
+} work_t;
+
+static void* gen_worker(void* arg) {
+  work_t* w = (work_t*)arg;
+  for (uint64_t slot = w->lo; slot < w->hi; ++slot) {
+    uint64_t s, d;
+    uint32_t ns;
+    sample_edge(w->t, w->seed, w->edge_begin + slot, &s, &d, &ns);
+    if (w->width == 4) {
+      ((uint32_t*)w->src)[slot] = (uint32_t)s;
+      ((uint32_t*)w->dst)[slot] = (uint32_t)d;
+    } else {
+      ((uint64_t*)w->src)[slot] = s;
+      ((uint64_t*)w->dst)[slot] = d;
+    }
+    if (w->n_samples) w->n_samples[slot] = ns;
+  }
+  return NULL;
+}
+
+static void* reduce_worker(void* arg) {
+  work_t* w = (work_t*)arg;
+  int shift = w->t->k - w->hist_bits;
+  for (uint64_t slot = w->lo; slot < w->hi; ++slot) {
+    uint64_t e = w->edge_begin + slot, s, d;
+    sample_edge(w->t, w->seed, e, &s, &d, NULL);
+    w->hist[s >> shift] += 1;
+    w->xor_acc ^= orc_edge_mix(e, s, d);
+  }
+  return NULL;
+}
+
+static int run_threads(work_t* proto, uint64_t m, int threads,
+                       void* (*fn)(void*), work_t** out_items) {
+  if (threads < 1) threads = 1;
+  if ((uint64_t)threads > m && m > 0) threads = (int)m;
+  if (m == 0) threads = 1;
+  work_t* items = (work_t*)calloc((size_t)threads, sizeof(work_t));
+  pthread_t* tid = (pthread_t*)calloc((size_t)threads, sizeof(pthread_t));
+  if (!items || !tid) { free(items); free(tid); return ORC_ENOMEM; }
+  for (int i = 0; i < threads; ++i) {
+    items[i] = *proto;
+    items[i].lo = m * (uint64_t)i / (uint64_t)threads;
+    items[i].hi = m * (uint64_t)(i + 1) / (uint64_t)threads;
+  }
+  for (int i = 1; i < threads; ++i) pthread_create(&tid[i], NULL, fn, &items[i]);
+  fn(&items[0]);
+  for (int i = 1; i < threads; ++i) pthread_join(tid[i], NULL);
+  free(tid);
+  *out_items = items;
+  return threads;
+}
+
+/* Edges e in [edge_begin, edge_begin + m) go to slot e - edge_begin.
+ * width is 4 (k <= 32) or 8 bytes per id. */
+int orc_generate(const orc_table* t, uint64_t seed, uint64_t edge_begin,
+                 uint64_t m, void* src, void* dst, int width,
+                 uint32_t* n_samples, int threads) {
+  if (edge_begin + m < edge_begin) return ORC_ERANGE;
+  if (width != 4 && width != 8) return ORC_EINVAL;
+  if (width == 4 && t->k > 32) return ORC_EINVAL;
+  if (m == 0) return ORC_OK;
+  work_t proto;
+  memset(&proto, 0, sizeof(proto));
+  proto.t = t; proto.seed = seed; proto.edge_begin = edge_begin;
+  proto.src = src; proto.dst = dst; proto.width = width;
+  proto.n_samples = n_samples;
+  work_t* items = NULL;
+  int nt = run_threads(&proto, m, threads, gen_worker, &items);
+  if (nt < 0) return nt;
+  free(items);
+  return ORC_OK;
+}
+
+/* Chunk reduction: histogram of the top hist_bits bits of each source id and
+ * the XOR over edges of orc_edge_mix(e, src, dst). */
+int orc_generate_reduce(const orc_table* t, uint64_t seed, uint64_t edge_begin,
+                        uint64_t m, int hist_bits, uint64_t* hist,
+                        uint64_t* xor_out, int threads) {
+  if (edge_begin + m < edge_begin) return ORC_ERANGE;
+  if (hist_bits < 0 || hist_bits > t->k || hist_bits > 24) return ORC_EINVAL;
+  uint64_t nbins = 1ull << hist_bits;
+  memset(hist, 0, nbins * sizeof(uint64_t));
+  *xor_out = 0;
+  if (m == 0) return ORC_OK;
+  work_t proto;
+  memset(&proto, 0, sizeof(proto));
+  proto.t = t; proto.seed = seed; proto.edge_begin = edge_begin;
+  proto.hist_bits = hist_bits;
+  if (threads < 1) threads = 1;
+  /* each worker gets its own histogram */
+  uint64_t* hists = (uint64_t*)calloc((size_t)threads * nbins, sizeof(uint64_t));
+  if (!hists) return ORC_ENOMEM;
+  if ((uint64_t)threads > m) threads = (int)m;
+  work_t* items = (work_t*)calloc((size_t)threads, sizeof(work_t));
+  pthread_t* tid = (pthread_t*)calloc((size_t)threads, sizeof(pthread_t));
+  if (!items || !tid) { free(hists); free(items); free(tid); return ORC_ENOMEM; }
+  for (int i = 0; i < threads; ++i) {
+    items[i] = proto;
+    items[i].lo = m * (uint64_t)i / (uint64_t)threads;
+    items[i].hi = m * (uint64_t)(i + 1) / (uint64_t)threads;
+    items[i].hist = hists + (size_t)i * nbins;
+  }
+  for (int i = 1; i < threads; ++i) pthread_create(&tid[i], NULL, reduce_worker, &items[i]);
+  reduce_worker(&items[0]);
+  for (int i = 1; i < threads; ++i) pthread_join(tid[i], NULL);
+  for (int i = 0; i < threads; ++i) {
+    for (uint64_t bin = 0; bin < nbins; ++bin) hist[bin] += items[i].hist[bin];
+    *xor_out ^= items[i].xor_acc;
+  }
+  free(hists); free(items); free(tid);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Flat accessors for the ctypes wrapper.
+ * ---------------------------------------------------------------------- */
+orc_table* orc_table_new(void) { return (orc_table*)calloc(1, sizeof(orc_table)); }
+void orc_table_delete(orc_table* t) { orc_free_table(t); free(t); }
+
+/* info[0..6] = k, mode, cap, bucket_bits, n_items, n_buckets, capacity */
+void orc_table_info(const orc_table* t, uint64_t info[7]) {
+  info[0] = (uint64_t)t->k; info[1] = (uint64_t)t->mode;
+  info[2] = (uint64_t)t->cap; info[3] = (uint64_t)t->bucket_bits;
+  info[4] = t->n_items; info[5] = t->n_buckets; info[6] = t->capacity;
+}
+
+/* Copies the per-item and per-bucket arrays (n_buckets entries each). */
+void orc_table_arrays(const orc_table* t, uint8_t* len, uint64_t* code,
+                      uint32_t* row, uint32_t* col, double* p, int64_t* w,
+                      uint32_t* thr, uint32_t* alias) {
+  size_t nb = (size_t)t->n_buckets;
+  if (len) memcpy(len, t->len, nb);
+  if (code) memcpy(code, t->code, nb * sizeof(uint64_t));
+  if (row) memcpy(row, t->row, nb * sizeof(uint32_t));
+  if (col) memcpy(col, t->col, nb * sizeof(uint32_t));
+  if (p) memcpy(p, t->p, nb * sizeof(double));
+  if (w) memcpy(w, t->w, nb * sizeof(int64_t));
+  if (thr) memcpy(thr, t->thr, nb * sizeof(uint32_t));
+  if (alias) memcpy(alias, t->alias, nb * sizeof(uint32_t));
+}
