@@ -1,0 +1,171 @@
+/*
+ * rmat.h -- C ABI of the MI355X (gfx950) linear-work R-MAT edge sampler.
+ *
+ * Method: Huebschle-Schneider & Sanders, "Linear Work Generation of R-MAT
+ * Graphs" (arXiv 1905.03525).  Sec. 1 defines the R-MAT process: a directed
+ * multigraph with n = 2^k nodes and m edges; each edge descends k times into
+ * one of the four quadrants of the adjacency matrix, upper left with
+ * probability a, upper right b, lower left c, lower right d (a+b+c+d = 1),
+ * fixing one row bit and one column bit per level.  Sec. 2 precomputes a
+ * table of quadrant paths with their probabilities (all paths of one length,
+ * or the variable-length set grown by a max-priority queue that always
+ * expands the most probable path), samples paths from it in constant time
+ * with a Walker alias structure, and concatenates their row/column bits until
+ * k bits are known.
+ *
+ * Conventions shared by every entry point:
+ *  - Letters: a = (row 0, col 0), b = (0, 1), c = (1, 0), d = (1, 1).  The
+ *    row id is the source, the column id the destination.  The root-most
+ *    letter is the most significant id bit.
+ *  - Ids are uint32 when k <= 32 and uint64 when k > 32.  Edge e of the
+ *    global stream goes to slot e - edge_begin of the output arrays.
+ *  - Randomness: Philox4x32-10 (Salmon et al., SC'11), key (seed_lo,
+ *    seed_hi), counter (e_lo, e_hi, j, 0); sample s of edge e is word s mod 4
+ *    of counter j = s / 4.  Each edge owns its counter stream, so any split
+ *    of [0, m) into calls produces the same edges, and letters left after
+ *    the k-th are discarded (the paper carries them to the next edge).
+ *  - Device pointers are HIP device addresses on the current device and are
+ *    owned by the caller.  Host pointers are plain host memory.
+ *  - Every function returns an rmat_status; none throws or aborts.  On error
+ *    rmat_last_error() returns a thread-local message and outputs are left
+ *    untouched (generation errors detected after a launch may have written
+ *    part of the output).
+ */
+#ifndef RMAT_H
+#define RMAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmat_table* rmat_table_t;
+
+/* Path sets of Sec. 2. */
+enum rmat_path_mode {
+  RMAT_FIXED = 0,    /* all 4^l paths of length l = floor(log4 bound) */
+  RMAT_VARIABLE = 1  /* priority-queue expansion, 1 + 3 ceil((bound-4)/3) paths */
+};
+
+enum rmat_status {
+  RMAT_OK = 0,
+  RMAT_EINVAL = -1,   /* invalid argument */
+  RMAT_ENOMEM = -2,   /* device or host allocation failed */
+  RMAT_EDEVICE = -3,  /* HIP runtime error or no usable gfx950 device */
+  RMAT_ERANGE = -4    /* edge_begin + m overflows 2^64 */
+};
+
+typedef struct rmat_info {
+  int32_t k;
+  int32_t path_mode;
+  int32_t depth_cap;       /* min(15, k): longest path in the table */
+  int32_t bucket_bits;     /* b: the alias table has 2^b buckets */
+  uint64_t table_bound;
+  uint64_t n_items;        /* |A|, number of paths */
+  uint64_t n_buckets;      /* 2^b; items n_items..2^b-1 are zero-weight padding */
+  uint64_t capacity;       /* C = 2^(32-b), fixed-point mass of one bucket */
+  uint32_t id_bytes;       /* 4 if k <= 32 else 8 */
+  uint32_t min_len;        /* shortest and longest path length */
+  uint32_t max_len;
+  uint32_t lds_resident;   /* 1 if generation stages the table in LDS */
+  double expected_len;     /* sum_j w_j L_j / 2^32: letters per sample */
+  uint64_t export_bytes;   /* bytes written by rmat_table_export */
+  uint64_t device_bytes;   /* device memory held by the table */
+} rmat_info;
+
+/*
+ * Builds the path table (Sec. 2, the priority-queue fragment or the
+ * fixed-length strategy) and its alias structure on the current device.
+ *
+ *  a, b, c, d   quadrant probabilities, each >= 0, |a+b+c+d - 1| <= 1e-9
+ *               (Sec. 1).  They are not renormalised.
+ *  k            log2 of the node count, 1..64.
+ *  table_bound  VARIABLE: 5..2^24, the table gets 1 + 3 ceil((bound-4)/3)
+ *               paths (fewer if every path shorter than min(15, k) is
+ *               expanded).  FIXED: 4..2^24, l = floor(log4 bound) must be
+ *               <= min(15, k).
+ *  path_mode    RMAT_FIXED or RMAT_VARIABLE.
+ *  out          receives the handle; valid only when RMAT_OK is returned.
+ *
+ * Tie-breaking of equal probabilities: probability descending, then path
+ * length ascending, then the path as base-4 digits (a<b<c<d) ascending; a
+ * path's probability is 1.0 multiplied by a (n_a times), then b, c and d,
+ * rounding after each product.  Paths of length min(15, k) are never
+ * expanded.  Fixed-point weights w_j sum to 2^32 and are p_j * 2^32 rounded
+ * by largest remainders (ties to the lower item index).
+ *
+ * Synchronous: the call returns after the device build finished.  The
+ * table is immutable afterwards and may be used from any stream.
+ * Errors: RMAT_EINVAL for any invalid argument, RMAT_ENOMEM, RMAT_EDEVICE.
+ */
+int rmat_build_table(double a, double b, double c, double d, int k,
+                     uint64_t table_bound, int path_mode, rmat_table_t* out);
+
+/* Releases the table's device memory.  NULL is accepted.  The caller must
+ * make sure no generation that uses it is still running. */
+int rmat_free_table(rmat_table_t t);
+
+/* Fills *out with the table's shape and statistics (host only, no sync). */
+int rmat_table_info(rmat_table_t t, rmat_info* out);
+
+/*
+ * Copies the table in a canonical host layout, for parity checks: seven
+ * arrays of n_buckets entries each, back to back, in this order:
+ *   uint64 w[]      fixed-point weights (sum 2^32; 0 for padding)
+ *   double p[]      path probabilities (canonical products; 0 for padding)
+ *   uint32 len[]    path lengths (0 for padding)
+ *   uint32 row[]    row bits of the path, root-most letter most significant
+ *   uint32 col[]    column bits
+ *   uint32 thr[]    bucket threshold T_i (C for a bucket that aliases itself)
+ *   uint32 alias[]  bucket alias A_i (i for a full bucket)
+ * nbytes must be at least rmat_info.export_bytes (= 36 * n_buckets).
+ * Synchronous.  Errors: RMAT_EINVAL (NULL or short buffer), RMAT_EDEVICE.
+ */
+int rmat_table_export(rmat_table_t t, void* host_buf, size_t nbytes);
+
+/*
+ * Generates edges e = edge_begin .. edge_begin + m - 1 (Sec. 2, the sampling
+ * loop; per-edge Philox streams as described above).
+ *
+ *  seed              64-bit Philox key.
+ *  out_src, out_dst  device arrays of m ids each (uint32 if k <= 32, else
+ *                    uint64), 4- or 8-byte aligned; slot i holds edge
+ *                    edge_begin + i.
+ *  stream            hipStream_t to launch on (NULL: the null stream).
+ *
+ * rmat_generate is synchronous; rmat_generate_async only enqueues.  m = 0 is
+ * a no-op.  Errors: RMAT_EINVAL (NULL table or outputs with m > 0),
+ * RMAT_ERANGE (edge_begin + m > 2^64), RMAT_EDEVICE (launch failure).
+ */
+int rmat_generate(rmat_table_t t, uint64_t seed, uint64_t edge_begin,
+                  uint64_t m, void* out_src, void* out_dst);
+int rmat_generate_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin,
+                        uint64_t m, void* out_src, void* out_dst, void* stream);
+
+/*
+ * Generates the same edges as rmat_generate but stores none of them; instead
+ * it reduces them on the device (a consumer that only needs a digest of a
+ * huge instance, generated chunk by chunk):
+ *  d_hist  device array of 2^hist_bits uint64 counters, incremented by the
+ *          histogram of src >> (k - hist_bits)  (hist_bits in 0..min(k, 20));
+ *  d_xor   device uint64, XOR-ed with the XOR over the edges of
+ *          mix(e, src, dst) = fmix64(e ^ fmix64(src ^ rotl64(dst, 32))),
+ *          fmix64 being MurmurHash3's 64-bit finaliser.
+ * The caller zeroes both before the first chunk; further chunks accumulate.
+ * Asynchronous on `stream`.  Errors as for rmat_generate_async, and
+ * RMAT_EINVAL for hist_bits out of range.
+ */
+int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed,
+                               uint64_t edge_begin, uint64_t m, int hist_bits,
+                               void* d_hist, void* d_xor, void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char* rmat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMAT_H */

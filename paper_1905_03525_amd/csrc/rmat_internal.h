@@ -1,0 +1,100 @@
+// rmat_internal.h -- types shared by the host runtime (api.cpp) and the HIP
+// kernels of the R-MAT sampler.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmat {
+
+constexpr int kMaxDepthCap = 15;       // longest path: 16-bit fields per id half
+constexpr int kBuildThreads = 1024;    // one workgroup builds one table
+constexpr int kMaxClasses = 4096;      // letter-count classes of depth < 15: 3060
+constexpr uint64_t kMaxBound = 1ull << 24;
+
+// Hot-path bucket record, 16 bytes (one ds_read_b128):
+//   x  thr_abs: bucket i keeps its own item for x < i*C + T_i (a full bucket
+//      stores i*C and an alias equal to itself, so the test never matters)
+//   y  own item's path word, z  alias item's path word:
+//      bits 31..16 = row bits left-aligned in 16 bits,
+//      bits 15..0  = column bits left-aligned in 16 bits
+//   w  own length | alias length << 16
+struct BucketRecord {
+  uint32_t thr_abs, self_word, alias_word, lens;
+};
+
+// Device-side results of a table build, read back by the host.
+struct BuildStats {
+  int32_t error;           // 0 = ok, else an internal error code (see below)
+  uint32_t n_items;
+  uint32_t min_len, max_len;
+  uint64_t sum_wl;         // sum_j w_j * L_j, exact
+  uint64_t residual;       // units handed out by largest remainders
+};
+
+enum BuildError : int32_t {
+  kBuildOk = 0,
+  kBuildItemCount = 1,     // leaf count differs from 1 + 3t
+  kBuildResidual = 2,      // largest-remainder residual outside [0, n]
+  kBuildAlias = 3,         // alias sweep invariant violated
+  kBuildClasses = 4,       // more letter-count classes than kMaxClasses
+};
+
+// Everything one table build needs; arrays are device memory.
+struct BuildJob {
+  double q[4];             // a, b, c, d
+  int32_t k, mode, cap, bucket_bits;
+  int32_t fixed_len;       // FIXED: l; VARIABLE: 0
+  uint32_t n_items;        // expected |A|
+  uint64_t n_expand;       // t: expanded nodes (VARIABLE), (4^l - 1) / 3 (FIXED)
+  uint64_t n_buckets, capacity;
+  // outputs (n_buckets entries each)
+  BucketRecord* records;
+  double* item_p;
+  uint64_t* item_w;
+  uint32_t *item_len, *item_row, *item_col;
+  uint32_t *thr, *alias;
+  BuildStats* stats;
+  // scratch
+  uint32_t* lvl_code;      // n_expand entries: expanded nodes, level by level
+  uint32_t* lvl_first;     // index of the first expanded child
+  uint32_t* lvl_size;      // leaves below the node
+  uint32_t* lvl_off;       // tree-order index of the node's first leaf
+  uint8_t* lvl_mask;       // which of the 4 children are expanded
+  uint32_t* light_idx;     // n_buckets entries each
+  uint32_t* heavy_idx;
+  uint64_t* light_cum;     // inclusive prefix sums of light deficits C - w
+  uint64_t* heavy_cum;     // inclusive prefix sums of heavy excesses w - C
+};
+
+// Scratch bytes a build needs beyond the table itself.
+inline uint64_t build_scratch_bytes(uint64_t n_expand, uint64_t n_buckets) {
+  return n_expand * (4 * 4 + 1) + 256 + n_buckets * (4 + 4 + 8 + 8) + 256;
+}
+
+// Launchers (defined in the .hip files); return hipSuccess or the launch error.
+hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s);
+
+struct GenerateArgs {
+  const BucketRecord* records;
+  uint32_t n_buckets;
+  int32_t bucket_bits;
+  int32_t k;
+  uint32_t lds;            // stage the table in LDS
+  uint64_t seed;
+  uint64_t edge_begin, m;
+  void* out_src;
+  void* out_dst;
+  // reduction variant
+  int32_t hist_bits;
+  unsigned long long* hist;
+  unsigned long long* xor_out;
+};
+
+hipError_t launch_generate(const GenerateArgs& a, hipStream_t s);
+hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s);
+
+// Largest table (in buckets) that generation stages in LDS.
+uint32_t lds_table_limit();
+
+}  // namespace rmat

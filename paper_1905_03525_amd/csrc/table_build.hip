@@ -1,0 +1,596 @@
+// table_build.hip -- builds the path table and its alias structure on the GPU.
+//
+// One 1024-thread workgroup builds one table, so a batch of tables is a
+// single launch.  The result is bit-identical to the sequential definition
+// (Sec. 2: the max-priority queue that always expands the most probable path,
+// then a Walker alias table), reached by a data-parallel route:
+//
+//  1. The queue expands nodes in a fixed total order (probability descending,
+//     then depth, then base-4 code), and a node never precedes its parent in
+//     that order, so the expanded set is exactly the first t nodes of the
+//     order.  All nodes with the same letter counts share one probability, so
+//     the t-th node is found from at most 3060 letter-count classes (depth
+//     < 15) sorted in LDS, plus a walk over the digits of the codes inside
+//     the last, partly expanded class group.  Expansion is then a test
+//     against that boundary node.  (Sec. 5, Parallelization, notes the same
+//     idea: expand every entry above a probability threshold.)
+//  2. The tree is expanded level by level with block-wide prefix sums;
+//     subtree leaf counts (bottom-up) and leaf offsets (top-down) place every
+//     leaf at its tree-order index without sorting.
+//  3. Weights p * 2^32 are rounded by largest remainders: floors, then a
+//     radix select of the residual's worth of largest fractional parts.
+//  4. The alias sweep (lights and heavies in index order, the current heavy
+//     paying for each light) is evaluated in closed form from two prefix
+//     sums: light i aliases the first heavy whose cumulative excess reaches
+//     the lights' cumulative deficit before i, and a heavy whose cumulative
+//     excess E falls short of the total deficit keeps C + E - D(i) where
+//     D(i) is the first cumulative deficit above E, aliasing the next heavy.
+//     Sec. 5 cites a parallel construction of the same kind [HubSan19].
+#include "rmat_internal.h"
+
+namespace rmat {
+namespace {
+
+constexpr int kWaves = kBuildThreads / 64;
+
+// ---------------------------------------------------------------- helpers --
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+  uint32_t lo = __shfl_up(static_cast<uint32_t>(v), d, 64);
+  uint32_t hi = __shfl_up(static_cast<uint32_t>(v >> 32), d, 64);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int d) {
+  uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), d, 64);
+  uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), d, 64);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Exclusive prefix sum over the workgroup; *total gets the sum of all v.
+__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* s_warp, uint64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t y = shfl_up_u64(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_warp[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    uint64_t y = lane < kWaves ? s_warp[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < kWaves; d <<= 1) {
+      uint64_t z = shfl_up_u64(y, d);
+      if (lane >= d) y += z;
+    }
+    if (lane < kWaves) s_warp[lane] = y;
+  }
+  __syncthreads();
+  uint64_t base = wave > 0 ? s_warp[wave - 1] : 0;
+  *total = s_warp[kWaves - 1];
+  __syncthreads();
+  return base + x - v;
+}
+
+__device__ uint64_t block_sum(uint64_t v, uint64_t* s_warp) {
+  uint64_t total;
+  block_exclusive_scan(v, s_warp, &total);
+  return total;
+}
+
+__device__ uint32_t block_min_max(uint32_t vmin, uint32_t vmax, uint32_t* s_u32, uint32_t* out_max) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    vmin = min(vmin, static_cast<uint32_t>(__shfl_xor(vmin, d, 64)));
+    vmax = max(vmax, static_cast<uint32_t>(__shfl_xor(vmax, d, 64)));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { s_u32[wave] = vmin; s_u32[kWaves + wave] = vmax; }
+  __syncthreads();
+  uint32_t mn = 0xFFFFFFFFu, mx = 0;
+  for (int w = 0; w < kWaves; ++w) { mn = min(mn, s_u32[w]); mx = max(mx, s_u32[kWaves + w]); }
+  __syncthreads();
+  *out_max = mx;
+  return mn;
+}
+
+// Probability of a path from its letter counts: 1.0 times a (na times), then
+// b, c, d, rounding after every product.
+__device__ __forceinline__ double path_prob(const double q[4], int na, int nb, int nc, int nd) {
+  double p = 1.0;
+  for (int i = 0; i < na; ++i) p = __dmul_rn(p, q[0]);
+  for (int i = 0; i < nb; ++i) p = __dmul_rn(p, q[1]);
+  for (int i = 0; i < nc; ++i) p = __dmul_rn(p, q[2]);
+  for (int i = 0; i < nd; ++i) p = __dmul_rn(p, q[3]);
+  return p;
+}
+
+// Letter counts of a base-4 code of `depth` digits (a=0, b=1, c=2, d=3).
+__device__ __forceinline__ void letter_counts(uint32_t code, int depth, int n[4]) {
+  const uint32_t mask = ((depth >= 16) ? 0xFFFFFFFFu : ((1u << (2 * depth)) - 1u)) & 0x55555555u;
+  const uint32_t lo = code & mask, hi = (code >> 1) & mask;
+  n[3] = __popc(hi & lo);
+  n[2] = __popc(hi & ~lo & mask);
+  n[1] = __popc(~hi & lo & mask);
+  n[0] = depth - n[1] - n[2] - n[3];
+}
+
+// Row bits (digit bit 1) and column bits (digit bit 0) of a code, root-most
+// digit most significant.
+__device__ __forceinline__ void split_code(uint32_t code, int depth, uint32_t* row, uint32_t* col) {
+  uint32_t r = 0, c = 0;
+  for (int pos = depth - 1; pos >= 0; --pos) {
+    uint32_t digit = (code >> (2 * pos)) & 3u;
+    r = (r << 1) | (digit >> 1);
+    c = (c << 1) | (digit & 1u);
+  }
+  *row = r;
+  *col = c;
+}
+
+__device__ const uint64_t kFact[16] = {1ull, 1ull, 2ull, 6ull, 24ull, 120ull, 720ull, 5040ull, 40320ull,
+                                       362880ull, 3628800ull, 39916800ull, 479001600ull,
+                                       6227020800ull, 87178291200ull, 1307674368000ull};
+
+__device__ __forceinline__ uint64_t multinomial(int na, int nb, int nc, int nd) {
+  return kFact[na + nb + nc + nd] / (kFact[na] * kFact[nb] * kFact[nc] * kFact[nd]);
+}
+
+// Packed class key: counts of a, b, c, d (4 bits each) and depth.
+__device__ __forceinline__ uint32_t pack_class(int na, int nb, int nc, int nd) {
+  return na | (nb << 4) | (nc << 8) | (nd << 12) | ((na + nb + nc + nd) << 16);
+}
+__device__ __forceinline__ int class_n(uint32_t key, int x) { return (key >> (4 * x)) & 15; }
+__device__ __forceinline__ int class_depth(uint32_t key) { return key >> 16; }
+
+// Order of the priority queue: does (p1, D1) come strictly before (p2, D2)?
+__device__ __forceinline__ bool class_before(double p1, int d1, double p2, int d2) {
+  return p1 > p2 || (p1 == p2 && d1 < d2);
+}
+
+struct Boundary {
+  double p;
+  int depth;
+  uint32_t code;
+  int all;  // every expandable node is expanded
+};
+
+__device__ __forceinline__ bool node_expanded(const Boundary& B, int mode, int cap, int fixed_len, double p,
+                                              int depth, uint32_t code) {
+  if (depth >= cap) return false;
+  if (mode == 0) return depth < fixed_len;
+  if (B.all) return true;
+  if (p != B.p) return p > B.p;
+  if (depth != B.depth) return depth < B.depth;
+  return code <= B.code;
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t n, uint64_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t path_word(uint32_t len, uint32_t row, uint32_t col) {
+  return ((row << (16 - len)) << 16) | ((col << (16 - len)) & 0xFFFFu);
+}
+
+__device__ __forceinline__ uint64_t frac_key(double p, uint64_t* floor_out) {
+  double x = __dmul_rn(p, 4294967296.0);
+  double fl = floor(x);
+  *floor_out = static_cast<uint64_t>(fl);
+  return static_cast<uint64_t>(__double_as_longlong(x - fl));
+}
+
+// ------------------------------------------------------------------ kernel --
+__global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJob* __restrict__ jobs) {
+  const BuildJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+
+  __shared__ double s_cls_p[kMaxClasses];
+  __shared__ uint32_t s_cls_key[kMaxClasses];
+  __shared__ uint64_t s_warp[kWaves];
+  __shared__ uint32_t s_u32[2 * kWaves];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_lvl_start[kMaxDepthCap + 2];
+  __shared__ Boundary s_bnd;
+  __shared__ int s_error;
+  __shared__ uint64_t s_sel_prefix, s_sel_need;
+
+  const double q[4] = {J.q[0], J.q[1], J.q[2], J.q[3]};
+  const int cap = J.cap;
+  const uint32_t n = J.n_items;
+  const uint32_t nb = static_cast<uint32_t>(J.n_buckets);
+  const uint64_t C = J.capacity;
+
+  if (tid == 0) {
+    s_error = 0;
+    s_bnd.p = 0.0; s_bnd.depth = 0; s_bnd.code = 0; s_bnd.all = 0;
+  }
+  __syncthreads();
+
+  // ---- 1. boundary node (VARIABLE) ------------------------------------------
+  if (J.mode == 1) {
+    // letter-count classes of every depth < cap
+    if (tid == 0) {
+      int K = 0;
+      for (int D = 0; D < cap; ++D)
+        for (int na = D; na >= 0; --na)
+          for (int nb_ = D - na; nb_ >= 0; --nb_)
+            for (int nc = D - na - nb_; nc >= 0; --nc) {
+              if (K < kMaxClasses) s_cls_key[K] = pack_class(na, nb_, nc, D - na - nb_ - nc);
+              ++K;
+            }
+      if (K > kMaxClasses) s_error = kBuildClasses;
+      s_u32[0] = K;
+    }
+    __syncthreads();
+    const int K = s_u32[0];
+    for (int i = tid; i < kMaxClasses; i += kBuildThreads) {
+      if (i < K) {
+        uint32_t key = s_cls_key[i];
+        s_cls_p[i] = path_prob(q, class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3));
+      } else {
+        s_cls_p[i] = -1.0;  // sentinel, sorts last
+        s_cls_key[i] = 0xFFFF0000u;
+      }
+    }
+    __syncthreads();
+    // bitonic sort: "before" first
+    for (int size = 2; size <= kMaxClasses; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = tid; t < kMaxClasses / 2; t += kBuildThreads) {
+          int i = 2 * t - (t & (stride - 1));
+          int j = i + stride;
+          double pi = s_cls_p[i], pj = s_cls_p[j];
+          int di = class_depth(s_cls_key[i]), dj = class_depth(s_cls_key[j]);
+          bool up = (i & size) == 0;
+          bool swap = up ? class_before(pj, dj, pi, di) : class_before(pi, di, pj, dj);
+          if (swap) {
+            s_cls_p[i] = pj; s_cls_p[j] = pi;
+            uint32_t tk = s_cls_key[i]; s_cls_key[i] = s_cls_key[j]; s_cls_key[j] = tk;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // the group of classes holding the t-th node, then the node itself
+    if (tid == 0 && s_error == 0) {
+      uint64_t before = 0;
+      int g0 = -1, g1 = -1;
+      for (int g = 0; g < K;) {
+        int h = g;
+        uint64_t cnt = 0;
+        while (h < K && s_cls_p[h] == s_cls_p[g] && class_depth(s_cls_key[h]) == class_depth(s_cls_key[g])) {
+          uint32_t key = s_cls_key[h];
+          cnt += multinomial(class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3));
+          ++h;
+        }
+        if (before + cnt >= J.n_expand) { g0 = g; g1 = h; break; }
+        before += cnt;
+        g = h;
+      }
+      if (g0 < 0) {
+        s_bnd.all = 1;
+      } else {
+        uint64_t r = J.n_expand - before - 1;  // rank of the last expanded node in the group
+        const int D = class_depth(s_cls_key[g0]);
+        int used[4] = {0, 0, 0, 0};
+        uint32_t code = 0;
+        for (int pos = 0; pos < D; ++pos) {
+          int chosen = 3;
+          for (int x = 0; x < 4; ++x) {
+            uint64_t cnt = 0;
+            for (int g = g0; g < g1; ++g) {
+              uint32_t key = s_cls_key[g];
+              int rem[4];
+              bool ok = true;
+              for (int y = 0; y < 4; ++y) {
+                rem[y] = class_n(key, y) - used[y] - (y == x ? 1 : 0);
+                ok = ok && rem[y] >= 0;
+              }
+              if (ok) cnt += multinomial(rem[0], rem[1], rem[2], rem[3]);
+            }
+            if (r < cnt) { chosen = x; break; }
+            r -= cnt;
+          }
+          used[chosen]++;
+          code = code * 4 + chosen;
+        }
+        s_bnd.p = s_cls_p[g0];
+        s_bnd.depth = D;
+        s_bnd.code = code;
+      }
+    }
+    __syncthreads();
+  }
+  const Boundary B = s_bnd;
+  if (s_error) goto finish;
+
+  // ---- 2. leaves in tree order ----------------------------------------------
+  if (J.mode == 0) {
+    const int ell = J.fixed_len;
+    for (uint32_t j = tid; j < n; j += kBuildThreads) {
+      int cnt[4];
+      letter_counts(j, ell, cnt);
+      uint32_t r, c;
+      split_code(j, ell, &r, &c);
+      J.item_len[j] = ell;
+      J.item_row[j] = r;
+      J.item_col[j] = c;
+      J.item_p[j] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+    }
+  } else {
+    // level-by-level expansion
+    if (tid == 0) {
+      J.lvl_code[0] = 0;
+      s_lvl_start[0] = 0;
+      s_lvl_start[1] = 1;
+    }
+    __syncthreads();
+    int D = 0;
+    for (; D < cap; ++D) {
+      const uint32_t start = s_lvl_start[D], end = s_lvl_start[D + 1];
+      if (start == end) break;
+      uint32_t next = end;
+      for (uint32_t base = start; base < end; base += kBuildThreads) {
+        const uint32_t i = base + tid;
+        uint32_t mask = 0, code = 0;
+        if (i < end) {
+          code = J.lvl_code[i];
+          int cnt[4];
+          letter_counts(code, D, cnt);
+          for (int x = 0; x < 4; ++x) {
+            cnt[x]++;
+            double p = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+            cnt[x]--;
+            if (node_expanded(B, 1, cap, 0, p, D + 1, code * 4 + x)) mask |= 1u << x;
+          }
+        }
+        uint64_t total;
+        uint32_t pos = next + static_cast<uint32_t>(block_exclusive_scan(__popc(mask), s_warp, &total));
+        if (i < end) {
+          J.lvl_mask[i] = static_cast<uint8_t>(mask);
+          J.lvl_first[i] = pos;
+          for (int x = 0; x < 4; ++x)
+            if (mask & (1u << x)) {
+              if (pos < J.n_expand) J.lvl_code[pos] = code * 4 + x;
+              else s_error = kBuildItemCount;
+              ++pos;
+            }
+        }
+        next += static_cast<uint32_t>(total);
+      }
+      if (tid == 0) s_lvl_start[D + 2] = next;
+      __syncthreads();
+      if (s_error) goto finish;
+    }
+    const int levels = D;  // levels 0..levels-1 are non-empty
+    if (tid == 0 && s_lvl_start[levels] != J.n_expand) s_error = kBuildItemCount;
+    __syncthreads();
+    if (s_error) goto finish;
+    // bottom-up leaf counts
+    for (int L = levels - 1; L >= 0; --L) {
+      for (uint32_t i = s_lvl_start[L] + tid; i < s_lvl_start[L + 1]; i += kBuildThreads) {
+        uint32_t mask = J.lvl_mask[i], f = J.lvl_first[i], size = 0;
+        for (int x = 0; x < 4; ++x) size += (mask & (1u << x)) ? J.lvl_size[f++] : 1u;
+        J.lvl_size[i] = size;
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && J.lvl_size[0] != n) s_error = kBuildItemCount;
+    __syncthreads();
+    if (s_error) goto finish;
+    // top-down leaf placement
+    if (tid == 0) J.lvl_off[0] = 0;
+    __syncthreads();
+    for (int L = 0; L < levels; ++L) {
+      for (uint32_t i = s_lvl_start[L] + tid; i < s_lvl_start[L + 1]; i += kBuildThreads) {
+        uint32_t mask = J.lvl_mask[i], f = J.lvl_first[i], cur = J.lvl_off[i], code = J.lvl_code[i];
+        int cnt[4];
+        letter_counts(code, L, cnt);
+        for (int x = 0; x < 4; ++x) {
+          if (mask & (1u << x)) {
+            J.lvl_off[f] = cur;
+            cur += J.lvl_size[f];
+            ++f;
+          } else {
+            uint32_t cc = code * 4 + x, r, c;
+            split_code(cc, L + 1, &r, &c);
+            cnt[x]++;
+            J.item_len[cur] = L + 1;
+            J.item_row[cur] = r;
+            J.item_col[cur] = c;
+            J.item_p[cur] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+            cnt[x]--;
+            ++cur;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t j = n + tid; j < nb; j += kBuildThreads) {
+    J.item_len[j] = 0; J.item_row[j] = 0; J.item_col[j] = 0; J.item_p[j] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- 3. weights by largest remainders -------------------------------------
+  {
+    uint64_t part = 0;
+    for (uint32_t j = tid; j < n; j += kBuildThreads) {
+      uint64_t fl;
+      frac_key(J.item_p[j], &fl);
+      part += fl;
+    }
+    const uint64_t sum = block_sum(part, s_warp);
+    const int64_t R = static_cast<int64_t>(1ull << 32) - static_cast<int64_t>(sum);
+    if (R < 0 || R > static_cast<int64_t>(n)) {
+      if (tid == 0) s_error = kBuildResidual;
+      __syncthreads();
+      goto finish;
+    }
+    // radix select of the R-th largest fractional part (its bit pattern)
+    if (tid == 0) { s_sel_prefix = 0; s_sel_need = static_cast<uint64_t>(R); }
+    __syncthreads();
+    if (R > 0) {
+      uint64_t pmask = 0;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += kBuildThreads) s_hist[i] = 0;
+        __syncthreads();
+        const uint64_t prefix = s_sel_prefix;
+        for (uint32_t j = tid; j < n; j += kBuildThreads) {
+          uint64_t fl, key = frac_key(J.item_p[j], &fl);
+          if ((key & pmask) == prefix) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          uint64_t need = s_sel_need;
+          int bin = 255;
+          for (; bin > 0; --bin) {
+            if (need <= s_hist[bin]) break;
+            need -= s_hist[bin];
+          }
+          s_sel_need = need;
+          s_sel_prefix = prefix | (static_cast<uint64_t>(bin) << shift);
+        }
+        pmask |= 255ull << shift;
+        __syncthreads();
+      }
+    }
+    const uint64_t tau = s_sel_prefix, take_ties = (R > 0) ? s_sel_need : 0;
+    // items above tau round up; ties at tau round up in index order
+    uint64_t tie_base = 0;
+    for (uint32_t base = 0; base < n; base += kBuildThreads) {
+      const uint32_t j = base + tid;
+      uint64_t fl = 0, key = 0;
+      bool tie = false;
+      if (j < n) {
+        key = frac_key(J.item_p[j], &fl);
+        tie = (R > 0) && key == tau;
+      }
+      uint64_t total;
+      uint64_t rank = tie_base + block_exclusive_scan(tie ? 1u : 0u, s_warp, &total);
+      if (j < n) {
+        bool up = (R > 0) && (key > tau || (tie && rank < take_ties));
+        J.item_w[j] = fl + (up ? 1u : 0u);
+      }
+      tie_base += total;
+    }
+    for (uint32_t j = n + tid; j < nb; j += kBuildThreads) J.item_w[j] = 0;
+    if (tid == 0) J.stats->residual = static_cast<uint64_t>(R);
+    __syncthreads();
+  }
+
+  // ---- 4. alias table ----------------------------------------------------------
+  {
+    uint64_t nl = 0, dsum = 0, esum = 0;
+    for (uint32_t base = 0; base < nb; base += kBuildThreads) {
+      const uint32_t j = base + tid;
+      uint64_t w = 0;
+      bool light = false, valid = j < nb;
+      if (valid) { w = J.item_w[j]; light = w < C; }
+      uint64_t t_l, t_d, t_e;
+      uint64_t lrank = nl + block_exclusive_scan(valid && light ? 1u : 0u, s_warp, &t_l);
+      uint64_t dpre = dsum + block_exclusive_scan(valid && light ? C - w : 0u, s_warp, &t_d);
+      uint64_t epre = esum + block_exclusive_scan(valid && !light ? w - C : 0u, s_warp, &t_e);
+      if (valid) {
+        if (light) {
+          J.light_idx[lrank] = j;
+          J.light_cum[lrank] = dpre + (C - w);
+        } else {
+          uint64_t hrank = j - lrank;
+          J.heavy_idx[hrank] = j;
+          J.heavy_cum[hrank] = epre + (w - C);
+        }
+      }
+      nl += t_l; dsum += t_d; esum += t_e;
+    }
+    __syncthreads();
+    const uint32_t n_light = static_cast<uint32_t>(nl), n_heavy = nb - n_light;
+    if (dsum != esum || n_heavy == 0) {
+      if (tid == 0) s_error = kBuildAlias;
+      __syncthreads();
+      goto finish;
+    }
+    for (uint32_t li = tid; li < n_light; li += kBuildThreads) {
+      const uint32_t j = J.light_idx[li];
+      const uint64_t prev = li > 0 ? J.light_cum[li - 1] : 0;
+      const uint32_t h = lower_bound_u64(J.heavy_cum, n_heavy, prev);
+      J.thr[j] = static_cast<uint32_t>(J.item_w[j]);
+      J.alias[j] = J.heavy_idx[h < n_heavy ? h : n_heavy - 1];
+    }
+    for (uint32_t hi = tid; hi < n_heavy; hi += kBuildThreads) {
+      const uint32_t j = J.heavy_idx[hi];
+      const uint64_t E = J.heavy_cum[hi];
+      if (E < dsum && hi + 1 < n_heavy) {
+        const uint32_t i = upper_bound_u64(J.light_cum, n_light, E);
+        J.thr[j] = static_cast<uint32_t>(C + E - J.light_cum[i < n_light ? i : n_light - 1]);
+        J.alias[j] = J.heavy_idx[hi + 1];
+      } else {
+        J.thr[j] = static_cast<uint32_t>(C);
+        J.alias[j] = j;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 5. hot-path records and statistics --------------------------------------
+  {
+    uint64_t wl = 0;
+    uint32_t mn = 0xFFFFFFFFu, mx = 0;
+    for (uint32_t i = tid; i < nb; i += kBuildThreads) {
+      const uint32_t a = J.alias[i];
+      const uint32_t ls = J.item_len[i], la = J.item_len[a];
+      BucketRecord r;
+      r.thr_abs = static_cast<uint32_t>(static_cast<uint64_t>(i) * C + (a == i ? 0u : J.thr[i]));
+      r.self_word = path_word(ls, J.item_row[i], J.item_col[i]);
+      r.alias_word = path_word(la, J.item_row[a], J.item_col[a]);
+      r.lens = ls | (la << 16);
+      J.records[i] = r;
+      if (i < n) {
+        wl += J.item_w[i] * ls;
+        mn = min(mn, ls);
+        mx = max(mx, ls);
+      }
+    }
+    const uint64_t sum_wl = block_sum(wl, s_warp);
+    uint32_t vmax;
+    const uint32_t vmin = block_min_max(mn, mx, s_u32, &vmax);
+    if (tid == 0) {
+      J.stats->sum_wl = sum_wl;
+      J.stats->min_len = vmin;
+      J.stats->max_len = vmax;
+    }
+  }
+
+finish:
+  __syncthreads();
+  if (tid == 0) {
+    J.stats->error = s_error;
+    J.stats->n_items = n;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(table_build_kernel, dim3(n_jobs), dim3(kBuildThreads), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+}  // namespace rmat

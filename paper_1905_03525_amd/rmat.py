@@ -1,0 +1,193 @@
+"""ctypes binding of librmat.so: the C ABI of include/rmat.h under the same
+names.  Argument marshalling only; every step runs in the HIP library.  torch
+supplies device memory and streams.  Importing this module loads nothing;
+the first call loads librmat.so and raises if it is missing (there is no
+fallback)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librmat.so")
+
+RMAT_FIXED = 0
+RMAT_VARIABLE = 1
+
+RMAT_OK = 0
+RMAT_EINVAL = -1
+RMAT_ENOMEM = -2
+RMAT_EDEVICE = -3
+RMAT_ERANGE = -4
+_STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE: "RMAT_EDEVICE",
+           RMAT_ERANGE: "RMAT_ERANGE"}
+
+# Every symbol include/rmat.h declares (checked by the CPU test suite).
+EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
+            "rmat_generate_async", "rmat_generate_reduce_async", "rmat_last_error"]
+
+
+class RmatError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rmat_info(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("path_mode", ctypes.c_int32), ("depth_cap", ctypes.c_int32),
+                ("bucket_bits", ctypes.c_int32), ("table_bound", ctypes.c_uint64), ("n_items", ctypes.c_uint64),
+                ("n_buckets", ctypes.c_uint64), ("capacity", ctypes.c_uint64), ("id_bytes", ctypes.c_uint32),
+                ("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("lds_resident", ctypes.c_uint32),
+                ("expected_len", ctypes.c_double), ("export_bytes", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads librmat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1905_03525_amd.build "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, c_int = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    L.rmat_build_table.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, ctypes.POINTER(vp)]
+    L.rmat_free_table.argtypes = [vp]
+    L.rmat_table_info.argtypes = [vp, ctypes.POINTER(rmat_info)]
+    L.rmat_table_export.argtypes = [vp, vp, ctypes.c_size_t]
+    L.rmat_generate.argtypes = [vp, u64, u64, u64, vp, vp]
+    L.rmat_generate_async.argtypes = [vp, u64, u64, u64, vp, vp, vp]
+    L.rmat_generate_reduce_async.argtypes = [vp, u64, u64, u64, c_int, vp, vp, vp]
+    L.rmat_last_error.argtypes = []
+    L.rmat_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "rmat_last_error":
+            getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, func: str):
+    if status != RMAT_OK:
+        raise RmatError(status, func, load().rmat_last_error().decode())
+
+
+def _ptr(x) -> int | None:
+    """Device pointer of a torch tensor, or an int address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Table:
+    """Owning handle of an rmat_table_t."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            _check(load().rmat_free_table(self.handle), "rmat_free_table")
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rmat_free_table(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def rmat_build_table(a: float, b: float, c: float, d: float, k: int, table_bound: int, path_mode: int) -> Table:
+    h = ctypes.c_void_p()
+    _check(load().rmat_build_table(a, b, c, d, k, table_bound, path_mode, ctypes.byref(h)), "rmat_build_table")
+    return Table(h.value)
+
+
+def rmat_free_table(t: Table):
+    t.close()
+
+
+def rmat_table_info(t: Table) -> dict:
+    info = rmat_info()
+    _check(load().rmat_table_info(t.handle, ctypes.byref(info)), "rmat_table_info")
+    return {name: getattr(info, name) for name, _ in rmat_info._fields_}
+
+
+def rmat_table_export(t: Table) -> dict:
+    """Canonical table arrays (see include/rmat.h) as numpy arrays."""
+    info = rmat_table_info(t)
+    nb = info["n_buckets"]
+    buf = np.zeros(info["export_bytes"], dtype=np.uint8)
+    _check(load().rmat_table_export(t.handle, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes), "rmat_table_export")
+    out, off = {}, 0
+    for name, dt in (("w", np.uint64), ("p", np.float64), ("len", np.uint32), ("row", np.uint32),
+                     ("col", np.uint32), ("thr", np.uint32), ("alias", np.uint32)):
+        n = nb * np.dtype(dt).itemsize
+        out[name] = buf[off:off + n].view(dt).copy()
+        off += n
+    return out
+
+
+def rmat_generate(t: Table, seed: int, edge_begin: int, m: int, out_src, out_dst):
+    _check(load().rmat_generate(t.handle, seed, edge_begin, m, _ptr(out_src), _ptr(out_dst)), "rmat_generate")
+
+
+def rmat_generate_async(t: Table, seed: int, edge_begin: int, m: int, out_src, out_dst, stream=None):
+    _check(load().rmat_generate_async(t.handle, seed, edge_begin, m, _ptr(out_src), _ptr(out_dst),
+                                      _stream(stream)), "rmat_generate_async")
+
+
+def rmat_generate_reduce_async(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int, d_hist, d_xor,
+                               stream=None):
+    _check(load().rmat_generate_reduce_async(t.handle, seed, edge_begin, m, hist_bits, _ptr(d_hist), _ptr(d_xor),
+                                             _stream(stream)), "rmat_generate_reduce_async")
+
+
+def rmat_last_error() -> str:
+    return load().rmat_last_error().decode()
+
+
+def id_dtype(k: int):
+    """torch dtype holding the ids of a table with this k (bit patterns)."""
+    import torch
+    return torch.int32 if k <= 32 else torch.int64
+
+
+def to_numpy_ids(x, k: int) -> np.ndarray:
+    """Device id tensor -> numpy array of uint32 / uint64."""
+    a = x.cpu().numpy()
+    return a.view(np.uint32 if k <= 32 else np.uint64)
+
+
+def generate_edges(t: Table, seed: int, edge_begin: int, m: int, device="cuda", stream=None):
+    """Allocates (src, dst) on the device and enqueues rmat_generate_async on
+    `stream` (default: torch's current stream)."""
+    import torch
+    k = rmat_table_info(t)["k"]
+    src = torch.empty(m, dtype=id_dtype(k), device=device)
+    dst = torch.empty(m, dtype=id_dtype(k), device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device)
+    rmat_generate_async(t, seed, edge_begin, m, src, dst, stream)
+    return src, dst

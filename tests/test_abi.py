@@ -1,0 +1,62 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid tables before touching a device."""
+from __future__ import annotations
+
+import os
+import re
+
+import pytest
+
+import paper_1905_03525_amd as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(rmat\w*)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = R.load()
+    declared = _declared()
+    assert declared, "no declarations found"
+    missing = [n for n in sorted(declared) if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(R.rmat.EXPORTED) <= declared
+
+
+@pytest.mark.parametrize("args", [
+    (0.5, 0.5, 0.1, -0.1, 10, 100, R.RMAT_VARIABLE),
+    (0.5, 0.2, 0.2, 0.2, 10, 100, R.RMAT_VARIABLE),
+    (0.25, 0.25, 0.25, 0.25, 0, 100, R.RMAT_VARIABLE),
+    (0.25, 0.25, 0.25, 0.25, 65, 100, R.RMAT_VARIABLE),
+    (0.25, 0.25, 0.25, 0.25, 10, 4, R.RMAT_VARIABLE),
+    (0.25, 0.25, 0.25, 0.25, 10, 3, R.RMAT_FIXED),
+    (0.25, 0.25, 0.25, 0.25, 2, 256, R.RMAT_FIXED),
+    (0.25, 0.25, 0.25, 0.25, 20, 2**24 + 1, R.RMAT_VARIABLE),
+    (0.25, 0.25, 0.25, 0.25, 20, 100, 2),
+    (float("nan"), 0.5, 0.25, 0.25, 10, 100, R.RMAT_VARIABLE),
+    (float("inf"), 0.5, 0.25, 0.25, 10, 100, R.RMAT_VARIABLE),
+])
+def test_invalid_tables_rejected_on_host(args):
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_build_table(*args)
+    assert ei.value.status == R.RMAT_EINVAL
+    assert R.rmat_last_error()
+
+
+def test_null_handles():
+    import ctypes
+    L = R.load()
+    assert L.rmat_free_table(None) == R.RMAT_OK
+    assert L.rmat_generate(None, 1, 0, 10, None, None) == R.RMAT_EINVAL
+    assert L.rmat_table_info(None, None) == R.RMAT_EINVAL
+    assert L.rmat_table_export(None, None, 0) == R.RMAT_EINVAL
+    assert L.rmat_build_table(0.25, 0.25, 0.25, 0.25, 10, 100, 1, ctypes.cast(0, ctypes.POINTER(ctypes.c_void_p))) \
+        == R.RMAT_EINVAL

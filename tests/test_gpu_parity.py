@@ -1,0 +1,186 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Tables must match the oracle bit for bit (weights, canonical probabilities,
+paths, thresholds, aliases); edges must match exactly (integer work).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+G500 = (0.57, 0.19, 0.19, 0.05)
+SKEW = (0.9, 0.025, 0.025, 0.05)
+CFG3 = (0.45, 0.22, 0.22, 0.11)
+
+
+def _dirichlet(seed):
+    q = np.random.default_rng(seed).dirichlet([4, 2, 2, 1])
+    q[3] = 1.0 - q[0] - q[1] - q[2]
+    return tuple(float(x) for x in q)
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_03525_amd as R
+    R.load()
+    return R
+
+
+def _gen(R, t, k, seed, e0, m):
+    import torch
+    src, dst = R.generate_edges(t, seed, e0, m)
+    torch.cuda.synchronize()
+    return R.to_numpy_ids(src, k), R.to_numpy_ids(dst, k)
+
+
+TABLE_CASES = [
+    (G500, 16, 256, oracle.FIXED),
+    (G500, 26, 4096, oracle.VARIABLE),
+    (CFG3, 34, 1 << 16, oracle.VARIABLE),
+    (SKEW, 30, 8192, oracle.VARIABLE),
+    (SKEW, 30, 1 << 18, oracle.VARIABLE),
+    (G500, 30, 1 << 20, oracle.VARIABLE),
+    (G500, 30, 1 << 20, oracle.FIXED),
+    ((0.25, 0.25, 0.25, 0.25), 20, 100, oracle.VARIABLE),
+    ((0.25, 0.25, 0.25, 0.25), 20, 5000, oracle.VARIABLE),
+    ((0.25, 0.25, 0.25, 0.25), 12, 1 << 16, oracle.VARIABLE),
+    ((1.0, 0.0, 0.0, 0.0), 20, 300, oracle.VARIABLE),
+    ((0.5, 0.5, 0.0, 0.0), 20, 300, oracle.VARIABLE),
+    ((0.6, 0.0, 0.3, 0.1), 10, 64, oracle.FIXED),
+    (G500, 26, 5, oracle.VARIABLE),
+    (G500, 26, 6, oracle.VARIABLE),
+    (G500, 26, 7, oracle.VARIABLE),
+    (G500, 26, 4, oracle.FIXED),
+    (G500, 1, 100, oracle.VARIABLE),
+    (G500, 2, 1000, oracle.VARIABLE),
+    (G500, 3, 5000, oracle.VARIABLE),
+    (G500, 64, 4096, oracle.VARIABLE),
+] + [(_dirichlet(s), 10 + s, 64 + 997 * s, oracle.VARIABLE) for s in range(1, 12)]
+
+
+@pytest.mark.parametrize("q,k,bound,mode", TABLE_CASES)
+def test_table_parity(R, q, k, bound, mode):
+    t = R.rmat_build_table(*q, k, bound, mode)
+    g = R.rmat_table_export(t)
+    info = R.rmat_table_info(t)
+    o = oracle.build_table(*q, k, bound, mode)
+    assert info["n_items"] == o.n_items and info["bucket_bits"] == o.bucket_bits
+    assert info["capacity"] == o.capacity and info["depth_cap"] == o.cap
+    assert np.array_equal(g["len"], o.length.astype(np.uint32))
+    assert np.array_equal(g["row"], o.row) and np.array_equal(g["col"], o.col)
+    assert np.array_equal(g["p"].view(np.uint64), o.p.view(np.uint64))  # bit-exact FP64 products
+    assert np.array_equal(g["w"], o.w.astype(np.uint64))
+    assert np.array_equal(g["thr"], o.thr) and np.array_equal(g["alias"], o.alias)
+    assert info["expected_len"] == pytest.approx(o.expected_len, rel=0, abs=1e-12)
+    t.close()
+
+
+EDGE_CASES = [
+    # q, k, bound, mode, seed, edge_begin, m
+    (G500, 16, 256, oracle.FIXED, 1, 0, 1 << 20),          # workload of the 2^20-edge, k=16 instance
+    (G500, 26, 4096, oracle.VARIABLE, 7, 0, 300_001),
+    (G500, 26, 4096, oracle.VARIABLE, 7, 12_345_677, 100_000),
+    (CFG3, 34, 1 << 16, oracle.VARIABLE, 3, 2**30 * 5 + 11, 200_003),
+    (CFG3, 34, 1 << 16, oracle.VARIABLE, 3, 2**32 - 1000, 5000),   # crosses e_hi
+    (SKEW, 30, 8192, oracle.VARIABLE, 99, 1, 70_000),
+    (SKEW, 64, 8192, oracle.VARIABLE, 2**64 - 1, 2**64 - 5000, 5000),  # last edges of the stream
+    (G500, 32, 1024, oracle.FIXED, 5, 63, 65),
+    (G500, 33, 1024, oracle.FIXED, 5, 64, 64),
+    (G500, 31, 4096, oracle.VARIABLE, 5, 3, 1),
+    (G500, 1, 5, oracle.VARIABLE, 5, 0, 1000),
+    (G500, 5, 4096, oracle.VARIABLE, 5, 0, 10_000),
+    (_dirichlet(3), 48, 20_000, oracle.VARIABLE, 17, 10**12, 40_000),
+    (_dirichlet(4), 20, 1 << 14, oracle.FIXED, 18, 0, 40_000),
+    ((0.25, 0.25, 0.25, 0.25), 26, 5000, oracle.VARIABLE, 19, 0, 40_000),
+    ((1.0, 0.0, 0.0, 0.0), 26, 300, oracle.VARIABLE, 20, 0, 1000),
+    (G500, 28, 1 << 20, oracle.VARIABLE, 21, 0, 100_000),   # global-memory (L2) table
+]
+
+
+@pytest.mark.parametrize("q,k,bound,mode,seed,e0,m", EDGE_CASES)
+def test_edge_parity(R, q, k, bound, mode, seed, e0, m):
+    t = R.rmat_build_table(*q, k, bound, mode)
+    gs, gd = _gen(R, t, k, seed, e0, m)
+    o = oracle.build_table(*q, k, bound, mode)
+    os_, od = oracle.generate(o, seed, e0, m, threads=8)
+    assert gs.dtype == os_.dtype
+    bad = np.nonzero((gs != os_) | (gd != od))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first at slot {bad[:5]}"
+    t.close()
+
+
+def test_chunk_invariance_and_determinism(R):
+    k = 26
+    t = R.rmat_build_table(*G500, k, 4096, R.RMAT_VARIABLE)
+    s, d = _gen(R, t, k, 11, 1000, 500_000)
+    s2, d2 = _gen(R, t, k, 11, 1000, 500_000)
+    assert np.array_equal(s, s2) and np.array_equal(d, d2)
+    parts = [(1000, 1), (1001, 63), (1064, 200_000), (201_064, 299_936)]
+    cs = np.concatenate([_gen(R, t, k, 11, b, n)[0] for b, n in parts])
+    cd = np.concatenate([_gen(R, t, k, 11, b, n)[1] for b, n in parts])
+    assert np.array_equal(s, cs) and np.array_equal(d, cd)
+    t.close()
+
+
+def test_errors_and_noops(R):
+    import torch
+    t = R.rmat_build_table(*G500, 20, 4096, R.RMAT_VARIABLE)
+    R.rmat_generate(t, 1, 0, 0, None, None)  # m = 0 is a no-op
+    x = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_generate(t, 1, 2**64 - 2, 4, x, x)
+    assert ei.value.status == R.RMAT_ERANGE
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_generate(t, 1, 0, 4, None, x)
+    assert ei.value.status == R.RMAT_EINVAL
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_generate(t, 1, 0, 2, x.data_ptr() + 2, x)
+    assert ei.value.status == R.RMAT_EINVAL
+    t.close()
+
+
+def test_workload_k26_full_parity(R):
+    """The 2^30-edge, k = 26, 4096-entry variable-table instance (seed 7), in
+    the launch configuration the benchmark times: one call for all edges.
+    Every edge is compared with the oracle in 2^26-edge slices."""
+    import torch
+    k, m, seed = 26, 1 << 30, 7
+    t = R.rmat_build_table(*G500, k, 4096, R.RMAT_VARIABLE)
+    src, dst = R.generate_edges(t, seed, 0, m)
+    torch.cuda.synchronize()
+    assert int(src.max()) < 2**k and int(dst.max()) < 2**k and int(src.min()) >= 0
+    o = oracle.build_table(*G500, k, 4096, oracle.VARIABLE)
+    sl = 1 << 26
+    for i in range(m // sl):
+        gs = R.to_numpy_ids(src[i * sl:(i + 1) * sl], k)
+        gd = R.to_numpy_ids(dst[i * sl:(i + 1) * sl], k)
+        os_, od = oracle.generate(o, seed, i * sl, sl, threads=16)
+        assert np.array_equal(gs, os_) and np.array_equal(gd, od), f"slice {i}"
+    del src, dst
+    t.close()
+
+
+def test_chunk_reduce_parity(R):
+    """Device-side reduction (source-prefix histogram + XOR checksum) of a
+    k = 34 instance with a 2^16-entry table, one chunk at a slice of its
+    full size, compared with the oracle's reduction."""
+    import torch
+    k, seed = 34, 3
+    t = R.rmat_build_table(*CFG3, k, 1 << 16, R.RMAT_VARIABLE)
+    o = oracle.build_table(*CFG3, k, 1 << 16, oracle.VARIABLE)
+    for e0, m in ((0, 1 << 24), (15 * 2**30 + 2**30 - (1 << 22), 1 << 22), (12345, 1000)):
+        hist = torch.zeros(1 << 16, dtype=torch.int64, device="cuda")
+        xr = torch.zeros(1, dtype=torch.int64, device="cuda")
+        R.rmat_generate_reduce_async(t, seed, e0, m, 16, hist, xr, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        oh, ox = oracle.generate_reduce(o, seed, e0, m, hist_bits=16, threads=16)
+        assert np.array_equal(hist.cpu().numpy().view(np.uint64), oh)
+        assert int(xr.cpu().numpy().view(np.uint64)[0]) == ox
+    t.close()
