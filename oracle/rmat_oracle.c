@@ -544,7 +544,8 @@ static int run_threads(work_t* proto, uint64_t m, int threads,
 int orc_generate(const orc_table* t, uint64_t seed, uint64_t edge_begin,
                  uint64_t m, void* src, void* dst, int width,
                  uint32_t* n_samples, int threads) {
-  if (edge_begin + m < edge_begin) return ORC_ERANGE;
+  /* the last edge of the stream is 2^64 - 1 */
+  if (m > 0 && edge_begin + (m - 1) < edge_begin) return ORC_ERANGE;
   if (width != 4 && width != 8) return ORC_EINVAL;
   if (width == 4 && t->k > 32) return ORC_EINVAL;
   if (m == 0) return ORC_OK;
@@ -565,7 +566,7 @@ int orc_generate(const orc_table* t, uint64_t seed, uint64_t edge_begin,
 int orc_generate_reduce(const orc_table* t, uint64_t seed, uint64_t edge_begin,
                         uint64_t m, int hist_bits, uint64_t* hist,
                         uint64_t* xor_out, int threads) {
-  if (edge_begin + m < edge_begin) return ORC_ERANGE;
+  if (m > 0 && edge_begin + (m - 1) < edge_begin) return ORC_ERANGE;
   if (hist_bits < 0 || hist_bits > t->k || hist_bits > 24) return ORC_EINVAL;
   uint64_t nbins = 1ull << hist_bits;
   memset(hist, 0, nbins * sizeof(uint64_t));
