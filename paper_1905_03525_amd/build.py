@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librmat.so")
 
-SOURCES = ["table_build.hip", "generate.hip", "api.cpp"]
+SOURCES = ["table_build.hip", "generate.hip", "microbench.hip", "api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -27,7 +27,8 @@ def hipcc() -> str:
 
 def build(force: bool = True, verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    deps = srcs + [os.path.join(CSRC, "rmat_internal.h"), os.path.join(ROOT, "include", "rmat.h")]
+    deps = srcs + [os.path.join(CSRC, "rmat_internal.h"), os.path.join(ROOT, "include", "rmat.h"),
+                   os.path.join(ROOT, "include", "rmat_bench.h")]
     if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
         return LIB
     tmp = LIB + f".tmp{os.getpid()}"

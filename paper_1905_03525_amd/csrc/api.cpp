@@ -100,6 +100,25 @@ int check_device() {
 
 }  // namespace
 
+namespace rmat {
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  g_err[0] = '\0';
+  return RMAT_OK;
+}
+
+}  // namespace rmat
+
 extern "C" {
 
 const char* rmat_last_error(void) { return g_err; }

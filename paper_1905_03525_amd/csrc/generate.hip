@@ -3,89 +3,113 @@
 // the sampling loop), plus the variant that reduces edges on the device
 // instead of storing them.
 //
-// Work split: the absolute edge index space is cut into 64-edge blocks
-// aligned to multiples of 64, one block per wave at a time, so the high
-// counter word e >> 32 is uniform across a wave and every store instruction
-// covers 64 consecutive slots (256 or 512 contiguous bytes per id array).
+// Work split.  The absolute edge index space is cut into 64-edge blocks
+// aligned to multiples of 64, so the high counter word e >> 32 is uniform
+// across a wave and every store instruction covers 64 consecutive slots.  A
+// wave takes its blocks in tiles of up to 8 (wave, wave + W, wave + 2W, ...
+// for W waves in the grid) and runs each tile in three passes over a private
+// LDS area:
+//   1. every edge of the tile draws its first Philox block (4 samples); the
+//      row/column bits go to the LDS area, and edges still short of k
+//      letters (11% of them at k = 26 with the 4093-path table) are appended
+//      to a compact list;
+//   2. the listed edges continue 64 at a time with counter blocks 1, 2, ...,
+//      so a second Philox block is only paid for edges that need it;
+//   3. the tile is written out block by block, 64 consecutive ids per store,
+//      every cache line written once and whole.
 #include "rmat_internal.h"
 
 namespace rmat {
 namespace {
 
-constexpr int kGenThreads = 512;
+constexpr int kGenThreads = 1024;  // 16 waves share one LDS copy of the table
+constexpr int kWaves = kGenThreads / 64;
+constexpr uint32_t kMaxTile = 8;
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
-// multiplications, the key bumped by the Weyl constants between rounds.
-__device__ __forceinline__ void philox10(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3,
-                                         uint32_t k0, uint32_t k1) {
+// products (one v_mad_u64_u32 each) and three-input XORs (v_bitop3_b32,
+// truth table 0x96), the key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox10(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3, uint32_t k0,
+                                         uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = kPhiloxM0 * x0, hi0 = __umulhi(kPhiloxM0, x0);
-    const uint32_t lo1 = kPhiloxM1 * x2, hi1 = __umulhi(kPhiloxM1, x2);
-    const uint32_t y0 = hi1 ^ x1 ^ k0;
-    const uint32_t y2 = hi0 ^ x3 ^ k1;
-    x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+    const uint64_t p0 = static_cast<uint64_t>(x0) * kPhiloxM0;
+    const uint64_t p1 = static_cast<uint64_t>(x2) * kPhiloxM1;
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), x1, k0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), x3, k1, 0x96);
+    x0 = y0;
+    x1 = static_cast<uint32_t>(p1);
+    x2 = y2;
+    x3 = static_cast<uint32_t>(p0);
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
   }
 }
 
+// Row/column accumulators, left-aligned: letter t of the edge lands at bit
+// (W - 1 - t); ids are the top k bits at the end.
 struct Acc32 {
+  using Id = uint32_t;
+  using Packed = uint2;
   uint32_t row, col;
+  __device__ __forceinline__ void clear() { row = 0; col = 0; }
   __device__ __forceinline__ void append(uint32_t rowL, uint32_t colL, uint32_t filled) {
     row |= rowL >> filled;
     col |= colL >> filled;
   }
-  __device__ __forceinline__ uint32_t src(int k) const { return row >> (32 - k); }
-  __device__ __forceinline__ uint32_t dst(int k) const { return col >> (32 - k); }
+  __device__ __forceinline__ uint32_t src(uint32_t k) const { return row >> (32 - k); }
+  __device__ __forceinline__ uint32_t dst(uint32_t k) const { return col >> (32 - k); }
+  __device__ __forceinline__ Packed pack() const { return make_uint2(row, col); }
+  __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
 
 struct Acc64 {
+  using Id = uint64_t;
+  using Packed = ulonglong2;
   uint64_t row, col;
+  __device__ __forceinline__ void clear() { row = 0; col = 0; }
   __device__ __forceinline__ void append(uint32_t rowL, uint32_t colL, uint32_t filled) {
     row |= (static_cast<uint64_t>(rowL) << 32) >> filled;
     col |= (static_cast<uint64_t>(colL) << 32) >> filled;
   }
-  __device__ __forceinline__ uint64_t src(int k) const { return row >> (64 - k); }
-  __device__ __forceinline__ uint64_t dst(int k) const { return col >> (64 - k); }
+  __device__ __forceinline__ uint64_t src(uint32_t k) const { return row >> (64 - k); }
+  __device__ __forceinline__ uint64_t dst(uint32_t k) const { return col >> (64 - k); }
+  __device__ __forceinline__ Packed pack() const { return make_ulonglong2(row, col); }
+  __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
 
+// Up to four samples from one Philox block, stopping at k letters.  A sample
+// x picks bucket x >> (32 - b) and keeps the bucket's own path when x <
+// thr_abs (= bucket * C + T), else takes its alias.  The four bucket records
+// are read before any of them is used, so four LDS reads are in flight.
 template <typename Acc>
-struct IdOf;
-template <>
-struct IdOf<Acc32> { using type = uint32_t; };
-template <>
-struct IdOf<Acc64> { using type = uint64_t; };
-
-// One alias sample: bucket x >> (32 - b); own item when x < thr_abs.
-template <typename Acc>
-__device__ __forceinline__ void sample(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t x,
-                                       Acc& acc, uint32_t& filled) {
-  const BucketRecord r = tab[x >> shift];
-  const bool own = x < r.thr_abs;
-  const uint32_t word = own ? r.self_word : r.alias_word;
-  const uint32_t len = own ? (r.lens & 0xFFFFu) : (r.lens >> 16);
-  acc.append(word & 0xFFFF0000u, word << 16, filled);
-  filled += len;
-}
-
-// Draws edge e: Philox counter blocks j = 0, 1, ... until k letters are known.
-template <typename Acc>
-__device__ __forceinline__ void draw_edge(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k,
-                                          uint32_t key0, uint32_t key1, uint64_t e, Acc& acc) {
-  acc.row = 0;
-  acc.col = 0;
-  uint32_t filled = 0;
-  const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
-  for (uint32_t j = 0; filled < k; ++j) {
-    uint32_t x0 = e_lo, x1 = e_hi, x2 = j, x3 = 0;
-    philox10(x0, x1, x2, x3, key0, key1);
-    sample(tab, shift, x0, acc, filled);
-    if (filled < k) sample(tab, shift, x1, acc, filled);
-    if (filled < k) sample(tab, shift, x2, acc, filled);
-    if (filled < k) sample(tab, shift, x3, acc, filled);
+__device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
+                                        uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled) {
+  const BucketRecord r0 = tab[x0 >> shift], r1 = tab[x1 >> shift], r2 = tab[x2 >> shift], r3 = tab[x3 >> shift];
+  // keep the reads ahead of the branches below (an operand-only asm, no code)
+  __asm__ volatile("" ::"v"(r1.thr_abs), "v"(r1.self_word), "v"(r1.alias_word), "v"(r1.lens), "v"(r2.thr_abs),
+                   "v"(r2.self_word), "v"(r2.alias_word), "v"(r2.lens), "v"(r3.thr_abs), "v"(r3.self_word),
+                   "v"(r3.alias_word), "v"(r3.lens));
+  const bool o0 = x0 < r0.thr_abs, o1 = x1 < r1.thr_abs, o2 = x2 < r2.thr_abs, o3 = x3 < r3.thr_abs;
+  const uint32_t w0 = o0 ? r0.self_word : r0.alias_word, l0 = o0 ? (r0.lens & 0xFFFFu) : (r0.lens >> 16);
+  const uint32_t w1 = o1 ? r1.self_word : r1.alias_word, l1 = o1 ? (r1.lens & 0xFFFFu) : (r1.lens >> 16);
+  const uint32_t w2 = o2 ? r2.self_word : r2.alias_word, l2 = o2 ? (r2.lens & 0xFFFFu) : (r2.lens >> 16);
+  const uint32_t w3 = o3 ? r3.self_word : r3.alias_word, l3 = o3 ? (r3.lens & 0xFFFFu) : (r3.lens >> 16);
+  acc.append(w0 & 0xFFFF0000u, w0 << 16, filled);
+  filled += l0;
+  if (filled < k) {
+    acc.append(w1 & 0xFFFF0000u, w1 << 16, filled);
+    filled += l1;
+    if (filled < k) {
+      acc.append(w2 & 0xFFFF0000u, w2 << 16, filled);
+      filled += l2;
+      if (filled < k) {
+        acc.append(w3 & 0xFFFF0000u, w3 << 16, filled);
+        filled += l3;
+      }
+    }
   }
 }
 
@@ -95,6 +119,9 @@ struct Launch {
   uint32_t shift;  // 32 - b
   uint32_t k;
   uint32_t key0, key1;
+  uint32_t tile;        // blocks per tile
+  uint32_t lds_table;   // LDS bytes holding the table (0: read from global memory)
+  uint32_t wave_bytes;  // LDS bytes of one wave's tile area
   uint64_t edge_begin, m;
   uint64_t first_block, n_blocks;
   void* out_src;
@@ -103,37 +130,6 @@ struct Launch {
   unsigned long long* hist;
   unsigned long long* xor_out;
 };
-
-__device__ __forceinline__ const BucketRecord* stage_table(const Launch& P, bool lds, BucketRecord* s_tab) {
-  if (!lds) return P.records;
-  const uint4* src = reinterpret_cast<const uint4*>(P.records);
-  uint4* dst = reinterpret_cast<uint4*>(s_tab);
-  for (uint32_t i = threadIdx.x; i < P.n_buckets; i += blockDim.x) dst[i] = src[i];
-  __syncthreads();
-  return s_tab;
-}
-
-template <typename Acc, bool kLds>
-__global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
-  extern __shared__ BucketRecord s_tab[];
-  using Id = typename IdOf<Acc>::type;
-  const BucketRecord* tab = stage_table(P, kLds, s_tab);
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
-  Id* __restrict__ out_src = static_cast<Id*>(P.out_src);
-  Id* __restrict__ out_dst = static_cast<Id*>(P.out_dst);
-  const uint64_t end = P.edge_begin + (P.m - 1);  // last edge, no overflow
-  for (uint64_t blk = wave; blk < P.n_blocks; blk += n_waves) {
-    const uint64_t e = ((P.first_block + blk) << 6) + lane;
-    if (e < P.edge_begin || e > end) continue;
-    Acc acc;
-    draw_edge(tab, P.shift, P.k, P.key0, P.key1, e, acc);
-    const uint64_t slot = e - P.edge_begin;
-    out_src[slot] = static_cast<Id>(acc.src(P.k));
-    out_dst[slot] = static_cast<Id>(acc.dst(P.k));
-  }
-}
 
 // MurmurHash3's 64-bit finaliser.
 __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
@@ -145,78 +141,175 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
   return z;
 }
 
-template <typename Acc, bool kLds>
-__global__ __launch_bounds__(kGenThreads) void generate_reduce_kernel(Launch P) {
-  extern __shared__ BucketRecord s_tab[];
-  __shared__ unsigned long long s_xor[kGenThreads / 64];
-  const BucketRecord* tab = stage_table(P, kLds, s_tab);
+// Orders this wave's LDS accesses across the passes of a tile.
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+template <typename Acc, bool kLds, bool kReduce>
+__global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
+  extern __shared__ __align__(16) unsigned char s_mem[];
+  __shared__ unsigned long long s_xor[kWaves];
+  using Id = typename Acc::Id;
+  using Packed = typename Acc::Packed;
+
+  // stage the table
+  const BucketRecord* tab = P.records;
+  if (kLds) {
+    const uint4* src = reinterpret_cast<const uint4*>(P.records);
+    uint4* dst = reinterpret_cast<uint4*>(s_mem);
+    for (uint32_t i = threadIdx.x; i < P.n_buckets; i += kGenThreads) dst[i] = src[i];
+    __syncthreads();
+    tab = reinterpret_cast<const BucketRecord*>(s_mem);
+  }
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
-  const uint64_t end = P.edge_begin + (P.m - 1);
-  uint64_t x = 0;
-  for (uint64_t blk = wave; blk < P.n_blocks; blk += n_waves) {
-    const uint64_t e = ((P.first_block + blk) << 6) + lane;
-    if (e < P.edge_begin || e > end) continue;
-    Acc acc;
-    draw_edge(tab, P.shift, P.k, P.key0, P.key1, e, acc);
-    const uint64_t s = acc.src(P.k), d = acc.dst(P.k);
-    atomicAdd(&P.hist[P.hist_shift >= 64 ? 0 : (s >> P.hist_shift)], 1ull);
-    x ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
+  const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * kWaves + wave_in_wg;
+  const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * kWaves;
+  Packed* res = reinterpret_cast<Packed*>(s_mem + P.lds_table + wave_in_wg * P.wave_bytes);
+  uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.tile * 64);
+  const uint64_t last = P.edge_begin + (P.m - 1);  // last edge, no overflow
+  uint64_t xsum = 0;
+
+  for (uint64_t t0 = wave; t0 < P.n_blocks; t0 += n_waves * P.tile) {
+    const uint64_t left = (P.n_blocks - t0 + n_waves - 1) / n_waves;
+    const uint32_t nb_tile = left < P.tile ? static_cast<uint32_t>(left) : P.tile;
+
+    // pass 1: first Philox block of every edge of the tile
+    uint32_t n_ovf = 0;
+    for (uint32_t j = 0; j < nb_tile; ++j) {
+      const uint64_t base = (P.first_block + t0 + j * n_waves) << 6;  // wave-uniform
+      const uint64_t e = base + lane;
+      const uint64_t lo = P.edge_begin > base ? P.edge_begin - base : 0;
+      const uint64_t hi = last - base < 63 ? last - base : 63;
+      const uint64_t amask = (~0ull << lo) & (~0ull >> (63 - hi));
+      Acc acc;
+      acc.clear();
+      uint32_t filled = 0;
+      uint32_t x0 = static_cast<uint32_t>(e), x1 = static_cast<uint32_t>(base >> 32), x2 = 0, x3 = 0;
+      philox10(x0, x1, x2, x3, P.key0, P.key1);
+      sample4(tab, P.shift, P.k, x0, x1, x2, x3, acc, filled);
+      res[j * 64 + lane] = acc.pack();
+      const uint64_t ovf_mask = __ballot(filled < P.k) & amask;
+      if (ovf_mask != 0) {
+        if ((ovf_mask >> lane) & 1ull) {
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+              static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
+          ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
+        }
+        n_ovf += __popcll(ovf_mask);
+      }
+    }
+    wave_lds_fence();
+
+    // pass 2: the unfinished edges, 64 at a time, counter blocks 1, 2, ...
+    for (uint32_t q = 0; q < n_ovf; q += 64) {
+      if (q + lane < n_ovf) {
+        const uint32_t entry = ovf[q + lane];
+        const uint32_t idx = entry >> 6;
+        uint32_t filled = entry & 63u;
+        Acc acc;
+        acc.unpack(res[idx]);
+        const uint64_t e = ((P.first_block + t0 + (idx >> 6) * n_waves) << 6) + (idx & 63u);
+        const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
+        for (uint32_t jj = 1; filled < P.k; ++jj) {
+          uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = 0;
+          philox10(x0, x1, x2, x3, P.key0, P.key1);
+          sample4(tab, P.shift, P.k, x0, x1, x2, x3, acc, filled);
+        }
+        res[idx] = acc.pack();
+      }
+    }
+    wave_lds_fence();
+
+    // pass 3: write the tile out (or fold it into the reduction)
+    for (uint32_t j = 0; j < nb_tile; ++j) {
+      const uint64_t base = (P.first_block + t0 + j * n_waves) << 6;
+      const uint64_t e = base + lane;
+      Acc acc;
+      acc.unpack(res[j * 64 + lane]);
+      if (e >= P.edge_begin && e <= last) {
+        if (kReduce) {
+          const uint64_t s = acc.src(P.k), d = acc.dst(P.k);
+          atomicAdd(&P.hist[P.hist_shift >= 64 ? 0 : (s >> P.hist_shift)], 1ull);
+          xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
+        } else {
+          const uint64_t slot = e - P.edge_begin;
+          static_cast<Id*>(P.out_src)[slot] = static_cast<Id>(acc.src(P.k));
+          static_cast<Id*>(P.out_dst)[slot] = static_cast<Id>(acc.dst(P.k));
+        }
+      }
+    }
+    wave_lds_fence();
   }
-  for (int o = 32; o >= 1; o >>= 1) {
-    const uint32_t lo = __shfl_xor(static_cast<uint32_t>(x), o, 64);
-    const uint32_t hi = __shfl_xor(static_cast<uint32_t>(x >> 32), o, 64);
-    x ^= (static_cast<uint64_t>(hi) << 32) | lo;
-  }
-  if (lane == 0) s_xor[threadIdx.x >> 6] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int w = 0; w < kGenThreads / 64; ++w) t ^= s_xor[w];
-    atomicXor(P.xor_out, t);
+
+  if (kReduce) {
+    uint64_t x = xsum;
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint32_t lo = __shfl_xor(static_cast<uint32_t>(x), o, 64);
+      const uint32_t hi = __shfl_xor(static_cast<uint32_t>(x >> 32), o, 64);
+      x ^= (static_cast<uint64_t>(hi) << 32) | lo;
+    }
+    if (lane == 0) s_xor[wave_in_wg] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int w = 0; w < kWaves; ++w) t ^= s_xor[w];
+      atomicXor(P.xor_out, t);
+    }
   }
 }
 
-int g_cu_count = 0;
+struct DeviceLimits {
+  int cu_count = 0;
+  int lds_per_block = 0;
+};
 
-int cu_count() {
-  if (g_cu_count == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-      g_cu_count = n;
-    else
-      g_cu_count = 256;
+DeviceLimits g_limits;
+
+const DeviceLimits& limits() {
+  if (g_limits.cu_count == 0) {
+    int dev = 0, n = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0)
+      lds = 64 * 1024;
+    g_limits.cu_count = n;
+    g_limits.lds_per_block = lds;
   }
-  return g_cu_count;
+  return g_limits;
 }
 
-template <typename Acc, bool kLds>
-hipError_t launch_one(const Launch& P, bool reduce, hipStream_t s) {
-  const size_t lds = kLds ? static_cast<size_t>(P.n_buckets) * sizeof(BucketRecord) : 0;
-  const void* fn = reduce ? reinterpret_cast<const void*>(&generate_reduce_kernel<Acc, kLds>)
-                          : reinterpret_cast<const void*>(&generate_kernel<Acc, kLds>);
+template <typename Acc, bool kLds, bool kReduce>
+hipError_t launch_one(const Launch& P0, hipStream_t s) {
+  const DeviceLimits& D = limits();
+  Launch P = P0;
+  P.lds_table = kLds ? P0.n_buckets * static_cast<uint32_t>(sizeof(BucketRecord)) : 0;
+  const uint32_t per_block_bytes = 64 * sizeof(typename Acc::Packed) + 64 * sizeof(uint16_t);
+  const uint32_t budget = static_cast<uint32_t>(D.lds_per_block) - 1024;  // room for static LDS
+  if (P.lds_table + kWaves * per_block_bytes > budget) return hipErrorInvalidValue;
+  uint32_t tile = (budget - P.lds_table) / (kWaves * per_block_bytes);
+  if (tile > kMaxTile) tile = kMaxTile;
+  P.tile = tile;
+  P.wave_bytes = tile * per_block_bytes;
+  const size_t lds = P.lds_table + static_cast<size_t>(kWaves) * P.wave_bytes;
+  const void* fn = reinterpret_cast<const void*>(&generate_kernel<Acc, kLds, kReduce>);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  const uint64_t waves_needed = P.n_blocks;
-  const uint64_t wgs_needed = (waves_needed + kGenThreads / 64 - 1) / (kGenThreads / 64);
-  const uint64_t per_cu = kLds ? (lds > 80 * 1024 ? 1 : (lds > 40 * 1024 ? 2 : 4)) : 4;
-  uint64_t grid = static_cast<uint64_t>(cu_count()) * per_cu;
+  // persistent grid: as many workgroups as fit on the device at once
+  const uint64_t per_cu = lds > 80 * 1024 ? 1 : 2;
+  const uint64_t waves_needed = (P.n_blocks + tile - 1) / tile;
+  const uint64_t wgs_needed = (waves_needed + kWaves - 1) / kWaves;
+  uint64_t grid = static_cast<uint64_t>(D.cu_count) * per_cu;
   if (grid > wgs_needed) grid = wgs_needed;
   if (grid < 1) grid = 1;
-  if (reduce)
-    hipLaunchKernelGGL((generate_reduce_kernel<Acc, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
-                       lds, s, P);
-  else
-    hipLaunchKernelGGL((generate_kernel<Acc, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads), lds, s,
-                       P);
+  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
+                     lds, s, P);
   return hipGetLastError();
 }
 
-hipError_t dispatch(const GenerateArgs& a, bool reduce, hipStream_t s) {
+template <bool kReduce>
+hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   if (a.m == 0) return hipSuccess;
   Launch P;
   P.records = a.records;
@@ -225,6 +318,9 @@ hipError_t dispatch(const GenerateArgs& a, bool reduce, hipStream_t s) {
   P.k = static_cast<uint32_t>(a.k);
   P.key0 = static_cast<uint32_t>(a.seed);
   P.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.tile = 1;
+  P.lds_table = 0;
+  P.wave_bytes = 0;
   P.edge_begin = a.edge_begin;
   P.m = a.m;
   P.first_block = a.edge_begin >> 6;
@@ -235,17 +331,25 @@ hipError_t dispatch(const GenerateArgs& a, bool reduce, hipStream_t s) {
   P.hist = a.hist;
   P.xor_out = a.xor_out;
   const bool wide = a.k > 32;
-  if (a.lds) {
-    return wide ? launch_one<Acc64, true>(P, reduce, s) : launch_one<Acc32, true>(P, reduce, s);
-  }
-  return wide ? launch_one<Acc64, false>(P, reduce, s) : launch_one<Acc32, false>(P, reduce, s);
+  if (a.lds)
+    return wide ? launch_one<Acc64, true, kReduce>(P, s) : launch_one<Acc32, true, kReduce>(P, s);
+  return wide ? launch_one<Acc64, false, kReduce>(P, s) : launch_one<Acc32, false, kReduce>(P, s);
 }
 
 }  // namespace
 
-uint32_t lds_table_limit() { return 8192; }
+// Largest power-of-two table (in buckets) staged in LDS: it must leave room
+// for one tile block per wave of the widest (64-bit id) layout.
+uint32_t lds_table_limit() {
+  const DeviceLimits& D = limits();
+  const int64_t room = static_cast<int64_t>(D.lds_per_block) - 1024 -
+                       static_cast<int64_t>(kWaves) * (64 * sizeof(ulonglong2) + 64 * sizeof(uint16_t));
+  uint32_t nb = 1;
+  while (static_cast<int64_t>(2 * nb) * static_cast<int64_t>(sizeof(BucketRecord)) <= room && nb < (1u << 13)) nb <<= 1;
+  return static_cast<int64_t>(nb) * static_cast<int64_t>(sizeof(BucketRecord)) <= room ? nb : 0;
+}
 
-hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispatch(a, false, s); }
-hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return dispatch(a, true, s); }
+hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispatch<false>(a, s); }
+hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return dispatch<true>(a, s); }
 
 }  // namespace rmat

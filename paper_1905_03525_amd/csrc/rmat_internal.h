@@ -19,7 +19,7 @@ constexpr uint64_t kMaxBound = 1ull << 24;
 //      bits 31..16 = row bits left-aligned in 16 bits,
 //      bits 15..0  = column bits left-aligned in 16 bits
 //   w  own length | alias length << 16
-struct BucketRecord {
+struct alignas(16) BucketRecord {
   uint32_t thr_abs, self_word, alias_word, lens;
 };
 
@@ -96,5 +96,11 @@ hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s);
 
 // Largest table (in buckets) that generation stages in LDS.
 uint32_t lds_table_limit();
+
+// Error reporting shared by every exported function (defined in api.cpp):
+// set_error stores the thread-local message and returns `code`;
+// check_launch maps hipGetLastError() to RMAT_OK / RMAT_EDEVICE.
+int set_error(int code, const char* fmt, ...);
+int check_launch(const char* what);
 
 }  // namespace rmat
