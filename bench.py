@@ -24,6 +24,37 @@ WORKLOAD = dict(name="rmat_k26_ef16_var4096", a=0.57, b=0.19, c=0.19, d=0.05, k=
                 table_bound=4096, path_mode="variable", seed=7)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_EDGE = 8  # two uint32 ids written per edge
+# integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one 32-bit op per lane per cycle)
+INT_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+OPS_PER_PHILOX_BLOCK = 40  # 20 products 32x32->64 + 20 three-input XORs (10 rounds)
+OPS_PER_SAMPLE = 11        # shift, compare, 2 selects, row/col split (2), 2 shifts, 2 ORs, add
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "generate_k26_ef16_traffic.txt")
+
+
+def samples_per_edge(table_export: dict, k: int):
+    """E[N] and E[ceil(N/4)] for N = samples until k letters, from the
+    table's own weights and path lengths (renewal recursion over the letter
+    count)."""
+    import numpy as np
+    w = table_export["w"].astype(np.float64) / 2.0**32
+    L = table_export["len"].astype(np.int64)
+    pl = np.bincount(L[w > 0], weights=w[w > 0], minlength=16)
+    state = np.zeros(k)
+    state[0] = 1.0
+    en, eb = 0.0, 0.0
+    for n in range(1, 4 * k + 8):
+        nxt = np.zeros(k)
+        done = 0.0
+        for f in np.nonzero(state)[0]:
+            for length in np.nonzero(pl)[0]:
+                if f + length >= k:
+                    done += state[f] * pl[length]
+                else:
+                    nxt[f + length] += state[f] * pl[length]
+        en += n * done
+        eb += ((n + 3) // 4) * done
+        state = nxt
+    return en, eb
 
 
 def cpu_baseline(budget_s: float = 12.0) -> dict:
@@ -99,10 +130,15 @@ def main():
     tb = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
     build_ms = (time.perf_counter() - build_t0) * 1e3
     info = R.rmat_table_info(tb)
+    en, eb = samples_per_edge(R.rmat_table_export(tb), k)
     tb.close()
 
+    from paper_1905_03525_amd.profile_summary import read_traffic
+    traffic = read_traffic(TRAFFIC_SUMMARY)
     value = m * args.steps / wall
-    achieved_gbs = BYTES_PER_EDGE * m / avg_kern_s / 1e9
+    ops_per_edge = eb * OPS_PER_PHILOX_BLOCK + en * OPS_PER_SAMPLE
+    achieved_ops = ops_per_edge * m / avg_kern_s
+    hbm_gbs = BYTES_PER_EDGE * m / avg_kern_s / 1e9
     out = {
         "metric": "edges/s & HBM write GB/s (k=26, ef16); batched vs per-instance speedup",
         "value": value,
@@ -121,9 +157,15 @@ def main():
                    "id_bits": 32, "n_items": info["n_items"], "expected_len": info["expected_len"]},
         "hbm_write_gbs": BYTES_PER_EDGE * value / 1e9,
         "generate_kernel_ms": avg_kern_s * 1e3,
+        "generate_kernel_hbm_write_gbs": hbm_gbs,
+        "generate_kernel_hbm_frac": hbm_gbs / HBM_PEAK_GBS,
         "table_build_ms": build_ms,
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None},
+        "samples_per_edge": en,
+        "philox_blocks_per_edge": eb,
+        "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": INT_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved_ops / INT_PEAK_OPS,
+                     "ops_per_edge": ops_per_edge,
+                     "traffic": traffic},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
