@@ -129,12 +129,22 @@ __device__ __forceinline__ void split_code(uint32_t code, int depth, uint32_t* r
   *col = c;
 }
 
-__device__ const uint64_t kFact[16] = {1ull, 1ull, 2ull, 6ull, 24ull, 120ull, 720ull, 5040ull, 40320ull,
-                                       362880ull, 3628800ull, 39916800ull, 479001600ull,
-                                       6227020800ull, 87178291200ull, 1307674368000ull};
+// Binomial coefficient C(n, r), 0 <= n <= 17, computed directly (used once
+// per entry to fill the LDS table of the build kernel).
+__device__ __forceinline__ uint32_t binom_direct(int n, int r) {
+  if (r < 0 || r > n) return 0;
+  uint32_t c = 1;
+  for (int i = 1; i <= r; ++i) c = c * static_cast<uint32_t>(n - r + i) / static_cast<uint32_t>(i);
+  return c;
+}
 
-__device__ __forceinline__ uint64_t multinomial(int na, int nb, int nc, int nd) {
-  return kFact[na + nb + nc + nd] / (kFact[na] * kFact[nb] * kFact[nc] * kFact[nd]);
+constexpr int kBinomN = 18;  // rows 0..17: enough for C(D + 3, 3) with D <= 14
+
+// Number of distinct paths with the given letter counts (a multinomial
+// coefficient), as a product of binomials from the LDS table.
+__device__ __forceinline__ uint64_t multinomial(const uint32_t* bt, int na, int nb, int nc, int nd) {
+  const int D = na + nb + nc + nd;
+  return static_cast<uint64_t>(bt[D * kBinomN + na]) * bt[(D - na) * kBinomN + nb] * bt[(nc + nd) * kBinomN + nc];
 }
 
 // Packed class key: counts of a, b, c, d (4 bits each) and depth.
@@ -209,6 +219,8 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
   __shared__ Boundary s_bnd;
   __shared__ int s_error;
   __shared__ uint64_t s_sel_prefix, s_sel_need;
+  __shared__ uint64_t s_warp_before;
+  __shared__ uint32_t s_binom[kBinomN * kBinomN];
 
   const double q[4] = {J.q[0], J.q[1], J.q[2], J.q[3]};
   const int cap = J.cap;
@@ -220,29 +232,31 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
     s_error = 0;
     s_bnd.p = 0.0; s_bnd.depth = 0; s_bnd.code = 0; s_bnd.all = 0;
   }
+  for (int i = tid; i < kBinomN * kBinomN; i += kBuildThreads) s_binom[i] = binom_direct(i / kBinomN, i % kBinomN);
   __syncthreads();
+  const uint32_t* bt = s_binom;
 
   // ---- 1. boundary node (VARIABLE) ------------------------------------------
   if (J.mode == 1) {
-    // letter-count classes of every depth < cap
-    if (tid == 0) {
-      int K = 0;
-      for (int D = 0; D < cap; ++D)
-        for (int na = D; na >= 0; --na)
-          for (int nb_ = D - na; nb_ >= 0; --nb_)
-            for (int nc = D - na - nb_; nc >= 0; --nc) {
-              if (K < kMaxClasses) s_cls_key[K] = pack_class(na, nb_, nc, D - na - nb_ - nc);
-              ++K;
-            }
-      if (K > kMaxClasses) s_error = kBuildClasses;
-      s_u32[0] = K;
-    }
-    __syncthreads();
-    const int K = s_u32[0];
+    // letter-count classes of every depth < cap: depth D has C(D+3, 3) of them
+    // (cap <= 15: at most 3060 <= kMaxClasses)
+    int K = 0;
+    for (int D = 0; D < cap; ++D) K += static_cast<int>(bt[(D + 3) * kBinomN + 3]);
     for (int i = tid; i < kMaxClasses; i += kBuildThreads) {
       if (i < K) {
-        uint32_t key = s_cls_key[i];
-        s_cls_p[i] = path_prob(q, class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3));
+        // decode class i: depth, then counts of a, b, c (d takes the rest)
+        int r = i, D = 0;
+        while (r >= static_cast<int>(bt[(D + 3) * kBinomN + 3])) { r -= static_cast<int>(bt[(D + 3) * kBinomN + 3]); ++D; }
+        int na = D;
+        while (r >= static_cast<int>(bt[(D - na + 2) * kBinomN + 2])) {
+          r -= static_cast<int>(bt[(D - na + 2) * kBinomN + 2]);
+          --na;
+        }
+        int nb_ = D - na;
+        while (r >= D - na - nb_ + 1) { r -= D - na - nb_ + 1; --nb_; }
+        const int nc = D - na - nb_ - r, nd = r;
+        s_cls_key[i] = pack_class(na, nb_, nc, nd);
+        s_cls_p[i] = path_prob(q, na, nb_, nc, nd);
       } else {
         s_cls_p[i] = -1.0;  // sentinel, sorts last
         s_cls_key[i] = 0xFFFF0000u;
@@ -267,22 +281,49 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
         __syncthreads();
       }
     }
-    // the group of classes holding the t-th node, then the node itself
-    if (tid == 0 && s_error == 0) {
-      uint64_t before = 0;
-      int g0 = -1, g1 = -1;
-      for (int g = 0; g < K;) {
-        int h = g;
-        uint64_t cnt = 0;
-        while (h < K && s_cls_p[h] == s_cls_p[g] && class_depth(s_cls_key[h]) == class_depth(s_cls_key[g])) {
-          uint32_t key = s_cls_key[h];
-          cnt += multinomial(class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3));
-          ++h;
+    // the group of classes (equal probability and depth) holding the t-th
+    // node: prefix sums of the class sizes in sorted order
+    constexpr int kPer = kMaxClasses / kBuildThreads;
+    if (tid == 0) { s_u32[0] = 0xFFFFFFFFu; s_u32[1] = 0xFFFFFFFFu; s_u32[2] = 0; }
+    uint64_t cnt_local[kPer], sum_local = 0;
+    for (int u = 0; u < kPer; ++u) {
+      const int i = tid * kPer + u;
+      const uint32_t key = s_cls_key[i];
+      cnt_local[u] = i < K ? multinomial(bt, class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3)) : 0;
+      sum_local += cnt_local[u];
+    }
+    uint64_t total_nodes;
+    uint64_t cum = block_exclusive_scan(sum_local, s_warp, &total_nodes);
+    for (int u = 0; u < kPer; ++u) {  // the class whose range covers node n_expand
+      const int i = tid * kPer + u;
+      if (cum < J.n_expand && J.n_expand <= cum + cnt_local[u]) s_u32[0] = i;
+      cum += cnt_local[u];
+    }
+    __syncthreads();
+    const uint32_t hit = s_u32[0];
+    if (hit != 0xFFFFFFFFu) {  // first and last class of the hit class's group
+      const double hp = s_cls_p[hit];
+      const int hd = class_depth(s_cls_key[hit]);
+      for (int i = tid; i < K; i += kBuildThreads)
+        if (s_cls_p[i] == hp && class_depth(s_cls_key[i]) == hd) {
+          atomicMin(&s_u32[1], static_cast<uint32_t>(i));
+          atomicMax(&s_u32[2], static_cast<uint32_t>(i + 1));
         }
-        if (before + cnt >= J.n_expand) { g0 = g; g1 = h; break; }
-        before += cnt;
-        g = h;
+    }
+    __syncthreads();
+    // nodes before the group
+    if (hit != 0xFFFFFFFFu) {
+      cum = block_exclusive_scan(sum_local, s_warp, &total_nodes);
+      for (int u = 0; u < kPer; ++u) {
+        if (tid * kPer + u == static_cast<int>(s_u32[1])) s_warp_before = cum;
+        cum += cnt_local[u];
       }
+    }
+    __syncthreads();
+    if (tid == 0 && s_error == 0) {
+      const int g0 = hit == 0xFFFFFFFFu ? -1 : static_cast<int>(s_u32[1]);
+      const int g1 = hit == 0xFFFFFFFFu ? -1 : static_cast<int>(s_u32[2]);
+      const uint64_t before = g0 < 0 ? 0 : s_warp_before;
       if (g0 < 0) {
         s_bnd.all = 1;
       } else {
@@ -302,7 +343,7 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
                 rem[y] = class_n(key, y) - used[y] - (y == x ? 1 : 0);
                 ok = ok && rem[y] >= 0;
               }
-              if (ok) cnt += multinomial(rem[0], rem[1], rem[2], rem[3]);
+              if (ok) cnt += multinomial(bt, rem[0], rem[1], rem[2], rem[3]);
             }
             if (r < cnt) { chosen = x; break; }
             r -= cnt;
