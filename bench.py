@@ -5,9 +5,11 @@ the 4096-entry variable-length path table for a=0.57, b=c=0.19, d=0.05,
 k=26 (validation, path enumeration, quantisation, alias table, bucket
 records), then generate m = 16 * 2^26 = 2^30 edges (Philox draws, alias
 lookups, concatenation, stores of uint32 source and destination ids) into
-device memory.  One JSON line is printed.
+device memory.  One JSON line is printed.  Beside it: the 512-instance
+batched workload as one hipGraph launch against 512 plain launches
+(`batched_speedup`), and the CPU oracle on a bounded sample (`cpu_baseline`).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batch]
 """
 from __future__ import annotations
 
@@ -74,12 +76,68 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
             "sample": f"edges [0, {done}) of the same instance in 2^24-edge slices, {el:.1f} s"}
 
 
+def batched_vs_plain(R, reps: int = 3) -> dict:
+    """The 512-instance workload: one hipGraph launch of the batch (all 512
+    table builds and every instance's edges) against 512 plain
+    rmat_build_table + rmat_generate_async calls on one stream, both timed by
+    the host clock from the first call to the final synchronisation."""
+    import torch
+    from paper_1905_03525_amd import workloads
+    insts = workloads.batch_instances()
+    rep = R.rmat_batch_autotune(insts)
+    for p in insts:
+        p["out_src"] = torch.empty(p["m"], dtype=torch.int32, device="cuda")
+        p["out_dst"] = torch.empty(p["m"], dtype=torch.int32, device="cuda")
+    total = sum(p["m"] for p in insts)
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        tables = []
+        for p in insts:
+            t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+            R.rmat_generate_async(t, p["seed"], 0, p["m"], p["out_src"], p["out_dst"], stream)
+            tables.append(t)
+        torch.cuda.synchronize()
+        for t in tables:
+            t.close()
+
+    b = R.rmat_batch_create(insts, rep["work_blocks"])
+    info = R.rmat_batch_get_info(b)
+    R.rmat_batch_launch_graph(b, stream)   # capture + warm-up
+    R.rmat_batch_check(b)
+    plain()                                # warm-up
+    t_graph, t_plain = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R.rmat_batch_launch_graph(b, stream)
+        torch.cuda.synchronize()
+        t_graph.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        plain()
+        t_plain.append(time.perf_counter() - t0)
+    R.rmat_batch_check(b)
+    b.close()
+    for p in insts:
+        p["out_src"] = p["out_dst"] = None
+    torch.cuda.empty_cache()
+    tg, tp = sorted(t_graph)[len(t_graph) // 2], sorted(t_plain)[len(t_plain) // 2]
+    bounds = [p["table_bound"] for p in insts]
+    return {"workload": "batch512_k10-24_ef4-32_dirichlet4221", "instances": len(insts), "total_edges": total,
+            "graph_ms": tg * 1e3, "plain_ms": tp * 1e3, "speedup": tp / tg, "graph_edges_per_s": total / tg,
+            "plain_edges_per_s": total / tp, "autotune_search_s": rep["search_seconds"],
+            "autotune_calibration_ns_per_edge_op": rep["calibration_ns"], "work_blocks": rep["work_blocks"],
+            "n_work_items": info["n_work_items"], "tile_blocks": info["tile_blocks"],
+            "bounds_histogram": {str(v): bounds.count(v) for v in sorted(set(bounds))}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sampler needs no second one "
@@ -167,6 +225,12 @@ def main():
                      "ops_per_edge": ops_per_edge,
                      "traffic": traffic},
     }
+    del src, dst
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        bt = batched_vs_plain(R)
+        out["batched_speedup"] = bt["speedup"]
+        out["batched"] = bt
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

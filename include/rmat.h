@@ -161,6 +161,103 @@ int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed,
                                uint64_t edge_begin, uint64_t m, int hist_bits,
                                void* d_hist, void* d_xor, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent instances (each its own a..d, k, table, seed,
+ * edge range and outputs) built and generated together.  The method is the
+ * same per instance (Sec. 2); batching only changes how work reaches the
+ * device: one table-build launch for all tables and one persistent
+ * generation launch in which workgroups claim runs of 64-edge blocks and
+ * restage the LDS table when the instance changes.  Every instance's output
+ * equals that of rmat_build_table + rmat_generate with the same arguments.
+ * ---------------------------------------------------------------------- */
+typedef struct rmat_instance {
+  double a, b, c, d;     /* quadrant probabilities, as for rmat_build_table */
+  int32_t k;
+  int32_t path_mode;     /* RMAT_FIXED or RMAT_VARIABLE */
+  uint64_t table_bound;  /* 0: to be chosen by rmat_batch_autotune */
+  uint64_t seed;
+  uint64_t edge_begin;
+  uint64_t m;
+  void* out_src;         /* device arrays of m ids (uint32 if k <= 32, else uint64) */
+  void* out_dst;
+} rmat_instance;
+
+typedef struct rmat_batch* rmat_batch_t;
+
+typedef struct rmat_batch_info {
+  uint32_t n_instances;
+  uint32_t n_launches;    /* generation launches per run (one per id width / table residency) */
+  uint32_t n_work_items;  /* runs of blocks claimed by workgroups */
+  uint32_t work_blocks;   /* 64-edge blocks per work item */
+  uint32_t tile_blocks;   /* blocks per wave tile in the generation kernel */
+  uint32_t max_buckets;   /* largest table */
+  uint64_t total_edges;
+  uint64_t device_bytes;  /* tables, build scratch and work lists held by the batch */
+} rmat_batch_info;
+
+typedef struct rmat_autotune_report {
+  double search_seconds;     /* wall time of rmat_batch_autotune */
+  double calibration_ns;     /* measured device time per (edge x integer op), ns */
+  uint32_t n_tuned;          /* instances whose table_bound was chosen */
+  uint32_t n_candidates;     /* candidate tables built per tuned instance */
+  uint32_t work_blocks;      /* suggested work-item size for rmat_batch_create */
+  uint32_t reserved;
+} rmat_autotune_report;
+
+/*
+ * Validates every instance (as rmat_build_table and rmat_generate would),
+ * sizes and allocates all tables, their build scratch and the work list, and
+ * uploads them.  Nothing is built yet.  work_blocks: 64-edge blocks per work
+ * item (0: 2048).  The instance array is copied; outputs must stay valid for
+ * every run.  Errors: RMAT_EINVAL (naming the instance), RMAT_ERANGE,
+ * RMAT_ENOMEM, RMAT_EDEVICE.
+ */
+int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rmat_batch_t* out);
+
+/* Enqueues one run on `stream`: all tables are (re)built in one launch, then
+ * every instance is generated by persistent launches.  No allocation, memset
+ * or host synchronisation, so the call may be captured in a hipGraph. */
+int rmat_batch_enqueue(rmat_batch_t b, void* stream);
+
+/* Same run as one hipGraph launch: the first call captures
+ * rmat_batch_enqueue into a graph (on a private stream) and instantiates it;
+ * every call launches it on `stream`. */
+int rmat_batch_launch_graph(rmat_batch_t b, void* stream);
+
+/* Synchronises the device and reports table-build failures of the last run
+ * (RMAT_EINVAL / RMAT_EDEVICE naming the instance). */
+int rmat_batch_check(rmat_batch_t b);
+
+/* Shape and statistics of instance i's table, as rmat_table_info gives them
+ * (synchronous; after a run).  RMAT_EINVAL if the table was not built. */
+int rmat_batch_table_info(rmat_batch_t b, int i, rmat_info* out);
+
+/* Table i of the batch in the layout of rmat_table_export (after a run). */
+int rmat_batch_table_export(rmat_batch_t b, int i, void* host_buf, size_t nbytes);
+
+int rmat_batch_get_info(rmat_batch_t b, rmat_batch_info* out);
+
+/* Releases the batch (its graph, tables and lists).  NULL is accepted. */
+int rmat_batch_free(rmat_batch_t b);
+
+/*
+ * Chooses table_bound for every instance whose table_bound is 0 (in place;
+ * path_mode is kept).  Candidates are the LDS-resident powers of two
+ * 2^8 .. 2^13 (FIXED: 4^4 .. 4^6, at most 4^min(15,k)).  All candidate
+ * tables are built on the device in one launch; each one's path-length law
+ * gives the exact expected Philox blocks and samples per edge (Sec. 2: a
+ * longer expected path means fewer samples per edge), and the cost of an
+ * instance is m x (40 x blocks + 11 x samples) integer ops at the generation
+ * kernel's measured MI355X rate, plus the time to stage the table into LDS
+ * once per work item.  The rate is a fixed constant, so the same instances
+ * always get the same bounds; report->calibration_ns is the rate measured
+ * live (one 2^24-edge generation per process), for comparison.  The choice
+ * changes the edges (a different table), which is why it is written back.
+ * report may be NULL.  Synchronous.  Errors: RMAT_EINVAL (naming the
+ * instance), RMAT_ENOMEM, RMAT_EDEVICE.
+ */
+int rmat_batch_autotune(rmat_instance* inst, int n, rmat_autotune_report* report);
+
 /* Thread-local description of the last error ("" if none). */
 const char* rmat_last_error(void);
 

@@ -1,0 +1,580 @@
+// batch.cpp -- batches of independent instances (include/rmat.h): one
+// table-build launch for all tables, then persistent generation launches
+// over a list of work items, capturable in a hipGraph; and the autotuner that
+// picks each instance's table size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rmat.h"
+#include "rmat_internal.h"
+
+namespace {
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Instances of one id width and table residency share a generation launch.
+struct Group {
+  int wide, lds;
+  uint32_t max_buckets;
+  uint32_t n_items;
+  rmat::GenWorkItem* items;  // device, this group's items in instance order
+  unsigned int* counter;     // device, zeroed by the build launch
+};
+
+}  // namespace
+
+struct rmat_batch {
+  int n = 0;
+  uint32_t work_blocks = 0;
+  std::vector<rmat_instance> inst;
+  std::vector<rmat::Shape> shape;
+  std::vector<rmat::TableView> views;
+  std::vector<Group> groups;
+  void* d_tables = nullptr;  // all tables
+  void* d_aux = nullptr;     // build scratch, build jobs, instances, items, counters
+  rmat::BuildJob* d_jobs = nullptr;
+  rmat::GenInst* d_insts = nullptr;
+  uint64_t device_bytes = 0, total_edges = 0;
+  uint32_t n_items = 0, max_buckets = 0, tile = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+using rmat::set_error;
+
+void destroy(rmat_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_tables) (void)hipFree(b->d_tables);
+  if (b->d_aux) (void)hipFree(b->d_aux);
+  delete b;
+}
+
+int validate_instance(const rmat_instance& x, int i, rmat::Shape* S) {
+  const double q[4] = {x.a, x.b, x.c, x.d};
+  int rc = rmat::validate_and_size(q, x.k, x.table_bound, x.path_mode, S);
+  if (rc) {
+    char msg[512];
+    std::snprintf(msg, sizeof(msg), "instance %d: %s", i, rmat_last_error());
+    return set_error(rc, "%s", msg);
+  }
+  if (x.m > 0 && x.edge_begin + (x.m - 1) < x.edge_begin)
+    return set_error(RMAT_ERANGE, "instance %d: edge_begin + m exceeds 2^64", i);
+  if (x.m > 0) {
+    if (!x.out_src || !x.out_dst) return set_error(RMAT_EINVAL, "instance %d: NULL output pointer", i);
+    const uintptr_t align = x.k <= 32 ? 4 : 8;
+    if ((reinterpret_cast<uintptr_t>(x.out_src) | reinterpret_cast<uintptr_t>(x.out_dst)) % align)
+      return set_error(RMAT_EINVAL, "instance %d: output pointers must be %u-byte aligned", i, (unsigned)align);
+  }
+  return RMAT_OK;
+}
+
+// A set of tables laid out in one allocation, their build scratch and jobs
+// (plus `extra` bytes for the caller) in another.
+struct TableSet {
+  void* d_tables = nullptr;
+  void* d_aux = nullptr;
+  std::vector<rmat::TableView> views;
+  std::vector<rmat::BuildJob> jobs;
+  rmat::BuildJob* d_jobs = nullptr;
+  char* d_extra = nullptr;
+  uint64_t bytes = 0, table_bytes = 0;
+};
+
+int alloc_tables(const std::vector<rmat::Shape>& shapes, const std::vector<rmat_instance>& params, uint64_t extra,
+                 TableSet* T) {
+  const size_t n = shapes.size();
+  std::vector<uint64_t> toff(n), soff(n);
+  uint64_t tb = 0, sb = 0;
+  for (size_t i = 0; i < n; ++i) {
+    toff[i] = tb;
+    tb += align_up(rmat::table_bytes(shapes[i]), 256);
+    soff[i] = sb;
+    sb += align_up(rmat::scratch_bytes(shapes[i]), 256);
+  }
+  const uint64_t jobs_off = sb;
+  sb += align_up(n * sizeof(rmat::BuildJob), 256);
+  const uint64_t extra_off = sb;
+  sb += align_up(extra, 256);
+  hipError_t e = hipMalloc(&T->d_tables, tb);
+  if (e != hipSuccess) return rmat::hip_fail(e, "hipMalloc(batch tables)");
+  e = hipMalloc(&T->d_aux, sb);
+  if (e != hipSuccess) {
+    (void)hipFree(T->d_tables);
+    T->d_tables = nullptr;
+    return rmat::hip_fail(e, "hipMalloc(batch scratch)");
+  }
+  T->bytes = tb + sb;
+  T->table_bytes = tb;
+  char* aux = static_cast<char*>(T->d_aux);
+  T->d_jobs = reinterpret_cast<rmat::BuildJob*>(aux + jobs_off);
+  T->d_extra = aux + extra_off;
+  T->views.resize(n);
+  T->jobs.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    T->views[i] = rmat::place_table(static_cast<char*>(T->d_tables) + toff[i], shapes[i]);
+    const rmat_instance& x = params[i];
+    const double q[4] = {x.a, x.b, x.c, x.d};
+    rmat::fill_job(&T->jobs[i], q, x.k, x.path_mode, shapes[i], T->views[i], aux + soff[i]);
+  }
+  return RMAT_OK;
+}
+
+void free_tables(TableSet* T) {
+  if (T->d_tables) (void)hipFree(T->d_tables);
+  if (T->d_aux) (void)hipFree(T->d_aux);
+  T->d_tables = T->d_aux = nullptr;
+}
+
+int enqueue(rmat_batch* b, hipStream_t s) {
+  hipError_t e = rmat::launch_table_build(b->d_jobs, b->n, s);
+  if (e != hipSuccess) return rmat::hip_fail(e, "batch table build launch");
+  for (const Group& g : b->groups) {
+    rmat::BatchArgs a;
+    a.insts = b->d_insts;
+    a.items = g.items;
+    a.n_items = g.n_items;
+    a.counter = g.counter;
+    a.max_buckets = g.max_buckets;
+    a.wide = g.wide;
+    a.lds = g.lds;
+    e = rmat::launch_generate_batch(a, s);
+    if (e != hipSuccess) return rmat::hip_fail(e, "batch generation launch");
+  }
+  return RMAT_OK;
+}
+
+// E[ceil(N/4)] and E[N] for N = samples until k letters, given the law of
+// one sample's path length (mass[L] / 2^32): a renewal recursion over the
+// number of letters known.
+void sample_laws(const uint64_t mass[16], int k, double* blocks, double* samples) {
+  double pl[16];
+  for (int L = 0; L < 16; ++L) pl[L] = static_cast<double>(mass[L]) / 4294967296.0;
+  std::vector<double> state(k, 0.0), next(k, 0.0);
+  state[0] = 1.0;
+  double en = 0.0, eb = 0.0, left = 1.0;
+  for (int n = 1; n <= 4 * k + 8 && left > 1e-15; ++n) {
+    std::fill(next.begin(), next.end(), 0.0);
+    double done = 0.0;
+    for (int f = 0; f < k; ++f) {
+      if (state[f] == 0.0) continue;
+      for (int L = 1; L < 16; ++L) {
+        if (pl[L] == 0.0) continue;
+        if (f + L >= k) done += state[f] * pl[L];
+        else next[f + L] += state[f] * pl[L];
+      }
+    }
+    en += n * done;
+    eb += ((n + 3) / 4) * done;
+    left -= done;
+    state.swap(next);
+  }
+  *blocks = eb;
+  *samples = en;
+}
+
+constexpr double kOpsPerBlock = 40.0;  // Philox4x32-10: 20 products + 20 three-input XORs
+constexpr double kOpsPerSample = 11.0;
+// Device time per (edge x op) that the cost model uses: the generation kernel's
+// rate on MI355X at k = 26 (2^30 edges, 88.6 ops per edge, 4.45 ms).  A fixed
+// constant rather than the live calibration keeps the choice reproducible.
+constexpr double kNsPerEdgeOp = 4.45e6 / (1073741824.0 * 88.6);
+// Staging one table into a workgroup's LDS: ~1 us of latency plus its bytes at
+// 64 B per clock (2.2 GHz), during which the other workgroups keep generating.
+constexpr double kStageLatencyNs = 1000.0;
+constexpr double kStageBytesPerNs = 64.0 * 2.2;
+constexpr double kResidentWorkgroups = 256.0;
+
+// Device time per (edge x op), measured once per process by generating 2^24
+// edges of the 4093-path table at k = 26.
+double g_calibration_ns = 0.0;
+
+int calibrate(double* ns) {
+  if (g_calibration_ns > 0.0) {
+    *ns = g_calibration_ns;
+    return RMAT_OK;
+  }
+  rmat_table_t t = nullptr;
+  int rc = rmat_build_table(0.57, 0.19, 0.19, 0.05, 26, 4096, RMAT_VARIABLE, &t);
+  if (rc) return rc;
+  const uint64_t m = 1ull << 24;
+  void* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, 2 * m * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    rmat_free_table(t);
+    return rmat::hip_fail(e, "hipMalloc(calibration)");
+  }
+  uint32_t* src = static_cast<uint32_t*>(buf);
+  hipEvent_t a = nullptr, z = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&z);
+  float best = 1e30f;
+  for (int rep = 0; rep < 4 && rc == RMAT_OK; ++rep) {
+    (void)hipEventRecord(a, nullptr);
+    rc = rmat_generate_async(t, 1, 0, m, src, src + m, nullptr);
+    (void)hipEventRecord(z, nullptr);
+    (void)hipEventSynchronize(z);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, z);
+    if (rep > 0) best = std::min(best, ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  (void)hipFree(buf);
+  if (rc == RMAT_OK) {
+    uint64_t mass[16] = {0};
+    rmat_info info;
+    rmat_table_info(t, &info);
+    // the length law from the exported table
+    std::vector<char> ex(info.export_bytes);
+    rc = rmat_table_export(t, ex.data(), ex.size());
+    if (rc == RMAT_OK) {
+      const uint64_t nb = info.n_buckets;
+      const uint64_t* w = reinterpret_cast<const uint64_t*>(ex.data());
+      const uint32_t* len = reinterpret_cast<const uint32_t*>(ex.data() + 16 * nb);
+      for (uint64_t j = 0; j < nb; ++j) mass[len[j] & 15] += w[j];
+      double eb, en;
+      sample_laws(mass, 26, &eb, &en);
+      g_calibration_ns = best * 1e6 / (static_cast<double>(m) * (kOpsPerBlock * eb + kOpsPerSample * en));
+    }
+  }
+  rmat_free_table(t);
+  if (rc) return rc;
+  *ns = g_calibration_ns;
+  return RMAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rmat_batch_t* out) {
+  rmat::clear_error();
+  if (!out) return set_error(RMAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!inst || n <= 0) return set_error(RMAT_EINVAL, "empty instance list");
+  rmat_batch* b = new (std::nothrow) rmat_batch();
+  if (!b) return set_error(RMAT_ENOMEM, "host allocation of the batch failed");
+  b->n = n;
+  b->work_blocks = work_blocks ? work_blocks : 2048;
+  b->inst.assign(inst, inst + n);
+  b->shape.resize(n);
+  int rc = RMAT_OK;
+  for (int i = 0; i < n && rc == RMAT_OK; ++i) rc = validate_instance(b->inst[i], i, &b->shape[i]);
+  if (rc == RMAT_OK) rc = rmat::check_device();
+  if (rc) {
+    destroy(b);
+    return rc;
+  }
+  // groups by id width and table residency; work items in instance order
+  const uint32_t lds_limit = rmat::lds_table_limit();
+  std::vector<rmat::GenWorkItem> items;
+  std::vector<uint32_t> group_first;
+  for (int wide = 0; wide < 2; ++wide)
+    for (int lds = 1; lds >= 0; --lds) {
+      Group g;
+      g.wide = wide;
+      g.lds = lds;
+      g.max_buckets = 0;
+      g.items = nullptr;
+      g.counter = nullptr;
+      const uint32_t first_item = static_cast<uint32_t>(items.size());
+      for (int i = 0; i < n; ++i) {
+        const rmat_instance& x = b->inst[i];
+        const rmat::Shape& S = b->shape[i];
+        if ((x.k > 32) != (wide != 0) || (S.n_buckets <= lds_limit) != (lds != 0)) continue;
+        g.max_buckets = std::max<uint32_t>(g.max_buckets, static_cast<uint32_t>(S.n_buckets));
+        if (x.m == 0) continue;
+        const uint64_t first = x.edge_begin >> 6;
+        const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - first + 1;
+        for (uint64_t f = 0; f < nblk; f += b->work_blocks) {
+          rmat::GenWorkItem w;
+          w.inst = static_cast<uint32_t>(i);
+          w.first = f;
+          w.n_blocks = static_cast<uint32_t>(std::min<uint64_t>(b->work_blocks, nblk - f));
+          items.push_back(w);
+        }
+      }
+      g.n_items = static_cast<uint32_t>(items.size()) - first_item;
+      b->max_buckets = std::max(b->max_buckets, g.max_buckets);
+      if (g.n_items == 0) continue;
+      if (rmat::tile_blocks(g.max_buckets, wide, lds) == 0) {
+        destroy(b);
+        return set_error(RMAT_EINVAL, "a table of %u buckets leaves no LDS for the generation tiles", g.max_buckets);
+      }
+      b->groups.push_back(g);
+      group_first.push_back(first_item);
+    }
+  b->n_items = static_cast<uint32_t>(items.size());
+  if (b->groups.size() > static_cast<size_t>(n)) {  // cannot happen: every group holds an instance
+    destroy(b);
+    return set_error(RMAT_EDEVICE, "internal: more generation groups than instances");
+  }
+  // device memory: tables | scratch, jobs, instances, items, counters (one 256-byte line each)
+  const uint64_t inst_bytes = align_up(n * sizeof(rmat::GenInst), 256);
+  const uint64_t item_bytes = align_up(items.size() * sizeof(rmat::GenWorkItem), 256);
+  const uint64_t ctr_bytes = 256 * std::max<size_t>(1, b->groups.size());
+  TableSet T;
+  rc = alloc_tables(b->shape, b->inst, inst_bytes + item_bytes + ctr_bytes, &T);
+  if (rc) {
+    destroy(b);
+    return rc;
+  }
+  b->d_tables = T.d_tables;
+  b->d_aux = T.d_aux;
+  b->views = T.views;
+  b->d_jobs = T.d_jobs;
+  b->device_bytes = T.bytes;
+  b->d_insts = reinterpret_cast<rmat::GenInst*>(T.d_extra);
+  auto* d_items = reinterpret_cast<rmat::GenWorkItem*>(T.d_extra + inst_bytes);
+  auto* d_counters = reinterpret_cast<unsigned int*>(T.d_extra + inst_bytes + item_bytes);
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    b->groups[gi].items = d_items + group_first[gi];
+    b->groups[gi].counter = d_counters + 64 * gi;
+    T.jobs[gi].reset_counter = b->groups[gi].counter;  // build job gi zeroes group gi's counter
+  }
+  std::vector<rmat::GenInst> dinst(n);
+  for (int i = 0; i < n; ++i) {
+    const rmat_instance& x = b->inst[i];
+    rmat::GenInst& d = dinst[i];
+    d.records = b->views[i].records;
+    d.n_buckets = static_cast<uint32_t>(b->shape[i].n_buckets);
+    d.shift = 32u - static_cast<uint32_t>(b->shape[i].bucket_bits);
+    d.k = static_cast<uint32_t>(x.k);
+    d.key0 = static_cast<uint32_t>(x.seed);
+    d.key1 = static_cast<uint32_t>(x.seed >> 32);
+    d.edge_begin = x.edge_begin;
+    d.m = x.m;
+    d.first_block = x.edge_begin >> 6;
+    d.n_blocks = x.m ? ((x.edge_begin + (x.m - 1)) >> 6) - d.first_block + 1 : 0;
+    d.out_src = x.out_src;
+    d.out_dst = x.out_dst;
+    b->total_edges += x.m;
+  }
+  // every byte 0xFF: each table's build status reads -1 (not built) until the first run
+  hipError_t e = hipMemset(b->d_tables, 0xFF, T.table_bytes);
+  if (e == hipSuccess) e = hipMemcpy(b->d_jobs, T.jobs.data(), n * sizeof(rmat::BuildJob), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_insts, dinst.data(), n * sizeof(rmat::GenInst), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(d_items, items.data(), items.size() * sizeof(rmat::GenWorkItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(d_counters, 0, ctr_bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    destroy(b);
+    return rmat::hip_fail(e, "batch upload");
+  }
+  for (const Group& g : b->groups) b->tile = std::max(b->tile, rmat::tile_blocks(g.max_buckets, g.wide, g.lds));
+  *out = b;
+  return RMAT_OK;
+}
+
+int rmat_batch_enqueue(rmat_batch_t b, void* stream) {
+  rmat::clear_error();
+  if (!b) return set_error(RMAT_EINVAL, "NULL batch");
+  return enqueue(b, static_cast<hipStream_t>(stream));
+}
+
+int rmat_batch_launch_graph(rmat_batch_t b, void* stream) {
+  rmat::clear_error();
+  if (!b) return set_error(RMAT_EINVAL, "NULL batch");
+  if (!b->exec) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return rmat::hip_fail(e, "hipStreamCreate(capture)");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? enqueue(b, cs) : rmat::hip_fail(e, "hipStreamBeginCapture");
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e2 != hipSuccess) return rmat::hip_fail(e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return rmat::hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = g;
+  }
+  hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return rmat::hip_fail(e, "hipGraphLaunch");
+  return RMAT_OK;
+}
+
+int rmat_batch_check(rmat_batch_t b) {
+  rmat::clear_error();
+  if (!b) return set_error(RMAT_EINVAL, "NULL batch");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return rmat::hip_fail(e, "batch run");
+  for (int i = 0; i < b->n; ++i) {
+    int32_t err = 0;
+    e = hipMemcpy(&err, &b->views[i].stats->error, sizeof(err), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return rmat::hip_fail(e, "batch check");
+    if (err != 0)
+      return set_error(err == rmat::kBuildResidual ? RMAT_EINVAL : RMAT_EDEVICE,
+                       "instance %d: table build failed on the device (code %d)", i, err);
+  }
+  return RMAT_OK;
+}
+
+int rmat_batch_table_export(rmat_batch_t b, int i, void* host_buf, size_t nbytes) {
+  rmat::clear_error();
+  if (!b || i < 0 || i >= b->n) return set_error(RMAT_EINVAL, "NULL batch or instance index out of range");
+  return rmat::export_table(b->views[i], b->shape[i].n_buckets, host_buf, nbytes);
+}
+
+int rmat_batch_table_info(rmat_batch_t b, int i, rmat_info* out) {
+  rmat::clear_error();
+  if (!b || !out || i < 0 || i >= b->n) return set_error(RMAT_EINVAL, "NULL batch or info pointer, or index out of range");
+  rmat::BuildStats st;
+  hipError_t e = hipMemcpy(&st, b->views[i].stats, sizeof(st), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return rmat::hip_fail(e, "batch table info");
+  if (st.error != 0) return set_error(RMAT_EINVAL, "instance %d: table not built (code %d)", i, st.error);
+  const rmat_instance& x = b->inst[i];
+  rmat::fill_info(out, x.k, x.path_mode, x.table_bound, b->shape[i], st, rmat::table_bytes(b->shape[i]));
+  return RMAT_OK;
+}
+
+int rmat_batch_get_info(rmat_batch_t b, rmat_batch_info* out) {
+  rmat::clear_error();
+  if (!b || !out) return set_error(RMAT_EINVAL, "NULL batch or info pointer");
+  out->n_instances = static_cast<uint32_t>(b->n);
+  out->n_launches = static_cast<uint32_t>(b->groups.size());
+  out->n_work_items = b->n_items;
+  out->work_blocks = b->work_blocks;
+  out->tile_blocks = b->tile;
+  out->max_buckets = b->max_buckets;
+  out->total_edges = b->total_edges;
+  out->device_bytes = b->device_bytes;
+  return RMAT_OK;
+}
+
+int rmat_batch_free(rmat_batch_t b) {
+  rmat::clear_error();
+  destroy(b);
+  return RMAT_OK;
+}
+
+int rmat_batch_autotune(rmat_instance* inst, int n, rmat_autotune_report* report) {
+  rmat::clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!inst || n <= 0) return set_error(RMAT_EINVAL, "empty instance list");
+  // candidate bounds per instance to tune (host only)
+  std::vector<int> who;
+  std::vector<rmat_instance> cand;
+  std::vector<rmat::Shape> shapes;
+  uint32_t n_tuned = 0;
+  for (int i = 0; i < n; ++i) {
+    if (inst[i].table_bound != 0) continue;
+    ++n_tuned;
+    const int cap = std::min(std::max(inst[i].k, 1), rmat::kMaxDepthCap);
+    std::vector<uint64_t> bounds;
+    if (inst[i].path_mode == RMAT_FIXED) {
+      for (int l = std::min(4, cap); l <= std::min(6, cap); ++l) bounds.push_back(1ull << (2 * l));
+    } else {
+      for (int e2 = 8; e2 <= 13; ++e2) bounds.push_back(1ull << e2);
+    }
+    for (uint64_t bound : bounds) {
+      rmat_instance c = inst[i];
+      c.table_bound = bound;
+      rmat::Shape S;
+      const double q[4] = {c.a, c.b, c.c, c.d};
+      if (rmat::validate_and_size(q, c.k, c.table_bound, c.path_mode, &S) != RMAT_OK) {
+        char msg[512];
+        std::snprintf(msg, sizeof(msg), "instance %d: %s", i, rmat_last_error());
+        return set_error(RMAT_EINVAL, "%s", msg);
+      }
+      cand.push_back(c);
+      shapes.push_back(S);
+      who.push_back(i);
+    }
+  }
+  int rc = rmat::check_device();
+  if (rc) return rc;
+  double ns = 0.0;
+  if ((rc = calibrate(&ns))) return rc;
+  // keep the LDS-resident candidates (every VARIABLE bound up to 2^13 and FIXED up to 4^6 is)
+  const uint32_t lds_limit = rmat::lds_table_limit();
+  uint32_t n_cand = 0;
+  {
+    std::vector<int> w2;
+    std::vector<rmat_instance> c2;
+    std::vector<rmat::Shape> s2;
+    std::vector<uint32_t> per(n, 0);
+    for (size_t c = 0; c < cand.size(); ++c) {
+      if (shapes[c].n_buckets > lds_limit) continue;
+      w2.push_back(who[c]);
+      c2.push_back(cand[c]);
+      s2.push_back(shapes[c]);
+      n_cand = std::max(n_cand, ++per[who[c]]);
+    }
+    for (int i = 0; i < n; ++i)
+      if (inst[i].table_bound == 0 && per[i] == 0)
+        return set_error(RMAT_EINVAL, "instance %d: no candidate table fits in LDS", i);
+    who.swap(w2);
+    cand.swap(c2);
+    shapes.swap(s2);
+  }
+  uint64_t total_blocks = 0;
+  for (int i = 0; i < n; ++i) total_blocks += (inst[i].m + 63) / 64;
+  uint32_t work_blocks = static_cast<uint32_t>(std::min<uint64_t>(
+      8192, std::max<uint64_t>(128, total_blocks / (static_cast<uint64_t>(256) * 8))));
+  if (!cand.empty()) {
+    TableSet T;
+    if ((rc = alloc_tables(shapes, cand, 0, &T))) return rc;
+    hipError_t e = hipMemcpy(T.d_jobs, T.jobs.data(), T.jobs.size() * sizeof(rmat::BuildJob), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = rmat::launch_table_build(T.d_jobs, static_cast<int>(T.jobs.size()), nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    std::vector<rmat::BuildStats> st(cand.size());
+    for (size_t c = 0; c < cand.size() && e == hipSuccess; ++c)
+      e = hipMemcpy(&st[c], T.views[c].stats, sizeof(rmat::BuildStats), hipMemcpyDeviceToHost);
+    free_tables(&T);
+    if (e != hipSuccess) return rmat::hip_fail(e, "autotune candidate tables");
+    // choose per instance
+    std::vector<double> best(n, 1e300);
+    std::vector<uint64_t> chosen(n, 0);
+    for (size_t c = 0; c < cand.size(); ++c) {
+      if (st[c].error != 0) continue;
+      const int i = who[c];
+      double eb, en;
+      sample_laws(st[c].len_mass, cand[c].k, &eb, &en);
+      const double gen = static_cast<double>(cand[c].m) * kNsPerEdgeOp * (kOpsPerBlock * eb + kOpsPerSample * en);
+      const double items = std::ceil(static_cast<double>((cand[c].m + 63) / 64) / work_blocks);
+      const double stage_one = kStageLatencyNs + static_cast<double>(shapes[c].n_buckets) * 16.0 / kStageBytesPerNs;
+      const double stage = items * stage_one / kResidentWorkgroups;
+      const double cost = gen + stage;
+      if (cost < best[i]) {
+        best[i] = cost;
+        chosen[i] = cand[c].table_bound;
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      if (inst[i].table_bound == 0 && chosen[i] == 0)
+        return set_error(RMAT_EDEVICE, "instance %d: every candidate table failed", i);
+    for (int i = 0; i < n; ++i)
+      if (inst[i].table_bound == 0) inst[i].table_bound = chosen[i];
+  }
+  if (report) {
+    report->search_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    report->calibration_ns = ns;
+    report->n_tuned = n_tuned;
+    report->n_candidates = n_cand;
+    report->work_blocks = work_blocks;
+    report->reserved = 0;
+  }
+  return RMAT_OK;
+}
+
+}  // extern "C"

@@ -113,22 +113,29 @@ __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, ui
   }
 }
 
-struct Launch {
-  const BucketRecord* records;
-  uint32_t n_buckets;
-  uint32_t shift;  // 32 - b
-  uint32_t k;
-  uint32_t key0, key1;
+using Inst = GenInst;
+
+// LDS layout shared by both kernels: [table | per-wave tile areas].
+struct TileLayout {
   uint32_t tile;        // blocks per tile
   uint32_t lds_table;   // LDS bytes holding the table (0: read from global memory)
   uint32_t wave_bytes;  // LDS bytes of one wave's tile area
-  uint64_t edge_begin, m;
-  uint64_t first_block, n_blocks;
-  void* out_src;
-  void* out_dst;
+};
+
+struct Launch {
+  Inst I;
+  TileLayout L;
   uint32_t hist_shift;
   unsigned long long* hist;
   unsigned long long* xor_out;
+};
+
+struct BatchLaunch {
+  const Inst* insts;
+  const GenWorkItem* items;
+  uint32_t n_items;
+  unsigned int* counter;  // reset to 0 by the batch's table-build launch
+  TileLayout L;
 };
 
 // MurmurHash3's 64-bit finaliser.
@@ -144,51 +151,40 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
 // Orders this wave's LDS accesses across the passes of a tile.
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-template <typename Acc, bool kLds, bool kReduce>
-__global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
-  extern __shared__ __align__(16) unsigned char s_mem[];
-  __shared__ unsigned long long s_xor[kWaves];
+// Blocks t0 + j*stride of one instance for one wave, t0 = wave_blk,
+// wave_blk + stride*tile, ... below blk_end, in tiles of L.tile blocks:
+//   1. first Philox block of every edge into the wave's LDS area, unfinished
+//      edges listed;
+//   2. the listed edges finished 64 at a time;
+//   3. the tile stored (or reduced).
+template <typename Acc, bool kReduce>
+__device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
+                                           uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
+                                           typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
+                                           unsigned long long* hist, uint64_t& xsum) {
   using Id = typename Acc::Id;
-  using Packed = typename Acc::Packed;
-
-  // stage the table
-  const BucketRecord* tab = P.records;
-  if (kLds) {
-    const uint4* src = reinterpret_cast<const uint4*>(P.records);
-    uint4* dst = reinterpret_cast<uint4*>(s_mem);
-    for (uint32_t i = threadIdx.x; i < P.n_buckets; i += kGenThreads) dst[i] = src[i];
-    __syncthreads();
-    tab = reinterpret_cast<const BucketRecord*>(s_mem);
-  }
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * kWaves + wave_in_wg;
-  const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * kWaves;
-  Packed* res = reinterpret_cast<Packed*>(s_mem + P.lds_table + wave_in_wg * P.wave_bytes);
-  uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.tile * 64);
-  const uint64_t last = P.edge_begin + (P.m - 1);  // last edge, no overflow
-  uint64_t xsum = 0;
-
-  for (uint64_t t0 = wave; t0 < P.n_blocks; t0 += n_waves * P.tile) {
-    const uint64_t left = (P.n_blocks - t0 + n_waves - 1) / n_waves;
-    const uint32_t nb_tile = left < P.tile ? static_cast<uint32_t>(left) : P.tile;
+  const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
+  for (uint64_t t0 = wave_blk; t0 < blk_end; t0 += stride * L.tile) {
+    const uint64_t left = (blk_end - t0 + stride - 1) / stride;
+    const uint32_t nb_tile = left < L.tile ? static_cast<uint32_t>(left) : L.tile;
 
     // pass 1: first Philox block of every edge of the tile
     uint32_t n_ovf = 0;
     for (uint32_t j = 0; j < nb_tile; ++j) {
-      const uint64_t base = (P.first_block + t0 + j * n_waves) << 6;  // wave-uniform
+      const uint64_t base = (I.first_block + t0 + j * stride) << 6;  // wave-uniform
       const uint64_t e = base + lane;
-      const uint64_t lo = P.edge_begin > base ? P.edge_begin - base : 0;
+      const uint64_t lo = I.edge_begin > base ? I.edge_begin - base : 0;
       const uint64_t hi = last - base < 63 ? last - base : 63;
       const uint64_t amask = (~0ull << lo) & (~0ull >> (63 - hi));
       Acc acc;
       acc.clear();
       uint32_t filled = 0;
       uint32_t x0 = static_cast<uint32_t>(e), x1 = static_cast<uint32_t>(base >> 32), x2 = 0, x3 = 0;
-      philox10(x0, x1, x2, x3, P.key0, P.key1);
-      sample4(tab, P.shift, P.k, x0, x1, x2, x3, acc, filled);
+      philox10(x0, x1, x2, x3, I.key0, I.key1);
+      sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
       res[j * 64 + lane] = acc.pack();
-      const uint64_t ovf_mask = __ballot(filled < P.k) & amask;
+      const uint64_t ovf_mask = __ballot(filled < I.k) & amask;
       if (ovf_mask != 0) {
         if ((ovf_mask >> lane) & 1ull) {
           const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
@@ -208,12 +204,12 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
         uint32_t filled = entry & 63u;
         Acc acc;
         acc.unpack(res[idx]);
-        const uint64_t e = ((P.first_block + t0 + (idx >> 6) * n_waves) << 6) + (idx & 63u);
+        const uint64_t e = ((I.first_block + t0 + (idx >> 6) * stride) << 6) + (idx & 63u);
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
-        for (uint32_t jj = 1; filled < P.k; ++jj) {
+        for (uint32_t jj = 1; filled < I.k; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = 0;
-          philox10(x0, x1, x2, x3, P.key0, P.key1);
-          sample4(tab, P.shift, P.k, x0, x1, x2, x3, acc, filled);
+          philox10(x0, x1, x2, x3, I.key0, I.key1);
+          sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
         }
         res[idx] = acc.pack();
       }
@@ -222,25 +218,51 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
 
     // pass 3: write the tile out (or fold it into the reduction)
     for (uint32_t j = 0; j < nb_tile; ++j) {
-      const uint64_t base = (P.first_block + t0 + j * n_waves) << 6;
+      const uint64_t base = (I.first_block + t0 + j * stride) << 6;
       const uint64_t e = base + lane;
       Acc acc;
       acc.unpack(res[j * 64 + lane]);
-      if (e >= P.edge_begin && e <= last) {
+      if (e >= I.edge_begin && e <= last) {
         if (kReduce) {
-          const uint64_t s = acc.src(P.k), d = acc.dst(P.k);
-          atomicAdd(&P.hist[P.hist_shift >= 64 ? 0 : (s >> P.hist_shift)], 1ull);
+          const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
+          atomicAdd(&hist[hist_shift >= 64 ? 0 : (s >> hist_shift)], 1ull);
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
         } else {
-          const uint64_t slot = e - P.edge_begin;
-          static_cast<Id*>(P.out_src)[slot] = static_cast<Id>(acc.src(P.k));
-          static_cast<Id*>(P.out_dst)[slot] = static_cast<Id>(acc.dst(P.k));
+          const uint64_t slot = e - I.edge_begin;
+          static_cast<Id*>(I.out_src)[slot] = static_cast<Id>(acc.src(I.k));
+          static_cast<Id*>(I.out_dst)[slot] = static_cast<Id>(acc.dst(I.k));
         }
       }
     }
     wave_lds_fence();
   }
+}
 
+__device__ __forceinline__ void stage_table(const BucketRecord* src_rec, uint32_t n_buckets, unsigned char* s_mem) {
+  const uint4* src = reinterpret_cast<const uint4*>(src_rec);
+  uint4* dst = reinterpret_cast<uint4*>(s_mem);
+  for (uint32_t i = threadIdx.x; i < n_buckets; i += kGenThreads) dst[i] = src[i];
+}
+
+template <typename Acc, bool kLds, bool kReduce>
+__global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
+  extern __shared__ __align__(16) unsigned char s_mem[];
+  __shared__ unsigned long long s_xor[kWaves];
+  using Packed = typename Acc::Packed;
+  const BucketRecord* tab = P.I.records;
+  if (kLds) {
+    stage_table(P.I.records, P.I.n_buckets, s_mem);
+    __syncthreads();
+    tab = reinterpret_cast<const BucketRecord*>(s_mem);
+  }
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * kWaves + wave_in_wg;
+  const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * kWaves;
+  Packed* res = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
+  uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
+  uint64_t xsum = 0;
+  run_blocks<Acc, kReduce>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.hist, xsum);
   if (kReduce) {
     uint64_t x = xsum;
     for (int o = 32; o >= 1; o >>= 1) {
@@ -255,6 +277,38 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
       for (int w = 0; w < kWaves; ++w) t ^= s_xor[w];
       atomicXor(P.xor_out, t);
     }
+  }
+}
+
+// Persistent kernel over the work items of a batch.  A workgroup claims an
+// item, restages the table only when the instance changes (items are in
+// instance order), and its 16 waves share the item's blocks.
+template <typename Acc, bool kLds>
+__global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch B) {
+  extern __shared__ __align__(16) unsigned char s_mem[];
+  __shared__ uint32_t s_item;
+  using Packed = typename Acc::Packed;
+  const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Packed* res = reinterpret_cast<Packed*>(s_mem + B.L.lds_table + wave_in_wg * B.L.wave_bytes);
+  uint16_t* ovf = reinterpret_cast<uint16_t*>(res + B.L.tile * 64);
+  uint32_t cur = 0xFFFFFFFFu;
+  uint64_t xsum = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(B.counter, 1u);
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();  // everyone has read s_item (and finished the previous item)
+    if (item >= B.n_items) break;
+    const GenWorkItem W = B.items[item];
+    const Inst I = B.insts[W.inst];
+    if (kLds && W.inst != cur) {
+      stage_table(I.records, I.n_buckets, s_mem);
+      __syncthreads();
+    }
+    cur = W.inst;
+    const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
+    run_blocks<Acc, false>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0, nullptr,
+                           xsum);
   }
 }
 
@@ -278,29 +332,36 @@ const DeviceLimits& limits() {
   return g_limits;
 }
 
-template <typename Acc, bool kLds, bool kReduce>
-hipError_t launch_one(const Launch& P0, hipStream_t s) {
+// Tile size and LDS bytes for a table of `buckets` (staged when lds).
+template <typename Acc>
+TileLayout layout_for(uint32_t buckets, bool lds, size_t* lds_bytes) {
   const DeviceLimits& D = limits();
-  Launch P = P0;
-  P.lds_table = kLds ? P0.n_buckets * static_cast<uint32_t>(sizeof(BucketRecord)) : 0;
+  TileLayout L;
+  L.lds_table = lds ? buckets * static_cast<uint32_t>(sizeof(BucketRecord)) : 0;
   const uint32_t per_block_bytes = 64 * sizeof(typename Acc::Packed) + 64 * sizeof(uint16_t);
   const uint32_t budget = static_cast<uint32_t>(D.lds_per_block) - 1024;  // room for static LDS
-  if (P.lds_table + kWaves * per_block_bytes > budget) return hipErrorInvalidValue;
-  uint32_t tile = (budget - P.lds_table) / (kWaves * per_block_bytes);
+  uint32_t tile = 0;
+  if (L.lds_table + kWaves * per_block_bytes <= budget) tile = (budget - L.lds_table) / (kWaves * per_block_bytes);
   if (tile > kMaxTile) tile = kMaxTile;
-  P.tile = tile;
-  P.wave_bytes = tile * per_block_bytes;
-  const size_t lds = P.lds_table + static_cast<size_t>(kWaves) * P.wave_bytes;
-  const void* fn = reinterpret_cast<const void*>(&generate_kernel<Acc, kLds, kReduce>);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-  }
-  // persistent grid: as many workgroups as fit on the device at once
-  const uint64_t per_cu = lds > 80 * 1024 ? 1 : 2;
-  const uint64_t waves_needed = (P.n_blocks + tile - 1) / tile;
+  L.tile = tile;
+  L.wave_bytes = tile * per_block_bytes;
+  *lds_bytes = L.lds_table + static_cast<size_t>(kWaves) * L.wave_bytes;
+  return L;
+}
+
+uint64_t persistent_grid(size_t lds_bytes) {
+  const uint64_t per_cu = lds_bytes > 80 * 1024 ? 1 : 2;
+  return static_cast<uint64_t>(limits().cu_count) * per_cu;
+}
+
+template <typename Acc, bool kLds, bool kReduce>
+hipError_t launch_one(Launch P, hipStream_t s) {
+  size_t lds = 0;
+  P.L = layout_for<Acc>(P.I.n_buckets, kLds, &lds);
+  if (P.L.tile == 0) return hipErrorInvalidValue;
+  const uint64_t waves_needed = (P.I.n_blocks + P.L.tile - 1) / P.L.tile;
   const uint64_t wgs_needed = (waves_needed + kWaves - 1) / kWaves;
-  uint64_t grid = static_cast<uint64_t>(D.cu_count) * per_cu;
+  uint64_t grid = persistent_grid(lds);
   if (grid > wgs_needed) grid = wgs_needed;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
@@ -312,21 +373,18 @@ template <bool kReduce>
 hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   if (a.m == 0) return hipSuccess;
   Launch P;
-  P.records = a.records;
-  P.n_buckets = a.n_buckets;
-  P.shift = 32u - static_cast<uint32_t>(a.bucket_bits);
-  P.k = static_cast<uint32_t>(a.k);
-  P.key0 = static_cast<uint32_t>(a.seed);
-  P.key1 = static_cast<uint32_t>(a.seed >> 32);
-  P.tile = 1;
-  P.lds_table = 0;
-  P.wave_bytes = 0;
-  P.edge_begin = a.edge_begin;
-  P.m = a.m;
-  P.first_block = a.edge_begin >> 6;
-  P.n_blocks = ((a.edge_begin + (a.m - 1)) >> 6) - P.first_block + 1;
-  P.out_src = a.out_src;
-  P.out_dst = a.out_dst;
+  P.I.records = a.records;
+  P.I.n_buckets = a.n_buckets;
+  P.I.shift = 32u - static_cast<uint32_t>(a.bucket_bits);
+  P.I.k = static_cast<uint32_t>(a.k);
+  P.I.key0 = static_cast<uint32_t>(a.seed);
+  P.I.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.I.edge_begin = a.edge_begin;
+  P.I.m = a.m;
+  P.I.first_block = a.edge_begin >> 6;
+  P.I.n_blocks = ((a.edge_begin + (a.m - 1)) >> 6) - P.I.first_block + 1;
+  P.I.out_src = a.out_src;
+  P.I.out_dst = a.out_dst;
   P.hist_shift = static_cast<uint32_t>(a.k - a.hist_bits);
   P.hist = a.hist;
   P.xor_out = a.xor_out;
@@ -334,6 +392,30 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   if (a.lds)
     return wide ? launch_one<Acc64, true, kReduce>(P, s) : launch_one<Acc32, true, kReduce>(P, s);
   return wide ? launch_one<Acc64, false, kReduce>(P, s) : launch_one<Acc32, false, kReduce>(P, s);
+}
+
+template <typename Acc, bool kLds>
+hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
+  BatchLaunch B;
+  B.insts = a.insts;
+  B.items = a.items;
+  B.n_items = a.n_items;
+  B.counter = a.counter;
+  size_t lds = 0;
+  B.L = layout_for<Acc>(a.max_buckets, kLds, &lds);
+  if (B.L.tile == 0) return hipErrorInvalidValue;
+  uint64_t grid = persistent_grid(lds);
+  if (grid > a.n_items) grid = a.n_items;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((generate_batch_kernel<Acc, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads), lds,
+                     s, B);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t allow_full_lds(F* fn) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             limits().lds_per_block - 1024);
 }
 
 }  // namespace
@@ -351,5 +433,34 @@ uint32_t lds_table_limit() {
 
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispatch<false>(a, s); }
 hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return dispatch<true>(a, s); }
+
+hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s) {
+  if (a.n_items == 0) return hipSuccess;
+  if (a.wide) return a.lds ? launch_batch<Acc64, true>(a, s) : launch_batch<Acc64, false>(a, s);
+  return a.lds ? launch_batch<Acc32, true>(a, s) : launch_batch<Acc32, false>(a, s);
+}
+
+uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds) {
+  size_t bytes = 0;
+  return wide ? layout_for<Acc64>(table_buckets, lds != 0, &bytes).tile
+              : layout_for<Acc32>(table_buckets, lds != 0, &bytes).tile;
+}
+
+hipError_t prepare_kernels() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipSuccess;
+  const hipError_t r[] = {
+      allow_full_lds(&generate_kernel<Acc32, true, false>), allow_full_lds(&generate_kernel<Acc32, false, false>),
+      allow_full_lds(&generate_kernel<Acc64, true, false>), allow_full_lds(&generate_kernel<Acc64, false, false>),
+      allow_full_lds(&generate_kernel<Acc32, true, true>),  allow_full_lds(&generate_kernel<Acc32, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, true, true>),  allow_full_lds(&generate_kernel<Acc64, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc32, true>),  allow_full_lds(&generate_batch_kernel<Acc32, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true>),  allow_full_lds(&generate_batch_kernel<Acc64, false>)};
+  for (hipError_t x : r)
+    if (x != hipSuccess) e = x;
+  if (e == hipSuccess) done = true;
+  return e;
+}
 
 }  // namespace rmat

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rmat.h"
+
 namespace rmat {
 
 constexpr int kMaxDepthCap = 15;       // longest path: 16-bit fields per id half
@@ -30,6 +32,7 @@ struct BuildStats {
   uint32_t min_len, max_len;
   uint64_t sum_wl;         // sum_j w_j * L_j, exact
   uint64_t residual;       // units handed out by largest remainders
+  uint64_t len_mass[16];   // sum of w_j over the items of length L (the length law, times 2^32)
 };
 
 enum BuildError : int32_t {
@@ -55,6 +58,7 @@ struct BuildJob {
   uint32_t *item_len, *item_row, *item_col;
   uint32_t *thr, *alias;
   BuildStats* stats;
+  unsigned int* reset_counter;  // if set, zeroed by this build (a batch's work counter)
   // scratch
   uint32_t* lvl_code;      // n_expand entries: expanded nodes, level by level
   uint32_t* lvl_first;     // index of the first expanded child
@@ -74,6 +78,47 @@ inline uint64_t build_scratch_bytes(uint64_t n_expand, uint64_t n_buckets) {
 
 // Launchers (defined in the .hip files); return hipSuccess or the launch error.
 hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s);
+
+// One instance of a batched generation (device array).  Block indices are
+// relative to first_block = edge_begin >> 6.
+struct GenInst {
+  const BucketRecord* records;
+  uint32_t n_buckets;
+  uint32_t shift;  // 32 - b
+  uint32_t k;
+  uint32_t key0, key1;
+  uint64_t edge_begin, m;
+  uint64_t first_block, n_blocks;
+  void* out_src;
+  void* out_dst;
+};
+
+// A run of 64-edge blocks of one instance; a batch lists them in instance
+// order and workgroups claim them through an atomic counter.
+struct GenWorkItem {
+  uint32_t inst;
+  uint32_t n_blocks;
+  uint64_t first;  // first block, relative to the instance's first block
+};
+
+struct BatchArgs {
+  const GenInst* insts;
+  const GenWorkItem* items;
+  uint32_t n_items;
+  unsigned int* counter;   // must be 0 when the launch starts
+  uint32_t max_buckets;    // largest table of the batch (LDS staging size)
+  int wide;                // k > 32 (64-bit ids)
+  int lds;                 // tables staged in LDS
+};
+
+hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s);
+
+// Blocks per tile the generation kernels use for a table of this size.
+uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds);
+
+// One-time kernel attributes (dynamic LDS above 64 KB).  Not a stream
+// operation; call outside any graph capture before the first launch.
+hipError_t prepare_kernels();
 
 struct GenerateArgs {
   const BucketRecord* records;
@@ -96,6 +141,40 @@ hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s);
 
 // Largest table (in buckets) that generation stages in LDS.
 uint32_t lds_table_limit();
+
+// ---- host-side helpers shared by api.cpp and batch.cpp ----------------------
+
+// Shape of a table (step A1): sizes derived from the arguments alone.
+struct Shape {
+  int cap, fixed_len, bucket_bits;
+  uint64_t n_expand, n_items, n_buckets, capacity;
+};
+
+// Validates (a, b, c, d, k, bound, mode) and sizes the table; RMAT_OK or
+// RMAT_EINVAL with the message set.
+int validate_and_size(const double q[4], int k, uint64_t bound, int mode, Shape* s);
+
+// Device pointers of one built table.
+struct TableView {
+  BucketRecord* records;
+  double* p;
+  uint64_t* w;
+  uint32_t *len, *row, *col, *thr, *alias;
+  BuildStats* stats;
+};
+
+uint64_t table_bytes(const Shape& S);    // the table itself (kept)
+uint64_t scratch_bytes(const Shape& S);  // its build scratch
+TableView place_table(char* base, const Shape& S);
+void fill_job(BuildJob* job, const double q[4], int k, int mode, const Shape& S, const TableView& V, char* scratch);
+int export_table(const TableView& V, uint64_t n_buckets, void* host_buf, size_t nbytes);
+// rmat_info of a built table from its shape and device statistics.
+void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const Shape& S, const BuildStats& stats,
+               uint64_t device_bytes);
+// Clears the calling thread's error message (every entry point starts so).
+void clear_error();
+int check_device();
+int hip_fail(hipError_t e, const char* what);
 
 // Error reporting shared by every exported function (defined in api.cpp):
 // set_error stores the thread-local message and returns `code`;

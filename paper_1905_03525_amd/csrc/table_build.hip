@@ -221,6 +221,7 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
   __shared__ uint64_t s_sel_prefix, s_sel_need;
   __shared__ uint64_t s_warp_before;
   __shared__ uint32_t s_binom[kBinomN * kBinomN];
+  __shared__ unsigned long long s_len_mass[16];
 
   const double q[4] = {J.q[0], J.q[1], J.q[2], J.q[3]};
   const int cap = J.cap;
@@ -231,7 +232,9 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
   if (tid == 0) {
     s_error = 0;
     s_bnd.p = 0.0; s_bnd.depth = 0; s_bnd.code = 0; s_bnd.all = 0;
+    if (J.reset_counter) *J.reset_counter = 0u;
   }
+  if (tid < 16) s_len_mass[tid] = 0ull;
   for (int i = tid; i < kBinomN * kBinomN; i += kBuildThreads) s_binom[i] = binom_direct(i / kBinomN, i % kBinomN);
   __syncthreads();
   const uint32_t* bt = s_binom;
@@ -606,6 +609,7 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
         wl += J.item_w[i] * ls;
         mn = min(mn, ls);
         mx = max(mx, ls);
+        atomicAdd(&s_len_mass[ls & 15u], static_cast<unsigned long long>(J.item_w[i]));
       }
     }
     const uint64_t sum_wl = block_sum(wl, s_warp);
@@ -616,6 +620,7 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
       J.stats->min_len = vmin;
       J.stats->max_len = vmax;
     }
+    if (tid < 16) J.stats->len_mass[tid] = s_len_mass[tid];
   }
 
 finish:

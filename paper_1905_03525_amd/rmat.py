@@ -26,7 +26,9 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
 
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
 EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
-            "rmat_generate_async", "rmat_generate_reduce_async", "rmat_last_error"]
+            "rmat_generate_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
+            "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
+            "rmat_batch_free", "rmat_batch_autotune", "rmat_last_error"]
 
 
 class RmatError(RuntimeError):
@@ -42,6 +44,26 @@ class rmat_info(ctypes.Structure):
                 ("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("lds_resident", ctypes.c_uint32),
                 ("expected_len", ctypes.c_double), ("export_bytes", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64)]
+
+
+class rmat_instance(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double), ("d", ctypes.c_double),
+                ("k", ctypes.c_int32), ("path_mode", ctypes.c_int32), ("table_bound", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("edge_begin", ctypes.c_uint64), ("m", ctypes.c_uint64),
+                ("out_src", ctypes.c_void_p), ("out_dst", ctypes.c_void_p)]
+
+
+class rmat_batch_info(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_uint32), ("n_launches", ctypes.c_uint32),
+                ("n_work_items", ctypes.c_uint32), ("work_blocks", ctypes.c_uint32),
+                ("tile_blocks", ctypes.c_uint32), ("max_buckets", ctypes.c_uint32),
+                ("total_edges", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64)]
+
+
+class rmat_autotune_report(ctypes.Structure):
+    _fields_ = [("search_seconds", ctypes.c_double), ("calibration_ns", ctypes.c_double),
+                ("n_tuned", ctypes.c_uint32), ("n_candidates", ctypes.c_uint32),
+                ("work_blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -64,6 +86,15 @@ def load() -> ctypes.CDLL:
     L.rmat_generate.argtypes = [vp, u64, u64, u64, vp, vp]
     L.rmat_generate_async.argtypes = [vp, u64, u64, u64, vp, vp, vp]
     L.rmat_generate_reduce_async.argtypes = [vp, u64, u64, u64, c_int, vp, vp, vp]
+    L.rmat_batch_create.argtypes = [ctypes.POINTER(rmat_instance), c_int, ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.rmat_batch_enqueue.argtypes = [vp, vp]
+    L.rmat_batch_launch_graph.argtypes = [vp, vp]
+    L.rmat_batch_check.argtypes = [vp]
+    L.rmat_batch_table_info.argtypes = [vp, c_int, ctypes.POINTER(rmat_info)]
+    L.rmat_batch_table_export.argtypes = [vp, c_int, vp, ctypes.c_size_t]
+    L.rmat_batch_get_info.argtypes = [vp, ctypes.POINTER(rmat_batch_info)]
+    L.rmat_batch_free.argtypes = [vp]
+    L.rmat_batch_autotune.argtypes = [ctypes.POINTER(rmat_instance), c_int, ctypes.POINTER(rmat_autotune_report)]
     L.rmat_last_error.argtypes = []
     L.rmat_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -134,12 +165,7 @@ def rmat_table_info(t: Table) -> dict:
     return {name: getattr(info, name) for name, _ in rmat_info._fields_}
 
 
-def rmat_table_export(t: Table) -> dict:
-    """Canonical table arrays (see include/rmat.h) as numpy arrays."""
-    info = rmat_table_info(t)
-    nb = info["n_buckets"]
-    buf = np.zeros(info["export_bytes"], dtype=np.uint8)
-    _check(load().rmat_table_export(t.handle, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes), "rmat_table_export")
+def _split_export(buf: np.ndarray, nb: int) -> dict:
     out, off = {}, 0
     for name, dt in (("w", np.uint64), ("p", np.float64), ("len", np.uint32), ("row", np.uint32),
                      ("col", np.uint32), ("thr", np.uint32), ("alias", np.uint32)):
@@ -147,6 +173,15 @@ def rmat_table_export(t: Table) -> dict:
         out[name] = buf[off:off + n].view(dt).copy()
         off += n
     return out
+
+
+def rmat_table_export(t: Table) -> dict:
+    """Canonical table arrays (see include/rmat.h) as numpy arrays."""
+    info = rmat_table_info(t)
+    nb = info["n_buckets"]
+    buf = np.zeros(info["export_bytes"], dtype=np.uint8)
+    _check(load().rmat_table_export(t.handle, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes), "rmat_table_export")
+    return _split_export(buf, nb)
 
 
 def rmat_generate(t: Table, seed: int, edge_begin: int, m: int, out_src, out_dst):
@@ -191,3 +226,99 @@ def generate_edges(t: Table, seed: int, edge_begin: int, m: int, device="cuda", 
         stream = torch.cuda.current_stream(src.device)
     rmat_generate_async(t, seed, edge_begin, m, src, dst, stream)
     return src, dst
+
+
+# ---------------------------------------------------------------------------
+# batches
+
+def make_instances(params) -> "ctypes.Array":
+    """Array of rmat_instance from dicts with keys a, b, c, d, k, path_mode,
+    table_bound, seed, edge_begin, m, out_src, out_dst (tensors or ints)."""
+    arr = (rmat_instance * len(params))()
+    for x, p in zip(arr, params):
+        x.a, x.b, x.c, x.d = p["a"], p["b"], p["c"], p["d"]
+        x.k, x.path_mode = p["k"], p.get("path_mode", RMAT_VARIABLE)
+        x.table_bound, x.seed = p.get("table_bound", 0), p["seed"]
+        x.edge_begin, x.m = p.get("edge_begin", 0), p["m"]
+        x.out_src, x.out_dst = _ptr(p.get("out_src")), _ptr(p.get("out_dst"))
+    return arr
+
+
+class Batch:
+    """Owning handle of an rmat_batch_t."""
+
+    def __init__(self, handle: int, n: int):
+        self.handle = handle
+        self.n = n
+
+    def close(self):
+        if self.handle:
+            _check(load().rmat_batch_free(self.handle), "rmat_batch_free")
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rmat_batch_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def rmat_batch_create(instances, work_blocks: int = 0) -> Batch:
+    """instances: an rmat_instance array (make_instances) or a list of dicts."""
+    arr = instances if isinstance(instances, ctypes.Array) else make_instances(instances)
+    h = ctypes.c_void_p()
+    _check(load().rmat_batch_create(arr, len(arr), work_blocks, ctypes.byref(h)), "rmat_batch_create")
+    return Batch(h.value, len(arr))
+
+
+def rmat_batch_enqueue(b: Batch, stream=None):
+    _check(load().rmat_batch_enqueue(b.handle, _stream(stream)), "rmat_batch_enqueue")
+
+
+def rmat_batch_launch_graph(b: Batch, stream=None):
+    _check(load().rmat_batch_launch_graph(b.handle, _stream(stream)), "rmat_batch_launch_graph")
+
+
+def rmat_batch_check(b: Batch):
+    _check(load().rmat_batch_check(b.handle), "rmat_batch_check")
+
+
+def rmat_batch_get_info(b: Batch) -> dict:
+    info = rmat_batch_info()
+    _check(load().rmat_batch_get_info(b.handle, ctypes.byref(info)), "rmat_batch_get_info")
+    return {name: getattr(info, name) for name, _ in rmat_batch_info._fields_}
+
+
+def rmat_batch_table_info(b: Batch, i: int) -> dict:
+    info = rmat_info()
+    _check(load().rmat_batch_table_info(b.handle, i, ctypes.byref(info)), "rmat_batch_table_info")
+    return {name: getattr(info, name) for name, _ in rmat_info._fields_}
+
+
+def rmat_batch_table_export(b: Batch, i: int) -> dict:
+    n_buckets = rmat_batch_table_info(b, i)["n_buckets"]
+    buf = np.zeros(36 * n_buckets, dtype=np.uint8)
+    _check(load().rmat_batch_table_export(b.handle, i, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+           "rmat_batch_table_export")
+    return _split_export(buf, n_buckets)
+
+
+def rmat_batch_free(b: Batch):
+    b.close()
+
+
+def rmat_batch_autotune(instances) -> dict:
+    """Fills table_bound in place for entries that hold 0 (an rmat_instance
+    array; a list of dicts is updated too) and returns the report."""
+    arr = instances if isinstance(instances, ctypes.Array) else make_instances(instances)
+    rep = rmat_autotune_report()
+    _check(load().rmat_batch_autotune(arr, len(arr), ctypes.byref(rep)), "rmat_batch_autotune")
+    if not isinstance(instances, ctypes.Array):
+        for p, x in zip(instances, arr):
+            p["table_bound"] = x.table_bound
+    return {name: getattr(rep, name) for name, _ in rmat_autotune_report._fields_}

@@ -60,3 +60,48 @@ def test_null_handles():
     assert L.rmat_table_export(None, None, 0) == R.RMAT_EINVAL
     assert L.rmat_build_table(0.25, 0.25, 0.25, 0.25, 10, 100, 1, ctypes.cast(0, ctypes.POINTER(ctypes.c_void_p))) \
         == R.RMAT_EINVAL
+
+
+def _inst(**kw):
+    p = dict(a=0.57, b=0.19, c=0.19, d=0.05, k=16, path_mode=R.RMAT_VARIABLE, table_bound=256, seed=1,
+             edge_begin=0, m=0, out_src=None, out_dst=None)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(k=0), R.RMAT_EINVAL),
+    (dict(a=0.6), R.RMAT_EINVAL),
+    (dict(table_bound=3), R.RMAT_EINVAL),
+    (dict(path_mode=R.RMAT_FIXED, table_bound=4 ** 6, k=4), R.RMAT_EINVAL),
+    (dict(m=10), R.RMAT_EINVAL),                                  # NULL outputs
+    (dict(m=10, out_src=6, out_dst=8), R.RMAT_EINVAL),            # 6 not 4-byte aligned
+    (dict(m=10, k=40, out_src=12, out_dst=16), R.RMAT_EINVAL),    # 64-bit ids need 8-byte alignment
+    (dict(m=2, edge_begin=2 ** 64 - 1, out_src=16, out_dst=32), R.RMAT_ERANGE),
+])
+def test_batch_invalid_instance_rejected_on_host(bad, status):
+    insts = [_inst(), _inst(seed=2), _inst(**bad)]
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_batch_create(insts)
+    assert ei.value.status == status
+    assert "instance 2" in str(ei.value)
+
+
+def test_batch_null_handles():
+    import ctypes
+    L = R.load()
+    assert L.rmat_batch_free(None) == R.RMAT_OK
+    assert L.rmat_batch_enqueue(None, None) == R.RMAT_EINVAL
+    assert L.rmat_batch_launch_graph(None, None) == R.RMAT_EINVAL
+    assert L.rmat_batch_check(None) == R.RMAT_EINVAL
+    assert L.rmat_batch_get_info(None, None) == R.RMAT_EINVAL
+    assert L.rmat_batch_table_info(None, 0, None) == R.RMAT_EINVAL
+    assert L.rmat_batch_table_export(None, 0, None, 0) == R.RMAT_EINVAL
+    assert L.rmat_batch_create(None, 0, 0, ctypes.cast(0, ctypes.POINTER(ctypes.c_void_p))) == R.RMAT_EINVAL
+    assert L.rmat_batch_autotune(None, 0, None) == R.RMAT_EINVAL
+
+
+def test_autotune_rejects_invalid_instance_on_host():
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_batch_autotune([_inst(table_bound=0), _inst(table_bound=0, b=0.5)])
+    assert ei.value.status == R.RMAT_EINVAL and "instance 1" in str(ei.value)

@@ -1,0 +1,170 @@
+"""Batches through the C ABI: every instance of a batch equals the plain
+per-instance path (rmat_build_table + rmat_generate with the same
+arguments) and the CPU oracle; graph replays equal the eager run; the
+autotuner is deterministic; the 512-instance workload at full size."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_03525_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+G500 = (0.57, 0.19, 0.19, 0.05)
+CFG3 = (0.45, 0.22, 0.22, 0.11)
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_03525_amd as R
+    R.load()
+    return R
+
+
+def _alloc(R, insts):
+    import torch
+    for p in insts:
+        dt = R.id_dtype(p["k"])
+        p["out_src"] = torch.full((p["m"],), -1, dtype=dt, device="cuda")
+        p["out_dst"] = torch.full((p["m"],), -1, dtype=dt, device="cuda")
+    torch.cuda.synchronize()
+
+
+def _plain(R, p):
+    """Plain path: own table, own launch."""
+    import torch
+    t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+    s, d = R.generate_edges(t, p["seed"], p["edge_begin"], p["m"])
+    torch.cuda.synchronize()
+    return t, s, d
+
+
+def _mixed():
+    """Uneven instances: both id widths, both table residencies, FIXED and
+    VARIABLE, unaligned and huge edge_begin, m = 0 and m = 1."""
+    q = lambda s: workloads.dirichlet_q(np.random.default_rng(1000 + s))  # noqa: E731
+    V, F = oracle.VARIABLE, oracle.FIXED
+    rows = [
+        # q, k, bound, mode, seed, edge_begin, m
+        (G500, 16, 256, F, 1, 0, 1 << 16),
+        (G500, 26, 4096, V, 7, 12_345_677, 100_003),
+        (CFG3, 34, 1 << 16, V, 3, 2**32 - 3000, 9000),    # 64-bit ids, L2 table, crosses e_hi
+        (q(1), 12, 300, V, 11, 5, 40_000),
+        (q(2), 40, 8192, V, 12, 10**12 + 1, 30_001),      # 64-bit ids, LDS table
+        (q(3), 20, 4**5, F, 13, 0, 0),                    # no edges: table only
+        (q(4), 24, 1 << 15, V, 14, 63, 65),               # L2 table, 32-bit ids
+        (q(5), 10, 5, V, 15, 0, 1),
+        (q(6), 64, 2000, V, 2**64 - 1, 2**64 - 777, 777),  # last edges of the stream
+        (q(7), 30, 5000, V, 16, 3, 50_000),
+        (q(8), 3, 100, V, 17, 0, 4096),
+        (G500, 26, 4096, V, 7, 0, 64 * 2048 * 3 + 5),     # several work items of one instance
+    ]
+    return [dict(a=x[0][0], b=x[0][1], c=x[0][2], d=x[0][3], k=x[1], table_bound=x[2], path_mode=x[3], seed=x[4],
+                 edge_begin=x[5], m=x[6]) for x in rows]
+
+
+@pytest.mark.parametrize("work_blocks", [0, 3, 1])
+def test_batch_equals_plain_and_oracle(R, work_blocks):
+    import torch
+    insts = _mixed()
+    _alloc(R, insts)
+    with R.rmat_batch_create(insts, work_blocks) as b:
+        info = R.rmat_batch_get_info(b)
+        assert info["n_instances"] == len(insts) and info["n_launches"] == 4
+        assert info["total_edges"] == sum(p["m"] for p in insts)
+        R.rmat_batch_enqueue(b, torch.cuda.current_stream())
+        R.rmat_batch_check(b)
+        for i, p in enumerate(insts):
+            t, s, d = _plain(R, p)
+            assert torch.equal(s, p["out_src"]) and torch.equal(d, p["out_dst"]), f"instance {i} differs from plain"
+            gt, bt = R.rmat_table_export(t), R.rmat_batch_table_export(b, i)
+            for key in gt:
+                assert np.array_equal(gt[key], bt[key]), f"instance {i} table {key}"
+            assert R.rmat_batch_table_info(b, i) == R.rmat_table_info(t)
+            t.close()
+            o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+            os_, od = oracle.generate(o, p["seed"], p["edge_begin"], p["m"], threads=8)
+            assert np.array_equal(R.to_numpy_ids(p["out_src"], p["k"]), os_), f"instance {i} src vs oracle"
+            assert np.array_equal(R.to_numpy_ids(p["out_dst"], p["k"]), od), f"instance {i} dst vs oracle"
+
+
+def test_batch_graph_replays_equal_eager(R):
+    import torch
+    insts = workloads.batch_instances(40, k_min=8, k_max=16)
+    for j, p in enumerate(insts):
+        p["table_bound"] = 256 << (j % 6)
+    _alloc(R, insts)
+    stream = torch.cuda.current_stream()
+    with R.rmat_batch_create(insts, 16) as b:
+        R.rmat_batch_enqueue(b, stream)
+        R.rmat_batch_check(b)
+        ref = [(p["out_src"].clone(), p["out_dst"].clone()) for p in insts]
+        other = R.rmat_build_table(*G500, 20, 1000, R.RMAT_VARIABLE)
+        for rep in range(4):
+            for p in insts:   # eager work between replays: clear the outputs, run an unrelated launch
+                p["out_src"].fill_(-1)
+                p["out_dst"].fill_(-1)
+            R.generate_edges(other, rep, 0, 1 << 16)
+            torch.cuda.synchronize()
+            R.rmat_batch_launch_graph(b, stream)
+            R.rmat_batch_check(b)
+            for i, p in enumerate(insts):
+                assert torch.equal(ref[i][0], p["out_src"]) and torch.equal(ref[i][1], p["out_dst"]), \
+                    f"replay {rep}, instance {i}"
+        other.close()
+
+
+def test_autotune_deterministic(R):
+    insts = workloads.batch_instances(64)
+    insts[5]["table_bound"] = 777
+    a = [dict(p) for p in insts]
+    rep1 = R.rmat_batch_autotune(a)
+    b = [dict(p) for p in insts]
+    rep2 = R.rmat_batch_autotune(b)
+    assert [p["table_bound"] for p in a] == [p["table_bound"] for p in b]
+    assert a[5]["table_bound"] == 777
+    assert all(p["table_bound"] in {256, 512, 1024, 2048, 4096, 8192} for j, p in enumerate(a) if j != 5)
+    for rep in (rep1, rep2):
+        assert rep["n_tuned"] == 63 and rep["n_candidates"] == 6
+        assert 128 <= rep["work_blocks"] <= 8192
+        assert rep["calibration_ns"] > 0 and rep["search_seconds"] > 0
+
+
+def test_batch_workload_512_full(R):
+    """The 512-instance workload at full size (about 1.7e10 edges): autotuned
+    bounds, one graph launch, every instance equal to its plain launch on the
+    device, and oracle samples at both ends and in the middle of each."""
+    import torch
+    insts = workloads.batch_instances()
+    rep = R.rmat_batch_autotune(insts)
+    _alloc(R, insts)
+    stream = torch.cuda.current_stream()
+    m_max = max(p["m"] for p in insts)
+    s_all = torch.empty(m_max, dtype=torch.int32, device="cuda")
+    d_all = torch.empty(m_max, dtype=torch.int32, device="cuda")
+    with R.rmat_batch_create(insts, rep["work_blocks"]) as b:
+        R.rmat_batch_launch_graph(b, stream)
+        R.rmat_batch_check(b)
+        rng = np.random.default_rng(512)
+        for i, p in enumerate(insts):
+            t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+            s, d = s_all[:p["m"]], d_all[:p["m"]]
+            R.rmat_generate_async(t, p["seed"], 0, p["m"], s, d, stream)
+            torch.cuda.synchronize()
+            assert torch.equal(s, p["out_src"]) and torch.equal(d, p["out_dst"]), f"instance {i} differs from plain"
+            t.close()
+            o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+            m = p["m"]
+            for e0 in (0, int(rng.integers(0, m - 256)), m - 256):
+                os_, od = oracle.generate(o, p["seed"], e0, 256, threads=1)
+                gs = R.to_numpy_ids(p["out_src"][e0:e0 + 256], p["k"])
+                gd = R.to_numpy_ids(p["out_dst"][e0:e0 + 256], p["k"])
+                assert np.array_equal(gs, os_) and np.array_equal(gd, od), f"instance {i} at {e0} vs oracle"
+    for p in insts:
+        p["out_src"] = p["out_dst"] = None
+    torch.cuda.empty_cache()
