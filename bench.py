@@ -7,9 +7,12 @@ records), then generate m = 16 * 2^26 = 2^30 edges (Philox draws, alias
 lookups, concatenation, stores of uint32 source and destination ids) into
 device memory.  One JSON line is printed.  Beside it: the 512-instance
 batched workload as one hipGraph launch against 512 plain launches
-(`batched_speedup`), and the CPU oracle on a bounded sample (`cpu_baseline`).
+(`batched_speedup`), a window of the served request stream against plain
+per-request launches (`served`), and the CPU oracle on a bounded sample
+(`cpu_baseline`).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batch]
+                    [--served-window S] [--served-reading A|B]
 """
 from __future__ import annotations
 
@@ -131,6 +134,53 @@ def batched_vs_plain(R, reps: int = 3) -> dict:
             "bounds_histogram": {str(v): bounds.count(v) for v in sorted(set(bounds))}}
 
 
+def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0) -> dict:
+    """The served workload: a Poisson stream of R-MAT requests (k per
+    `reading`, edge factor 8 or 16, Dirichlet(4,2,2,1) parameters, table bound
+    4096) at `rate` requests/s; the first `window_s` seconds of arrivals go
+    through the request server (200 GB output arena, device table cache,
+    continuous batching), outputs released as each request completes.  The
+    same requests are then generated one after another by plain
+    rmat_build_table + rmat_generate_async calls."""
+    import torch
+    from paper_1905_03525_amd import workloads
+    reqs = workloads.served_requests(rate=rate, duration=window_s, arrival_seed=2019, reading=reading)
+    for p in reqs:
+        p["flags"] = R.RMAT_REQ_DISCARD
+    total = sum(p["m"] for p in reqs)
+    with R.rmat_server_create() as s:
+        t0 = time.perf_counter()
+        out = R.rmat_server_run_trace(s, reqs, [p["t_arrival"] for p in reqs])
+        wall = time.perf_counter() - t0
+        st = R.rmat_server_get_stats(s)
+    assert all(c["status"] == 0 for c in out)
+    lat = sorted(c["t_done"] - c["t_submit"] for c in out)
+    wait = sorted(c["t_admit"] - c["t_submit"] for c in out)
+    pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))] * 1e3  # noqa: E731
+    # plain per-request launches of the same requests, back to back
+    m_max = max(p["m"] for p in reqs)
+    src = torch.empty(m_max, dtype=torch.int32, device="cuda")
+    dst = torch.empty(m_max, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in reqs:
+        t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+        R.rmat_generate_async(t, p["seed"], 0, p["m"], src, dst, stream)
+        torch.cuda.synchronize()
+        t.close()
+    plain = time.perf_counter() - t0
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"workload": f"served_poisson{rate:g}_k12-28{reading}_ef8-16_var4096", "reading": reading,
+            "window_s": window_s, "requests": len(reqs), "total_edges": total, "wall_s": wall,
+            "edges_per_s": total / wall, "hbm_write_gbs": 8 * total / wall / 1e9,
+            "p50_latency_ms": pct(lat, 0.5), "p99_latency_ms": pct(lat, 0.99), "p50_wait_ms": pct(wait, 0.5),
+            "p99_wait_ms": pct(wait, 0.99), "table_hit_rate": st["table_hits"] / max(1, st["admitted"]),
+            "rounds": st["rounds"], "arena_peak_gb": st["arena_peak"] / 1e9,
+            "plain_edges_per_s": total / plain, "served_over_plain": plain / wall}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +188,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched comparison")
+    ap.add_argument("--served-window", type=float, default=3.0,
+                    help="seconds of the 2000 requests/s stream to serve (0: skip; the full stream is 60)")
+    ap.add_argument("--served-reading", default="A", choices=["A", "B"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sampler needs no second one "
@@ -231,6 +284,8 @@ def main():
         bt = batched_vs_plain(R)
         out["batched_speedup"] = bt["speedup"]
         out["batched"] = bt
+    if args.served_window > 0:
+        out["served"] = served_vs_plain(R, args.served_window, args.served_reading)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

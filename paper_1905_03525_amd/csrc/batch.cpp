@@ -148,6 +148,7 @@ int enqueue(rmat_batch* b, hipStream_t s) {
     a.max_buckets = g.max_buckets;
     a.wide = g.wide;
     a.lds = g.lds;
+    a.digest = 0;
     e = rmat::launch_generate_batch(a, s);
     if (e != hipSuccess) return rmat::hip_fail(e, "batch generation launch");
   }
@@ -359,6 +360,7 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
     d.n_blocks = x.m ? ((x.edge_begin + (x.m - 1)) >> 6) - d.first_block + 1 : 0;
     d.out_src = x.out_src;
     d.out_dst = x.out_dst;
+    d.digest = nullptr;
     b->total_edges += x.m;
   }
   // every byte 0xFF: each table's build status reads -1 (not built) until the first run

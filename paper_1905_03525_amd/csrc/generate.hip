@@ -148,6 +148,16 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
   return z;
 }
 
+// XOR over the 64 lanes of a wave, in every lane.
+__device__ __forceinline__ uint64_t wave_xor(uint64_t x) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t lo = __shfl_xor(static_cast<uint32_t>(x), o, 64);
+    const uint32_t hi = __shfl_xor(static_cast<uint32_t>(x >> 32), o, 64);
+    x ^= (static_cast<uint64_t>(hi) << 32) | lo;
+  }
+  return x;
+}
+
 // Orders this wave's LDS accesses across the passes of a tile.
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
@@ -157,7 +167,7 @@ __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOM
 //      edges listed;
 //   2. the listed edges finished 64 at a time;
 //   3. the tile stored (or reduced).
-template <typename Acc, bool kReduce>
+template <typename Acc, bool kReduce, bool kDigest = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
@@ -229,8 +239,13 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
         } else {
           const uint64_t slot = e - I.edge_begin;
-          static_cast<Id*>(I.out_src)[slot] = static_cast<Id>(acc.src(I.k));
-          static_cast<Id*>(I.out_dst)[slot] = static_cast<Id>(acc.dst(I.k));
+          const Id s = static_cast<Id>(acc.src(I.k)), d = static_cast<Id>(acc.dst(I.k));
+          static_cast<Id*>(I.out_src)[slot] = s;
+          static_cast<Id*>(I.out_dst)[slot] = d;
+          if (kDigest) {
+            const uint64_t s64 = s, d64 = d;
+            xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
+          }
         }
       }
     }
@@ -264,12 +279,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   uint64_t xsum = 0;
   run_blocks<Acc, kReduce>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.hist, xsum);
   if (kReduce) {
-    uint64_t x = xsum;
-    for (int o = 32; o >= 1; o >>= 1) {
-      const uint32_t lo = __shfl_xor(static_cast<uint32_t>(x), o, 64);
-      const uint32_t hi = __shfl_xor(static_cast<uint32_t>(x >> 32), o, 64);
-      x ^= (static_cast<uint64_t>(hi) << 32) | lo;
-    }
+    const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
 // Persistent kernel over the work items of a batch.  A workgroup claims an
 // item, restages the table only when the instance changes (items are in
 // instance order), and its 16 waves share the item's blocks.
-template <typename Acc, bool kLds>
+template <typename Acc, bool kLds, bool kDigest>
 __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch B) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ uint32_t s_item;
@@ -292,7 +302,6 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
   Packed* res = reinterpret_cast<Packed*>(s_mem + B.L.lds_table + wave_in_wg * B.L.wave_bytes);
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + B.L.tile * 64);
   uint32_t cur = 0xFFFFFFFFu;
-  uint64_t xsum = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(B.counter, 1u);
     __syncthreads();
@@ -307,8 +316,13 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     }
     cur = W.inst;
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
-    run_blocks<Acc, false>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0, nullptr,
-                           xsum);
+    uint64_t xsum = 0;
+    run_blocks<Acc, false, kDigest>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0,
+                                    nullptr, xsum);
+    if (kDigest && I.digest != nullptr) {
+      const uint64_t x = wave_xor(xsum);
+      if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(I.digest, x);
+    }
   }
 }
 
@@ -385,6 +399,7 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.I.n_blocks = ((a.edge_begin + (a.m - 1)) >> 6) - P.I.first_block + 1;
   P.I.out_src = a.out_src;
   P.I.out_dst = a.out_dst;
+  P.I.digest = nullptr;
   P.hist_shift = static_cast<uint32_t>(a.k - a.hist_bits);
   P.hist = a.hist;
   P.xor_out = a.xor_out;
@@ -394,7 +409,7 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   return wide ? launch_one<Acc64, false, kReduce>(P, s) : launch_one<Acc32, false, kReduce>(P, s);
 }
 
-template <typename Acc, bool kLds>
+template <typename Acc, bool kLds, bool kDigest>
 hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   BatchLaunch B;
   B.insts = a.insts;
@@ -407,8 +422,8 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   uint64_t grid = persistent_grid(lds);
   if (grid > a.n_items) grid = a.n_items;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((generate_batch_kernel<Acc, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads), lds,
-                     s, B);
+  hipLaunchKernelGGL((generate_batch_kernel<Acc, kLds, kDigest>), dim3(static_cast<uint32_t>(grid)),
+                     dim3(kGenThreads), lds, s, B);
   return hipGetLastError();
 }
 
@@ -436,8 +451,12 @@ hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return
 
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s) {
   if (a.n_items == 0) return hipSuccess;
-  if (a.wide) return a.lds ? launch_batch<Acc64, true>(a, s) : launch_batch<Acc64, false>(a, s);
-  return a.lds ? launch_batch<Acc32, true>(a, s) : launch_batch<Acc32, false>(a, s);
+  if (a.digest) {
+    if (a.wide) return a.lds ? launch_batch<Acc64, true, true>(a, s) : launch_batch<Acc64, false, true>(a, s);
+    return a.lds ? launch_batch<Acc32, true, true>(a, s) : launch_batch<Acc32, false, true>(a, s);
+  }
+  if (a.wide) return a.lds ? launch_batch<Acc64, true, false>(a, s) : launch_batch<Acc64, false, false>(a, s);
+  return a.lds ? launch_batch<Acc32, true, false>(a, s) : launch_batch<Acc32, false, false>(a, s);
 }
 
 uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds) {
@@ -455,8 +474,14 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_kernel<Acc64, true, false>), allow_full_lds(&generate_kernel<Acc64, false, false>),
       allow_full_lds(&generate_kernel<Acc32, true, true>),  allow_full_lds(&generate_kernel<Acc32, false, true>),
       allow_full_lds(&generate_kernel<Acc64, true, true>),  allow_full_lds(&generate_kernel<Acc64, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true>),  allow_full_lds(&generate_batch_kernel<Acc32, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true>),  allow_full_lds(&generate_batch_kernel<Acc64, false>)};
+      allow_full_lds(&generate_batch_kernel<Acc32, true, false>),
+      allow_full_lds(&generate_batch_kernel<Acc32, false, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, false, false>),
+      allow_full_lds(&generate_batch_kernel<Acc32, true, true>),
+      allow_full_lds(&generate_batch_kernel<Acc32, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true, true>),
+      allow_full_lds(&generate_batch_kernel<Acc64, false, true>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

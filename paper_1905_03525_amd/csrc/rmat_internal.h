@@ -91,6 +91,9 @@ struct GenInst {
   uint64_t first_block, n_blocks;
   void* out_src;
   void* out_dst;
+  // if set (launches with digests enabled), XOR-ed with the XOR over the
+  // generated edges of fmix64(e ^ fmix64(src ^ rotl64(dst, 32)))
+  unsigned long long* digest;
 };
 
 // A run of 64-edge blocks of one instance; a batch lists them in instance
@@ -109,6 +112,7 @@ struct BatchArgs {
   uint32_t max_buckets;    // largest table of the batch (LDS staging size)
   int wide;                // k > 32 (64-bit ids)
   int lds;                 // tables staged in LDS
+  int digest;              // honour GenInst::digest
 };
 
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s);

@@ -28,7 +28,12 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
 EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
             "rmat_generate_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
             "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
-            "rmat_batch_free", "rmat_batch_autotune", "rmat_last_error"]
+            "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
+            "rmat_server_step", "rmat_server_drain", "rmat_server_poll", "rmat_server_release",
+            "rmat_server_run_trace", "rmat_server_get_stats", "rmat_server_clock", "rmat_server_free",
+            "rmat_last_error"]
+RMAT_REQ_DIGEST = 1
+RMAT_REQ_DISCARD = 2
 
 
 class RmatError(RuntimeError):
@@ -66,6 +71,35 @@ class rmat_autotune_report(ctypes.Structure):
                 ("work_blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class rmat_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_table_bound", ctypes.c_uint64),
+                ("tick_blocks", ctypes.c_uint64), ("request_quantum", ctypes.c_uint64),
+                ("max_active", ctypes.c_uint32), ("table_slots", ctypes.c_uint32), ("work_blocks", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32), ("max_builds", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class rmat_request(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double), ("d", ctypes.c_double),
+                ("k", ctypes.c_int32), ("path_mode", ctypes.c_int32), ("table_bound", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("edge_begin", ctypes.c_uint64), ("m", ctypes.c_uint64),
+                ("out_src", ctypes.c_void_p), ("out_dst", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class rmat_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("table_hit", ctypes.c_uint32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("digest", ctypes.c_uint64), ("out_src", ctypes.c_void_p), ("out_dst", ctypes.c_void_p)]
+
+
+class rmat_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("rounds", ctypes.c_uint64), ("table_builds", ctypes.c_uint64),
+                ("table_hits", ctypes.c_uint64), ("edges_done", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_peak", ctypes.c_uint64), ("active", ctypes.c_uint32), ("pending", ctypes.c_uint32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -95,11 +129,23 @@ def load() -> ctypes.CDLL:
     L.rmat_batch_get_info.argtypes = [vp, ctypes.POINTER(rmat_batch_info)]
     L.rmat_batch_free.argtypes = [vp]
     L.rmat_batch_autotune.argtypes = [ctypes.POINTER(rmat_instance), c_int, ctypes.POINTER(rmat_autotune_report)]
+    L.rmat_server_create.argtypes = [ctypes.POINTER(rmat_server_config), ctypes.POINTER(vp)]
+    L.rmat_server_submit.argtypes = [vp, ctypes.POINTER(rmat_request), ctypes.c_double, ctypes.POINTER(u64)]
+    L.rmat_server_step.argtypes = [vp, ctypes.POINTER(c_int)]
+    L.rmat_server_drain.argtypes = [vp]
+    L.rmat_server_poll.argtypes = [vp, ctypes.POINTER(rmat_completion), c_int, ctypes.POINTER(c_int)]
+    L.rmat_server_release.argtypes = [vp, u64]
+    L.rmat_server_run_trace.argtypes = [vp, ctypes.POINTER(rmat_request), ctypes.POINTER(ctypes.c_double), c_int,
+                                        ctypes.POINTER(rmat_completion)]
+    L.rmat_server_get_stats.argtypes = [vp, ctypes.POINTER(rmat_server_stats)]
+    L.rmat_server_clock.argtypes = [vp]
+    L.rmat_server_free.argtypes = [vp]
     L.rmat_last_error.argtypes = []
     L.rmat_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "rmat_last_error":
             getattr(L, name).restype = c_int
+    L.rmat_server_clock.restype = ctypes.c_double
     _lib = L
     return L
 
@@ -322,3 +368,107 @@ def rmat_batch_autotune(instances) -> dict:
         for p, x in zip(instances, arr):
             p["table_bound"] = x.table_bound
     return {name: getattr(rep, name) for name, _ in rmat_autotune_report._fields_}
+
+
+# ---------------------------------------------------------------------------
+# request server
+
+def _struct_dict(x) -> dict:
+    return {name: getattr(x, name) for name, _ in x._fields_}
+
+
+def make_request(p: dict) -> rmat_request:
+    r = rmat_request()
+    r.a, r.b, r.c, r.d = p["a"], p["b"], p["c"], p["d"]
+    r.k, r.path_mode = p["k"], p.get("path_mode", RMAT_VARIABLE)
+    r.table_bound, r.seed = p["table_bound"], p["seed"]
+    r.edge_begin, r.m = p.get("edge_begin", 0), p["m"]
+    r.out_src, r.out_dst = _ptr(p.get("out_src")), _ptr(p.get("out_dst"))
+    r.flags = p.get("flags", 0)
+    return r
+
+
+class Server:
+    """Owning handle of an rmat_server_t."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            _check(load().rmat_server_free(self.handle), "rmat_server_free")
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rmat_server_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def rmat_server_create(**cfg) -> Server:
+    """Keyword arguments are rmat_server_config fields (0 / absent: default)."""
+    c = rmat_server_config()
+    for key, val in cfg.items():
+        setattr(c, key, val)
+    h = ctypes.c_void_p()
+    _check(load().rmat_server_create(ctypes.byref(c), ctypes.byref(h)), "rmat_server_create")
+    return Server(h.value)
+
+
+def rmat_server_submit(s: Server, p: dict, t_arrival: float = -1.0) -> int:
+    r = make_request(p)
+    t = ctypes.c_uint64()
+    _check(load().rmat_server_submit(s.handle, ctypes.byref(r), t_arrival, ctypes.byref(t)), "rmat_server_submit")
+    return t.value
+
+
+def rmat_server_step(s: Server) -> bool:
+    busy = ctypes.c_int()
+    _check(load().rmat_server_step(s.handle, ctypes.byref(busy)), "rmat_server_step")
+    return bool(busy.value)
+
+
+def rmat_server_drain(s: Server):
+    _check(load().rmat_server_drain(s.handle), "rmat_server_drain")
+
+
+def rmat_server_poll(s: Server, max_n: int = 4096) -> list:
+    buf = (rmat_completion * max_n)()
+    n = ctypes.c_int()
+    _check(load().rmat_server_poll(s.handle, buf, max_n, ctypes.byref(n)), "rmat_server_poll")
+    return [_struct_dict(buf[i]) for i in range(n.value)]
+
+
+def rmat_server_release(s: Server, ticket: int):
+    _check(load().rmat_server_release(s.handle, ticket), "rmat_server_release")
+
+
+def rmat_server_run_trace(s: Server, requests: list, t_arrival) -> list:
+    """Serves `requests` (dicts) arriving at t_arrival (seconds, ascending);
+    returns one completion dict per request, in request order."""
+    n = len(requests)
+    arr = (rmat_request * n)(*[make_request(p) for p in requests])
+    ts = (ctypes.c_double * n)(*[float(t) for t in t_arrival])
+    out = (rmat_completion * n)()
+    _check(load().rmat_server_run_trace(s.handle, arr, ts, n, out), "rmat_server_run_trace")
+    return [_struct_dict(out[i]) for i in range(n)]
+
+
+def rmat_server_get_stats(s: Server) -> dict:
+    st = rmat_server_stats()
+    _check(load().rmat_server_get_stats(s.handle, ctypes.byref(st)), "rmat_server_get_stats")
+    return _struct_dict(st)
+
+
+def rmat_server_clock(s: Server) -> float:
+    return load().rmat_server_clock(s.handle)
+
+
+def rmat_server_free(s: Server):
+    s.close()

@@ -1,0 +1,180 @@
+// Host-only fake of the HIP runtime calls and of the sampler's kernel
+// launchers, for testing the server's scheduling logic with g++ and the host
+// sanitizers.  "Device" memory is host memory; a launch acts at once on it:
+// the table build writes a tag naming its parameters, the batch generation
+// checks its work list and records which edges of which request it covered
+// and XORs a per-edge word into the request's digest.  Events complete at
+// random (seeded), never out of order.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <random>
+#include <vector>
+
+#include "rmat_internal.h"
+#include "sim_hash.h"
+
+namespace {
+std::mt19937_64 g_rng(1);
+double g_ready_p = 0.5;
+int g_fail = 0;
+std::map<uint64_t, std::vector<uint32_t>> g_cov;  // request seed -> per-edge write count
+uint64_t g_launches = 0;
+
+void fail(const char* what) {
+  std::fprintf(stderr, "fake device: %s\n", what);
+  g_fail = 1;
+}
+}  // namespace
+
+struct ihipStream_t {
+  int dummy;
+};
+struct ihipEvent_t {
+  bool recorded = false, ready = false;
+};
+
+extern "C" {
+void sim_seed(uint64_t s, double ready_p) {
+  g_rng.seed(s);
+  g_ready_p = ready_p;
+}
+int sim_failed() { return g_fail; }
+uint64_t sim_launches() { return g_launches; }
+// 0 if every edge of the request with this seed was generated exactly once,
+// else -1; forgets the request.
+int sim_take_coverage(uint64_t seed, uint64_t m) {
+  auto it = g_cov.find(seed);
+  if (m == 0) return it == g_cov.end() ? 0 : -1;
+  if (it == g_cov.end() || it->second.size() != m) return -1;
+  for (uint32_t c : it->second)
+    if (c != 1) return -1;
+  g_cov.erase(it);
+  return 0;
+}
+}
+
+hipError_t hipMalloc(void** p, size_t n) {
+  *p = std::aligned_alloc(256, (n + 255) / 256 * 256);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipFree(void* p) {
+  std::free(p);
+  return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) { return hipMalloc(p, n); }
+hipError_t hipHostFree(void* p) { return hipFree(p); }
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
+  std::memmove(d, s, n);
+  return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t) {
+  return hipMemcpy(d, s, n, k);
+}
+hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
+  std::memset(p, 0, sizeof(*p));
+  std::strcpy(p->gcnArchName, "gfx950:sramecc+:xnack-");
+  p->multiProcessorCount = 256;
+  return hipSuccess;
+}
+hipError_t hipDeviceSynchronize() { return hipSuccess; }
+hipError_t hipGetLastError() { return hipSuccess; }
+const char* hipGetErrorString(hipError_t) { return "fake device error"; }
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+  *s = new ihipStream_t();
+  return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) {
+  delete s;
+  return hipSuccess;
+}
+hipError_t hipEventCreate(hipEvent_t* e) {
+  *e = new ihipEvent_t();
+  return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
+  e->recorded = true;
+  e->ready = false;
+  return hipSuccess;
+}
+hipError_t hipEventQuery(hipEvent_t e) {
+  if (!e->recorded) return hipSuccess;
+  if (!e->ready && std::uniform_real_distribution<double>(0, 1)(g_rng) < g_ready_p) e->ready = true;
+  return e->ready ? hipSuccess : hipErrorNotReady;
+}
+hipError_t hipEventSynchronize(hipEvent_t e) {
+  e->ready = true;
+  return hipSuccess;
+}
+hipError_t hipEventDestroy(hipEvent_t e) {
+  delete e;
+  return hipSuccess;
+}
+
+namespace rmat {
+
+hipError_t launch_table_build(const BuildJob* jobs, int n, hipStream_t) {
+  ++g_launches;
+  for (int j = 0; j < n; ++j) {
+    const BuildJob& J = jobs[j];
+    if (!J.records || !J.stats || J.n_buckets == 0) fail("build job without outputs");
+    uint64_t tag[2] = {sim::table_tag(J.q, J.k, J.mode), J.n_buckets};
+    std::memcpy(J.records, tag, sizeof(tag));
+    std::memset(J.stats, 0, sizeof(BuildStats));
+    J.stats->error = sim::build_fails(J.q) ? kBuildResidual : kBuildOk;
+    J.stats->n_items = J.n_items;
+    J.stats->min_len = J.stats->max_len = 1;
+    if (J.reset_counter) *J.reset_counter = 0;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
+  ++g_launches;
+  if (a.n_items == 0) return hipSuccess;
+  if (*a.counter != 0) fail("work counter not zero at launch");
+  for (uint32_t it = 0; it < a.n_items; ++it) {
+    const GenWorkItem& W = a.items[it];
+    const GenInst& I = a.insts[W.inst];
+    uint64_t tag[2];
+    std::memcpy(tag, I.records, sizeof(tag));
+    if (tag[1] != I.n_buckets) fail("instance table of another size");
+    if (W.n_blocks == 0 || W.first + W.n_blocks > I.n_blocks) fail("work item outside its instance");
+    if ((I.k > 32) != (a.wide != 0)) fail("id width of the launch");
+    if ((I.n_buckets <= lds_table_limit()) != (a.lds != 0)) fail("table residency of the launch");
+    if (I.n_buckets > a.max_buckets) fail("table larger than the launch's LDS layout");
+    if (I.first_block != I.edge_begin >> 6) fail("first block");
+    const uint64_t seed = static_cast<uint64_t>(I.key0) | static_cast<uint64_t>(I.key1) << 32;
+    std::vector<uint32_t>& cov = g_cov[seed];
+    if (cov.size() != I.m) cov.assign(I.m, 0);
+    const uint64_t last = I.edge_begin + (I.m - 1);
+    for (uint64_t b = W.first; b < W.first + W.n_blocks; ++b) {
+      const uint64_t base = (I.first_block + b) << 6;
+      for (uint64_t l = 0; l < 64; ++l) {
+        const uint64_t e = base + l;
+        if (e < I.edge_begin || e > last) continue;
+        ++cov[e - I.edge_begin];
+        if (a.digest && I.digest) *I.digest ^= sim::edge_word(e, seed, tag[0]);
+      }
+    }
+  }
+  *a.counter = a.n_items;
+  return hipSuccess;
+}
+
+hipError_t launch_generate(const GenerateArgs&, hipStream_t) { return hipSuccess; }
+hipError_t launch_generate_reduce(const GenerateArgs&, hipStream_t) { return hipSuccess; }
+hipError_t prepare_kernels() { return hipSuccess; }
+uint32_t lds_table_limit() { return 8192; }
+uint32_t tile_blocks(uint32_t, int, int) { return 8; }
+
+}  // namespace rmat

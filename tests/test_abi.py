@@ -105,3 +105,22 @@ def test_autotune_rejects_invalid_instance_on_host():
     with pytest.raises(R.RmatError) as ei:
         R.rmat_batch_autotune([_inst(table_bound=0), _inst(table_bound=0, b=0.5)])
     assert ei.value.status == R.RMAT_EINVAL and "instance 1" in str(ei.value)
+
+
+def test_server_null_handles_and_config_checks():
+    import ctypes
+    L = R.load()
+    assert L.rmat_server_free(None) == R.RMAT_OK
+    assert L.rmat_server_submit(None, None, -1.0, None) == R.RMAT_EINVAL
+    assert L.rmat_server_step(None, None) == R.RMAT_EINVAL
+    assert L.rmat_server_drain(None) == R.RMAT_EINVAL
+    assert L.rmat_server_poll(None, None, 0, None) == R.RMAT_EINVAL
+    assert L.rmat_server_release(None, 1) == R.RMAT_EINVAL
+    assert L.rmat_server_run_trace(None, None, None, 0, None) == R.RMAT_EINVAL
+    assert L.rmat_server_get_stats(None, None) == R.RMAT_EINVAL
+    assert L.rmat_server_clock(None) == 0.0
+    assert L.rmat_server_create(None, ctypes.cast(0, ctypes.POINTER(ctypes.c_void_p))) == R.RMAT_EINVAL
+    for bad in (dict(table_slots=4, max_active=8), dict(max_table_bound=3), dict(max_inflight=9)):
+        with pytest.raises(R.RmatError) as ei:
+            R.rmat_server_create(**bad)
+        assert ei.value.status == R.RMAT_EINVAL

@@ -1,0 +1,188 @@
+"""The request server through the C ABI: a request's edges and digest are the
+same served alone and in a mix of concurrent requests (tolerance 0), equal
+the plain launch and the oracle; admission waits for arena space and cache
+slots; errors are reported."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_03525_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+G500 = (0.57, 0.19, 0.19, 0.05)
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_03525_amd as R
+    R.load()
+    return R
+
+
+def _requests(n=48, seed=5):
+    """Mixed small requests: repeated parameter sets (cache hits), FIXED and
+    VARIABLE, 64-bit ids, an L2-resident table, unaligned edge ranges, m = 0."""
+    rng = np.random.default_rng(seed)
+    pool = [workloads.dirichlet_q(np.random.default_rng(100 + j)) for j in range(6)] + [G500]
+    out = []
+    for i in range(n):
+        q = pool[int(rng.integers(len(pool)))]
+        k = int(rng.integers(8, 19))
+        mode, bound = oracle.VARIABLE, int(rng.choice([256, 1000, 4096, 8192]))
+        if i % 7 == 3:
+            mode, bound = oracle.FIXED, 4 ** int(rng.integers(2, 5))
+        if i % 11 == 5:
+            k = 36                              # 64-bit ids
+        if i % 13 == 6:
+            bound = 1 << 15                     # table read from L2
+        m = int(rng.choice([8, 16])) << min(k, 16)
+        e0 = int(rng.integers(0, 1000)) if i % 3 == 0 else 0
+        if i == 17:
+            m = 0
+        out.append(dict(a=q[0], b=q[1], c=q[2], d=q[3], k=k, path_mode=mode, table_bound=bound, seed=1000 + i,
+                        edge_begin=e0, m=m, flags=1))   # RMAT_REQ_DIGEST
+    return out
+
+
+def _with_outputs(R, reqs):
+    """Copies of the requests; the even ones write into caller tensors, the
+    odd ones into the server's arena."""
+    import torch
+    out = []
+    for i, p in enumerate(reqs):
+        q = dict(p)
+        if i % 2 == 0 and p["m"]:
+            dt = R.id_dtype(p["k"])
+            q["out_src"] = torch.full((p["m"],), -1, dtype=dt, device="cuda")
+            q["out_dst"] = torch.full((p["m"],), -1, dtype=dt, device="cuda")
+        out.append(q)
+    torch.cuda.synchronize()
+    return out
+
+
+def _serve_alone(R, reqs, **cfg):
+    """Each request alone on an idle server; returns the completions."""
+    res = []
+    with R.rmat_server_create(**cfg) as s:
+        for p in reqs:
+            t = R.rmat_server_submit(s, p)
+            R.rmat_server_drain(s)
+            (c,) = R.rmat_server_poll(s)
+            assert c["ticket"] == t and c["status"] == 0
+            if p["m"] and p.get("out_src") is None and not p["flags"] & 2:
+                R.rmat_server_release(s, t)
+            res.append(c)
+    return res
+
+
+def test_served_alone_equals_mix_equals_oracle(R):
+    import torch
+    reqs = _requests()
+    small = dict(hbm_budget_bytes=1 << 30, max_table_bound=1 << 15, tick_blocks=1 << 10, request_quantum=96,
+                 max_active=6, table_slots=6, work_blocks=32, max_builds=3)
+    alone_reqs = _with_outputs(R, reqs)
+    alone = _serve_alone(R, alone_reqs, **small)
+    # the mix: everything submitted at once; small rounds force chunking, waiting and slot reuse
+    mix_reqs = _with_outputs(R, reqs)
+    with R.rmat_server_create(**small) as s:
+        tickets = [R.rmat_server_submit(s, p) for p in mix_reqs]
+        R.rmat_server_drain(s)
+        done = {c["ticket"]: c for c in R.rmat_server_poll(s, 1000)}
+        st = R.rmat_server_get_stats(s)
+        assert st["completed"] == len(reqs) and st["failed"] == 0 and st["rounds"] > 10
+        assert st["table_hits"] > 0 and st["arena_peak"] <= 1 << 30
+        for i, (p, t) in enumerate(zip(mix_reqs, tickets)):
+            c = done[t]
+            assert c["status"] == 0 and c["t_submit"] <= c["t_admit"] <= c["t_done"]
+            assert c["digest"] == alone[i]["digest"], f"request {i}: digest alone != in the mix"
+            o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+            _, ox = oracle.generate_reduce(o, p["seed"], p["edge_begin"], p["m"], 0, threads=8)
+            assert c["digest"] == ox, f"request {i}: digest vs oracle"
+            if p.get("out_src") is not None:
+                a = alone_reqs[i]
+                assert torch.equal(a["out_src"], p["out_src"]) and torch.equal(a["out_dst"], p["out_dst"]), \
+                    f"request {i}: edges alone != in the mix"
+                os_, od = oracle.generate(o, p["seed"], p["edge_begin"], p["m"], threads=8)
+                assert np.array_equal(R.to_numpy_ids(p["out_src"], p["k"]), os_), f"request {i} src vs oracle"
+                assert np.array_equal(R.to_numpy_ids(p["out_dst"], p["k"]), od), f"request {i} dst vs oracle"
+            elif p["m"]:
+                assert c["out_src"] is not None
+                R.rmat_server_release(s, t)
+        assert R.rmat_server_get_stats(s)["arena_bytes"] == 0
+
+
+def test_served_into_caller_outputs_equals_plain(R):
+    import torch
+    reqs = _requests(16, seed=9)
+    for p in reqs:
+        dt = R.id_dtype(p["k"])
+        p["out_src"] = torch.full((max(p["m"], 1),), -1, dtype=dt, device="cuda")
+        p["out_dst"] = torch.full((max(p["m"], 1),), -1, dtype=dt, device="cuda")
+        p["flags"] = 0
+    torch.cuda.synchronize()
+    with R.rmat_server_create(hbm_budget_bytes=1 << 24, max_table_bound=1 << 15, tick_blocks=512,
+                              request_quantum=64, max_active=4, work_blocks=16) as s:
+        for p in reqs:
+            R.rmat_server_submit(s, p)
+        R.rmat_server_drain(s)
+        cs = R.rmat_server_poll(s, 100)
+        assert len(cs) == len(reqs) and all(c["status"] == 0 and c["digest"] == 0 for c in cs)
+        assert R.rmat_server_get_stats(s)["arena_peak"] == 0
+    for i, p in enumerate(reqs):
+        if not p["m"]:
+            continue
+        t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+        s_, d_ = R.generate_edges(t, p["seed"], p["edge_begin"], p["m"])
+        torch.cuda.synchronize()
+        assert torch.equal(s_, p["out_src"][:p["m"]]) and torch.equal(d_, p["out_dst"][:p["m"]]), f"request {i}"
+        t.close()
+
+
+def test_trace_and_backpressure(R):
+    """A Poisson trace at 2000 requests/s into a 64 MiB arena: requests wait
+    for space, every one completes with its alone digest."""
+    reqs = workloads.served_requests(rate=2000.0, duration=0.1, arrival_seed=3, k_min=10, k_max=18)
+    assert len(reqs) > 100
+    for p in reqs:
+        p["flags"] = 3   # digest + discard
+    cfg = dict(hbm_budget_bytes=64 << 20, max_active=32, work_blocks=64)
+    alone = _serve_alone(R, [dict(p, flags=1) for p in reqs[:40]], **cfg)
+    with R.rmat_server_create(**cfg) as s:
+        out = R.rmat_server_run_trace(s, reqs, [p["t_arrival"] for p in reqs])
+        st = R.rmat_server_get_stats(s)
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["arena_bytes"] == 0
+    assert st["arena_peak"] <= 64 << 20
+    for i, (p, c) in enumerate(zip(reqs, out)):
+        assert c["status"] == 0
+        assert abs(c["t_submit"] - p["t_arrival"]) < 1e-9
+        assert c["t_submit"] <= c["t_admit"] <= c["t_done"]
+        assert c["out_src"] is None
+        if i < len(alone):
+            assert c["digest"] == alone[i]["digest"], f"request {i}"
+
+
+def test_server_errors(R):
+    with R.rmat_server_create(hbm_budget_bytes=1 << 20, max_table_bound=4096) as s:
+        good = dict(a=0.57, b=0.19, c=0.19, d=0.05, k=16, path_mode=1, table_bound=4096, seed=1, m=1000)
+        for bad, status in [(dict(table_bound=8192), R.RMAT_EINVAL),        # above max_table_bound
+                            (dict(m=1 << 20), R.RMAT_EINVAL),               # outputs larger than the arena
+                            (dict(out_src=256), R.RMAT_EINVAL),             # one output pointer only
+                            (dict(flags=8), R.RMAT_EINVAL),
+                            (dict(edge_begin=2**64 - 10, m=20), R.RMAT_ERANGE),
+                            (dict(a=0.7), R.RMAT_EINVAL)]:
+            with pytest.raises(R.RmatError) as ei:
+                R.rmat_server_submit(s, dict(good, **bad))
+            assert ei.value.status == status
+        with pytest.raises(R.RmatError):
+            R.rmat_server_release(s, 12345)
+        with pytest.raises(R.RmatError):
+            R.rmat_server_run_trace(s, [good, good], [0.2, 0.1])
+        assert R.rmat_server_get_stats(s)["submitted"] == 0
+    with pytest.raises(R.RmatError):
+        R.rmat_server_create(table_slots=4, max_active=8)
