@@ -149,13 +149,18 @@ int rmat_generate_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin,
  * it reduces them on the device (a consumer that only needs a digest of a
  * huge instance, generated chunk by chunk):
  *  d_hist  device array of 2^hist_bits uint64 counters, incremented by the
- *          histogram of src >> (k - hist_bits)  (hist_bits in 0..min(k, 20));
+ *          histogram of src >> (k - hist_bits)  (hist_bits in 0..min(k, 16));
  *  d_xor   device uint64, XOR-ed with the XOR over the edges of
  *          mix(e, src, dst) = fmix64(e ^ fmix64(src ^ rotl64(dst, 32))),
  *          fmix64 being MurmurHash3's 64-bit finaliser.
  * The caller zeroes both before the first chunk; further chunks accumulate.
- * Asynchronous on `stream`.  Errors as for rmat_generate_async, and
- * RMAT_EINVAL for hist_bits out of range.
+ * The edges are generated in sub-chunks of up to 2^28 into a workspace the
+ * table owns (2 bytes per edge of a sub-chunk plus 64 MB of per-workgroup
+ * counts), allocated by the first call that needs it and freed with the
+ * table; reductions on one table must therefore not overlap on the device
+ * (issue them on one stream).  Asynchronous on `stream` once the workspace
+ * exists.  Errors as for rmat_generate_async, and RMAT_EINVAL for hist_bits
+ * out of range.
  */
 int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed,
                                uint64_t edge_begin, uint64_t m, int hist_bits,

@@ -40,6 +40,14 @@ int rmat_bench_philox(uint64_t n_blocks, int variant, uint64_t seed, void* d_out
  * XOR-folds the data into d_out[0]. */
 int rmat_bench_lds_read(uint64_t n_reads, uint32_t table_bytes, int width, void* d_out, void* stream);
 
+/* Performs n_reads (a multiple of 8) random reads of `width` bytes (4, 8 or
+ * 16) per lane from the device table d_table of table_bytes (a power of two;
+ * one of L2 size stays in L2), in 256 * blocks_per_cu (1..4) workgroups of
+ * 512 lanes with 8 independent address streams per lane, and XOR-folds the
+ * data into d_out[0]: the random-gather ceiling of a table read from L2. */
+int rmat_bench_gather(uint64_t n_reads, const void* d_table, uint64_t table_bytes, int width, int blocks_per_cu,
+                      void* d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -19,6 +20,8 @@ struct rmat_table {
   int device;
   void* d_mem;  // records, item arrays, bucket arrays, stats
   rmat::TableView v;
+  void* d_reduce = nullptr;    // reduction workspace: 16-bit bins, then per-workgroup partial counts
+  uint64_t reduce_edges = 0;   // bins it holds
 };
 
 namespace {
@@ -284,6 +287,7 @@ int rmat_build_table(double a, double b, double c, double d, int k, uint64_t tab
 int rmat_free_table(rmat_table_t t) {
   g_err[0] = '\0';
   if (!t) return RMAT_OK;
+  if (t->d_reduce) (void)hipFree(t->d_reduce);
   hipError_t e = hipFree(t->d_mem);
   delete t;
   if (e != hipSuccess) return rmat::hip_fail(e, "hipFree(table)");
@@ -311,13 +315,28 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
   rmat::GenerateArgs a;
   std::memset(&a, 0, sizeof(a));
   if (reduce) {
-    const int hmax = t->info.k < 20 ? t->info.k : 20;
+    const int hmax = t->info.k < 16 ? t->info.k : 16;
     if (hist_bits < 0 || hist_bits > hmax)
       return set_error(RMAT_EINVAL, "hist_bits %d outside 0..%d", hist_bits, hmax);
     if (!d_hist || !d_xor) return set_error(RMAT_EINVAL, "NULL histogram or checksum pointer");
+    // workspace: bins for one sub-chunk, grown on demand (a larger one replaces it)
+    const uint64_t want = std::min<uint64_t>(rmat::kReduceChunk, (m + (1u << 20) - 1) & ~static_cast<uint64_t>((1u << 20) - 1));
+    if (t->reduce_edges < want) {
+      if (t->d_reduce) {
+        (void)hipFree(t->d_reduce);
+        t->d_reduce = nullptr;
+        t->reduce_edges = 0;
+      }
+      hipError_t e = hipMalloc(&t->d_reduce, want * sizeof(uint16_t) + rmat::reduce_partials_bytes());
+      if (e != hipSuccess) return rmat::hip_fail(e, "hipMalloc(reduction workspace)");
+      t->reduce_edges = want;
+    }
     a.hist_bits = hist_bits;
     a.hist = static_cast<unsigned long long*>(d_hist);
     a.xor_out = static_cast<unsigned long long*>(d_xor);
+    a.bins = static_cast<uint16_t*>(t->d_reduce);
+    a.bins_cap = t->reduce_edges;
+    a.partials = reinterpret_cast<uint32_t*>(static_cast<char*>(t->d_reduce) + t->reduce_edges * sizeof(uint16_t));
   } else {
     if (!out_src || !out_dst) return set_error(RMAT_EINVAL, "NULL output pointer");
     const uintptr_t align = t->info.id_bytes;

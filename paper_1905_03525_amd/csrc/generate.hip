@@ -126,7 +126,7 @@ struct Launch {
   Inst I;
   TileLayout L;
   uint32_t hist_shift;
-  unsigned long long* hist;
+  uint16_t* bins;  // reduction: source prefix of edge e at bins[e - I.edge_begin]
   unsigned long long* xor_out;
 };
 
@@ -171,7 +171,7 @@ template <typename Acc, bool kReduce, bool kDigest = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
-                                           unsigned long long* hist, uint64_t& xsum) {
+                                           uint16_t* bins, uint64_t& xsum) {
   using Id = typename Acc::Id;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
@@ -235,7 +235,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       if (e >= I.edge_begin && e <= last) {
         if (kReduce) {
           const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
-          atomicAdd(&hist[hist_shift >= 64 ? 0 : (s >> hist_shift)], 1ull);
+          bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
         } else {
           const uint64_t slot = e - I.edge_begin;
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   Packed* res = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
   uint64_t xsum = 0;
-  run_blocks<Acc, kReduce>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.hist, xsum);
+  run_blocks<Acc, kReduce>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.bins, xsum);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
@@ -357,6 +357,13 @@ TileLayout layout_for(uint32_t buckets, bool lds, size_t* lds_bytes) {
   uint32_t tile = 0;
   if (L.lds_table + kWaves * per_block_bytes <= budget) tile = (budget - L.lds_table) / (kWaves * per_block_bytes);
   if (tile > kMaxTile) tile = kMaxTile;
+  if (!lds) {
+    // a table read from L2 leaves the LDS to the tiles: keep them small enough
+    // for two workgroups per CU, twice the loads in flight
+    const uint32_t half = static_cast<uint32_t>(D.lds_per_block) / 2 - 1024;
+    const uint32_t t2 = half / (kWaves * per_block_bytes);
+    if (t2 >= 1 && t2 < tile) tile = t2;
+  }
   L.tile = tile;
   L.wave_bytes = tile * per_block_bytes;
   *lds_bytes = L.lds_table + static_cast<size_t>(kWaves) * L.wave_bytes;
@@ -364,7 +371,7 @@ TileLayout layout_for(uint32_t buckets, bool lds, size_t* lds_bytes) {
 }
 
 uint64_t persistent_grid(size_t lds_bytes) {
-  const uint64_t per_cu = lds_bytes > 80 * 1024 ? 1 : 2;
+  const uint64_t per_cu = 2 * (lds_bytes + 1024) <= static_cast<uint64_t>(limits().lds_per_block) ? 2 : 1;
   return static_cast<uint64_t>(limits().cu_count) * per_cu;
 }
 
@@ -381,6 +388,65 @@ hipError_t launch_one(Launch P, hipStream_t s) {
   hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
                      lds, s, P);
   return hipGetLastError();
+}
+
+// Histogram of 16-bit bin values: each workgroup counts its slice of the
+// values in LDS, one window of 2^15 bins at a time (128 KB of uint32
+// counters), and writes the window's counts to its own row of `partials`
+// (row (w * G + g), kHistWindow entries).  No global atomics.
+constexpr int kHistThreads = 1024;
+constexpr uint32_t kHistWindow = 1u << 15;
+
+__global__ __launch_bounds__(kHistThreads) void hist_partial_kernel(const uint16_t* __restrict__ bins, uint64_t n,
+                                                                    uint32_t n_windows,
+                                                                    uint32_t* __restrict__ partials) {
+  extern __shared__ uint32_t s_cnt[];
+  const uint32_t G = gridDim.x, g = blockIdx.x;
+  const uint64_t n8 = n / 8;  // whole 16-byte groups of 8 values
+  const uint64_t lo8 = n8 * g / G, hi8 = n8 * (g + 1) / G;
+  const uint4* v8 = reinterpret_cast<const uint4*>(bins);
+  for (uint32_t w = 0; w < n_windows; ++w) {
+    for (uint32_t j = threadIdx.x; j < kHistWindow; j += kHistThreads) s_cnt[j] = 0;
+    __syncthreads();
+    auto count = [w](uint32_t v) {
+      if ((v >> 15) == w) atomicAdd(&s_cnt[v & (kHistWindow - 1)], 1u);
+    };
+    for (uint64_t i = lo8 + threadIdx.x; i < hi8; i += kHistThreads) {
+      const uint4 q = v8[i];
+      count(q.x & 0xFFFFu);
+      count(q.x >> 16);
+      count(q.y & 0xFFFFu);
+      count(q.y >> 16);
+      count(q.z & 0xFFFFu);
+      count(q.z >> 16);
+      count(q.w & 0xFFFFu);
+      count(q.w >> 16);
+    }
+    if (g == G - 1)
+      for (uint64_t i = n8 * 8 + threadIdx.x; i < n; i += kHistThreads) count(bins[i]);
+    __syncthreads();
+    uint32_t* out = partials + (static_cast<uint64_t>(w) * G + g) * kHistWindow;
+    for (uint32_t j = threadIdx.x; j < kHistWindow; j += kHistThreads) out[j] = s_cnt[j];
+    __syncthreads();  // the next window clears s_cnt
+  }
+}
+
+// hist[b] += sum over the G partial rows of bin b (one thread per bin, so a
+// plain read-modify-write).
+__global__ __launch_bounds__(256) void hist_merge_kernel(const uint32_t* __restrict__ partials, uint32_t G,
+                                                         uint32_t n_bins, unsigned long long* __restrict__ hist) {
+  const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= n_bins) return;
+  const uint32_t w = b / kHistWindow, j = b % kHistWindow;
+  uint64_t sum = 0;
+  for (uint32_t g = 0; g < G; ++g) sum += partials[(static_cast<uint64_t>(w) * G + g) * kHistWindow + j];
+  hist[b] += sum;
+}
+
+uint32_t hist_groups(uint64_t n) {
+  const uint64_t want = (n + 65535) / 65536;
+  const uint64_t cus = static_cast<uint64_t>(limits().cu_count);
+  return static_cast<uint32_t>(want < 1 ? 1 : (want > cus ? cus : want));
 }
 
 template <bool kReduce>
@@ -401,12 +467,36 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.I.out_dst = a.out_dst;
   P.I.digest = nullptr;
   P.hist_shift = static_cast<uint32_t>(a.k - a.hist_bits);
-  P.hist = a.hist;
+  P.bins = a.bins;
   P.xor_out = a.xor_out;
   const bool wide = a.k > 32;
-  if (a.lds)
-    return wide ? launch_one<Acc64, true, kReduce>(P, s) : launch_one<Acc32, true, kReduce>(P, s);
-  return wide ? launch_one<Acc64, false, kReduce>(P, s) : launch_one<Acc32, false, kReduce>(P, s);
+  auto gen = [&](const Launch& L) {
+    if (a.lds) return wide ? launch_one<Acc64, true, kReduce>(L, s) : launch_one<Acc32, true, kReduce>(L, s);
+    return wide ? launch_one<Acc64, false, kReduce>(L, s) : launch_one<Acc32, false, kReduce>(L, s);
+  };
+  if (!kReduce) return gen(P);
+  // reduction: sub-chunks of at most bins_cap edges, each generated into the
+  // 16-bit bin buffer, then counted and merged into the caller's histogram
+  const uint32_t n_bins = 1u << a.hist_bits;
+  const uint32_t n_windows = (n_bins + kHistWindow - 1) / kHistWindow;
+  for (uint64_t off = 0; off < a.m; off += a.bins_cap) {
+    const uint64_t len = a.m - off < a.bins_cap ? a.m - off : a.bins_cap;
+    Launch L = P;
+    L.I.edge_begin = a.edge_begin + off;
+    L.I.m = len;
+    L.I.first_block = L.I.edge_begin >> 6;
+    L.I.n_blocks = ((L.I.edge_begin + (len - 1)) >> 6) - L.I.first_block + 1;
+    hipError_t e = gen(L);
+    if (e != hipSuccess) return e;
+    const uint32_t G = hist_groups(len);
+    hipLaunchKernelGGL(hist_partial_kernel, dim3(G), dim3(kHistThreads), kHistWindow * sizeof(uint32_t), s, a.bins,
+                       len, n_windows, a.partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(hist_merge_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, a.partials, G, n_bins,
+                       a.hist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename Acc, bool kLds, bool kDigest>
@@ -446,6 +536,10 @@ uint32_t lds_table_limit() {
   return static_cast<int64_t>(nb) * static_cast<int64_t>(sizeof(BucketRecord)) <= room ? nb : 0;
 }
 
+uint64_t reduce_partials_bytes() {
+  return 2ull * static_cast<uint64_t>(limits().cu_count) * kHistWindow * sizeof(uint32_t);
+}
+
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispatch<false>(a, s); }
 hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return dispatch<true>(a, s); }
 
@@ -481,7 +575,8 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_batch_kernel<Acc32, true, true>),
       allow_full_lds(&generate_batch_kernel<Acc32, false, true>),
       allow_full_lds(&generate_batch_kernel<Acc64, true, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, true>)};
+      allow_full_lds(&generate_batch_kernel<Acc64, false, true>),
+      allow_full_lds(&hist_partial_kernel)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

@@ -125,6 +125,36 @@ __global__ __launch_bounds__(512) void lds_read_kernel(uint64_t n_reads, uint32_
   if ((threadIdx.x & 63) == 0) atomicXor(out, static_cast<unsigned long long>(acc));
 }
 
+// Random reads of kWidth bytes from a table in global memory (an L2-sized
+// table stays in L2): eight independent address streams per lane.
+template <int kWidth>
+__global__ __launch_bounds__(512) void gather_kernel(const char* __restrict__ base, uint64_t n_reads, uint32_t mask,
+                                                     unsigned long long* out) {
+  uint32_t s[8];
+  for (int i = 0; i < 8; ++i) s[i] = (blockIdx.x * blockDim.x + threadIdx.x) * 0x9E3779B9u + 0x7F4A7C15u * (i + 1);
+  uint32_t acc = 0;
+  for (uint64_t r = 0; r < n_reads; r += 8) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      s[i] ^= s[i] << 13;
+      s[i] ^= s[i] >> 17;
+      s[i] ^= s[i] << 5;
+      const uint64_t off = static_cast<uint64_t>((s[i] >> 4) & mask) * kWidth;
+      if (kWidth == 16) {
+        const uint4 v = *reinterpret_cast<const uint4*>(base + off);
+        acc ^= v.x ^ v.w;
+      } else if (kWidth == 8) {
+        const uint2 v = *reinterpret_cast<const uint2*>(base + off);
+        acc ^= v.x ^ v.y;
+      } else {
+        acc ^= *reinterpret_cast<const uint32_t*>(base + off);
+      }
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) acc ^= __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicXor(out, static_cast<unsigned long long>(acc));
+}
+
 int grid_for(uint64_t work_items) {
   uint64_t g = (work_items + kMbThreads - 1) / kMbThreads;
   const uint64_t cap = 256ull * 32;
@@ -183,6 +213,23 @@ int rmat_bench_lds_read(uint64_t n_reads, uint32_t table_bytes, int width, void*
   if (width == 8) hipLaunchKernelGGL(rmat::lds_read_kernel<8>, g, b, 0, s, n_reads, mask, out);
   if (width == 4) hipLaunchKernelGGL(rmat::lds_read_kernel<4>, g, b, 0, s, n_reads, mask, out);
   return rmat::check_launch("rmat_bench_lds_read");
+}
+
+int rmat_bench_gather(uint64_t n_reads, const void* d_table, uint64_t table_bytes, int width, int blocks_per_cu,
+                      void* d_out, void* stream) {
+  if (!d_out || !d_table || (width != 4 && width != 8 && width != 16) || table_bytes < 16 ||
+      table_bytes > (1ull << 32) || (table_bytes & (table_bytes - 1)) || blocks_per_cu < 1 || blocks_per_cu > 4 ||
+      (n_reads % 8))
+    return rmat::set_error(RMAT_EINVAL, "rmat_bench_gather: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* out = static_cast<unsigned long long*>(d_out);
+  const uint32_t mask = static_cast<uint32_t>(table_bytes / width - 1);
+  const char* base = static_cast<const char*>(d_table);
+  const dim3 g(256 * blocks_per_cu), b(512);
+  if (width == 16) hipLaunchKernelGGL(rmat::gather_kernel<16>, g, b, 0, s, base, n_reads, mask, out);
+  if (width == 8) hipLaunchKernelGGL(rmat::gather_kernel<8>, g, b, 0, s, base, n_reads, mask, out);
+  if (width == 4) hipLaunchKernelGGL(rmat::gather_kernel<4>, g, b, 0, s, base, n_reads, mask, out);
+  return rmat::check_launch("rmat_bench_gather");
 }
 
 }  // extern "C"

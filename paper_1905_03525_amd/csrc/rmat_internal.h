@@ -134,11 +134,20 @@ struct GenerateArgs {
   uint64_t edge_begin, m;
   void* out_src;
   void* out_dst;
-  // reduction variant
+  // reduction variant: the edges are generated in sub-chunks of at most
+  // bins_cap edges into `bins` (16-bit source prefixes), counted per
+  // workgroup into `partials` (reduce_partials_bytes()) and merged into hist
   int32_t hist_bits;
   unsigned long long* hist;
   unsigned long long* xor_out;
+  uint16_t* bins;
+  uint64_t bins_cap;
+  uint32_t* partials;
 };
+
+// Largest sub-chunk of a reduction (edges) and the workspace it needs.
+constexpr uint64_t kReduceChunk = 1ull << 28;
+uint64_t reduce_partials_bytes();
 
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s);
 hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s);

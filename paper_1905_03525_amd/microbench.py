@@ -16,6 +16,8 @@ def _lib():
         L.rmat_bench_copy.argtypes = [vp, vp, u64, vp]
         L.rmat_bench_philox.argtypes = [u64, ctypes.c_int, u64, vp, vp]
         L.rmat_bench_lds_read.argtypes = [u64, ctypes.c_uint32, ctypes.c_int, vp, vp]
+        L.rmat_bench_gather.argtypes = [u64, vp, u64, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.rmat_bench_gather.restype = ctypes.c_int
         for n in ("rmat_bench_write", "rmat_bench_copy", "rmat_bench_philox", "rmat_bench_lds_read"):
             getattr(L, n).restype = ctypes.c_int
         L._bench_ready = True
@@ -94,6 +96,18 @@ def lds_read_rate(table_bytes=65536, width=16, n_reads=1 << 14) -> float:
     return threads * n_reads / t
 
 
+def gather_rate(table_bytes=1 << 20, width=16, blocks_per_cu=2, n_reads=1 << 12) -> float:
+    """Random reads of `width` bytes per second from a device table of
+    table_bytes (L2-resident when it fits)."""
+    import torch
+    tab = torch.randint(0, 1 << 30, (table_bytes // 4,), dtype=torch.int32, device="cuda")
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    L = _lib()
+    t = _time(lambda s: _check(L.rmat_bench_gather(n_reads, tab.data_ptr(), table_bytes, width, blocks_per_cu,
+                                                   out.data_ptr(), s.cuda_stream), "rmat_bench_gather"))
+    return 256 * blocks_per_cu * 512 * n_reads / t
+
+
 def all_ceilings() -> dict:
     return {
         "write_gbs_16B": write_bandwidth(vec_bytes=16),
@@ -102,6 +116,8 @@ def all_ceilings() -> dict:
         "philox_blocks_per_s": {f"v{v}": philox_rate(v) for v in range(3)},
         "lds_reads_per_s": {f"{w}B_{tb // 1024}KB": lds_read_rate(tb, w) for w in (4, 8, 16)
                             for tb in (16384, 65536)},
+        "gather_reads_per_s": {f"{w}B_{tb >> 10}KB_x{bp}": gather_rate(tb, w, bp) for w in (4, 16)
+                               for tb in (1 << 20, 1 << 16) for bp in (1, 2, 4)},
     }
 
 

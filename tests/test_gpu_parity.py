@@ -184,3 +184,103 @@ def test_chunk_reduce_parity(R):
         assert np.array_equal(hist.cpu().numpy().view(np.uint64), oh)
         assert int(xr.cpu().numpy().view(np.uint64)[0]) == ox
     t.close()
+
+
+def _k34_golden():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "k34_chunk_digests.txt")
+    rows = []
+    for ln in open(path):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        c, e0, m, h, tot, x = ln.split()
+        rows.append((int(c), int(e0), int(m), h, int(tot), int(x, 16)))
+    return rows
+
+
+REDUCE_CASES = [
+    # q, k, bound, mode, seed, edge_begin, m, hist_bits
+    (G500, 20, 4096, oracle.VARIABLE, 9, 0, 100_000, 0),
+    (G500, 20, 4096, oracle.VARIABLE, 9, 77, 100_003, 5),
+    (G500, 12, 256, oracle.FIXED, 9, 63, 70_001, 12),
+    (CFG3, 40, 20_000, oracle.VARIABLE, 4, 2**32 - 5000, 50_000, 16),
+    (SKEW, 64, 8192, oracle.VARIABLE, 5, 2**64 - 40_000, 40_000, 16),
+    (G500, 26, 1 << 18, oracle.VARIABLE, 6, 1, 300_000, 15),     # L2 table, one LDS window
+    (G500, 26, 4096, oracle.VARIABLE, 7, 2**28 - 1000, 3000, 16),  # across a sub-chunk boundary of a longer call
+]
+
+
+@pytest.mark.parametrize("q,k,bound,mode,seed,e0,m,hb", REDUCE_CASES)
+def test_reduce_parity_cases(R, q, k, bound, mode, seed, e0, m, hb):
+    import torch
+    t = R.rmat_build_table(*q, k, bound, mode)
+    o = oracle.build_table(*q, k, bound, mode)
+    hist = torch.zeros(1 << hb, dtype=torch.int64, device="cuda")
+    xr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    R.rmat_generate_reduce_async(t, seed, e0, m, hb, hist, xr, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    oh, ox = oracle.generate_reduce(o, seed, e0, m, hist_bits=hb, threads=8)
+    assert np.array_equal(hist.cpu().numpy().view(np.uint64), oh)
+    assert int(xr.cpu().numpy().view(np.uint64)[0]) == ox
+    t.close()
+
+
+def test_reduce_spanning_sub_chunks_equals_pieces(R):
+    """A reduction longer than one workspace sub-chunk (2^28 edges) equals
+    the sum / XOR of reductions of its pieces, and the oracle on its ends."""
+    import torch
+    t = R.rmat_build_table(*G500, 30, 4096, R.RMAT_VARIABLE)
+    s = torch.cuda.current_stream()
+    e0, m = 12_345, (1 << 28) + (1 << 20) + 17
+    whole = torch.zeros(1 << 16, dtype=torch.int64, device="cuda")
+    wx = torch.zeros(1, dtype=torch.int64, device="cuda")
+    R.rmat_generate_reduce_async(t, 11, e0, m, 16, whole, wx, s)
+    parts = torch.zeros(1 << 16, dtype=torch.int64, device="cuda")
+    px = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for a, b in ((0, 1 << 20), (1 << 20, 1 << 27), (1 << 27, m)):
+        R.rmat_generate_reduce_async(t, 11, e0 + a, b - a, 16, parts, px, s)
+    torch.cuda.synchronize()
+    assert torch.equal(whole, parts) and torch.equal(wx, px)
+    assert int(whole.sum().item()) == m
+    t.close()
+
+
+def test_reduce_errors(R):
+    import torch
+    t = R.rmat_build_table(*G500, 20, 4096, R.RMAT_VARIABLE)
+    hist = torch.zeros(1 << 17, dtype=torch.int64, device="cuda")
+    xr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for hb in (-1, 17):
+        with pytest.raises(R.RmatError) as ei:
+            R.rmat_generate_reduce_async(t, 1, 0, 10, hb, hist, xr)
+        assert ei.value.status == R.RMAT_EINVAL
+    t.close()
+    t = R.rmat_build_table(*G500, 10, 256, R.RMAT_VARIABLE)
+    with pytest.raises(R.RmatError):
+        R.rmat_generate_reduce_async(t, 1, 0, 10, 11, hist, xr)   # more bins than k bits
+    R.rmat_generate_reduce_async(t, 1, 0, 0, 10, hist, xr)        # m = 0: no-op
+    t.close()
+
+
+def test_k34_all_chunks_match_oracle(R):
+    """The k = 34, m = 2^34 instance at full size: all 16 chunks of 2^30
+    edges reduced on the device (source-prefix histogram + XOR checksum), in
+    the launch configuration the benchmark times, against the oracle's
+    reduction of the same chunks (stored by tests/golden/make_k34_chunk_digests.py)."""
+    import hashlib
+    import torch
+    rows = _k34_golden()
+    assert len(rows) == 16
+    t = R.rmat_build_table(*CFG3, 34, 1 << 16, R.RMAT_VARIABLE)
+    hist = torch.zeros(1 << 16, dtype=torch.int64, device="cuda")
+    xr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for c, e0, m, h, tot, x in rows:
+        hist.zero_()
+        xr.zero_()
+        R.rmat_generate_reduce_async(t, 3, e0, m, 16, hist, xr, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        hv = hist.cpu().numpy().view(np.uint64)
+        assert int(hv.sum()) == tot == m, f"chunk {c}"
+        assert hashlib.sha256(hv.astype("<u8").tobytes()).hexdigest() == h, f"chunk {c} histogram"
+        assert int(xr.cpu().numpy().view(np.uint64)[0]) == x, f"chunk {c} checksum"
+    t.close()
