@@ -17,6 +17,8 @@
 //      so a second Philox block is only paid for edges that need it;
 //   3. the tile is written out block by block, 64 consecutive ids per store,
 //      every cache line written once and whole.
+#include <type_traits>
+
 #include "rmat_internal.h"
 
 namespace rmat {
@@ -43,6 +45,49 @@ __device__ __forceinline__ void philox10(uint32_t& x0, uint32_t& x1, uint32_t& x
     x1 = static_cast<uint32_t>(p1);
     x2 = y2;
     x3 = static_cast<uint32_t>(p0);
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+}
+
+// The first counter block of an edge, (e_lo, e_hi, 0, 0) with e_hi the same
+// across the wave: rounds 1 and 2 are specialised (a zero word's product is
+// zero; what depends only on e_hi and the key stays on the scalar unit); the
+// output equals philox10 on that counter.
+__device__ __forceinline__ void philox10_first(uint32_t e_lo, uint32_t e_hi, uint32_t k0, uint32_t k1, uint32_t& x0,
+                                               uint32_t& x1, uint32_t& x2, uint32_t& x3) {
+  const uint64_t p0 = static_cast<uint64_t>(e_lo) * kPhiloxM0;
+  const uint32_t a0 = e_hi ^ k0;  // hi(0 * M1) ^ e_hi ^ k0
+  const uint32_t a2 = static_cast<uint32_t>(p0 >> 32) ^ k1;
+  const uint32_t a3 = static_cast<uint32_t>(p0);  // and a1 = lo(0 * M1) = 0
+  k0 += kPhiloxW0;
+  k1 += kPhiloxW1;
+  const uint64_t q0 = static_cast<uint64_t>(a0) * kPhiloxM0;
+  const uint64_t q1 = static_cast<uint64_t>(a2) * kPhiloxM1;
+  const uint32_t b0 = static_cast<uint32_t>(q1 >> 32) ^ k0;  // ^ a1 = 0
+  const uint32_t b1 = static_cast<uint32_t>(q1);
+  const uint32_t b2 = (static_cast<uint32_t>(q0 >> 32) ^ k1) ^ a3;
+  const uint32_t b3 = static_cast<uint32_t>(q0);  // uniform
+  k0 += kPhiloxW0;
+  k1 += kPhiloxW1;
+  const uint64_t r0 = static_cast<uint64_t>(b0) * kPhiloxM0;
+  const uint64_t r1 = static_cast<uint64_t>(b2) * kPhiloxM1;
+  x0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(r1 >> 32), b1, k0, 0x96);
+  x1 = static_cast<uint32_t>(r1);
+  x2 = static_cast<uint32_t>(r0 >> 32) ^ (b3 ^ k1);
+  x3 = static_cast<uint32_t>(r0);
+  k0 += kPhiloxW0;
+  k1 += kPhiloxW1;
+#pragma unroll
+  for (int r = 3; r < 10; ++r) {
+    const uint64_t m0 = static_cast<uint64_t>(x0) * kPhiloxM0;
+    const uint64_t m1 = static_cast<uint64_t>(x2) * kPhiloxM1;
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(m1 >> 32), x1, k0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(m0 >> 32), x3, k1, 0x96);
+    x0 = y0;
+    x1 = static_cast<uint32_t>(m1);
+    x2 = y2;
+    x3 = static_cast<uint32_t>(m0);
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
   }
@@ -161,6 +206,15 @@ __device__ __forceinline__ uint64_t wave_xor(uint64_t x) {
 // Orders this wave's LDS accesses across the passes of a tile.
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
+// Lanes of block `rel` (within the instance) whose edge lies in
+// [edge_begin, last]: every lane except in the first and the last block.
+__device__ __forceinline__ uint64_t block_mask(const GenInst& I, uint64_t rel, uint64_t last) {
+  uint64_t mask = ~0ull;
+  if (rel == 0) mask <<= (I.edge_begin & 63u);
+  if (rel == I.n_blocks - 1) mask &= ~0ull >> (63u - (last & 63u));
+  return mask;
+}
+
 // Blocks t0 + j*stride of one instance for one wave, t0 = wave_blk,
 // wave_blk + stride*tile, ... below blk_end, in tiles of L.tile blocks:
 //   1. first Philox block of every edge into the wave's LDS area, unfinished
@@ -179,30 +233,38 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     const uint64_t left = (blk_end - t0 + stride - 1) / stride;
     const uint32_t nb_tile = left < L.tile ? static_cast<uint32_t>(left) : L.tile;
 
-    // pass 1: first Philox block of every edge of the tile
+    // pass 1: first Philox block of every edge of the tile; whole blocks
+    // (every block but an instance's first and last) take a copy of the body
+    // without lane masks
     uint32_t n_ovf = 0;
-    for (uint32_t j = 0; j < nb_tile; ++j) {
-      const uint64_t base = (I.first_block + t0 + j * stride) << 6;  // wave-uniform
-      const uint64_t e = base + lane;
-      const uint64_t lo = I.edge_begin > base ? I.edge_begin - base : 0;
-      const uint64_t hi = last - base < 63 ? last - base : 63;
-      const uint64_t amask = (~0ull << lo) & (~0ull >> (63 - hi));
+    auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole) {
       Acc acc;
       acc.clear();
       uint32_t filled = 0;
-      uint32_t x0 = static_cast<uint32_t>(e), x1 = static_cast<uint32_t>(base >> 32), x2 = 0, x3 = 0;
-      philox10(x0, x1, x2, x3, I.key0, I.key1);
+      uint32_t x0, x1, x2, x3;
+      philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.key0, I.key1, x0, x1,
+                     x2, x3);
       sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
       res[j * 64 + lane] = acc.pack();
-      const uint64_t ovf_mask = __ballot(filled < I.k) & amask;
+      const bool need = decltype(whole)::value ? filled < I.k : (filled < I.k && ((amask >> lane) & 1ull));
+      const uint64_t ovf_mask = __ballot(need);
       if (ovf_mask != 0) {
-        if ((ovf_mask >> lane) & 1ull) {
+        if (need) {
           const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
               static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
           ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
         }
         n_ovf += __popcll(ovf_mask);
       }
+    };
+    for (uint32_t j = 0; j < nb_tile; ++j) {
+      const uint64_t rel = t0 + j * stride;                 // block index within the instance
+      const uint64_t base = (I.first_block + rel) << 6;     // wave-uniform
+      const uint64_t amask = block_mask(I, rel, last);
+      if (amask == ~0ull)
+        first_block(j, base, amask, std::true_type{});
+      else
+        first_block(j, base, amask, std::false_type{});
     }
     wave_lds_fence();
 
@@ -227,12 +289,11 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     wave_lds_fence();
 
     // pass 3: write the tile out (or fold it into the reduction)
-    for (uint32_t j = 0; j < nb_tile; ++j) {
-      const uint64_t base = (I.first_block + t0 + j * stride) << 6;
+    auto emit = [&](uint32_t j, uint64_t base) {
       const uint64_t e = base + lane;
       Acc acc;
       acc.unpack(res[j * 64 + lane]);
-      if (e >= I.edge_begin && e <= last) {
+      {
         if (kReduce) {
           const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
           bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
@@ -247,6 +308,16 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
             xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
           }
         }
+      }
+    };
+    for (uint32_t j = 0; j < nb_tile; ++j) {
+      const uint64_t rel = t0 + j * stride;
+      const uint64_t base = (I.first_block + rel) << 6;
+      const uint64_t amask = block_mask(I, rel, last);
+      if (amask == ~0ull) {
+        emit(j, base);
+      } else if ((amask >> lane) & 1ull) {
+        emit(j, base);
       }
     }
     wave_lds_fence();
