@@ -76,6 +76,12 @@ def lib():
         L.orc_generate_reduce.restype = ctypes.c_int
         L.orc_edge_mix.argtypes = [ctypes.c_uint64] * 3
         L.orc_edge_mix.restype = ctypes.c_uint64
+        L.orc_generate_ex.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_uint64]
+        L.orc_generate_ex.restype = ctypes.c_int
+        L.orc_scramble.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_scramble.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -98,6 +104,11 @@ def canonical_product(q, counts) -> float:
     qa = (ctypes.c_double * 4)(*[float(v) for v in q])
     ca = (ctypes.c_int * 4)(*[int(v) for v in counts])
     return float(lib().orc_canonical_product(qa, ca))
+
+
+def scramble(k: int, key: int, x: int) -> int:
+    """The scramble bijection pi of [0, 2^k) under `key` (reading R19)."""
+    return int(lib().orc_scramble(k, key, x))
 
 
 def edge_mix(e: int, src: int, dst: int) -> int:
@@ -154,17 +165,23 @@ def build_table(a, b, c, d, k, bound, mode) -> Table:
                  n_items=int(info[4]), n_buckets=nb, capacity=int(info[6]), handle=h, **arrs)
 
 
+UNDIRECTED = 1
+SCRAMBLE = 2
+
+
 def generate(t: Table, seed: int, edge_begin: int, m: int, threads: int = 1,
-             width: int | None = None, samples: bool = False):
-    """Edges [edge_begin, edge_begin + m) as (src, dst[, samples per edge])."""
+             width: int | None = None, samples: bool = False, flags: int = 0, scramble_key: int = 0):
+    """Edges [edge_begin, edge_begin + m) as (src, dst[, samples per edge]).
+    flags: UNDIRECTED (mirror to the upper triangle) and/or SCRAMBLE (relabel
+    ids by the keyed bijection), Sec. 5 generalizations, reading R19."""
     if width is None:
         width = 4 if t.k <= 32 else 8
     dt = np.uint32 if width == 4 else np.uint64
     src = np.zeros(m, dt)
     dst = np.zeros(m, dt)
     ns = np.zeros(m, np.uint32) if samples else None
-    rc = lib().orc_generate(t.handle, seed, edge_begin, m, _ptr(src), _ptr(dst), width,
-                            _ptr(ns) if samples else None, int(threads))
+    rc = lib().orc_generate_ex(t.handle, seed, edge_begin, m, _ptr(src), _ptr(dst), width,
+                               _ptr(ns) if samples else None, int(threads), int(flags), int(scramble_key))
     if rc != 0:
         raise OracleError(rc, "generate")
     return (src, dst, ns) if samples else (src, dst)

@@ -53,6 +53,14 @@
  *      bit of the k-bit row and column ids.
  *  R12 letters left over after the k-th are discarded (each edge has its own
  *      counter stream), instead of being carried over to the next edge.
+ *  R19 Sec. 5 (Generalizations) epilogue, optional per call: an undirected
+ *      graph mirrors each edge of the lower-left triangle (row > column) to
+ *      the upper right, i.e. swaps its ids; the scramble relabels every id by
+ *      one keyed bijection pi of [0, 2^k), applied after the mirror.  pi is
+ *      three rounds of x = (x * M_r + C_r) mod 2^k, x = x XOR (x >> ceil(k/2)),
+ *      with M_r (odd) and C_r the outputs of SplitMix64 [Steele, Lea, Flood,
+ *      OOPSLA'14] seeded with the scramble key, drawn in the order M_0, C_0,
+ *      M_1, C_1, M_2, C_2 (M_r with its lowest bit set).
  */
 #include <math.h>
 #include <pthread.h>
@@ -459,6 +467,62 @@ static void sample_edge(const orc_table* t, uint64_t seed, uint64_t e,
   if (n_samples) *n_samples = s;
 }
 
+/* ------------------------------------------------------------------------
+ * Epilogue of Sec. 5 (reading R19): mirror to the upper triangle, scramble.
+ * ---------------------------------------------------------------------- */
+#define ORC_UNDIRECTED 1
+#define ORC_SCRAMBLE 2
+
+/* SplitMix64: one step of the generator (state advanced in place). */
+static uint64_t splitmix64_next(uint64_t* state) {
+  uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+typedef struct {
+  uint64_t mul[3], add[3];
+} scramble_t;
+
+static scramble_t scramble_keys(uint64_t key) {
+  scramble_t p;
+  uint64_t st = key;
+  for (int r = 0; r < 3; ++r) {
+    p.mul[r] = splitmix64_next(&st) | 1ull;
+    p.add[r] = splitmix64_next(&st);
+  }
+  return p;
+}
+
+static uint64_t scramble_id(const scramble_t* p, int k, uint64_t x) {
+  const uint64_t mask = k >= 64 ? ~0ull : ((1ull << k) - 1);
+  const int h = (k + 1) / 2;
+  for (int r = 0; r < 3; ++r) {
+    x = (x * p->mul[r] + p->add[r]) & mask;
+    x ^= x >> h;
+  }
+  return x;
+}
+
+/* pi(x) for one id, for tests. */
+uint64_t orc_scramble(int k, uint64_t key, uint64_t x) {
+  scramble_t p = scramble_keys(key);
+  return scramble_id(&p, k, x);
+}
+
+static void epilogue(int flags, const scramble_t* p, int k, uint64_t* s, uint64_t* d) {
+  if ((flags & ORC_UNDIRECTED) && *s > *d) {
+    uint64_t t = *s;
+    *s = *d;
+    *d = t;
+  }
+  if (flags & ORC_SCRAMBLE) {
+    *s = scramble_id(p, k, *s);
+    *d = scramble_id(p, k, *d);
+  }
+}
+
 /* MurmurHash3's 64-bit finaliser (A. Appleby, public domain). */
 static uint64_t fmix64(uint64_t z) {
   z ^= z >> 33;
@@ -482,6 +546,8 @@ typedef struct {
   void* dst;
   int width; /* bytes per id: 4 or 8 */
   uint32_t* n_samples;
+  int flags; /* ORC_UNDIRECTED | ORC_SCRAMBLE */
+  scramble_t scr;
   /* reduction outputs */
   int hist_bits;
   uint64_t* hist;
@@ -494,6 +560,7 @@ static void* gen_worker(void* arg) {
     uint64_t s, d;
     uint32_t ns;
     sample_edge(w->t, w->seed, w->edge_begin + slot, &s, &d, &ns);
+    epilogue(w->flags, &w->scr, w->t->k, &s, &d);
     if (w->width == 4) {
       ((uint32_t*)w->src)[slot] = (uint32_t)s;
       ((uint32_t*)w->dst)[slot] = (uint32_t)d;
@@ -540,25 +607,35 @@ static int run_threads(work_t* proto, uint64_t m, int threads,
 }
 
 /* Edges e in [edge_begin, edge_begin + m) go to slot e - edge_begin.
- * width is 4 (k <= 32) or 8 bytes per id. */
-int orc_generate(const orc_table* t, uint64_t seed, uint64_t edge_begin,
-                 uint64_t m, void* src, void* dst, int width,
-                 uint32_t* n_samples, int threads) {
+ * width is 4 (k <= 32) or 8 bytes per id.  flags: ORC_UNDIRECTED and/or
+ * ORC_SCRAMBLE (with scramble_key), reading R19. */
+int orc_generate_ex(const orc_table* t, uint64_t seed, uint64_t edge_begin,
+                    uint64_t m, void* src, void* dst, int width,
+                    uint32_t* n_samples, int threads, int flags, uint64_t scramble_key) {
   /* the last edge of the stream is 2^64 - 1 */
   if (m > 0 && edge_begin + (m - 1) < edge_begin) return ORC_ERANGE;
   if (width != 4 && width != 8) return ORC_EINVAL;
   if (width == 4 && t->k > 32) return ORC_EINVAL;
+  if (flags & ~(ORC_UNDIRECTED | ORC_SCRAMBLE)) return ORC_EINVAL;
   if (m == 0) return ORC_OK;
   work_t proto;
   memset(&proto, 0, sizeof(proto));
   proto.t = t; proto.seed = seed; proto.edge_begin = edge_begin;
   proto.src = src; proto.dst = dst; proto.width = width;
   proto.n_samples = n_samples;
+  proto.flags = flags;
+  proto.scr = scramble_keys(scramble_key);
   work_t* items = NULL;
   int nt = run_threads(&proto, m, threads, gen_worker, &items);
   if (nt < 0) return nt;
   free(items);
   return ORC_OK;
+}
+
+int orc_generate(const orc_table* t, uint64_t seed, uint64_t edge_begin,
+                 uint64_t m, void* src, void* dst, int width,
+                 uint32_t* n_samples, int threads) {
+  return orc_generate_ex(t, seed, edge_begin, m, src, dst, width, n_samples, threads, 0, 0);
 }
 
 /* Chunk reduction: histogram of the top hist_bits bits of each source id and

@@ -435,3 +435,58 @@ def test_invalid_inputs_rejected(args):
     with pytest.raises(oracle.OracleError) as ei:
         oracle.build_table(*args)
     assert ei.value.name == "EINVAL"
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5 generalizations: undirected mirror and id scramble (reading R19)
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 7, 10, 16])
+@pytest.mark.parametrize("key", [0, 1, 0x0123456789ABCDEF, 2**64 - 1])
+def test_scramble_is_a_permutation(k, key):
+    """The scramble relabels ids: a bijection of [0, 2^k) for every key."""
+    img = sorted(oracle.scramble(k, key, x) for x in range(1 << k))
+    assert img == list(range(1 << k))
+
+
+def test_scramble_depends_on_key_and_k():
+    a = [oracle.scramble(16, 1, x) for x in range(256)]
+    b = [oracle.scramble(16, 2, x) for x in range(256)]
+    assert a != b and a != list(range(256))
+    # ids stay below 2^k for k up to 64
+    for k in (31, 32, 33, 63, 64):
+        for x in (0, 1, (1 << k) - 1, (1 << (k - 1)) + 12345):
+            assert 0 <= oracle.scramble(k, 99, x) < (1 << k)
+
+
+@pytest.mark.parametrize("k,bound,e0,m", [(12, 256, 0, 5000), (26, 4096, 2**32 - 100, 3000), (64, 2000, 2**64 - 500, 500),
+                                          (33, 1000, 7, 2000)])
+def test_undirected_mirrors_the_lower_triangle(k, bound, e0, m):
+    """Sec. 5: an undirected graph mirrors edges of the lower-left triangle
+    (row > column) to the upper right: (min, max) of the directed edge."""
+    t = oracle.build_table(0.57, 0.19, 0.19, 0.05, k, bound, oracle.VARIABLE)
+    s, d = oracle.generate(t, 3, e0, m)
+    us, ud = oracle.generate(t, 3, e0, m, flags=oracle.UNDIRECTED)
+    assert np.array_equal(us, np.minimum(s, d)) and np.array_equal(ud, np.maximum(s, d))
+    assert np.all(us <= ud)
+
+
+def test_scramble_relabels_every_id_by_the_same_map():
+    """The scramble is one map applied to sources and destinations alike, after
+    the mirror; the degree sequence of the graph is unchanged."""
+    k, key = 12, 0xC0FFEE
+    t = oracle.build_table(0.45, 0.22, 0.22, 0.11, k, 1000, oracle.VARIABLE)
+    s, d = oracle.generate(t, 8, 0, 1 << 15)
+    pi = np.array([oracle.scramble(k, key, x) for x in range(1 << k)], dtype=np.uint32)
+    ss, sd = oracle.generate(t, 8, 0, 1 << 15, flags=oracle.SCRAMBLE, scramble_key=key)
+    assert np.array_equal(ss, pi[s]) and np.array_equal(sd, pi[d])
+    bs, bd = oracle.generate(t, 8, 0, 1 << 15, flags=oracle.SCRAMBLE | oracle.UNDIRECTED, scramble_key=key)
+    assert np.array_equal(bs, pi[np.minimum(s, d)]) and np.array_equal(bd, pi[np.maximum(s, d)])
+    deg = np.sort(np.bincount(s, minlength=1 << k))
+    sdeg = np.sort(np.bincount(ss, minlength=1 << k))
+    assert np.array_equal(deg, sdeg)
+
+
+def test_epilogue_rejects_unknown_flags():
+    t = oracle.build_table(0.57, 0.19, 0.19, 0.05, 10, 256, oracle.VARIABLE)
+    with pytest.raises(oracle.OracleError):
+        oracle.generate(t, 1, 0, 10, flags=4)
