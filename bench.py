@@ -329,6 +329,17 @@ def main():
                      "ops_per_edge": ops_per_edge,
                      "traffic": traffic},
     }
+    # the Sec. 5 epilogue (undirected mirror + id scramble) on the same instance
+    t_epi = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+    R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
+    ea, eb_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record(stream)
+    R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
+    eb_.record(stream)
+    torch.cuda.synchronize()
+    out["undirected_scrambled_kernel_ms"] = ea.elapsed_time(eb_)
+    out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
+    t_epi.close()
     del src, dst
     torch.cuda.empty_cache()
     if not args.no_batch:

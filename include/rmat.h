@@ -145,6 +145,24 @@ int rmat_generate_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin,
                         uint64_t m, void* out_src, void* out_dst, void* stream);
 
 /*
+ * Generalizations of Sec. 5 applied to each edge before it is stored (the
+ * same edges as rmat_generate_async otherwise):
+ *  RMAT_UNDIRECTED  an undirected graph: an edge in the lower-left triangle
+ *                   (src > dst) is mirrored to the upper right, i.e. its ids
+ *                   are swapped, so src <= dst for every edge;
+ *  RMAT_SCRAMBLE    both ids are relabelled by one bijection pi of [0, 2^k)
+ *                   chosen by scramble_key (after the mirror): three rounds
+ *                   of x = (x * M_r + C_r) mod 2^k, x ^= x >> ceil(k/2), with
+ *                   M_r (odd) and C_r the SplitMix64 outputs of the key in the
+ *                   order M_0, C_0, M_1, C_1, M_2, C_2 (M_r with bit 0 set).
+ * flags 0 is rmat_generate_async.  Errors as for rmat_generate_async, and
+ * RMAT_EINVAL for unknown flags.
+ */
+enum rmat_generate_flags { RMAT_UNDIRECTED = 1, RMAT_SCRAMBLE = 2 };
+int rmat_generate_ex_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, int flags,
+                           uint64_t scramble_key, void* out_src, void* out_dst, void* stream);
+
+/*
  * Generates the same edges as rmat_generate but stores none of them; instead
  * it reduces them on the device (a consumer that only needs a digest of a
  * huge instance, generated chunk by chunk):
@@ -185,6 +203,9 @@ typedef struct rmat_instance {
   uint64_t m;
   void* out_src;         /* device arrays of m ids (uint32 if k <= 32, else uint64) */
   void* out_dst;
+  int32_t flags;         /* RMAT_UNDIRECTED | RMAT_SCRAMBLE, as for rmat_generate_ex_async */
+  int32_t reserved;
+  uint64_t scramble_key;
 } rmat_instance;
 
 typedef struct rmat_batch* rmat_batch_t;

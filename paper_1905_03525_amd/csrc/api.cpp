@@ -201,6 +201,25 @@ void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const S
   I->device_bytes = device_bytes;
 }
 
+// SplitMix64 [Steele, Lea, Flood, OOPSLA'14]: state advanced by the golden
+// gamma, output mixed by two multiply-xorshift steps.
+static uint64_t splitmix64(uint64_t& state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void scramble_params(uint64_t key, int k, GenInst* I) {
+  uint64_t st = key;
+  for (int r = 0; r < 3; ++r) {
+    I->scr_mul[r] = splitmix64(st) | 1ull;
+    I->scr_add[r] = splitmix64(st);
+  }
+  I->scr_mask = k >= 64 ? ~0ull : ((1ull << k) - 1);
+  I->scr_shift = static_cast<uint32_t>((k + 1) / 2);
+}
+
 void clear_error() { g_err[0] = '\0'; }
 
 int check_device() {
@@ -308,8 +327,10 @@ int rmat_table_export(rmat_table_t t, void* host_buf, size_t nbytes) {
 }
 
 static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, void* out_src,
-                           void* out_dst, void* stream, bool reduce, int hist_bits, void* d_hist, void* d_xor) {
+                           void* out_dst, void* stream, bool reduce, int hist_bits, void* d_hist, void* d_xor,
+                           int flags = 0, uint64_t scramble_key = 0) {
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (flags & ~(RMAT_UNDIRECTED | RMAT_SCRAMBLE)) return set_error(RMAT_EINVAL, "unknown flags 0x%x", flags);
   if (m == 0) return RMAT_OK;
   if (edge_begin + (m - 1) < edge_begin) return set_error(RMAT_ERANGE, "edge_begin + m exceeds 2^64");
   rmat::GenerateArgs a;
@@ -353,6 +374,8 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
   a.seed = seed;
   a.edge_begin = edge_begin;
   a.m = m;
+  a.epi = static_cast<uint32_t>(flags);
+  a.scramble_key = scramble_key;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = reduce ? rmat::launch_generate_reduce(a, s) : rmat::launch_generate(a, s);
   if (e != hipSuccess) return rmat::hip_fail(e, reduce ? "generate_reduce launch" : "generate launch");
@@ -363,6 +386,13 @@ int rmat_generate_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint
                         void* out_dst, void* stream) {
   g_err[0] = '\0';
   return generate_common(t, seed, edge_begin, m, out_src, out_dst, stream, false, 0, nullptr, nullptr);
+}
+
+int rmat_generate_ex_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, int flags,
+                           uint64_t scramble_key, void* out_src, void* out_dst, void* stream) {
+  g_err[0] = '\0';
+  return generate_common(t, seed, edge_begin, m, out_src, out_dst, stream, false, 0, nullptr, nullptr, flags,
+                         scramble_key);
 }
 
 int rmat_generate(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, void* out_src, void* out_dst) {

@@ -70,6 +70,7 @@ int validate_instance(const rmat_instance& x, int i, rmat::Shape* S) {
   }
   if (x.m > 0 && x.edge_begin + (x.m - 1) < x.edge_begin)
     return set_error(RMAT_ERANGE, "instance %d: edge_begin + m exceeds 2^64", i);
+  if (x.flags & ~(RMAT_UNDIRECTED | RMAT_SCRAMBLE)) return set_error(RMAT_EINVAL, "instance %d: unknown flags", i);
   if (x.m > 0) {
     if (!x.out_src || !x.out_dst) return set_error(RMAT_EINVAL, "instance %d: NULL output pointer", i);
     const uintptr_t align = x.k <= 32 ? 4 : 8;
@@ -361,6 +362,8 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
     d.out_src = x.out_src;
     d.out_dst = x.out_dst;
     d.digest = nullptr;
+    d.epi = static_cast<uint32_t>(x.flags);
+    if (d.epi) rmat::scramble_params(x.scramble_key, x.k, &d);
     b->total_edges += x.m;
   }
   // every byte 0xFF: each table's build status reads -1 (not built) until the first run

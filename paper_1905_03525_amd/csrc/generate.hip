@@ -183,6 +183,19 @@ struct BatchLaunch {
   TileLayout L;
 };
 
+// The scramble bijection of [0, 2^k): three rounds of an affine map with an
+// odd multiplier followed by an xor-shift, each a bijection mod 2^k.  In
+// 32-bit arithmetic when the ids are (k <= 32: the low k bits agree).
+template <typename Id>
+__device__ __forceinline__ Id scramble_id(Id x, const Inst& I) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    x = (x * static_cast<Id>(I.scr_mul[r]) + static_cast<Id>(I.scr_add[r])) & static_cast<Id>(I.scr_mask);
+    x ^= x >> I.scr_shift;
+  }
+  return x;
+}
+
 // MurmurHash3's 64-bit finaliser.
 __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
   z ^= z >> 33;
@@ -300,7 +313,18 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
         } else {
           const uint64_t slot = e - I.edge_begin;
-          const Id s = static_cast<Id>(acc.src(I.k)), d = static_cast<Id>(acc.dst(I.k));
+          Id s = static_cast<Id>(acc.src(I.k)), d = static_cast<Id>(acc.dst(I.k));
+          if (I.epi != 0) {  // uniform
+            if (I.epi & kEpiUndirected) {
+              const Id lo = s < d ? s : d;
+              d = s < d ? d : s;
+              s = lo;
+            }
+            if (I.epi & kEpiScramble) {
+              s = scramble_id(s, I);
+              d = scramble_id(d, I);
+            }
+          }
           static_cast<Id*>(I.out_src)[slot] = s;
           static_cast<Id*>(I.out_dst)[slot] = d;
           if (kDigest) {
@@ -537,6 +561,11 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.I.out_src = a.out_src;
   P.I.out_dst = a.out_dst;
   P.I.digest = nullptr;
+  P.I.epi = 0;
+  if (!kReduce && a.epi) {
+    P.I.epi = a.epi;
+    scramble_params(a.scramble_key, a.k, &P.I);
+  }
   P.hist_shift = static_cast<uint32_t>(a.k - a.hist_bits);
   P.bins = a.bins;
   P.xor_out = a.xor_out;

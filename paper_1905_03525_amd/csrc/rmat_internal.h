@@ -94,7 +94,19 @@ struct GenInst {
   // if set (launches with digests enabled), XOR-ed with the XOR over the
   // generated edges of fmix64(e ^ fmix64(src ^ rotl64(dst, 32)))
   unsigned long long* digest;
+  // epilogue applied to each edge before it is stored (Sec. 5): bit 0 mirrors
+  // an edge with src > dst, bit 1 relabels both ids by the scramble
+  uint32_t epi;
+  uint32_t scr_shift;             // ceil(k / 2)
+  uint64_t scr_mask;              // 2^k - 1
+  uint64_t scr_mul[3], scr_add[3];
 };
+
+constexpr uint32_t kEpiUndirected = 1, kEpiScramble = 2;
+
+// The scramble's round constants for a key: SplitMix64 outputs in the order
+// M0, C0, M1, C1, M2, C2, each M with its lowest bit set; also mask and shift.
+void scramble_params(uint64_t key, int k, GenInst* I);
 
 // A run of 64-edge blocks of one instance; a batch lists them in instance
 // order and workgroups claim them through an atomic counter.
@@ -134,6 +146,8 @@ struct GenerateArgs {
   uint64_t edge_begin, m;
   void* out_src;
   void* out_dst;
+  uint32_t epi;             // kEpiUndirected | kEpiScramble
+  uint64_t scramble_key;
   // reduction variant: the edges are generated in sub-chunks of at most
   // bins_cap edges into `bins` (16-bit source prefixes), counted per
   // workgroup into `partials` (reduce_partials_bytes()) and merged into hist

@@ -233,7 +233,7 @@ int validate_request(const rmat_server* s, const rmat_request& r, rmat::Shape* S
     return set_error(RMAT_EINVAL, "output pointers must be %u-byte aligned", (unsigned)idb);
   if (!r.out_src && r.m > 0 && 2 * align_up(r.m * idb, 256) > s->cfg.hbm_budget_bytes)
     return set_error(RMAT_EINVAL, "outputs of %llu edges exceed the whole arena", (unsigned long long)r.m);
-  if (r.flags & ~static_cast<uint32_t>(RMAT_REQ_DIGEST | RMAT_REQ_DISCARD))
+  if (r.flags & ~static_cast<uint32_t>(RMAT_REQ_DIGEST | RMAT_REQ_DISCARD | RMAT_REQ_UNDIRECTED | RMAT_REQ_SCRAMBLE))
     return set_error(RMAT_EINVAL, "unknown request flags 0x%x", r.flags);
   return RMAT_OK;
 }
@@ -464,6 +464,9 @@ int issue_round(rmat_server* s, bool* launched) {
     I.out_src = q->out_src;
     I.out_dst = q->out_dst;
     I.digest = nullptr;  // set below once the packet layout is known
+    I.epi = ((q->r.flags & RMAT_REQ_UNDIRECTED) ? rmat::kEpiUndirected : 0u) |
+            ((q->r.flags & RMAT_REQ_SCRAMBLE) ? rmat::kEpiScramble : 0u);
+    if (I.epi) rmat::scramble_params(q->r.scramble_key, q->r.k, &I);
     insts.push_back(I);
     R.inst_req.push_back(q);
     for (uint64_t f = 0; f < take; f += c.work_blocks) {

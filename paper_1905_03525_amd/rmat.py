@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(PKG, "librmat.so")
 
 RMAT_FIXED = 0
 RMAT_VARIABLE = 1
+RMAT_UNDIRECTED = 1
+RMAT_SCRAMBLE = 2
 
 RMAT_OK = 0
 RMAT_EINVAL = -1
@@ -26,7 +28,7 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
 
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
 EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
-            "rmat_generate_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
+            "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
             "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
             "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
             "rmat_server_step", "rmat_server_drain", "rmat_server_poll", "rmat_server_release",
@@ -34,6 +36,8 @@ EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_tabl
             "rmat_last_error"]
 RMAT_REQ_DIGEST = 1
 RMAT_REQ_DISCARD = 2
+RMAT_REQ_UNDIRECTED = 4
+RMAT_REQ_SCRAMBLE = 8
 
 
 class RmatError(RuntimeError):
@@ -55,7 +59,8 @@ class rmat_instance(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double), ("d", ctypes.c_double),
                 ("k", ctypes.c_int32), ("path_mode", ctypes.c_int32), ("table_bound", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("edge_begin", ctypes.c_uint64), ("m", ctypes.c_uint64),
-                ("out_src", ctypes.c_void_p), ("out_dst", ctypes.c_void_p)]
+                ("out_src", ctypes.c_void_p), ("out_dst", ctypes.c_void_p), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("scramble_key", ctypes.c_uint64)]
 
 
 class rmat_batch_info(ctypes.Structure):
@@ -83,7 +88,7 @@ class rmat_request(ctypes.Structure):
                 ("k", ctypes.c_int32), ("path_mode", ctypes.c_int32), ("table_bound", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("edge_begin", ctypes.c_uint64), ("m", ctypes.c_uint64),
                 ("out_src", ctypes.c_void_p), ("out_dst", ctypes.c_void_p), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("scramble_key", ctypes.c_uint64)]
 
 
 class rmat_completion(ctypes.Structure):
@@ -120,6 +125,7 @@ def load() -> ctypes.CDLL:
     L.rmat_generate.argtypes = [vp, u64, u64, u64, vp, vp]
     L.rmat_generate_async.argtypes = [vp, u64, u64, u64, vp, vp, vp]
     L.rmat_generate_reduce_async.argtypes = [vp, u64, u64, u64, c_int, vp, vp, vp]
+    L.rmat_generate_ex_async.argtypes = [vp, u64, u64, u64, c_int, u64, vp, vp, vp]
     L.rmat_batch_create.argtypes = [ctypes.POINTER(rmat_instance), c_int, ctypes.c_uint32, ctypes.POINTER(vp)]
     L.rmat_batch_enqueue.argtypes = [vp, vp]
     L.rmat_batch_launch_graph.argtypes = [vp, vp]
@@ -239,6 +245,12 @@ def rmat_generate_async(t: Table, seed: int, edge_begin: int, m: int, out_src, o
                                       _stream(stream)), "rmat_generate_async")
 
 
+def rmat_generate_ex_async(t: Table, seed: int, edge_begin: int, m: int, flags: int, scramble_key: int, out_src,
+                           out_dst, stream=None):
+    _check(load().rmat_generate_ex_async(t.handle, seed, edge_begin, m, flags, scramble_key, _ptr(out_src),
+                                         _ptr(out_dst), _stream(stream)), "rmat_generate_ex_async")
+
+
 def rmat_generate_reduce_async(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int, d_hist, d_xor,
                                stream=None):
     _check(load().rmat_generate_reduce_async(t.handle, seed, edge_begin, m, hist_bits, _ptr(d_hist), _ptr(d_xor),
@@ -287,6 +299,7 @@ def make_instances(params) -> "ctypes.Array":
         x.table_bound, x.seed = p.get("table_bound", 0), p["seed"]
         x.edge_begin, x.m = p.get("edge_begin", 0), p["m"]
         x.out_src, x.out_dst = _ptr(p.get("out_src")), _ptr(p.get("out_dst"))
+        x.flags, x.scramble_key = p.get("gen_flags", 0), p.get("scramble_key", 0)
     return arr
 
 
@@ -385,6 +398,7 @@ def make_request(p: dict) -> rmat_request:
     r.edge_begin, r.m = p.get("edge_begin", 0), p["m"]
     r.out_src, r.out_dst = _ptr(p.get("out_src")), _ptr(p.get("out_dst"))
     r.flags = p.get("flags", 0)
+    r.scramble_key = p.get("scramble_key", 0)
     return r
 
 

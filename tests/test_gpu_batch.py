@@ -39,7 +39,10 @@ def _plain(R, p):
     """Plain path: own table, own launch."""
     import torch
     t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
-    s, d = R.generate_edges(t, p["seed"], p["edge_begin"], p["m"])
+    s = torch.empty(p["m"], dtype=R.id_dtype(p["k"]), device="cuda")
+    d = torch.empty_like(s)
+    R.rmat_generate_ex_async(t, p["seed"], p["edge_begin"], p["m"], p.get("gen_flags", 0), p.get("scramble_key", 0),
+                             s, d, torch.cuda.current_stream())
     torch.cuda.synchronize()
     return t, s, d
 
@@ -64,8 +67,12 @@ def _mixed():
         (q(8), 3, 100, V, 17, 0, 4096),
         (G500, 26, 4096, V, 7, 0, 64 * 2048 * 3 + 5),     # several work items of one instance
     ]
-    return [dict(a=x[0][0], b=x[0][1], c=x[0][2], d=x[0][3], k=x[1], table_bound=x[2], path_mode=x[3], seed=x[4],
-                 edge_begin=x[5], m=x[6]) for x in rows]
+    out = [dict(a=x[0][0], b=x[0][1], c=x[0][2], d=x[0][3], k=x[1], table_bound=x[2], path_mode=x[3], seed=x[4],
+                edge_begin=x[5], m=x[6]) for x in rows]
+    # Sec. 5 epilogues on some instances
+    for i, (fl, key) in {1: (3, 0xBEEF), 2: (2, 7), 3: (1, 0), 8: (3, 2**64 - 1)}.items():
+        out[i]["gen_flags"], out[i]["scramble_key"] = fl, key
+    return out
 
 
 @pytest.mark.parametrize("work_blocks", [0, 3, 1])
@@ -88,7 +95,8 @@ def test_batch_equals_plain_and_oracle(R, work_blocks):
             assert R.rmat_batch_table_info(b, i) == R.rmat_table_info(t)
             t.close()
             o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
-            os_, od = oracle.generate(o, p["seed"], p["edge_begin"], p["m"], threads=8)
+            os_, od = oracle.generate(o, p["seed"], p["edge_begin"], p["m"], threads=8, flags=p.get("gen_flags", 0),
+                                      scramble_key=p.get("scramble_key", 0))
             assert np.array_equal(R.to_numpy_ids(p["out_src"], p["k"]), os_), f"instance {i} src vs oracle"
             assert np.array_equal(R.to_numpy_ids(p["out_dst"], p["k"]), od), f"instance {i} dst vs oracle"
 

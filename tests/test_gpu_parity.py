@@ -284,3 +284,53 @@ def test_k34_all_chunks_match_oracle(R):
         assert hashlib.sha256(hv.astype("<u8").tobytes()).hexdigest() == h, f"chunk {c} histogram"
         assert int(xr.cpu().numpy().view(np.uint64)[0]) == x, f"chunk {c} checksum"
     t.close()
+
+
+EPILOGUE_CASES = [
+    # q, k, bound, mode, seed, edge_begin, m, flags, scramble_key
+    (G500, 16, 256, oracle.FIXED, 1, 0, 1 << 16, 1, 0),
+    (G500, 26, 4096, oracle.VARIABLE, 7, 12_345_677, 100_003, 2, 0xABCDEF),
+    (G500, 26, 4096, oracle.VARIABLE, 7, 3, 100_000, 3, 2**64 - 1),
+    (CFG3, 34, 1 << 16, oracle.VARIABLE, 3, 2**32 - 3000, 9000, 3, 12345),   # 64-bit ids, L2 table
+    (SKEW, 64, 8192, oracle.VARIABLE, 9, 2**64 - 5000, 5000, 3, 1),
+    (G500, 32, 1024, oracle.FIXED, 5, 63, 65, 2, 77),
+    (G500, 33, 1024, oracle.FIXED, 5, 64, 64, 1, 0),
+    (G500, 31, 4096, oracle.VARIABLE, 5, 3, 1, 3, 5),
+    (G500, 1, 5, oracle.VARIABLE, 5, 0, 1000, 3, 6),
+    (_dirichlet(5), 48, 20_000, oracle.VARIABLE, 17, 10**12, 40_000, 2, 99),
+    (G500, 28, 1 << 20, oracle.VARIABLE, 21, 0, 100_000, 3, 4),           # L2 table, 32-bit ids
+]
+
+
+@pytest.mark.parametrize("q,k,bound,mode,seed,e0,m,flags,key", EPILOGUE_CASES)
+def test_epilogue_parity(R, q, k, bound, mode, seed, e0, m, flags, key):
+    """Sec. 5 generalizations: undirected mirror and id scramble, bit-exact."""
+    import torch
+    t = R.rmat_build_table(*q, k, bound, mode)
+    src = torch.empty(m, dtype=R.id_dtype(k), device="cuda")
+    dst = torch.empty(m, dtype=R.id_dtype(k), device="cuda")
+    R.rmat_generate_ex_async(t, seed, e0, m, flags, key, src, dst, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    o = oracle.build_table(*q, k, bound, mode)
+    os_, od = oracle.generate(o, seed, e0, m, threads=8, flags=flags, scramble_key=key)
+    gs, gd = R.to_numpy_ids(src, k), R.to_numpy_ids(dst, k)
+    bad = np.nonzero((gs != os_) | (gd != od))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first at slot {bad[:5]}"
+    if flags & 1 and not flags & 2:
+        assert np.all(gs <= gd)
+    t.close()
+
+
+def test_epilogue_flags_zero_is_plain_and_bad_flags_rejected(R):
+    import torch
+    t = R.rmat_build_table(*G500, 20, 4096, R.RMAT_VARIABLE)
+    a = torch.empty(5000, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    R.rmat_generate_ex_async(t, 3, 11, 5000, 0, 123, a, b)
+    s, d = R.generate_edges(t, 3, 11, 5000)
+    torch.cuda.synchronize()
+    assert torch.equal(a, s) and torch.equal(b, d)
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_generate_ex_async(t, 3, 0, 10, 4, 0, a, b)
+    assert ei.value.status == R.RMAT_EINVAL
+    t.close()

@@ -144,6 +144,36 @@ def test_served_into_caller_outputs_equals_plain(R):
         t.close()
 
 
+def test_served_epilogues_match_oracle(R):
+    """Requests with the Sec. 5 epilogues (undirected, scramble) served in a
+    mix equal the oracle with the same flags."""
+    import torch
+    reqs = _requests(12, seed=13)
+    combos = [(4, 0), (8, 0xABC), (12, 2**63 + 5)]
+    for i, p in enumerate(reqs):
+        fl, key = combos[i % 3]
+        p["flags"], p["scramble_key"] = fl, key
+        dt = R.id_dtype(p["k"])
+        p["out_src"] = torch.full((max(p["m"], 1),), -1, dtype=dt, device="cuda")
+        p["out_dst"] = torch.full((max(p["m"], 1),), -1, dtype=dt, device="cuda")
+    torch.cuda.synchronize()
+    with R.rmat_server_create(hbm_budget_bytes=1 << 24, max_table_bound=1 << 15, tick_blocks=256,
+                              request_quantum=48, max_active=3, work_blocks=8) as s:
+        for p in reqs:
+            R.rmat_server_submit(s, p)
+        R.rmat_server_drain(s)
+        assert all(c["status"] == 0 for c in R.rmat_server_poll(s, 100))
+    for i, p in enumerate(reqs):
+        if not p["m"]:
+            continue
+        o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+        of = (1 if p["flags"] & 4 else 0) | (2 if p["flags"] & 8 else 0)
+        os_, od = oracle.generate(o, p["seed"], p["edge_begin"], p["m"], threads=8, flags=of,
+                                  scramble_key=p["scramble_key"])
+        assert np.array_equal(R.to_numpy_ids(p["out_src"][:p["m"]], p["k"]), os_), f"request {i} src"
+        assert np.array_equal(R.to_numpy_ids(p["out_dst"][:p["m"]], p["k"]), od), f"request {i} dst"
+
+
 def test_trace_and_backpressure(R):
     """A Poisson trace at 2000 requests/s into a 64 MiB arena: requests wait
     for space, every one completes with its alone digest."""
@@ -173,7 +203,7 @@ def test_server_errors(R):
         for bad, status in [(dict(table_bound=8192), R.RMAT_EINVAL),        # above max_table_bound
                             (dict(m=1 << 20), R.RMAT_EINVAL),               # outputs larger than the arena
                             (dict(out_src=256), R.RMAT_EINVAL),             # one output pointer only
-                            (dict(flags=8), R.RMAT_EINVAL),
+                            (dict(flags=16), R.RMAT_EINVAL),
                             (dict(edge_begin=2**64 - 10, m=20), R.RMAT_ERANGE),
                             (dict(a=0.7), R.RMAT_EINVAL)]:
             with pytest.raises(R.RmatError) as ei:
