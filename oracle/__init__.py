@@ -82,6 +82,16 @@ def lib():
         L.orc_generate_ex.restype = ctypes.c_int
         L.orc_scramble.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_scramble.restype = ctypes.c_uint64
+        L.orc_binomial.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
+                                   ctypes.c_double]
+        L.orc_binomial.restype = ctypes.c_uint64
+        L.orc_partition_counts.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                           ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        L.orc_partition_counts.restype = ctypes.c_int
+        L.orc_generate_partition.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                             ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p]
+        L.orc_generate_partition.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -196,3 +206,39 @@ def generate_reduce(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int
     if rc != 0:
         raise OracleError(rc, "generate_reduce")
     return hist, int(x[0])
+
+
+# ---------------------------------------------------------------------------
+# partitioned generation (Sec. 5, reading R20)
+
+def binomial(seed: int, r: int, c: int, level: int, n: int, p: float) -> int:
+    """Bin(n, p) drawn from the uniform stream of tree node (level, r, c)."""
+    return int(lib().orc_binomial(seed, r, c, level, n, p))
+
+
+def partition_counts(t: Table, seed: int, m: int, tbits: int, row_begin: int = 0, row_end: int | None = None):
+    """Edge counts of the 2^tbits x 2^tbits tiles in tile rows [row_begin,
+    row_end), as a (rows, 2^tbits) uint64 array."""
+    if row_end is None:
+        row_end = 1 << tbits
+    out = np.zeros(((row_end - row_begin), 1 << tbits), np.uint64)
+    rc = lib().orc_partition_counts(t.handle, seed, m, tbits, row_begin, row_end, _ptr(out))
+    if rc != 0:
+        raise OracleError(rc, "partition_counts")
+    return out
+
+
+def generate_partition(t: Table, seed: int, m: int, tbits: int, row_begin: int = 0, row_end: int | None = None):
+    """(counts, src, dst): the edges of the tiles in tile rows [row_begin,
+    row_end), tile by tile in row-major order."""
+    if row_end is None:
+        row_end = 1 << tbits
+    counts = partition_counts(t, seed, m, tbits, row_begin, row_end)
+    n = int(counts.sum())
+    dt = np.uint32 if t.k <= 32 else np.uint64
+    src, dst = np.zeros(n, dt), np.zeros(n, dt)
+    rc = lib().orc_generate_partition(t.handle, seed, m, tbits, row_begin, row_end, _ptr(src), _ptr(dst),
+                                      4 if t.k <= 32 else 8, _ptr(counts))
+    if rc != 0:
+        raise OracleError(rc, "generate_partition")
+    return counts, src, dst

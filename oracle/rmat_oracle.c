@@ -61,6 +61,18 @@
  *      with M_r (odd) and C_r the outputs of SplitMix64 [Steele, Lea, Flood,
  *      OOPSLA'14] seeded with the scramble key, drawn in the order M_0, C_0,
  *      M_1, C_1, M_2, C_2 (M_r with its lowest bit set).
+ *  R20 Sec. 5 partitioned generation: the adjacency matrix is cut into
+ *      2^t x 2^t tiles; the m edges are split over them top-down, each node
+ *      of the quadrant tree splitting its count n into (n_a, n_b, n_c, n_d)
+ *      by n_a = Bin(n, a), n_b = Bin(n - n_a, b / (b + c + d)),
+ *      n_c = Bin(n - n_a - n_b, c / (c + d)), n_d = the rest.  Bin(n, p) is
+ *      inversion for n min(p, 1-p) < 30 and BTPE [Kachitvichyanukul &
+ *      Schmeiser, CACM 1988] otherwise, with p > 1/2 drawn as n - Bin(n, 1-p).
+ *      Node (level l, row prefix R, column prefix C) draws its uniforms from
+ *      Philox4x32-10 under the seed with counter (R, C, i, 2^31 + l), two
+ *      53-bit uniforms per block.  Edge j of tile (R, C) samples the
+ *      remaining k - t letters with counter (j_lo, j_hi, s / 4,
+ *      1 + R 2^t + C) and gets the tile's prefixes: src = R 2^(k-t) + row.
  */
 #include <math.h>
 #include <pthread.h>
@@ -437,10 +449,18 @@ int orc_build_table(double a, double b, double c, double d, int k,
 /* ------------------------------------------------------------------------
  * Sampling (Sec. 2, the sampling loop, with readings R9-R12).
  * ---------------------------------------------------------------------- */
+static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t seed, uint64_t e,
+                           uint64_t* src, uint64_t* dst, uint32_t* n_samples);
+
 static void sample_edge(const orc_table* t, uint64_t seed, uint64_t e,
                         uint64_t* src, uint64_t* dst, uint32_t* n_samples) {
+  sample_letters(t, t->k, 0u, seed, e, src, dst, n_samples);
+}
+
+/* k letters of one edge from counter stream (e_lo, e_hi, j, stream). */
+static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t seed, uint64_t e,
+                           uint64_t* src, uint64_t* dst, uint32_t* n_samples) {
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  const int k = t->k;
   const int shift = 32 - t->bucket_bits;
   const uint32_t fmask = (uint32_t)(t->capacity - 1);
   uint64_t row = 0, col = 0;
@@ -448,7 +468,7 @@ static void sample_edge(const orc_table* t, uint64_t seed, uint64_t e,
   uint32_t s = 0, words[4] = {0, 0, 0, 0};
   while (filled < k) {
     if ((s & 3u) == 0) {
-      const uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), s >> 2, 0u};
+      const uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), s >> 2, stream};
       orc_philox4x32_10(ctr, key, words);
     }
     uint32_t x = words[s & 3u];
@@ -681,6 +701,218 @@ int orc_generate_reduce(const orc_table* t, uint64_t seed, uint64_t edge_begin,
 /* ------------------------------------------------------------------------
  * Flat accessors for the ctypes wrapper.
  * ---------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------
+ * Partitioned generation (Sec. 5, reading R20).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t key[2], ctr[4];
+  uint32_t words[4];
+  int used; /* uniforms taken from `words` (0, 1 or 2) */
+} ustream_t;
+
+static void ustream_init(ustream_t* u, uint64_t seed, uint32_t r, uint32_t c, int level) {
+  u->key[0] = (uint32_t)seed;
+  u->key[1] = (uint32_t)(seed >> 32);
+  u->ctr[0] = r;
+  u->ctr[1] = c;
+  u->ctr[2] = 0;
+  u->ctr[3] = 0x80000000u | (uint32_t)level;
+  u->used = 2;
+}
+
+/* A uniform in [0, 1) with 53 random bits: two Philox words per uniform. */
+static double uniform53(ustream_t* u) {
+  if (u->used == 2) {
+    orc_philox4x32_10(u->ctr, u->key, u->words);
+    u->ctr[2] += 1;
+    u->used = 0;
+  }
+  const uint64_t hi = u->words[2 * u->used], lo = u->words[2 * u->used + 1];
+  u->used += 1;
+  return (double)(((hi << 32) | lo) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Bin(n, p), 0 < p <= 1/2, by inversion (n p < 30): walk the pmf upwards
+ * from f(0) = (1-p)^n with f(x)/f(x-1) = ((n+1) p/(1-p)) / x - p/(1-p). */
+static uint64_t binomial_inversion(ustream_t* us, uint64_t n, double p) {
+  const double q = 1.0 - p, s = p / q, a = ((double)n + 1.0) * s;
+  const double f0 = pow(q, (double)n);
+  for (;;) {
+    double u = uniform53(us), f = f0;
+    uint64_t x = 0;
+    int restart = 0;
+    while (u > f) {
+      u -= f;
+      x += 1;
+      if (x > n || x > 110) { restart = 1; break; }
+      f *= a / (double)x - s;
+    }
+    if (!restart) return x;
+  }
+}
+
+/* Stirling-series remainder of ln(x!) at x + 1 = a: 1/(12a) - 1/(360a^3) + ... */
+static double stirling_tail(double a) {
+  const double a2 = a * a;
+  return (13860.0 - (462.0 - (132.0 - (99.0 - 140.0 / a2) / a2) / a2) / a2) / a / 166320.0;
+}
+
+/* Bin(n, p), 0 < p <= 1/2, n p >= 30: BTPE (triangle, parallelogram and two
+ * exponential tails over the pmf, squeeze, then the exact ratio). */
+static uint64_t binomial_btpe(ustream_t* us, uint64_t n, double p) {
+  const double dn = (double)n, r = p, q = 1.0 - p;
+  const double nrq = dn * r * q;
+  const double fm = dn * r + r;
+  const double M = floor(fm);
+  const double p1 = floor(2.195 * sqrt(nrq) - 4.6 * q) + 0.5;
+  const double xm = M + 0.5, xl = xm - p1, xr = xm + p1;
+  const double c = 0.134 + 20.5 / (15.3 + M);
+  double a = (fm - xl) / (fm - xl * r);
+  const double laml = a * (1.0 + a / 2.0);
+  a = (xr - fm) / (xr * q);
+  const double lamr = a * (1.0 + a / 2.0);
+  const double p2 = p1 * (1.0 + 2.0 * c), p3 = p2 + c / laml, p4 = p3 + c / lamr;
+  for (;;) {
+    const double u = uniform53(us) * p4;
+    double v = uniform53(us), y;
+    if (u <= p1) { /* triangle: accept at once */
+      return (uint64_t)floor(xm - p1 * v + u);
+    }
+    if (u <= p2) { /* parallelogram */
+      const double x = xl + (u - p1) / c;
+      v = v * c + 1.0 - fabs(M - x + 0.5) / p1;
+      if (v > 1.0) continue;
+      y = floor(x);
+    } else if (u <= p3) { /* left exponential tail */
+      y = floor(xl + log(v) / laml);
+      if (y < 0.0) continue;
+      v = v * (u - p2) * laml;
+    } else { /* right exponential tail */
+      y = floor(xr - log(v) / lamr);
+      if (y > dn) continue;
+      v = v * (u - p3) * lamr;
+    }
+    const double k = fabs(y - M);
+    if (k <= 20.0 || k >= nrq / 2.0 - 1.0) {
+      /* f(y) / f(M) by the pmf recurrence */
+      const double s = r / q, aa = s * (dn + 1.0);
+      double F = 1.0;
+      if (M < y) {
+        for (double i = M + 1.0; i <= y; i += 1.0) F *= aa / i - s;
+      } else if (M > y) {
+        for (double i = y + 1.0; i <= M; i += 1.0) F /= aa / i - s;
+      }
+      if (v <= F) return (uint64_t)y;
+      continue;
+    }
+    /* squeeze on ln f(y) / f(M) */
+    const double rho = (k / nrq) * ((k * (k / 3.0 + 0.625) + 0.1666666666666) / nrq + 0.5);
+    const double tt = -k * k / (2.0 * nrq);
+    const double A = log(v);
+    if (A < tt - rho) return (uint64_t)y;
+    if (A > tt + rho) continue;
+    /* the exact bound with Stirling's series for the four factorials */
+    const double x1 = y + 1.0, f1 = M + 1.0, z = dn + 1.0 - M, w = dn - y + 1.0;
+    const double bound = xm * log(f1 / x1) + (dn - M + 0.5) * log(z / w) + (y - M) * log(w * r / (x1 * q)) +
+                         stirling_tail(f1) + stirling_tail(z) - stirling_tail(x1) - stirling_tail(w);
+    if (A <= bound) return (uint64_t)y;
+  }
+}
+
+static uint64_t binomial(ustream_t* us, uint64_t n, double p) {
+  if (n == 0 || p <= 0.0) return 0;
+  if (p >= 1.0) return n;
+  const int flip = p > 0.5;
+  const double pp = flip ? 1.0 - p : p;
+  const uint64_t x = ((double)n * pp < 30.0) ? binomial_inversion(us, n, pp) : binomial_btpe(us, n, pp);
+  return flip ? n - x : x;
+}
+
+/* Bin(n, p) from the stream of node (level, r, c), for tests. */
+uint64_t orc_binomial(uint64_t seed, uint32_t r, uint32_t c, int level, uint64_t n, double p) {
+  ustream_t us;
+  ustream_init(&us, seed, r, c, level);
+  return binomial(&us, n, p);
+}
+
+/* Counts of the quadrant children of node (level, r, c) holding n edges. */
+static void split4(const double q[4], uint64_t seed, int level, uint32_t r, uint32_t c, uint64_t n,
+                   uint64_t out[4]) {
+  ustream_t us;
+  ustream_init(&us, seed, r, c, level);
+  const double bcd = q[1] + q[2] + q[3], cd = q[2] + q[3];
+  out[0] = binomial(&us, n, q[0]);
+  uint64_t rest = n - out[0];
+  out[1] = binomial(&us, rest, bcd > 0.0 ? q[1] / bcd : 0.0);
+  rest -= out[1];
+  out[2] = binomial(&us, rest, cd > 0.0 ? q[2] / cd : 0.0);
+  out[3] = rest - out[2];
+}
+
+static void partition_rec(const double q[4], uint64_t seed, int t, int level, uint32_t r, uint32_t c,
+                          uint64_t n, uint32_t row_begin, uint32_t row_end, uint64_t* counts) {
+  if (level == t) {
+    counts[(uint64_t)(r - row_begin) << t | c] = n;
+    return;
+  }
+  if (n == 0) return; /* counts start at zero */
+  uint64_t ch[4];
+  split4(q, seed, level, r, c, n, ch);
+  for (int quad = 0; quad < 4; ++quad) {
+    const uint32_t cr = 2 * r + (uint32_t)(quad >> 1), cc = 2 * c + (uint32_t)(quad & 1);
+    /* tile rows under the child: [cr, cr + 1) << (t - level - 1) */
+    const int sh = t - level - 1;
+    const uint64_t lo = (uint64_t)cr << sh, hi = (uint64_t)(cr + 1) << sh;
+    if (hi <= row_begin || lo >= row_end) continue;
+    partition_rec(q, seed, t, level + 1, cr, cc, ch[quad], row_begin, row_end, counts);
+  }
+}
+
+/* Edge counts of the tiles in tile rows [row_begin, row_end): row-major,
+ * (row_end - row_begin) x 2^t entries.  1 <= t <= min(k - 1, 15). */
+int orc_partition_counts(const orc_table* t, uint64_t seed, uint64_t m, int tbits,
+                         uint32_t row_begin, uint32_t row_end, uint64_t* counts) {
+  if (tbits < 1 || tbits > 15 || tbits >= t->k) return ORC_EINVAL;
+  if (row_begin >= row_end || row_end > (1u << tbits)) return ORC_EINVAL;
+  if (m > (1ull << 53)) return ORC_EINVAL;
+  memset(counts, 0, sizeof(uint64_t) * ((uint64_t)(row_end - row_begin) << tbits));
+  partition_rec(t->q, seed, tbits, 0, 0, 0, m, row_begin, row_end, counts);
+  return ORC_OK;
+}
+
+/* All edges of the tiles in tile rows [row_begin, row_end), tile by tile in
+ * row-major order, edge j of a tile in slot offset(tile) + j. */
+int orc_generate_partition(const orc_table* t, uint64_t seed, uint64_t m, int tbits,
+                           uint32_t row_begin, uint32_t row_end, void* src, void* dst, int width,
+                           const uint64_t* counts) {
+  if (tbits < 1 || tbits > 15 || tbits >= t->k) return ORC_EINVAL;
+  if (width != 4 && width != 8) return ORC_EINVAL;
+  if (width == 4 && t->k > 32) return ORC_EINVAL;
+  const int kk = t->k - tbits;
+  uint64_t slot = 0;
+  for (uint32_t r = row_begin; r < row_end; ++r) {
+    for (uint32_t c = 0; c < (1u << tbits); ++c) {
+      const uint64_t n = counts[(uint64_t)(r - row_begin) << tbits | c];
+      const uint32_t stream = 1u + ((r << tbits) | c);
+      for (uint64_t j = 0; j < n; ++j, ++slot) {
+        uint64_t s, d;
+        sample_letters(t, kk, stream, seed, j, &s, &d, NULL);
+        s |= (uint64_t)r << kk;
+        d |= (uint64_t)c << kk;
+        if (width == 4) {
+          ((uint32_t*)src)[slot] = (uint32_t)s;
+          ((uint32_t*)dst)[slot] = (uint32_t)d;
+        } else {
+          ((uint64_t*)src)[slot] = s;
+          ((uint64_t*)dst)[slot] = d;
+        }
+      }
+    }
+  }
+  (void)m;
+  return ORC_OK;
+}
+
 orc_table* orc_table_new(void) { return (orc_table*)calloc(1, sizeof(orc_table)); }
 void orc_table_delete(orc_table* t) { orc_free_table(t); free(t); }
 
