@@ -340,6 +340,22 @@ def main():
     out["undirected_scrambled_kernel_ms"] = ea.elapsed_time(eb_)
     out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
     t_epi.close()
+    # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
+    # tile rows [0, 64) per call, four calls; counting on the host included
+    t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    n_part = 0
+    for r0 in range(0, 256, 64):
+        cnt = R.rmat_partition_counts(t_part, w["seed"], m, 8, r0, r0 + 64)
+        n = int(cnt.sum())
+        R.rmat_generate_partition(t_part, w["seed"], m, 8, r0, r0 + 64, src, dst, n)
+        n_part += n
+    part_s = time.perf_counter() - p0
+    assert n_part == m
+    out["partitioned_edges_per_s"] = m / part_s
+    out["partitioned_config"] = {"tile_bits": 8, "row_ranges": 4}
+    t_part.close()
     del src, dst
     torch.cuda.empty_cache()
     if not args.no_batch:

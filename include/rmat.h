@@ -184,6 +184,35 @@ int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed,
                                uint64_t edge_begin, uint64_t m, int hist_bits,
                                void* d_hist, void* d_xor, void* stream);
 
+/*
+ * Partitioned, communication-free generation (Sec. 5): the adjacency matrix
+ * is cut into 2^t x 2^t tiles (t = tile_bits, 1 <= t <= min(k - 1, 15)); the
+ * m edges (m <= 2^53) are divided over the tiles top-down through the
+ * quadrant tree, and a call only visits the subtrees that meet tile rows
+ * [row_begin, row_end), so disjoint row ranges can be generated by separate
+ * calls (or processes, or GPUs) without communication and together hold
+ * exactly m edges.  Each node splits its count n into the four quadrants by
+ * n_a = Bin(n, a), n_b = Bin(n - n_a, b / (b+c+d)), n_c = Bin(n - n_a - n_b,
+ * c / (c+d)), n_d = the rest (inversion for n min(p, 1-p) < 30, else BTPE
+ * [Kachitvichyanukul & Schmeiser 1988]; node (level l, row prefix R, column
+ * prefix C) draws 53-bit uniforms from Philox4x32-10 with counter (R, C, i,
+ * 2^31 + l)).  Edge j of tile (R, C) samples the remaining k - t letters from
+ * the table with counter (j_lo, j_hi, block, 1 + R 2^t + C) and has
+ * src = R 2^(k-t) + row, dst = C 2^(k-t) + col.  (A different stream from
+ * rmat_generate: same law, different edges.)
+ *
+ * rmat_partition_counts writes (row_end - row_begin) x 2^t uint64 counts,
+ * row-major, to host memory.  rmat_generate_partition writes the edges of
+ * those tiles back to back in the same order (tile by tile, j ascending) to
+ * out_src / out_dst, which must hold exactly n_out = sum of the counts ids;
+ * it is synchronous.  At most 2^18 tiles per call.  Errors: RMAT_EINVAL
+ * (arguments, n_out not equal to the edge count), RMAT_ENOMEM, RMAT_EDEVICE.
+ */
+int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                          uint32_t row_end, uint64_t* counts);
+int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                            uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent instances (each its own a..d, k, table, seed,
  * edge range and outputs) built and generated together.  The method is the

@@ -22,7 +22,14 @@ struct rmat_table {
   rmat::TableView v;
   void* d_reduce = nullptr;    // reduction workspace: 16-bit bins, then per-workgroup partial counts
   uint64_t reduce_edges = 0;   // bins it holds
+  double q[4];                 // a, b, c, d as given
 };
+
+namespace rmat {
+const rmat_info* table_info_of(const rmat_table* t) { return &t->info; }
+const TableView* table_view_of(const rmat_table* t) { return &t->v; }
+const double* table_params_of(const rmat_table* t) { return t->q; }
+}  // namespace rmat
 
 namespace {
 
@@ -299,6 +306,7 @@ int rmat_build_table(double a, double b, double c, double d, int k, uint64_t tab
   }
 
   rmat::fill_info(&t->info, k, path_mode, table_bound, S, stats, tb);
+  std::memcpy(t->q, q, sizeof(t->q));
   *out = t;
   return RMAT_OK;
 }

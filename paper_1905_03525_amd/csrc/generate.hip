@@ -50,15 +50,15 @@ __device__ __forceinline__ void philox10(uint32_t& x0, uint32_t& x1, uint32_t& x
   }
 }
 
-// The first counter block of an edge, (e_lo, e_hi, 0, 0) with e_hi the same
-// across the wave: rounds 1 and 2 are specialised (a zero word's product is
+// The first counter block of an edge, (e_lo, e_hi, 0, ctr3) with e_hi and
+// ctr3 the same across the wave: rounds 1 and 2 are specialised (a zero word's product is
 // zero; what depends only on e_hi and the key stays on the scalar unit); the
 // output equals philox10 on that counter.
-__device__ __forceinline__ void philox10_first(uint32_t e_lo, uint32_t e_hi, uint32_t k0, uint32_t k1, uint32_t& x0,
-                                               uint32_t& x1, uint32_t& x2, uint32_t& x3) {
+__device__ __forceinline__ void philox10_first(uint32_t e_lo, uint32_t e_hi, uint32_t ctr3, uint32_t k0, uint32_t k1,
+                                               uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3) {
   const uint64_t p0 = static_cast<uint64_t>(e_lo) * kPhiloxM0;
   const uint32_t a0 = e_hi ^ k0;  // hi(0 * M1) ^ e_hi ^ k0
-  const uint32_t a2 = static_cast<uint32_t>(p0 >> 32) ^ k1;
+  const uint32_t a2 = static_cast<uint32_t>(p0 >> 32) ^ (ctr3 ^ k1);
   const uint32_t a3 = static_cast<uint32_t>(p0);  // and a1 = lo(0 * M1) = 0
   k0 += kPhiloxW0;
   k1 += kPhiloxW1;
@@ -255,7 +255,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       acc.clear();
       uint32_t filled = 0;
       uint32_t x0, x1, x2, x3;
-      philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.key0, I.key1, x0, x1,
+      philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1, x0, x1,
                      x2, x3);
       sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
       res[j * 64 + lane] = acc.pack();
@@ -292,7 +292,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         const uint64_t e = ((I.first_block + t0 + (idx >> 6) * stride) << 6) + (idx & 63u);
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
         for (uint32_t jj = 1; filled < I.k; ++jj) {
-          uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = 0;
+          uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
           sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
         }
@@ -313,7 +313,8 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
         } else {
           const uint64_t slot = e - I.edge_begin;
-          Id s = static_cast<Id>(acc.src(I.k)), d = static_cast<Id>(acc.dst(I.k));
+          Id s = static_cast<Id>(acc.src(I.k)) | static_cast<Id>(I.src_prefix);
+          Id d = static_cast<Id>(acc.dst(I.k)) | static_cast<Id>(I.dst_prefix);
           if (I.epi != 0) {  // uniform
             if (I.epi & kEpiUndirected) {
               const Id lo = s < d ? s : d;
@@ -561,6 +562,8 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.I.out_src = a.out_src;
   P.I.out_dst = a.out_dst;
   P.I.digest = nullptr;
+  P.I.ctr3 = 0;
+  P.I.src_prefix = P.I.dst_prefix = 0;
   P.I.epi = 0;
   if (!kReduce && a.epi) {
     P.I.epi = a.epi;

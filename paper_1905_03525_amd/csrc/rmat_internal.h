@@ -96,6 +96,8 @@ struct GenInst {
   unsigned long long* digest;
   // epilogue applied to each edge before it is stored (Sec. 5): bit 0 mirrors
   // an edge with src > dst, bit 1 relabels both ids by the scramble
+  uint32_t ctr3;                  // fourth Philox counter word: 0, or 1 + tile id (partitioned generation)
+  uint64_t src_prefix, dst_prefix;  // OR-ed into the ids (a tile's row and column offsets)
   uint32_t epi;
   uint32_t scr_shift;             // ceil(k / 2)
   uint64_t scr_mask;              // 2^k - 1

@@ -29,7 +29,7 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
 EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
             "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
-            "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
+            "rmat_partition_counts", "rmat_generate_partition", "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
             "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
             "rmat_server_step", "rmat_server_drain", "rmat_server_poll", "rmat_server_release",
             "rmat_server_run_trace", "rmat_server_get_stats", "rmat_server_clock", "rmat_server_free",
@@ -126,6 +126,8 @@ def load() -> ctypes.CDLL:
     L.rmat_generate_async.argtypes = [vp, u64, u64, u64, vp, vp, vp]
     L.rmat_generate_reduce_async.argtypes = [vp, u64, u64, u64, c_int, vp, vp, vp]
     L.rmat_generate_ex_async.argtypes = [vp, u64, u64, u64, c_int, u64, vp, vp, vp]
+    L.rmat_partition_counts.argtypes = [vp, u64, u64, c_int, ctypes.c_uint32, ctypes.c_uint32, vp]
+    L.rmat_generate_partition.argtypes = [vp, u64, u64, c_int, ctypes.c_uint32, ctypes.c_uint32, vp, vp, u64]
     L.rmat_batch_create.argtypes = [ctypes.POINTER(rmat_instance), c_int, ctypes.c_uint32, ctypes.POINTER(vp)]
     L.rmat_batch_enqueue.argtypes = [vp, vp]
     L.rmat_batch_launch_graph.argtypes = [vp, vp]
@@ -249,6 +251,38 @@ def rmat_generate_ex_async(t: Table, seed: int, edge_begin: int, m: int, flags: 
                            out_dst, stream=None):
     _check(load().rmat_generate_ex_async(t.handle, seed, edge_begin, m, flags, scramble_key, _ptr(out_src),
                                          _ptr(out_dst), _stream(stream)), "rmat_generate_ex_async")
+
+
+def rmat_partition_counts(t: Table, seed: int, m: int, tile_bits: int, row_begin: int = 0,
+                          row_end: int | None = None) -> np.ndarray:
+    """Edge counts of the tiles in tile rows [row_begin, row_end), shape (rows, 2^tile_bits)."""
+    if row_end is None:
+        row_end = 1 << tile_bits
+    out = np.zeros((row_end - row_begin, 1 << tile_bits), np.uint64)
+    _check(load().rmat_partition_counts(t.handle, seed, m, tile_bits, row_begin, row_end,
+                                        out.ctypes.data_as(ctypes.c_void_p)), "rmat_partition_counts")
+    return out
+
+
+def rmat_generate_partition(t: Table, seed: int, m: int, tile_bits: int, row_begin: int, row_end: int, out_src,
+                            out_dst, n_out: int):
+    _check(load().rmat_generate_partition(t.handle, seed, m, tile_bits, row_begin, row_end, _ptr(out_src),
+                                          _ptr(out_dst), n_out), "rmat_generate_partition")
+
+
+def generate_partition(t: Table, seed: int, m: int, tile_bits: int, row_begin: int = 0, row_end: int | None = None,
+                       device="cuda"):
+    """(counts, src, dst) of the tiles in tile rows [row_begin, row_end); the
+    outputs are allocated on the device."""
+    import torch
+    counts = rmat_partition_counts(t, seed, m, tile_bits, row_begin, row_end)
+    n = int(counts.sum())
+    k = rmat_table_info(t)["k"]
+    src = torch.empty(max(n, 1), dtype=id_dtype(k), device=device)
+    dst = torch.empty(max(n, 1), dtype=id_dtype(k), device=device)
+    rmat_generate_partition(t, seed, m, tile_bits, row_begin, row_end if row_end is not None else 1 << tile_bits,
+                            src, dst, n)
+    return counts, src[:n], dst[:n]
 
 
 def rmat_generate_reduce_async(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int, d_hist, d_xor,

@@ -74,6 +74,10 @@ hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t) {
   return hipMemcpy(d, s, n, k);
 }
+hipError_t hipMemset(void* d, int v, size_t n) {
+  std::memset(d, v, n);
+  return hipSuccess;
+}
 hipError_t hipGetDevice(int* d) {
   *d = 0;
   return hipSuccess;

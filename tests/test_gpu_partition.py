@@ -1,0 +1,81 @@
+"""Partitioned generation (Sec. 5) through the C ABI against the oracle:
+tile counts and every edge of every tile, bit-exact; disjoint row ranges
+generated separately add up to the whole graph."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+G500 = (0.57, 0.19, 0.19, 0.05)
+CFG3 = (0.45, 0.22, 0.22, 0.11)
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_03525_amd as R
+    R.load()
+    return R
+
+
+CASES = [
+    # q, k, bound, mode, seed, m, tile_bits, rows
+    (G500, 12, 256, oracle.FIXED, 3, 200_000, 3, None),
+    (G500, 26, 4096, oracle.VARIABLE, 7, 1 << 22, 6, (5, 9)),
+    (CFG3, 34, 1 << 16, oracle.VARIABLE, 3, 1 << 21, 4, None),          # 64-bit ids, L2 table
+    (G500, 40, 8192, oracle.VARIABLE, 9, 300_001, 10, (1000, 1024)),    # 64-bit ids, many small tiles
+    ((0.25, 0.25, 0.25, 0.25), 16, 1000, oracle.VARIABLE, 1, 100_000, 8, (0, 3)),
+    (G500, 2, 100, oracle.VARIABLE, 4, 10_000, 1, None),                 # one letter left per tile
+    (G500, 33, 4096, oracle.VARIABLE, 2, 70_000, 1, (1, 2)),
+]
+
+
+@pytest.mark.parametrize("q,k,bound,mode,seed,m,tb,rows", CASES)
+def test_partition_parity(R, q, k, bound, mode, seed, m, tb, rows):
+    r0, r1 = rows if rows else (0, 1 << tb)
+    t = R.rmat_build_table(*q, k, bound, mode)
+    counts, src, dst = R.generate_partition(t, seed, m, tb, r0, r1)
+    o = oracle.build_table(*q, k, bound, mode)
+    oc, os_, od = oracle.generate_partition(o, seed, m, tb, r0, r1)
+    assert np.array_equal(counts, oc)
+    gs, gd = R.to_numpy_ids(src, k), R.to_numpy_ids(dst, k)
+    bad = np.nonzero((gs != os_) | (gd != od))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+    if rows is None:
+        assert int(counts.sum()) == m
+    t.close()
+
+
+def test_row_ranges_add_up_to_the_graph(R):
+    """Disjoint row ranges, generated independently, concatenate to the full
+    partitioned graph (no communication between the ranges)."""
+    import torch
+    k, tb, m = 20, 5, 1 << 20
+    t = R.rmat_build_table(*G500, k, 4096, R.RMAT_VARIABLE)
+    full_c, full_s, full_d = R.generate_partition(t, 13, m, tb)
+    parts = [R.generate_partition(t, 13, m, tb, a, b) for a, b in ((0, 7), (7, 8), (8, 32))]
+    assert np.array_equal(np.concatenate([p[0] for p in parts]), full_c)
+    assert torch.equal(torch.cat([p[1] for p in parts]), full_s)
+    assert torch.equal(torch.cat([p[2] for p in parts]), full_d)
+    assert int(full_c.sum()) == m
+    t.close()
+
+
+def test_partition_errors(R):
+    import torch
+    t = R.rmat_build_table(*G500, 16, 256, R.RMAT_VARIABLE)
+    x = torch.empty(16, dtype=torch.int32, device="cuda")
+    for args in ((100, 0, 0, 1), (100, 16, 0, 1), (100, 3, 4, 4), (100, 3, 0, 9), (2 ** 53 + 1, 3, 0, 1)):
+        with pytest.raises(R.RmatError) as ei:
+            R.rmat_partition_counts(t, 1, *args)
+        assert ei.value.status == R.RMAT_EINVAL
+    with pytest.raises(R.RmatError) as ei:      # output size must equal the tiles' edge count
+        R.rmat_generate_partition(t, 1, 100, 2, 0, 4, x, x, 16)
+    assert ei.value.status == R.RMAT_EINVAL
+    t.close()

@@ -1,0 +1,67 @@
+"""The library's host-side tile counting (partitioned generation, Sec. 5)
+compiled with g++ against the fake device of tests/hostsim and compared,
+count for count, with the oracle: both take every integer decision of the
+binomial draws from the same sequence of floating-point operations."""
+from __future__ import annotations
+
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIM = os.path.join(ROOT, "tests", "hostsim")
+CSRC = os.path.join(ROOT, "paper_1905_03525_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("partsim") / "libpartsim.so")
+    cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
+           "-I", SIM, "-I", os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(CSRC, "api.cpp"),
+           os.path.join(CSRC, "partition.cpp"), os.path.join(SIM, "fake_device.cpp"), "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    L = ctypes.CDLL(out)
+    vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+    L.rmat_build_table.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, u64, ctypes.c_int, ctypes.POINTER(vp)]
+    L.rmat_partition_counts.argtypes = [vp, u64, u64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, vp]
+    L.rmat_free_table.argtypes = [vp]
+    L.rmat_last_error.restype = ctypes.c_char_p
+    return L
+
+
+CASES = [
+    # q, k, bound, seed, m, tile_bits, rows
+    ((0.57, 0.19, 0.19, 0.05), 12, 256, 3, 100_000, 3, None),
+    ((0.57, 0.19, 0.19, 0.05), 26, 4096, 7, 1 << 30, 6, None),
+    ((0.45, 0.22, 0.22, 0.11), 34, 1 << 16, 3, 1 << 34, 8, (17, 90)),
+    ((0.25, 0.25, 0.25, 0.25), 40, 1000, 11, 2 ** 53, 9, (500, 512)),
+    ((0.9, 0.025, 0.025, 0.05), 30, 8192, 12, 10 ** 12, 7, (0, 3)),
+    ((1.0, 0.0, 0.0, 0.0), 20, 300, 1, 123_456, 4, None),
+    ((0.5, 0.5, 0.0, 0.0), 20, 300, 2, 7, 5, None),
+    ((0.6, 0.1, 0.3, 0.0), 16, 64, 5, 0, 2, None),
+    ((0.57, 0.19, 0.19, 0.05), 64, 4096, 2 ** 64 - 1, 10 ** 15, 15, (32767, 32768)),
+]
+
+
+@pytest.mark.parametrize("q,k,bound,seed,m,tb,rows", CASES)
+def test_library_counts_equal_oracle(lib, q, k, bound, seed, m, tb, rows):
+    r0, r1 = rows if rows else (0, 1 << tb)
+    h = ctypes.c_void_p()
+    assert lib.rmat_build_table(*q, k, bound, 1, ctypes.byref(h)) == 0, lib.rmat_last_error()
+    got = np.zeros((r1 - r0, 1 << tb), np.uint64)
+    assert lib.rmat_partition_counts(h, seed, m, tb, r0, r1, got.ctypes.data_as(ctypes.c_void_p)) == 0, \
+        lib.rmat_last_error()
+    lib.rmat_free_table(h)
+    t = oracle.build_table(*q, k, bound, oracle.VARIABLE)
+    want = oracle.partition_counts(t, seed, m, tb, r0, r1)
+    assert np.array_equal(got, want)
+    if rows is None:
+        assert int(got.sum()) == m
