@@ -82,6 +82,9 @@ def lib():
         L.orc_generate_ex.restype = ctypes.c_int
         L.orc_scramble.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
         L.orc_scramble.restype = ctypes.c_uint64
+        L.orc_kron_build_table.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+        L.orc_kron_build_table.restype = ctypes.c_int
         L.orc_binomial.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
                                    ctypes.c_double]
         L.orc_binomial.restype = ctypes.c_uint64
@@ -163,6 +166,26 @@ def build_table(a, b, c, d, k, bound, mode) -> Table:
     if rc != 0:
         L.orc_table_delete(h)
         raise OracleError(rc, "build_table")
+    return _wrap_table(h)
+
+
+def kron_build_table(P, K: int, k: int, bound: int, mode: int) -> Table:
+    """Table of a K x K initiator P (K^2 probabilities, row-major; cell
+    (i, j) is letter K i + j); ids are k-digit base-K numbers (reading R21)."""
+    L = lib()
+    Pa = (ctypes.c_double * len(P))(*[float(x) for x in P])
+    if len(P) != K * K:
+        raise OracleError(-1, "kron_build_table: P must have K^2 entries")
+    h = L.orc_table_new()
+    rc = L.orc_kron_build_table(Pa, int(K), int(k), int(bound), int(mode), h)
+    if rc != 0:
+        L.orc_table_delete(h)
+        raise OracleError(rc, "kron_build_table")
+    return _wrap_table(h)
+
+
+def _wrap_table(h) -> Table:
+    L = lib()
     info = np.zeros(7, dtype=np.uint64)
     L.orc_table_info(h, _ptr(info))
     nb = int(info[5])

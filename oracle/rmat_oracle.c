@@ -187,6 +187,8 @@ typedef struct {
   int k, mode, cap, bucket_bits;
   uint64_t bound, n_items, n_buckets, capacity; /* capacity = C = 2^(32-b) */
   double q[4];
+  int K;          /* initiator size: 2 for R-MAT, K x K for a Kronecker table (R21) */
+  uint64_t powK[16];
   /* per item (n_buckets entries; items >= n_items are padding) */
   uint8_t* len;
   uint64_t* code;
@@ -439,6 +441,7 @@ int orc_build_table(double a, double b, double c, double d, int k,
   out->k = k;
   out->mode = mode;
   out->bound = bound;
+  out->K = 2;
   memcpy(out->q, q, sizeof(q));
   if ((rc = enumerate_leaves(out, NULL)) != ORC_OK) { orc_free_table(out); return rc; }
   if ((rc = quantise(out)) != ORC_OK) { orc_free_table(out); return rc; }
@@ -478,8 +481,13 @@ static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t 
     uint32_t item = (f < t->thr[bucket]) ? bucket : t->alias[bucket];
     int L = t->len[item];
     int take = (L < k - filled) ? L : (k - filled);
-    row = (row << take) | (uint64_t)(t->row[item] >> (L - take));
-    col = (col << take) | (uint64_t)(t->col[item] >> (L - take));
+    if (t->K > 2) { /* base-K digits (R21): the leading `take` digits of the path */
+      row = row * t->powK[take] + (uint64_t)t->row[item] / t->powK[L - take];
+      col = col * t->powK[take] + (uint64_t)t->col[item] / t->powK[L - take];
+    } else {
+      row = (row << take) | (uint64_t)(t->row[item] >> (L - take));
+      col = (col << take) | (uint64_t)(t->col[item] >> (L - take));
+    }
     filled += take;
   }
   *src = row;
@@ -637,6 +645,7 @@ int orc_generate_ex(const orc_table* t, uint64_t seed, uint64_t edge_begin,
   if (width != 4 && width != 8) return ORC_EINVAL;
   if (width == 4 && t->k > 32) return ORC_EINVAL;
   if (flags & ~(ORC_UNDIRECTED | ORC_SCRAMBLE)) return ORC_EINVAL;
+  if ((flags & ORC_SCRAMBLE) && t->K > 2) return ORC_EINVAL; /* pi is defined on [0, 2^k) */
   if (m == 0) return ORC_OK;
   work_t proto;
   memset(&proto, 0, sizeof(proto));
@@ -664,7 +673,7 @@ int orc_generate_reduce(const orc_table* t, uint64_t seed, uint64_t edge_begin,
                         uint64_t m, int hist_bits, uint64_t* hist,
                         uint64_t* xor_out, int threads) {
   if (m > 0 && edge_begin + (m - 1) < edge_begin) return ORC_ERANGE;
-  if (hist_bits < 0 || hist_bits > t->k || hist_bits > 24) return ORC_EINVAL;
+  if (hist_bits < 0 || hist_bits > t->k || hist_bits > 24 || t->K > 2) return ORC_EINVAL;
   uint64_t nbins = 1ull << hist_bits;
   memset(hist, 0, nbins * sizeof(uint64_t));
   *xor_out = 0;
@@ -872,7 +881,7 @@ static void partition_rec(const double q[4], uint64_t seed, int t, int level, ui
  * (row_end - row_begin) x 2^t entries.  1 <= t <= min(k - 1, 15). */
 int orc_partition_counts(const orc_table* t, uint64_t seed, uint64_t m, int tbits,
                          uint32_t row_begin, uint32_t row_end, uint64_t* counts) {
-  if (tbits < 1 || tbits > 15 || tbits >= t->k) return ORC_EINVAL;
+  if (tbits < 1 || tbits > 15 || tbits >= t->k || t->K > 2) return ORC_EINVAL;
   if (row_begin >= row_end || row_end > (1u << tbits)) return ORC_EINVAL;
   if (m > (1ull << 53)) return ORC_EINVAL;
   memset(counts, 0, sizeof(uint64_t) * ((uint64_t)(row_end - row_begin) << tbits));
@@ -910,6 +919,225 @@ int orc_generate_partition(const orc_table* t, uint64_t seed, uint64_t m, int tb
     }
   }
   (void)m;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * K x K stochastic Kronecker initiators (Sec. 5, reading R21): the same
+ * table over the K^2 cells of the initiator.  Letter x = K i + j is cell
+ * (i, j): row digit i, column digit j; ids are base-K numbers of k digits.
+ * ---------------------------------------------------------------------- */
+#define KRON_MAX_LETTERS 256
+
+typedef struct {
+  double p;
+  uint64_t code; /* base-K^2 digits, root-most letter most significant */
+  int depth;
+  uint8_t counts[KRON_MAX_LETTERS];
+} knode_t;
+
+static int knode_before(const knode_t* u, const knode_t* v) {
+  if (u->p != v->p) return u->p > v->p;
+  if (u->depth != v->depth) return u->depth < v->depth;
+  return u->code < v->code;
+}
+
+typedef struct {
+  knode_t* a;
+  size_t n, cap;
+} kheap_t;
+
+static int kheap_push(kheap_t* h, const knode_t* v) {
+  if (h->n == h->cap) {
+    size_t nc = h->cap ? 2 * h->cap : 256;
+    knode_t* na = (knode_t*)realloc(h->a, nc * sizeof(knode_t));
+    if (!na) return ORC_ENOMEM;
+    h->a = na;
+    h->cap = nc;
+  }
+  size_t i = h->n++;
+  h->a[i] = *v;
+  while (i > 0) {
+    size_t parent = (i - 1) / 2;
+    if (!knode_before(&h->a[i], &h->a[parent])) break;
+    knode_t tmp = h->a[i]; h->a[i] = h->a[parent]; h->a[parent] = tmp;
+    i = parent;
+  }
+  return ORC_OK;
+}
+
+static void kheap_pop(kheap_t* h, knode_t* top) {
+  *top = h->a[0];
+  h->a[0] = h->a[--h->n];
+  size_t i = 0;
+  for (;;) {
+    size_t l = 2 * i + 1, r = l + 1, best = i;
+    if (l < h->n && knode_before(&h->a[l], &h->a[best])) best = l;
+    if (r < h->n && knode_before(&h->a[r], &h->a[best])) best = r;
+    if (best == i) break;
+    knode_t tmp = h->a[i]; h->a[i] = h->a[best]; h->a[best] = tmp;
+    i = best;
+  }
+}
+
+/* 1.0 times each letter's probability n_x times, letters in order x = 0, 1, ... */
+static double kron_product(const double* P, int letters, const uint8_t* counts) {
+  double p = 1.0;
+  for (int x = 0; x < letters; ++x)
+    for (int i = 0; i < counts[x]; ++i) p = p * P[x];
+  return p;
+}
+
+/* The largest L with K^L <= 2^15: a path's row (column) value fits 15 bits. */
+static int kron_cap(int K) {
+  int L = 0;
+  uint64_t v = 1;
+  while (v * (uint64_t)K <= 32768u) { v *= (uint64_t)K; ++L; }
+  return L;
+}
+
+int orc_kron_build_table(const double* P, int K, int k, uint64_t bound, int mode, orc_table* out) {
+  memset(out, 0, sizeof(*out));
+  if (K < 2 || K > 16) return ORC_EINVAL;
+  const int letters = K * K;
+  double s = 0.0;
+  for (int x = 0; x < letters; ++x) {
+    if (!(P[x] >= 0.0) || isnan(P[x]) || isinf(P[x])) return ORC_EINVAL;
+    s += P[x];
+  }
+  if (fabs(s - 1.0) > 1e-9) return ORC_EINVAL;
+  /* n = K^k node ids must fit 64 bits */
+  if (k < 1) return ORC_EINVAL;
+  {
+    unsigned __int128 n = 1;
+    for (int i = 0; i < k; ++i) { n *= (unsigned)K; if (n > ((unsigned __int128)1 << 64)) return ORC_EINVAL; }
+  }
+  if (bound > (1ull << 24)) return ORC_EINVAL;
+  if (mode == ORC_VARIABLE) {
+    if (bound < (uint64_t)letters + 1) return ORC_EINVAL;
+  } else if (mode == ORC_FIXED) {
+    if (bound < (uint64_t)letters) return ORC_EINVAL;
+  } else {
+    return ORC_EINVAL;
+  }
+  out->k = k;
+  out->mode = mode;
+  out->bound = bound;
+  out->K = K;
+  out->powK[0] = 1;
+  for (int i = 1; i < 16; ++i) out->powK[i] = out->powK[i - 1] * (uint64_t)K;
+  const int cap = kron_cap(K) < k ? kron_cap(K) : k;
+  out->cap = cap;
+  size_t n = 0;
+  knode_t* leaves = NULL;
+  if (mode == ORC_FIXED) {
+    int ell = 0;
+    uint64_t sz = 1;
+    while (sz * (uint64_t)letters <= bound) { sz *= (uint64_t)letters; ++ell; }
+    if (ell < 1 || ell > cap) { orc_free_table(out); return ORC_EINVAL; }
+    n = (size_t)sz;
+    leaves = (knode_t*)calloc(n, sizeof(knode_t));
+    if (!leaves) return ORC_ENOMEM;
+    for (size_t code = 0; code < n; ++code) {
+      knode_t* v = &leaves[code];
+      v->code = code;
+      v->depth = ell;
+      uint64_t c = code;
+      for (int pos = 0; pos < ell; ++pos) { v->counts[c % (uint64_t)letters]++; c /= (uint64_t)letters; }
+      v->p = kron_product(P, letters, v->counts);
+    }
+  } else {
+    kheap_t q = {0, 0, 0};
+    size_t n_final = 0, cap_final = 0;
+    knode_t* final_leaves = NULL;
+    knode_t root;
+    memset(&root, 0, sizeof(root));
+    root.p = 1.0;
+    if (kheap_push(&q, &root)) return ORC_ENOMEM;
+    while (q.n > 0 && (uint64_t)(q.n + n_final) + (uint64_t)(letters - 1) < bound) {
+      knode_t v;
+      kheap_pop(&q, &v);
+      for (int x = 0; x < letters; ++x) {
+        knode_t c = v;
+        c.code = v.code * (uint64_t)letters + (uint64_t)x;
+        c.depth = v.depth + 1;
+        c.counts[x]++;
+        c.p = kron_product(P, letters, c.counts);
+        if (c.depth < cap) {
+          if (kheap_push(&q, &c)) { free(q.a); free(final_leaves); return ORC_ENOMEM; }
+        } else {
+          if (n_final == cap_final) {
+            cap_final = cap_final ? 2 * cap_final : 256;
+            knode_t* nf = (knode_t*)realloc(final_leaves, cap_final * sizeof(knode_t));
+            if (!nf) { free(q.a); free(final_leaves); return ORC_ENOMEM; }
+            final_leaves = nf;
+          }
+          final_leaves[n_final++] = c;
+        }
+      }
+    }
+    n = q.n + n_final;
+    leaves = (knode_t*)malloc(n * sizeof(knode_t));
+    if (!leaves) { free(q.a); free(final_leaves); return ORC_ENOMEM; }
+    if (q.n) memcpy(leaves, q.a, q.n * sizeof(knode_t));
+    if (n_final) memcpy(leaves + q.n, final_leaves, n_final * sizeof(knode_t));
+    free(q.a);
+    free(final_leaves);
+  }
+  if (n > (1u << 25)) { free(leaves); return ORC_EINVAL; }
+  /* tree order: left-aligned codes, code * letters^(cap - depth) */
+  uint64_t* lac = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* key = (uint64_t*)malloc(n * sizeof(uint64_t));
+  if (!lac || !key) { free(lac); free(key); free(leaves); return ORC_ENOMEM; }
+  for (size_t i = 0; i < n; ++i) {
+    uint64_t v = leaves[i].code;
+    for (int d = leaves[i].depth; d < cap; ++d) v *= (uint64_t)letters;
+    lac[i] = v;
+  }
+  /* sort indices by lac (insertion into a key of lac rank: lac < letters^cap <= 2^30) */
+  for (size_t i = 0; i < n; ++i) key[i] = (lac[i] << 25) | (uint64_t)i;
+  qsort(key, n, sizeof(uint64_t), cmp_u64);
+  free(lac);
+  uint64_t nb = 1;
+  int b = 0;
+  while (nb < n) { nb <<= 1; ++b; }
+  out->n_items = n;
+  out->n_buckets = nb;
+  out->bucket_bits = b;
+  out->capacity = 1ull << (32 - b);
+  out->len = (uint8_t*)calloc(nb, 1);
+  out->code = (uint64_t*)calloc(nb, sizeof(uint64_t));
+  out->row = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  out->col = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  out->p = (double*)calloc(nb, sizeof(double));
+  out->w = (int64_t*)calloc(nb, sizeof(int64_t));
+  out->thr = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  out->alias = (uint32_t*)calloc(nb, sizeof(uint32_t));
+  if (!out->len || !out->code || !out->row || !out->col || !out->p || !out->w || !out->thr || !out->alias) {
+    free(key); free(leaves); orc_free_table(out);
+    return ORC_ENOMEM;
+  }
+  for (size_t j = 0; j < n; ++j) {
+    const knode_t* v = &leaves[key[j] & ((1ull << 25) - 1)];
+    out->len[j] = (uint8_t)v->depth;
+    out->code[j] = v->code;
+    out->p[j] = v->p;
+    /* row / column values: the path's digits, root-most most significant */
+    uint64_t r = 0, c = 0, digits[16];
+    uint64_t code = v->code;
+    for (int pos = 0; pos < v->depth; ++pos) { digits[pos] = code % (uint64_t)letters; code /= (uint64_t)letters; }
+    for (int pos = v->depth - 1; pos >= 0; --pos) {
+      r = r * (uint64_t)K + digits[pos] / (uint64_t)K;
+      c = c * (uint64_t)K + digits[pos] % (uint64_t)K;
+    }
+    out->row[j] = (uint32_t)r;
+    out->col[j] = (uint32_t)c;
+  }
+  free(key);
+  free(leaves);
+  int rc;
+  if ((rc = quantise(out)) != ORC_OK) { orc_free_table(out); return rc; }
+  if ((rc = build_alias(out)) != ORC_OK) { orc_free_table(out); return rc; }
   return ORC_OK;
 }
 
