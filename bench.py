@@ -135,7 +135,7 @@ def batched_vs_plain(R, reps: int = 3) -> dict:
             "bounds_histogram": {str(v): bounds.count(v) for v in sorted(set(bounds))}}
 
 
-def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0) -> dict:
+def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0, plain: bool = True) -> dict:
     """The served workload: a Poisson stream of R-MAT requests (k per
     `reading`, edge factor 8 or 16, Dirichlet(4,2,2,1) parameters, table bound
     4096) at `rate` requests/s; the first `window_s` seconds of arrivals go
@@ -151,13 +151,23 @@ def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0
     total = sum(p["m"] for p in reqs)
     with R.rmat_server_create() as s:
         t0 = time.perf_counter()
-        out = R.rmat_server_run_trace(s, reqs, [p["t_arrival"] for p in reqs])
+        report = (lambda done, total: print(f"served {done} of {total} requests", file=sys.stderr, flush=True)) \
+            if window_s > 10 else None
+        out = R.rmat_server_run_trace(s, reqs, [p["t_arrival"] for p in reqs], report)
         wall = time.perf_counter() - t0
         st = R.rmat_server_get_stats(s)
     assert all(c["status"] == 0 for c in out)
     lat = sorted(c["t_done"] - c["t_submit"] for c in out)
     wait = sorted(c["t_admit"] - c["t_submit"] for c in out)
     pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))] * 1e3  # noqa: E731
+    res = {"workload": f"served_poisson{rate:g}_k12-28{reading}_ef8-16_var4096", "reading": reading,
+           "window_s": window_s, "requests": len(reqs), "total_edges": total, "wall_s": wall,
+           "edges_per_s": total / wall, "hbm_write_gbs": 8 * total / wall / 1e9,
+           "p50_latency_ms": pct(lat, 0.5), "p99_latency_ms": pct(lat, 0.99), "p50_wait_ms": pct(wait, 0.5),
+           "p99_wait_ms": pct(wait, 0.99), "table_hit_rate": st["table_hits"] / max(1, st["admitted"]),
+           "rounds": st["rounds"], "arena_peak_gb": st["arena_peak"] / 1e9}
+    if not plain:
+        return res
     # plain per-request launches of the same requests, back to back
     m_max = max(p["m"] for p in reqs)
     src = torch.empty(m_max, dtype=torch.int32, device="cuda")
@@ -165,21 +175,18 @@ def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for p in reqs:
+    for i, p in enumerate(reqs):
         t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
         R.rmat_generate_async(t, p["seed"], 0, p["m"], src, dst, stream)
         torch.cuda.synchronize()
         t.close()
-    plain = time.perf_counter() - t0
+        if window_s > 10 and i % 5000 == 4999:
+            print(f"plain {i + 1} of {len(reqs)} requests", file=sys.stderr, flush=True)
+    plain_s = time.perf_counter() - t0
     del src, dst
     torch.cuda.empty_cache()
-    return {"workload": f"served_poisson{rate:g}_k12-28{reading}_ef8-16_var4096", "reading": reading,
-            "window_s": window_s, "requests": len(reqs), "total_edges": total, "wall_s": wall,
-            "edges_per_s": total / wall, "hbm_write_gbs": 8 * total / wall / 1e9,
-            "p50_latency_ms": pct(lat, 0.5), "p99_latency_ms": pct(lat, 0.99), "p50_wait_ms": pct(wait, 0.5),
-            "p99_wait_ms": pct(wait, 0.99), "table_hit_rate": st["table_hits"] / max(1, st["admitted"]),
-            "rounds": st["rounds"], "arena_peak_gb": st["arena_peak"] / 1e9,
-            "plain_edges_per_s": total / plain, "served_over_plain": plain / wall}
+    res.update({"plain_edges_per_s": total / plain_s, "served_over_plain": plain_s / wall})
+    return res
 
 
 def k34_chunked(R) -> dict:
@@ -241,6 +248,7 @@ def main():
     ap.add_argument("--served-window", type=float, default=3.0,
                     help="seconds of the 2000 requests/s stream to serve (0: skip; the full stream is 60)")
     ap.add_argument("--served-reading", default="A", choices=["A", "B"])
+    ap.add_argument("--served-no-plain", action="store_true", help="skip the plain-launch comparison of the stream")
     ap.add_argument("--no-k34", action="store_true", help="skip the k=34 chunked instance")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -365,7 +373,7 @@ def main():
     if not args.no_k34:
         out["k34"] = k34_chunked(R)
     if args.served_window > 0:
-        out["served"] = served_vs_plain(R, args.served_window, args.served_reading)
+        out["served"] = served_vs_plain(R, args.served_window, args.served_reading, plain=not args.served_no_plain)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -73,6 +73,8 @@ typedef struct rmat_info {
   double expected_len;     /* sum_j w_j L_j / 2^32: letters per sample */
   uint64_t export_bytes;   /* bytes written by rmat_table_export */
   uint64_t device_bytes;   /* device memory held by the table */
+  uint32_t initiator_k;    /* 2 for R-MAT, K for a K x K Kronecker table */
+  uint32_t reserved;
 } rmat_info;
 
 /*
@@ -102,6 +104,27 @@ typedef struct rmat_info {
  */
 int rmat_build_table(double a, double b, double c, double d, int k,
                      uint64_t table_bound, int path_mode, rmat_table_t* out);
+
+/*
+ * Table of a K x K stochastic Kronecker initiator (Sec. 5 generalizations):
+ * P holds K^2 probabilities, row-major (cell (i, j) = letter K i + j: row
+ * digit i, column digit j), each >= 0, summing to 1 within 1e-9; 2 <= K <= 16;
+ * the graph has K^k nodes (K^k <= 2^64) with base-K ids of k digits, the
+ * root-most digit most significant.  The table is that of rmat_build_table
+ * over the K^2 letters: VARIABLE expands the most probable path while
+ * |A| + K^2 - 1 < table_bound (same tie order: probability descending, depth
+ * ascending, code ascending, probability = 1.0 times P_x n_x times in letter
+ * order), FIXED takes all paths of length floor(log_{K^2} table_bound); no
+ * path is longer than min(k, the largest L with K^L <= 2^15).  A sample
+ * appends base-K digits: row = row K^take + floor(rowval / K^(L - take)).
+ * K = 2 is rmat_build_table(P[0], P[1], P[2], P[3], ...).  For K > 2 the
+ * table is built on the host and copied to the device; rmat_generate and
+ * rmat_generate_async work on it (ids uint32 if K^k <= 2^32, else uint64),
+ * rmat_table_export exports it (row / col arrays hold digit values), and the
+ * epilogue flags, the reduction, partitioned generation and batches reject
+ * it (RMAT_EINVAL).  Errors: RMAT_EINVAL, RMAT_ENOMEM, RMAT_EDEVICE.
+ */
+int rmat_kron_build_table(const double* P, int K, int k, uint64_t table_bound, int path_mode, rmat_table_t* out);
 
 /* Releases the table's device memory.  NULL is accepted.  The caller must
  * make sure no generation that uses it is still running. */

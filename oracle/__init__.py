@@ -147,6 +147,7 @@ class Table:
     thr: np.ndarray      # uint32, per bucket
     alias: np.ndarray    # uint32, per bucket
     handle: "ctypes.c_void_p" = None
+    K: int = 2           # initiator size (2: R-MAT; K > 2: base-K digits, K^2-ary codes)
 
     def __del__(self):
         if self.handle is not None and _lib is not None:
@@ -186,7 +187,7 @@ def kron_build_table(P, K: int, k: int, bound: int, mode: int) -> Table:
 
 def _wrap_table(h) -> Table:
     L = lib()
-    info = np.zeros(7, dtype=np.uint64)
+    info = np.zeros(8, dtype=np.uint64)
     L.orc_table_info(h, _ptr(info))
     nb = int(info[5])
     arrs = dict(
@@ -195,7 +196,7 @@ def _wrap_table(h) -> Table:
         thr=np.zeros(nb, np.uint32), alias=np.zeros(nb, np.uint32))
     L.orc_table_arrays(h, *[_ptr(arrs[n]) for n in ("length", "code", "row", "col", "p", "w", "thr", "alias")])
     return Table(k=int(info[0]), mode=int(info[1]), cap=int(info[2]), bucket_bits=int(info[3]),
-                 n_items=int(info[4]), n_buckets=nb, capacity=int(info[6]), handle=h, **arrs)
+                 n_items=int(info[4]), n_buckets=nb, capacity=int(info[6]), handle=h, K=int(info[7]), **arrs)
 
 
 UNDIRECTED = 1
@@ -208,7 +209,7 @@ def generate(t: Table, seed: int, edge_begin: int, m: int, threads: int = 1,
     flags: UNDIRECTED (mirror to the upper triangle) and/or SCRAMBLE (relabel
     ids by the keyed bijection), Sec. 5 generalizations, reading R19."""
     if width is None:
-        width = 4 if t.k <= 32 else 8
+        width = 4 if t.K ** t.k <= 2 ** 32 else 8
     dt = np.uint32 if width == 4 else np.uint64
     src = np.zeros(m, dt)
     dst = np.zeros(m, dt)

@@ -501,6 +501,8 @@ static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t 
 #define ORC_UNDIRECTED 1
 #define ORC_SCRAMBLE 2
 
+static int ids_fit_32(const orc_table* t);
+
 /* SplitMix64: one step of the generator (state advanced in place). */
 static uint64_t splitmix64_next(uint64_t* state) {
   uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
@@ -643,7 +645,7 @@ int orc_generate_ex(const orc_table* t, uint64_t seed, uint64_t edge_begin,
   /* the last edge of the stream is 2^64 - 1 */
   if (m > 0 && edge_begin + (m - 1) < edge_begin) return ORC_ERANGE;
   if (width != 4 && width != 8) return ORC_EINVAL;
-  if (width == 4 && t->k > 32) return ORC_EINVAL;
+  if (width == 4 && !ids_fit_32(t)) return ORC_EINVAL;
   if (flags & ~(ORC_UNDIRECTED | ORC_SCRAMBLE)) return ORC_EINVAL;
   if ((flags & ORC_SCRAMBLE) && t->K > 2) return ORC_EINVAL; /* pi is defined on [0, 2^k) */
   if (m == 0) return ORC_OK;
@@ -1144,11 +1146,23 @@ int orc_kron_build_table(const double* P, int K, int k, uint64_t bound, int mode
 orc_table* orc_table_new(void) { return (orc_table*)calloc(1, sizeof(orc_table)); }
 void orc_table_delete(orc_table* t) { orc_free_table(t); free(t); }
 
-/* info[0..6] = k, mode, cap, bucket_bits, n_items, n_buckets, capacity */
-void orc_table_info(const orc_table* t, uint64_t info[7]) {
+/* info[0..7] = k, mode, cap, bucket_bits, n_items, n_buckets, capacity, K */
+void orc_table_info(const orc_table* t, uint64_t info[8]) {
   info[0] = (uint64_t)t->k; info[1] = (uint64_t)t->mode;
   info[2] = (uint64_t)t->cap; info[3] = (uint64_t)t->bucket_bits;
   info[4] = t->n_items; info[5] = t->n_buckets; info[6] = t->capacity;
+  info[7] = (uint64_t)t->K;
+}
+
+/* Do the ids of this table fit 32 bits (2^k, or K^k, at most 2^32)? */
+static int ids_fit_32(const orc_table* t) {
+  if (t->K <= 2) return t->k <= 32;
+  uint64_t n = 1;
+  for (int i = 0; i < t->k; ++i) {
+    n *= (uint64_t)t->K;
+    if (n > (1ull << 32)) return 0;
+  }
+  return 1;
 }
 
 /* Copies the per-item and per-bucket arrays (n_buckets entries each). */

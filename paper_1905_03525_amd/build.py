@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librmat.so")
 
-SOURCES = ["table_build.hip", "generate.hip", "microbench.hip", "api.cpp", "batch.cpp", "serve.cpp", "partition.cpp"]
+SOURCES = ["table_build.hip", "generate.hip", "microbench.hip", "api.cpp", "batch.cpp", "serve.cpp", "partition.cpp", "kron.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -206,6 +206,34 @@ void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const S
   I->expected_len = static_cast<double>(stats.sum_wl) / 4294967296.0;
   I->export_bytes = 36 * S.n_buckets;
   I->device_bytes = device_bytes;
+  I->initiator_k = 2;
+  I->reserved = 0;
+}
+
+int adopt_table(const rmat_info& info, const double q[4], int kron_K, const TableView& view, void* d_mem,
+                rmat_table_t* out) {
+  rmat_table* t = new (std::nothrow) rmat_table();
+  if (!t) return set_error(RMAT_ENOMEM, "host allocation of the table handle failed");
+  if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
+  t->info = info;
+  t->info.initiator_k = static_cast<uint32_t>(kron_K);
+  t->v = view;
+  t->d_mem = d_mem;
+  std::memcpy(t->q, q, sizeof(t->q));
+  if (kron_K > 2) {
+    t->info.id_bytes = 4;  // K^k <= 2^32 ?
+    uint64_t n = 1;
+    for (int i = 0; i < info.k; ++i) {
+      if (n > (~0ull) / static_cast<uint64_t>(kron_K)) {
+        t->info.id_bytes = 8;
+        break;
+      }
+      n *= static_cast<uint64_t>(kron_K);
+      if (n > (1ull << 32)) t->info.id_bytes = 8;
+    }
+  }
+  *out = t;
+  return RMAT_OK;
 }
 
 // SplitMix64 [Steele, Lea, Flood, OOPSLA'14]: state advanced by the golden
@@ -338,6 +366,8 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
                            void* out_dst, void* stream, bool reduce, int hist_bits, void* d_hist, void* d_xor,
                            int flags = 0, uint64_t scramble_key = 0) {
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (t->info.initiator_k > 2 && (reduce || flags))
+    return set_error(RMAT_EINVAL, "a K x K Kronecker table supports plain generation only");
   if (flags & ~(RMAT_UNDIRECTED | RMAT_SCRAMBLE)) return set_error(RMAT_EINVAL, "unknown flags 0x%x", flags);
   if (m == 0) return RMAT_OK;
   if (edge_begin + (m - 1) < edge_begin) return set_error(RMAT_ERANGE, "edge_begin + m exceeds 2^64");
@@ -384,6 +414,8 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
   a.m = m;
   a.epi = static_cast<uint32_t>(flags);
   a.scramble_key = scramble_key;
+  a.kron_k = t->info.initiator_k;
+  a.id_bytes = t->info.id_bytes;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = reduce ? rmat::launch_generate_reduce(a, s) : rmat::launch_generate(a, s);
   if (e != hipSuccess) return rmat::hip_fail(e, reduce ? "generate_reduce launch" : "generate launch");

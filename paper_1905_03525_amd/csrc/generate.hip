@@ -545,9 +545,93 @@ uint32_t hist_groups(uint64_t n) {
   return static_cast<uint32_t>(want < 1 ? 1 : (want > cus ? cus : want));
 }
 
+// K x K Kronecker tables (K > 2): one lane per edge, base-K digits,
+// row = row K^take + floor(rowval / K^(L - take)).  A secondary path: the
+// table is staged in LDS when it fits; no tile compaction.
+struct KronLaunch {
+  const BucketRecord* records;
+  uint32_t n_buckets, shift, k, key0, key1;
+  uint64_t edge_begin, m;
+  void* out_src;
+  void* out_dst;
+  uint64_t pow[16];  // K^0 .. K^15
+};
+
+template <typename Id, bool kLds>
+__global__ __launch_bounds__(kGenThreads) void kron_kernel(KronLaunch P) {
+  extern __shared__ __align__(16) unsigned char s_mem[];
+  __shared__ uint64_t s_pow[16];
+  if (threadIdx.x < 16) s_pow[threadIdx.x] = P.pow[threadIdx.x];
+  const BucketRecord* tab = P.records;
+  if (kLds) {
+    stage_table(P.records, P.n_buckets, s_mem);
+    tab = reinterpret_cast<const BucketRecord*>(s_mem);
+  }
+  __syncthreads();
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P.m; i += stride) {
+    const uint64_t e = P.edge_begin + i;
+    uint64_t row = 0, col = 0;
+    uint32_t filled = 0;
+    for (uint32_t j = 0; filled < P.k; ++j) {
+      uint32_t x[4] = {static_cast<uint32_t>(e), static_cast<uint32_t>(e >> 32), j, 0u};
+      philox10(x[0], x[1], x[2], x[3], P.key0, P.key1);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        if (filled < P.k) {
+          const BucketRecord r = tab[x[w] >> P.shift];
+          const bool own = x[w] < r.thr_abs;
+          const uint32_t word = own ? r.self_word : r.alias_word;
+          const uint32_t L = own ? (r.lens & 0xFFFFu) : (r.lens >> 16);
+          const uint32_t take = L < P.k - filled ? L : P.k - filled;
+          uint32_t rv = word >> 16, cv = word & 0xFFFFu;
+          if (take < L) {
+            const uint32_t dv = static_cast<uint32_t>(s_pow[L - take]);
+            rv /= dv;
+            cv /= dv;
+          }
+          const uint64_t mul = s_pow[take];
+          row = row * mul + rv;
+          col = col * mul + cv;
+          filled += take;
+        }
+      }
+    }
+    static_cast<Id*>(P.out_src)[i] = static_cast<Id>(row);
+    static_cast<Id*>(P.out_dst)[i] = static_cast<Id>(col);
+  }
+}
+
+template <typename Id, bool kLds>
+hipError_t launch_kron(const GenerateArgs& a, hipStream_t s) {
+  KronLaunch P;
+  P.records = a.records;
+  P.n_buckets = a.n_buckets;
+  P.shift = 32u - static_cast<uint32_t>(a.bucket_bits);
+  P.k = static_cast<uint32_t>(a.k);
+  P.key0 = static_cast<uint32_t>(a.seed);
+  P.key1 = static_cast<uint32_t>(a.seed >> 32);
+  P.edge_begin = a.edge_begin;
+  P.m = a.m;
+  P.out_src = a.out_src;
+  P.out_dst = a.out_dst;
+  P.pow[0] = 1;
+  for (int i = 1; i < 16; ++i) P.pow[i] = P.pow[i - 1] * a.kron_k;
+  const size_t lds = kLds ? static_cast<size_t>(a.n_buckets) * sizeof(BucketRecord) : 0;
+  uint64_t grid = (a.m + kGenThreads - 1) / kGenThreads;
+  const uint64_t cap = static_cast<uint64_t>(limits().cu_count) * (kLds ? 1 : 2);
+  if (grid > cap) grid = cap;
+  hipLaunchKernelGGL((kron_kernel<Id, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads), lds, s, P);
+  return hipGetLastError();
+}
+
 template <bool kReduce>
 hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   if (a.m == 0) return hipSuccess;
+  if (!kReduce && a.kron_k > 2) {
+    if (a.id_bytes == 4) return a.lds ? launch_kron<uint32_t, true>(a, s) : launch_kron<uint32_t, false>(a, s);
+    return a.lds ? launch_kron<uint64_t, true>(a, s) : launch_kron<uint64_t, false>(a, s);
+  }
   Launch P;
   P.I.records = a.records;
   P.I.n_buckets = a.n_buckets;
@@ -679,7 +763,9 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_batch_kernel<Acc32, false, true>),
       allow_full_lds(&generate_batch_kernel<Acc64, true, true>),
       allow_full_lds(&generate_batch_kernel<Acc64, false, true>),
-      allow_full_lds(&hist_partial_kernel)};
+      allow_full_lds(&hist_partial_kernel),
+      allow_full_lds(&kron_kernel<uint32_t, true>),
+      allow_full_lds(&kron_kernel<uint64_t, true>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

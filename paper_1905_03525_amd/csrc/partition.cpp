@@ -229,6 +229,7 @@ struct Counter {
 constexpr uint64_t kMaxTilesPerCall = 1ull << 18;
 
 int check_args(const rmat_info& info, uint64_t m, int tbits, uint32_t row_begin, uint32_t row_end) {
+  if (info.initiator_k > 2) return set_error(RMAT_EINVAL, "partitioned generation needs a 2 x 2 (R-MAT) table");
   if (tbits < 1 || tbits > 15 || tbits >= info.k)
     return set_error(RMAT_EINVAL, "tile_bits %d outside 1..min(k - 1, 15)", tbits);
   if (row_begin >= row_end || row_end > (1u << tbits))

@@ -150,6 +150,8 @@ struct GenerateArgs {
   void* out_dst;
   uint32_t epi;             // kEpiUndirected | kEpiScramble
   uint64_t scramble_key;
+  uint32_t kron_k;          // 2: R-MAT bit strings; K > 2: base-K digit values (Kronecker table)
+  uint32_t id_bytes;
   // reduction variant: the edges are generated in sub-chunks of at most
   // bins_cap edges into `bins` (16-bit source prefixes), counted per
   // workgroup into `partials` (reduce_partials_bytes()) and merged into hist

@@ -715,7 +715,7 @@ int rmat_server_release(rmat_server_t s, uint64_t ticket) {
 }
 
 int rmat_server_run_trace(rmat_server_t s, const rmat_request* reqs, const double* t_arrival, int n,
-                          rmat_completion* out) {
+                          rmat_completion* out, rmat_progress_fn progress, void* user) {
   rmat::clear_error();
   if (!s || n < 0 || (n > 0 && (!reqs || !t_arrival || !out))) return set_error(RMAT_EINVAL, "NULL argument");
   for (int i = 0; i < n; ++i) {
@@ -732,7 +732,12 @@ int rmat_server_run_trace(rmat_server_t s, const rmat_request* reqs, const doubl
   const double base = now(s);
   std::unordered_map<uint64_t, int> slot_of;
   int next = 0, done = 0;
+  double last_report = base;
   while (done < n) {
+    if (progress && now(s) - last_report >= 1.0) {
+      last_report = now(s);
+      progress(user, static_cast<uint64_t>(done), static_cast<uint64_t>(n));
+    }
     const double t = now(s) - base;
     while (next < n && t_arrival[next] <= t) {
       uint64_t ticket = 0;

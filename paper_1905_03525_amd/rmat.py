@@ -27,7 +27,7 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
            RMAT_ERANGE: "RMAT_ERANGE"}
 
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
-EXPORTED = ["rmat_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
+EXPORTED = ["rmat_build_table", "rmat_kron_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
             "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
             "rmat_partition_counts", "rmat_generate_partition", "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
             "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
@@ -52,7 +52,7 @@ class rmat_info(ctypes.Structure):
                 ("n_buckets", ctypes.c_uint64), ("capacity", ctypes.c_uint64), ("id_bytes", ctypes.c_uint32),
                 ("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("lds_resident", ctypes.c_uint32),
                 ("expected_len", ctypes.c_double), ("export_bytes", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("initiator_k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class rmat_instance(ctypes.Structure):
@@ -105,6 +105,8 @@ class rmat_server_stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64)]
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
+
 _lib = None
 
 
@@ -120,6 +122,8 @@ def load() -> ctypes.CDLL:
     vp, u64, c_int = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     L.rmat_build_table.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, ctypes.POINTER(vp)]
     L.rmat_free_table.argtypes = [vp]
+    L.rmat_kron_build_table.argtypes = [ctypes.POINTER(ctypes.c_double), c_int, c_int, u64, c_int,
+                                        ctypes.POINTER(vp)]
     L.rmat_table_info.argtypes = [vp, ctypes.POINTER(rmat_info)]
     L.rmat_table_export.argtypes = [vp, vp, ctypes.c_size_t]
     L.rmat_generate.argtypes = [vp, u64, u64, u64, vp, vp]
@@ -144,7 +148,7 @@ def load() -> ctypes.CDLL:
     L.rmat_server_poll.argtypes = [vp, ctypes.POINTER(rmat_completion), c_int, ctypes.POINTER(c_int)]
     L.rmat_server_release.argtypes = [vp, u64]
     L.rmat_server_run_trace.argtypes = [vp, ctypes.POINTER(rmat_request), ctypes.POINTER(ctypes.c_double), c_int,
-                                        ctypes.POINTER(rmat_completion)]
+                                        ctypes.POINTER(rmat_completion), PROGRESS_FN, vp]
     L.rmat_server_get_stats.argtypes = [vp, ctypes.POINTER(rmat_server_stats)]
     L.rmat_server_clock.argtypes = [vp]
     L.rmat_server_free.argtypes = [vp]
@@ -206,6 +210,14 @@ class Table:
 def rmat_build_table(a: float, b: float, c: float, d: float, k: int, table_bound: int, path_mode: int) -> Table:
     h = ctypes.c_void_p()
     _check(load().rmat_build_table(a, b, c, d, k, table_bound, path_mode, ctypes.byref(h)), "rmat_build_table")
+    return Table(h.value)
+
+
+def rmat_kron_build_table(P, K: int, k: int, table_bound: int, path_mode: int) -> Table:
+    """Table of a K x K Kronecker initiator P (K^2 probabilities, row-major)."""
+    arr = (ctypes.c_double * len(P))(*[float(x) for x in P])
+    h = ctypes.c_void_p()
+    _check(load().rmat_kron_build_table(arr, K, k, table_bound, path_mode, ctypes.byref(h)), "rmat_kron_build_table")
     return Table(h.value)
 
 
@@ -295,25 +307,28 @@ def rmat_last_error() -> str:
     return load().rmat_last_error().decode()
 
 
-def id_dtype(k: int):
-    """torch dtype holding the ids of a table with this k (bit patterns)."""
+def id_dtype(k: int, id_bytes: int | None = None):
+    """torch dtype holding the ids of a table with this k (bit patterns);
+    id_bytes overrides (Kronecker tables: 4 if K^k <= 2^32)."""
     import torch
+    if id_bytes is not None:
+        return torch.int32 if id_bytes == 4 else torch.int64
     return torch.int32 if k <= 32 else torch.int64
 
 
 def to_numpy_ids(x, k: int) -> np.ndarray:
-    """Device id tensor -> numpy array of uint32 / uint64."""
+    """Device id tensor -> numpy array of uint32 / uint64 (by the tensor's width)."""
     a = x.cpu().numpy()
-    return a.view(np.uint32 if k <= 32 else np.uint64)
+    return a.view(np.uint32 if a.dtype.itemsize == 4 else np.uint64)
 
 
 def generate_edges(t: Table, seed: int, edge_begin: int, m: int, device="cuda", stream=None):
     """Allocates (src, dst) on the device and enqueues rmat_generate_async on
     `stream` (default: torch's current stream)."""
     import torch
-    k = rmat_table_info(t)["k"]
-    src = torch.empty(m, dtype=id_dtype(k), device=device)
-    dst = torch.empty(m, dtype=id_dtype(k), device=device)
+    info = rmat_table_info(t)
+    src = torch.empty(m, dtype=id_dtype(info["k"], info["id_bytes"]), device=device)
+    dst = torch.empty(m, dtype=id_dtype(info["k"], info["id_bytes"]), device=device)
     if stream is None:
         stream = torch.cuda.current_stream(src.device)
     rmat_generate_async(t, seed, edge_begin, m, src, dst, stream)
@@ -497,14 +512,16 @@ def rmat_server_release(s: Server, ticket: int):
     _check(load().rmat_server_release(s.handle, ticket), "rmat_server_release")
 
 
-def rmat_server_run_trace(s: Server, requests: list, t_arrival) -> list:
+def rmat_server_run_trace(s: Server, requests: list, t_arrival, progress=None) -> list:
     """Serves `requests` (dicts) arriving at t_arrival (seconds, ascending);
-    returns one completion dict per request, in request order."""
+    returns one completion dict per request, in request order.  progress, if
+    given, is called as progress(done, total) about once a second."""
     n = len(requests)
     arr = (rmat_request * n)(*[make_request(p) for p in requests])
     ts = (ctypes.c_double * n)(*[float(t) for t in t_arrival])
     out = (rmat_completion * n)()
-    _check(load().rmat_server_run_trace(s.handle, arr, ts, n, out), "rmat_server_run_trace")
+    cb = PROGRESS_FN(lambda _u, done, total: progress(done, total)) if progress else PROGRESS_FN()
+    _check(load().rmat_server_run_trace(s.handle, arr, ts, n, out, cb, None), "rmat_server_run_trace")
     return [_struct_dict(out[i]) for i in range(n)]
 
 

@@ -167,7 +167,8 @@ void run_scenario(int sc, std::mt19937_64& rng) {
     double now = 0;
     for (double& v : t) v = (now += 2e-6 * static_cast<double>(uni(0, 10)));
     std::vector<rmat_completion> out(trace.size());
-    const int rc = rmat_server_run_trace(s, trace.data(), t.data(), static_cast<int>(trace.size()), out.data());
+    const int rc = rmat_server_run_trace(s, trace.data(), t.data(), static_cast<int>(trace.size()), out.data(),
+                                         nullptr, nullptr);
     CHECK(rc == RMAT_OK, "scenario %d: run_trace: %s", sc, rmat_last_error());
     if (rc == RMAT_OK)
       for (size_t i = 0; i < out.size(); ++i) check_completion(out[i], i);

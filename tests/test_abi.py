@@ -116,7 +116,7 @@ def test_server_null_handles_and_config_checks():
     assert L.rmat_server_drain(None) == R.RMAT_EINVAL
     assert L.rmat_server_poll(None, None, 0, None) == R.RMAT_EINVAL
     assert L.rmat_server_release(None, 1) == R.RMAT_EINVAL
-    assert L.rmat_server_run_trace(None, None, None, 0, None) == R.RMAT_EINVAL
+    assert L.rmat_server_run_trace(None, None, None, 0, None, R.rmat.PROGRESS_FN(), None) == R.RMAT_EINVAL
     assert L.rmat_server_get_stats(None, None) == R.RMAT_EINVAL
     assert L.rmat_server_clock(None) == 0.0
     assert L.rmat_server_create(None, ctypes.cast(0, ctypes.POINTER(ctypes.c_void_p))) == R.RMAT_EINVAL

@@ -1,0 +1,117 @@
+"""K x K stochastic Kronecker tables (Sec. 5) through the C ABI against the
+oracle: tables bit for bit, edges bit for bit (base-K ids), K = 2 equal to
+the R-MAT path, and the unsupported combinations rejected."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+P3 = [0.3, 0.1, 0.05, 0.1, 0.2, 0.05, 0.05, 0.05, 0.1]
+P4 = [x / 64 for x in (8, 4, 4, 2, 4, 8, 2, 4, 4, 2, 6, 2, 2, 4, 2, 6)]
+
+
+def _dirichlet(K, seed):
+    return list(np.random.default_rng(seed).dirichlet([1.0] * (K * K)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_03525_amd as R
+    R.load()
+    return R
+
+
+TABLES = [
+    (P3, 3, 12, 1000, oracle.VARIABLE),
+    (P3, 3, 12, 729, oracle.FIXED),
+    (P4, 4, 16, 4096, oracle.VARIABLE),
+    ([1 / 25] * 25, 5, 13, 625, oracle.FIXED),
+    (_dirichlet(8, 1), 8, 20, 8000, oracle.VARIABLE),
+    (_dirichlet(16, 2), 16, 16, 300, oracle.VARIABLE),
+    (P3, 3, 30, 20_000, oracle.VARIABLE),        # 32768 buckets: read from global memory
+    (_dirichlet(3, 3), 3, 40, 5000, oracle.VARIABLE),
+]
+
+
+@pytest.mark.parametrize("P,K,k,bound,mode", TABLES)
+def test_kron_table_parity(R, P, K, k, bound, mode):
+    t = R.rmat_kron_build_table(P, K, k, bound, mode)
+    g = R.rmat_table_export(t)
+    info = R.rmat_table_info(t)
+    o = oracle.kron_build_table(P, K, k, bound, mode)
+    assert info["initiator_k"] == K and info["n_items"] == o.n_items and info["bucket_bits"] == o.bucket_bits
+    assert info["depth_cap"] == o.cap
+    assert np.array_equal(g["len"], o.length.astype(np.uint32))
+    assert np.array_equal(g["row"], o.row) and np.array_equal(g["col"], o.col)
+    assert np.array_equal(g["p"].view(np.uint64), o.p.view(np.uint64))
+    assert np.array_equal(g["w"], o.w.astype(np.uint64))
+    assert np.array_equal(g["thr"], o.thr) and np.array_equal(g["alias"], o.alias)
+    t.close()
+
+
+EDGES = [
+    # P, K, k, bound, mode, seed, edge_begin, m
+    (P3, 3, 12, 1000, oracle.VARIABLE, 1, 0, 100_000),          # 3^12 < 2^32: uint32 ids
+    (P3, 3, 20, 1000, oracle.VARIABLE, 2, 7, 50_001),           # 3^20 > 2^32: uint64 ids
+    (P3, 3, 40, 5000, oracle.VARIABLE, 3, 2 ** 32 - 1000, 20_000),
+    (P4, 4, 16, 4096, oracle.VARIABLE, 4, 63, 65_537),          # 4^16 = 2^32: uint32 ids
+    ([1 / 25] * 25, 5, 27, 625, oracle.FIXED, 5, 10 ** 12, 30_000),
+    (_dirichlet(8, 1), 8, 21, 8000, oracle.VARIABLE, 6, 0, 40_000),   # 8^21 = 2^63
+    (_dirichlet(16, 2), 16, 16, 300, oracle.VARIABLE, 7, 2 ** 64 - 3000, 3000),  # 16^16 = 2^64
+    (P3, 3, 30, 20_000, oracle.VARIABLE, 8, 5, 30_000),           # table in global memory
+    (P3, 3, 1, 100, oracle.VARIABLE, 9, 0, 1000),                 # one digit
+]
+
+
+@pytest.mark.parametrize("P,K,k,bound,mode,seed,e0,m", EDGES)
+def test_kron_edge_parity(R, P, K, k, bound, mode, seed, e0, m):
+    import torch
+    t = R.rmat_kron_build_table(P, K, k, bound, mode)
+    src, dst = R.generate_edges(t, seed, e0, m)
+    torch.cuda.synchronize()
+    o = oracle.kron_build_table(P, K, k, bound, mode)
+    os_, od = oracle.generate(o, seed, e0, m, threads=8)
+    gs, gd = R.to_numpy_ids(src, k), R.to_numpy_ids(dst, k)
+    assert gs.dtype == os_.dtype
+    bad = np.nonzero((gs != os_) | (gd != od))[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+    t.close()
+
+
+def test_k2_is_the_rmat_path(R):
+    import torch
+    q = [0.57, 0.19, 0.19, 0.05]
+    a = R.rmat_kron_build_table(q, 2, 26, 4096, R.RMAT_VARIABLE)
+    b = R.rmat_build_table(*q, 26, 4096, R.RMAT_VARIABLE)
+    assert R.rmat_table_info(a) == R.rmat_table_info(b)
+    sa, da = R.generate_edges(a, 7, 0, 1 << 20)
+    sb, db = R.generate_edges(b, 7, 0, 1 << 20)
+    torch.cuda.synchronize()
+    assert torch.equal(sa, sb) and torch.equal(da, db)
+    a.close()
+    b.close()
+
+
+def test_kron_rejections(R):
+    import torch
+    t = R.rmat_kron_build_table(P3, 3, 10, 1000, R.RMAT_VARIABLE)
+    x = torch.empty(16, dtype=torch.int32, device="cuda")
+    h = torch.zeros(16, dtype=torch.int64, device="cuda")
+    with pytest.raises(R.RmatError):
+        R.rmat_generate_ex_async(t, 1, 0, 8, R.RMAT_UNDIRECTED, 0, x, x)
+    with pytest.raises(R.RmatError):
+        R.rmat_generate_reduce_async(t, 1, 0, 8, 4, h, h)
+    with pytest.raises(R.RmatError):
+        R.rmat_partition_counts(t, 1, 100, 2)
+    t.close()
+    for P, K, k, bound in (([0.2] * 9, 3, 5, 100), (P3, 3, 41, 100), (P3, 17, 5, 100), (P3, 3, 5, 9)):
+        with pytest.raises(R.RmatError) as ei:
+            R.rmat_kron_build_table(P, K, k, bound, R.RMAT_VARIABLE)
+        assert ei.value.status == R.RMAT_EINVAL
