@@ -85,6 +85,12 @@ def lib():
         L.orc_kron_build_table.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int,
                                            ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
         L.orc_kron_build_table.restype = ctypes.c_int
+        L.orc_perturbed_params.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                                                   ctypes.c_void_p]
+        L.orc_perturbed_params.restype = ctypes.c_int
+        L.orc_generate_set.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.orc_generate_set.restype = ctypes.c_int
         L.orc_binomial.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
                                    ctypes.c_double]
         L.orc_binomial.restype = ctypes.c_uint64
@@ -266,3 +272,32 @@ def generate_partition(t: Table, seed: int, m: int, tbits: int, row_begin: int =
     if rc != 0:
         raise OracleError(rc, "generate_partition")
     return counts, src, dst
+
+
+# ---------------------------------------------------------------------------
+# perturbed tables (Sec. 5, reading R22)
+
+def perturbed_params(a, b, c, d, n_tables: int, eps: float, seed: int) -> np.ndarray:
+    """(n_tables, 4) parameter sets: each entry scaled by 1 + eps (2u - 1),
+    u from SplitMix64(seed), then normalised."""
+    out = np.zeros((n_tables, 4), np.float64)
+    rc = lib().orc_perturbed_params(a, b, c, d, n_tables, eps, seed, _ptr(out))
+    if rc != 0:
+        raise OracleError(rc, "perturbed_params")
+    return out
+
+
+def build_perturbed_tables(a, b, c, d, k, bound, mode, n_tables: int, eps: float, seed: int) -> list:
+    return [build_table(*q, k, bound, mode) for q in perturbed_params(a, b, c, d, n_tables, eps, seed)]
+
+
+def generate_set(tables: list, seed: int, edge_begin: int, m: int):
+    """Edges [edge_begin, edge_begin + m), edge e from tables[e mod len(tables)]."""
+    width = 4 if tables[0].k <= 32 else 8
+    dt = np.uint32 if width == 4 else np.uint64
+    src, dst = np.zeros(m, dt), np.zeros(m, dt)
+    handles = (ctypes.c_void_p * len(tables))(*[t.handle for t in tables])
+    rc = lib().orc_generate_set(handles, len(tables), seed, edge_begin, m, _ptr(src), _ptr(dst), width)
+    if rc != 0:
+        raise OracleError(rc, "generate_set")
+    return src, dst

@@ -61,6 +61,11 @@
  *      with M_r (odd) and C_r the outputs of SplitMix64 [Steele, Lea, Flood,
  *      OOPSLA'14] seeded with the scramble key, drawn in the order M_0, C_0,
  *      M_1, C_1, M_2, C_2 (M_r with its lowest bit set).
+ *  R22 Sec. 5 perturbed tables: P tables (P a power of two <= 64) built from
+ *      (a, b, c, d) with each entry x multiplied by 1 + eps (2 u - 1) and then
+ *      normalised, u the 53-bit uniforms of SplitMix64 seeded with the
+ *      perturbation seed, drawn table by table, entries in the order a, b,
+ *      c, d; edge e is drawn from table e mod P.
  *  R20 Sec. 5 partitioned generation: the adjacency matrix is cut into
  *      2^t x 2^t tiles; the m edges are split over them top-down, each node
  *      of the quadrant tree splitting its count n into (n_a, n_b, n_c, n_d)
@@ -1140,6 +1145,48 @@ int orc_kron_build_table(const double* P, int K, int k, uint64_t bound, int mode
   int rc;
   if ((rc = quantise(out)) != ORC_OK) { orc_free_table(out); return rc; }
   if ((rc = build_alias(out)) != ORC_OK) { orc_free_table(out); return rc; }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Perturbed tables (Sec. 5, reading R22).
+ * ---------------------------------------------------------------------- */
+int orc_perturbed_params(double a, double b, double c, double d, int n_tables, double eps,
+                         uint64_t seed, double* out /* n_tables x 4 */) {
+  if (n_tables < 1 || n_tables > 64 || (n_tables & (n_tables - 1))) return ORC_EINVAL;
+  if (!(eps >= 0.0 && eps < 1.0)) return ORC_EINVAL;
+  const double q[4] = {a, b, c, d};
+  uint64_t st = seed;
+  for (int i = 0; i < n_tables; ++i) {
+    double v[4];
+    for (int x = 0; x < 4; ++x) {
+      const double u = (double)(splitmix64_next(&st) >> 11) * (1.0 / 9007199254740992.0);
+      v[x] = q[x] * (1.0 + eps * (2.0 * u - 1.0));
+    }
+    const double s = v[0] + v[1] + v[2] + v[3];
+    for (int x = 0; x < 4; ++x) out[4 * i + x] = v[x] / s;
+  }
+  return ORC_OK;
+}
+
+/* Edges of a set of tables: edge e from tables[e mod n_tables]. */
+int orc_generate_set(const orc_table* const* tables, int n_tables, uint64_t seed, uint64_t edge_begin,
+                     uint64_t m, void* src, void* dst, int width) {
+  if (m > 0 && edge_begin + (m - 1) < edge_begin) return ORC_ERANGE;
+  if (n_tables < 1 || (n_tables & (n_tables - 1))) return ORC_EINVAL;
+  for (uint64_t slot = 0; slot < m; ++slot) {
+    const uint64_t e = edge_begin + slot;
+    const orc_table* t = tables[e & (uint64_t)(n_tables - 1)];
+    uint64_t s, d;
+    sample_edge(t, seed, e, &s, &d, NULL);
+    if (width == 4) {
+      ((uint32_t*)src)[slot] = (uint32_t)s;
+      ((uint32_t*)dst)[slot] = (uint32_t)d;
+    } else {
+      ((uint64_t*)src)[slot] = s;
+      ((uint64_t*)dst)[slot] = d;
+    }
+  }
   return ORC_OK;
 }
 
