@@ -348,6 +348,17 @@ def main():
     out["undirected_scrambled_kernel_ms"] = ea.elapsed_time(eb_)
     out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
     t_epi.close()
+    # degree smoothing (Sec. 5): 8 perturbed tables of bound 1024 (eps 0.1),
+    # edge e from table e mod 8; the whole set stays LDS-resident
+    t_set = R.rmat_build_perturbed_table(w["a"], w["b"], w["c"], w["d"], k, 1024, R.RMAT_VARIABLE, 8, 0.1, 2019)
+    R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
+    ea.record(stream)
+    R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
+    eb_.record(stream)
+    torch.cuda.synchronize()
+    out["perturbed_set"] = {"tables": 8, "table_bound": 1024, "epsilon": 0.1,
+                            "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
+    t_set.close()
     # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
     # tile rows [0, 64) per call, four calls; counting on the host included
     t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)

@@ -74,7 +74,7 @@ typedef struct rmat_info {
   uint64_t export_bytes;   /* bytes written by rmat_table_export */
   uint64_t device_bytes;   /* device memory held by the table */
   uint32_t initiator_k;    /* 2 for R-MAT, K for a K x K Kronecker table */
-  uint32_t reserved;
+  uint32_t n_tables;       /* 1, or P for a set of perturbed tables (n_buckets each) */
 } rmat_info;
 
 /*
@@ -125,6 +125,25 @@ int rmat_build_table(double a, double b, double c, double d, int k,
  * it (RMAT_EINVAL).  Errors: RMAT_EINVAL, RMAT_ENOMEM, RMAT_EDEVICE.
  */
 int rmat_kron_build_table(const double* P, int K, int k, uint64_t table_bound, int path_mode, rmat_table_t* out);
+
+/*
+ * A set of P perturbed tables for degree smoothing (Sec. 5, in place of
+ * per-step parameter noise): table i is rmat_build_table of (a, b, c, d)
+ * with each entry x scaled by 1 + epsilon (2 u - 1) and the four then
+ * normalised (divided by their sum), u the 53-bit uniforms (high 53 bits)
+ * of SplitMix64 seeded with perturb_seed, drawn table by table in the order
+ * a, b, c, d.  Edge e is drawn from table e mod P (exactly the edge
+ * rmat_generate would draw from that table alone).  P (n_tables) is a power
+ * of two in 1..64; 0 <= epsilon < 1.  All P tables are built in one launch
+ * and have the same shape; rmat_table_info reports one member's shape with
+ * n_tables = P; rmat_table_export exports member 0 and
+ * rmat_table_export_member member i.  rmat_generate(_async),
+ * rmat_generate_ex_async and rmat_generate_reduce_async accept the set.
+ * Errors: as rmat_build_table; RMAT_EINVAL for n_tables or epsilon.
+ */
+int rmat_build_perturbed_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                               int n_tables, double epsilon, uint64_t perturb_seed, rmat_table_t* out);
+int rmat_table_export_member(rmat_table_t t, int i, void* host_buf, size_t nbytes);
 
 /* Releases the table's device memory.  NULL is accepted.  The caller must
  * make sure no generation that uses it is still running. */

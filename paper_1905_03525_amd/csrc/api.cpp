@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <vector>
 #include <new>
 
 #include "rmat_internal.h"
@@ -23,6 +24,7 @@ struct rmat_table {
   void* d_reduce = nullptr;    // reduction workspace: 16-bit bins, then per-workgroup partial counts
   uint64_t reduce_edges = 0;   // bins it holds
   double q[4];                 // a, b, c, d as given
+  std::vector<rmat::TableView> members;  // a perturbed set's tables (empty for one table)
 };
 
 namespace rmat {
@@ -207,7 +209,7 @@ void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const S
   I->export_bytes = 36 * S.n_buckets;
   I->device_bytes = device_bytes;
   I->initiator_k = 2;
-  I->reserved = 0;
+  I->n_tables = 1;
 }
 
 int adopt_table(const rmat_info& info, const double q[4], int kron_K, const TableView& view, void* d_mem,
@@ -238,7 +240,7 @@ int adopt_table(const rmat_info& info, const double q[4], int kron_K, const Tabl
 
 // SplitMix64 [Steele, Lea, Flood, OOPSLA'14]: state advanced by the golden
 // gamma, output mixed by two multiply-xorshift steps.
-static uint64_t splitmix64(uint64_t& state) {
+uint64_t splitmix64(uint64_t& state) {
   uint64_t z = (state += 0x9E3779B97F4A7C15ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -339,6 +341,107 @@ int rmat_build_table(double a, double b, double c, double d, int k, uint64_t tab
   return RMAT_OK;
 }
 
+int rmat_build_perturbed_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                               int n_tables, double epsilon, uint64_t perturb_seed, rmat_table_t* out) {
+  g_err[0] = '\0';
+  if (!out) return set_error(RMAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_tables < 1 || n_tables > 64 || (n_tables & (n_tables - 1)))
+    return set_error(RMAT_EINVAL, "n_tables %d is not a power of two in 1..64", n_tables);
+  if (!(epsilon >= 0.0 && epsilon < 1.0)) return set_error(RMAT_EINVAL, "epsilon must be in [0, 1)");
+  const double q0[4] = {a, b, c, d};
+  rmat::Shape S;
+  int rc = rmat::validate_and_size(q0, k, table_bound, path_mode, &S);
+  if (rc) return rc;
+  // parameter sets: each entry scaled by 1 + eps (2u - 1), u from SplitMix64, then normalised
+  std::vector<double> qs(4 * static_cast<size_t>(n_tables));
+  uint64_t st = perturb_seed;
+  for (int i = 0; i < n_tables; ++i) {
+    double v[4];
+    for (int x = 0; x < 4; ++x) {
+      const double u = static_cast<double>(rmat::splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+      v[x] = q0[x] * (1.0 + epsilon * (2.0 * u - 1.0));
+    }
+    const double sum = v[0] + v[1] + v[2] + v[3];
+    for (int x = 0; x < 4; ++x) qs[4 * i + x] = v[x] / sum;
+    rmat::Shape Si;
+    if ((rc = rmat::validate_and_size(&qs[4 * i], k, table_bound, path_mode, &Si))) return rc;
+  }
+  if ((rc = rmat::check_device())) return rc;
+  const uint64_t nb = S.n_buckets;
+  const uint64_t tb = rmat::table_bytes(S);
+  const uint64_t rec_bytes = (static_cast<uint64_t>(n_tables) * nb * sizeof(rmat::BucketRecord) + 255) / 256 * 256;
+  void* d_mem = nullptr;
+  hipError_t e = hipMalloc(&d_mem, tb * n_tables + rec_bytes);
+  if (e != hipSuccess) return rmat::hip_fail(e, "hipMalloc(perturbed tables)");
+  char* base = static_cast<char*>(d_mem);
+  auto* recs = reinterpret_cast<rmat::BucketRecord*>(base + tb * n_tables);
+  std::vector<rmat::TableView> views(n_tables);
+  for (int i = 0; i < n_tables; ++i) {
+    views[i] = rmat::place_table(base + tb * i, S);
+    views[i].records = recs + static_cast<uint64_t>(i) * nb;  // the members' records back to back
+  }
+  const uint64_t sb = (rmat::scratch_bytes(S) + 255) / 256 * 256;
+  void* scratch = nullptr;
+  e = hipMalloc(&scratch, sb * n_tables + sizeof(rmat::BuildJob) * n_tables + 256);
+  if (e != hipSuccess) {
+    (void)hipFree(d_mem);
+    return rmat::hip_fail(e, "hipMalloc(build scratch)");
+  }
+  std::vector<rmat::BuildJob> jobs(n_tables);
+  rmat::BuildStats init;
+  std::memset(&init, 0, sizeof(init));
+  init.error = -1;
+  for (int i = 0; i < n_tables && e == hipSuccess; ++i) {
+    rmat::fill_job(&jobs[i], &qs[4 * i], k, path_mode, S, views[i], static_cast<char*>(scratch) + sb * i);
+    e = hipMemcpy(views[i].stats, &init, sizeof(init), hipMemcpyHostToDevice);
+  }
+  auto* d_jobs = reinterpret_cast<rmat::BuildJob*>(static_cast<char*>(scratch) + sb * n_tables);
+  if (e == hipSuccess) e = hipMemcpy(d_jobs, jobs.data(), sizeof(rmat::BuildJob) * n_tables, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = rmat::launch_table_build(d_jobs, n_tables, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  std::vector<rmat::BuildStats> stats(n_tables);
+  for (int i = 0; i < n_tables && e == hipSuccess; ++i)
+    e = hipMemcpy(&stats[i], views[i].stats, sizeof(rmat::BuildStats), hipMemcpyDeviceToHost);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) {
+    (void)hipFree(d_mem);
+    return rmat::hip_fail(e, "perturbed table build");
+  }
+  for (int i = 0; i < n_tables; ++i)
+    if (stats[i].error != 0) {
+      (void)hipFree(d_mem);
+      return set_error(stats[i].error == rmat::kBuildResidual ? RMAT_EINVAL : RMAT_EDEVICE,
+                       "table %d: build failed on the device (code %d)", i, stats[i].error);
+    }
+  rmat_info info;
+  rmat::fill_info(&info, k, path_mode, table_bound, S, stats[0], tb * n_tables + rec_bytes);
+  info.n_tables = static_cast<uint32_t>(n_tables);
+  info.lds_resident = nb * n_tables <= rmat::lds_table_limit() ? 1 : 0;
+  rmat_table* t = new (std::nothrow) rmat_table();
+  if (!t) {
+    (void)hipFree(d_mem);
+    return set_error(RMAT_ENOMEM, "host allocation of the table handle failed");
+  }
+  if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
+  t->info = info;
+  t->d_mem = d_mem;
+  t->v = views[0];
+  t->members = views;
+  std::memcpy(t->q, q0, sizeof(t->q));
+  *out = t;
+  return RMAT_OK;
+}
+
+int rmat_table_export_member(rmat_table_t t, int i, void* host_buf, size_t nbytes) {
+  g_err[0] = '\0';
+  if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (i < 0 || static_cast<uint32_t>(i) >= t->info.n_tables)
+    return set_error(RMAT_EINVAL, "member %d outside 0..%u", i, t->info.n_tables - 1);
+  const rmat::TableView& V = t->members.empty() ? t->v : t->members[static_cast<size_t>(i)];
+  return rmat::export_table(V, t->info.n_buckets, host_buf, nbytes);
+}
+
 int rmat_free_table(rmat_table_t t) {
   g_err[0] = '\0';
   if (!t) return RMAT_OK;
@@ -416,6 +519,7 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
   a.scramble_key = scramble_key;
   a.kron_k = t->info.initiator_k;
   a.id_bytes = t->info.id_bytes;
+  a.n_tables = t->info.n_tables;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = reduce ? rmat::launch_generate_reduce(a, s) : rmat::launch_generate(a, s);
   if (e != hipSuccess) return rmat::hip_fail(e, reduce ? "generate_reduce launch" : "generate launch");

@@ -351,6 +351,7 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
     rmat::GenInst& d = dinst[i];
     d.records = b->views[i].records;
     d.n_buckets = static_cast<uint32_t>(b->shape[i].n_buckets);
+    d.table_mask = 0;
     d.shift = 32u - static_cast<uint32_t>(b->shape[i].bucket_bits);
     d.k = static_cast<uint32_t>(x.k);
     d.key0 = static_cast<uint32_t>(x.seed);

@@ -242,6 +242,9 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   using Id = typename Acc::Id;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
+  // edge e reads table e mod P; blocks start at multiples of 64 and P divides
+  // 64, so in pass 1 that is the lane's table for the whole run
+  const BucketRecord* __restrict__ tab_lane = tab + (lane & I.table_mask) * I.n_buckets;
   for (uint64_t t0 = wave_blk; t0 < blk_end; t0 += stride * L.tile) {
     const uint64_t left = (blk_end - t0 + stride - 1) / stride;
     const uint32_t nb_tile = left < L.tile ? static_cast<uint32_t>(left) : L.tile;
@@ -257,7 +260,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       uint32_t x0, x1, x2, x3;
       philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1, x0, x1,
                      x2, x3);
-      sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
+      sample4(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled);
       res[j * 64 + lane] = acc.pack();
       const bool need = decltype(whole)::value ? filled < I.k : (filled < I.k && ((amask >> lane) & 1ull));
       const uint64_t ovf_mask = __ballot(need);
@@ -291,10 +294,11 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         acc.unpack(res[idx]);
         const uint64_t e = ((I.first_block + t0 + (idx >> 6) * stride) << 6) + (idx & 63u);
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
+        const BucketRecord* __restrict__ tab_e = tab + ((idx & 63u) & I.table_mask) * I.n_buckets;
         for (uint32_t jj = 1; filled < I.k; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
-          sample4(tab, I.shift, I.k, x0, x1, x2, x3, acc, filled);
+          sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled);
         }
         res[idx] = acc.pack();
       }
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   using Packed = typename Acc::Packed;
   const BucketRecord* tab = P.I.records;
   if (kLds) {
-    stage_table(P.I.records, P.I.n_buckets, s_mem);
+    stage_table(P.I.records, P.I.n_buckets * (P.I.table_mask + 1), s_mem);
     __syncthreads();
     tab = reinterpret_cast<const BucketRecord*>(s_mem);
   }
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     const GenWorkItem W = B.items[item];
     const Inst I = B.insts[W.inst];
     if (kLds && W.inst != cur) {
-      stage_table(I.records, I.n_buckets, s_mem);
+      stage_table(I.records, I.n_buckets * (I.table_mask + 1), s_mem);
       __syncthreads();
     }
     cur = W.inst;
@@ -474,7 +478,7 @@ uint64_t persistent_grid(size_t lds_bytes) {
 template <typename Acc, bool kLds, bool kReduce>
 hipError_t launch_one(Launch P, hipStream_t s) {
   size_t lds = 0;
-  P.L = layout_for<Acc>(P.I.n_buckets, kLds, &lds);
+  P.L = layout_for<Acc>(P.I.n_buckets * (P.I.table_mask + 1), kLds, &lds);
   if (P.L.tile == 0) return hipErrorInvalidValue;
   const uint64_t waves_needed = (P.I.n_blocks + P.L.tile - 1) / P.L.tile;
   const uint64_t wgs_needed = (waves_needed + kWaves - 1) / kWaves;
@@ -635,6 +639,7 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   Launch P;
   P.I.records = a.records;
   P.I.n_buckets = a.n_buckets;
+  P.I.table_mask = a.n_tables > 1 ? a.n_tables - 1 : 0;
   P.I.shift = 32u - static_cast<uint32_t>(a.bucket_bits);
   P.I.k = static_cast<uint32_t>(a.k);
   P.I.key0 = static_cast<uint32_t>(a.seed);

@@ -229,7 +229,8 @@ struct Counter {
 constexpr uint64_t kMaxTilesPerCall = 1ull << 18;
 
 int check_args(const rmat_info& info, uint64_t m, int tbits, uint32_t row_begin, uint32_t row_end) {
-  if (info.initiator_k > 2) return set_error(RMAT_EINVAL, "partitioned generation needs a 2 x 2 (R-MAT) table");
+  if (info.initiator_k > 2 || info.n_tables > 1)
+    return set_error(RMAT_EINVAL, "partitioned generation needs a single 2 x 2 (R-MAT) table");
   if (tbits < 1 || tbits > 15 || tbits >= info.k)
     return set_error(RMAT_EINVAL, "tile_bits %d outside 1..min(k - 1, 15)", tbits);
   if (row_begin >= row_end || row_end > (1u << tbits))
@@ -306,6 +307,7 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     std::memset(&I, 0, sizeof(I));
     I.records = V.records;
     I.n_buckets = static_cast<uint32_t>(info.n_buckets);
+    I.table_mask = 0;
     I.shift = 32u - static_cast<uint32_t>(info.bucket_bits);
     I.k = static_cast<uint32_t>(kk);
     I.key0 = static_cast<uint32_t>(seed);

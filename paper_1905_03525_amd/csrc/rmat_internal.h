@@ -82,8 +82,9 @@ hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s)
 // One instance of a batched generation (device array).  Block indices are
 // relative to first_block = edge_begin >> 6.
 struct GenInst {
-  const BucketRecord* records;
+  const BucketRecord* records;  // table_mask + 1 tables of n_buckets records, back to back
   uint32_t n_buckets;
+  uint32_t table_mask;          // edge e reads table e & table_mask (perturbed sets; 0 otherwise)
   uint32_t shift;  // 32 - b
   uint32_t k;
   uint32_t key0, key1;
@@ -109,6 +110,9 @@ constexpr uint32_t kEpiUndirected = 1, kEpiScramble = 2;
 // The scramble's round constants for a key: SplitMix64 outputs in the order
 // M0, C0, M1, C1, M2, C2, each M with its lowest bit set; also mask and shift.
 void scramble_params(uint64_t key, int k, GenInst* I);
+
+// One SplitMix64 step [Steele, Lea, Flood, OOPSLA'14] (state advanced in place).
+uint64_t splitmix64(uint64_t& state);
 
 // A run of 64-edge blocks of one instance; a batch lists them in instance
 // order and workgroups claim them through an atomic counter.
@@ -152,6 +156,7 @@ struct GenerateArgs {
   uint64_t scramble_key;
   uint32_t kron_k;          // 2: R-MAT bit strings; K > 2: base-K digit values (Kronecker table)
   uint32_t id_bytes;
+  uint32_t n_tables;        // perturbed set size (1: a single table)
   // reduction variant: the edges are generated in sub-chunks of at most
   // bins_cap edges into `bins` (16-bit source prefixes), counted per
   // workgroup into `partials` (reduce_partials_bytes()) and merged into hist

@@ -27,7 +27,7 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
            RMAT_ERANGE: "RMAT_ERANGE"}
 
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
-EXPORTED = ["rmat_build_table", "rmat_kron_build_table", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
+EXPORTED = ["rmat_build_table", "rmat_kron_build_table", "rmat_build_perturbed_table", "rmat_table_export_member", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
             "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async", "rmat_batch_create", "rmat_batch_enqueue",
             "rmat_partition_counts", "rmat_generate_partition", "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
             "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
@@ -52,7 +52,7 @@ class rmat_info(ctypes.Structure):
                 ("n_buckets", ctypes.c_uint64), ("capacity", ctypes.c_uint64), ("id_bytes", ctypes.c_uint32),
                 ("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32), ("lds_resident", ctypes.c_uint32),
                 ("expected_len", ctypes.c_double), ("export_bytes", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64), ("initiator_k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("device_bytes", ctypes.c_uint64), ("initiator_k", ctypes.c_uint32), ("n_tables", ctypes.c_uint32)]
 
 
 class rmat_instance(ctypes.Structure):
@@ -122,6 +122,9 @@ def load() -> ctypes.CDLL:
     vp, u64, c_int = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     L.rmat_build_table.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, ctypes.POINTER(vp)]
     L.rmat_free_table.argtypes = [vp]
+    L.rmat_build_perturbed_table.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, c_int, ctypes.c_double, u64,
+                                                                      ctypes.POINTER(vp)]
+    L.rmat_table_export_member.argtypes = [vp, c_int, vp, ctypes.c_size_t]
     L.rmat_kron_build_table.argtypes = [ctypes.POINTER(ctypes.c_double), c_int, c_int, u64, c_int,
                                         ctypes.POINTER(vp)]
     L.rmat_table_info.argtypes = [vp, ctypes.POINTER(rmat_info)]
@@ -219,6 +222,21 @@ def rmat_kron_build_table(P, K: int, k: int, table_bound: int, path_mode: int) -
     h = ctypes.c_void_p()
     _check(load().rmat_kron_build_table(arr, K, k, table_bound, path_mode, ctypes.byref(h)), "rmat_kron_build_table")
     return Table(h.value)
+
+
+def rmat_build_perturbed_table(a, b, c, d, k, table_bound, path_mode, n_tables, epsilon, perturb_seed) -> Table:
+    h = ctypes.c_void_p()
+    _check(load().rmat_build_perturbed_table(a, b, c, d, k, table_bound, path_mode, n_tables, epsilon, perturb_seed,
+                                             ctypes.byref(h)), "rmat_build_perturbed_table")
+    return Table(h.value)
+
+
+def rmat_table_export_member(t: Table, i: int) -> dict:
+    info = rmat_table_info(t)
+    buf = np.zeros(info["export_bytes"], dtype=np.uint8)
+    _check(load().rmat_table_export_member(t.handle, i, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes),
+           "rmat_table_export_member")
+    return _split_export(buf, info["n_buckets"])
 
 
 def rmat_free_table(t: Table):
