@@ -17,6 +17,10 @@
 //      so a second Philox block is only paid for edges that need it;
 //   3. the tile is written out block by block, 64 consecutive ids per store,
 //      every cache line written once and whole.
+// The kernel is bound by instruction issue (vector and scalar together), so
+// a full tile of whole blocks -- all but a few tiles at the ends of a range --
+// takes an unrolled copy with no per-block lane masks or loop control, and
+// stores through one buffer descriptor per output array.
 #include <type_traits>
 
 #include "rmat_internal.h"
@@ -93,19 +97,22 @@ __device__ __forceinline__ void philox10_first(uint32_t e_lo, uint32_t e_hi, uin
   }
 }
 
-// Row/column accumulators, left-aligned: letter t of the edge lands at bit
-// (W - 1 - t); ids are the top k bits at the end.
+// Row/column accumulators, filled from bit 0 up: a path of L letters,
+// stored bit-reversed, is shifted to the current fill level and OR-ed in
+// (one v_lshl_or_b32 per half); letters past the register's width fall off
+// the top.  The id is the first k letters, the first one most significant:
+// the bit reversal of the accumulator, shifted down to k bits.
 struct Acc32 {
   using Id = uint32_t;
   using Packed = uint2;
   uint32_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
-  __device__ __forceinline__ void append(uint32_t rowL, uint32_t colL, uint32_t filled) {
-    row |= rowL >> filled;
-    col |= colL >> filled;
+  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t filled) {
+    row |= rowv << filled;
+    col |= colv << filled;
   }
-  __device__ __forceinline__ uint32_t src(uint32_t k) const { return row >> (32 - k); }
-  __device__ __forceinline__ uint32_t dst(uint32_t k) const { return col >> (32 - k); }
+  __device__ __forceinline__ uint32_t src(uint32_t k) const { return __builtin_bitreverse32(row) >> (32 - k); }
+  __device__ __forceinline__ uint32_t dst(uint32_t k) const { return __builtin_bitreverse32(col) >> (32 - k); }
   __device__ __forceinline__ Packed pack() const { return make_uint2(row, col); }
   __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
@@ -115,12 +122,12 @@ struct Acc64 {
   using Packed = ulonglong2;
   uint64_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
-  __device__ __forceinline__ void append(uint32_t rowL, uint32_t colL, uint32_t filled) {
-    row |= (static_cast<uint64_t>(rowL) << 32) >> filled;
-    col |= (static_cast<uint64_t>(colL) << 32) >> filled;
+  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t filled) {
+    row |= static_cast<uint64_t>(rowv) << filled;
+    col |= static_cast<uint64_t>(colv) << filled;
   }
-  __device__ __forceinline__ uint64_t src(uint32_t k) const { return row >> (64 - k); }
-  __device__ __forceinline__ uint64_t dst(uint32_t k) const { return col >> (64 - k); }
+  __device__ __forceinline__ uint64_t src(uint32_t k) const { return __builtin_bitreverse64(row) >> (64 - k); }
+  __device__ __forceinline__ uint64_t dst(uint32_t k) const { return __builtin_bitreverse64(col) >> (64 - k); }
   __device__ __forceinline__ Packed pack() const { return make_ulonglong2(row, col); }
   __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
@@ -129,30 +136,27 @@ struct Acc64 {
 // x picks bucket x >> (32 - b) and keeps the bucket's own path when x <
 // thr_abs (= bucket * C + T), else takes its alias.  The four bucket records
 // are read before any of them is used, so four LDS reads are in flight.
-template <typename Acc>
+template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
                                         uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled) {
   const BucketRecord r0 = tab[x0 >> shift], r1 = tab[x1 >> shift], r2 = tab[x2 >> shift], r3 = tab[x3 >> shift];
   // keep the reads ahead of the branches below (an operand-only asm, no code)
-  __asm__ volatile("" ::"v"(r1.thr_abs), "v"(r1.self_word), "v"(r1.alias_word), "v"(r1.lens), "v"(r2.thr_abs),
-                   "v"(r2.self_word), "v"(r2.alias_word), "v"(r2.lens), "v"(r3.thr_abs), "v"(r3.self_word),
-                   "v"(r3.alias_word), "v"(r3.lens));
+  __asm__ volatile("" ::"v"(r1.thr_abs), "v"(r1.rows), "v"(r1.cols), "v"(r1.lens), "v"(r2.thr_abs), "v"(r2.rows),
+                   "v"(r2.cols), "v"(r2.lens), "v"(r3.thr_abs), "v"(r3.rows), "v"(r3.cols), "v"(r3.lens));
   const bool o0 = x0 < r0.thr_abs, o1 = x1 < r1.thr_abs, o2 = x2 < r2.thr_abs, o3 = x3 < r3.thr_abs;
-  const uint32_t w0 = o0 ? r0.self_word : r0.alias_word, l0 = o0 ? (r0.lens & 0xFFFFu) : (r0.lens >> 16);
-  const uint32_t w1 = o1 ? r1.self_word : r1.alias_word, l1 = o1 ? (r1.lens & 0xFFFFu) : (r1.lens >> 16);
-  const uint32_t w2 = o2 ? r2.self_word : r2.alias_word, l2 = o2 ? (r2.lens & 0xFFFFu) : (r2.lens >> 16);
-  const uint32_t w3 = o3 ? r3.self_word : r3.alias_word, l3 = o3 ? (r3.lens & 0xFFFFu) : (r3.lens >> 16);
-  acc.append(w0 & 0xFFFF0000u, w0 << 16, filled);
-  filled += l0;
-  if (filled < k) {
-    acc.append(w1 & 0xFFFF0000u, w1 << 16, filled);
-    filled += l1;
+  // each field is the low half-word for the bucket's own item, else the high one
+  auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
+  acc.append(half(o0, r0.rows), half(o0, r0.cols), filled);
+  filled += half(o0, r0.lens);
+  if (kSure1 || filled < k) {
+    acc.append(half(o1, r1.rows), half(o1, r1.cols), filled);
+    filled += half(o1, r1.lens);
     if (filled < k) {
-      acc.append(w2 & 0xFFFF0000u, w2 << 16, filled);
-      filled += l2;
+      acc.append(half(o2, r2.rows), half(o2, r2.cols), filled);
+      filled += half(o2, r2.lens);
       if (filled < k) {
-        acc.append(w3 & 0xFFFF0000u, w3 << 16, filled);
-        filled += l3;
+        acc.append(half(o3, r3.rows), half(o3, r3.cols), filled);
+        filled += half(o3, r3.lens);
       }
     }
   }
@@ -196,6 +200,58 @@ __device__ __forceinline__ Id scramble_id(Id x, const Inst& I) {
   return x;
 }
 
+// The Sec. 5 epilogue on one edge, when the launch asks for it (uniform):
+// mirror to row <= column, then relabel both ids.
+template <bool kGeneral, typename Id>
+__device__ __forceinline__ void epilogue(const Inst& I, Id& s, Id& d) {
+  if (kGeneral && I.epi != 0) {
+    if (I.epi & kEpiUndirected) {
+      const Id lo = s < d ? s : d;
+      d = s < d ? d : s;
+      s = lo;
+    }
+    if (I.epi & kEpiScramble) {
+      s = scramble_id(s, I);
+      d = scramble_id(d, I);
+    }
+  }
+}
+
+// One id per lane of a 64-edge block to out[first_slot + lane].  The block's
+// address goes into a buffer descriptor (scalar work: dword 3 = 32-bit data
+// format, the gfx9 untyped-access value) so the lane's byte offset is the
+// store's only vector operand.  In an instance's first block first_slot
+// wraps below the buffer; the lanes before edge_begin are inactive there.
+constexpr int kBufferDword3 = 0x00020000;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void store_ids(void* out, uint64_t first_slot, uint32_t lane, uint32_t v) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(static_cast<uint32_t*>(out) + first_slot, 0, 64 * 4, kBufferDword3);
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(lane * 4), 0, 0);
+}
+
+__device__ __forceinline__ void store_ids(void* out, uint64_t first_slot, uint32_t lane, uint64_t v) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(static_cast<uint64_t*>(out) + first_slot, 0, 64 * 8, kBufferDword3);
+  u32x2 w;
+  w.x = static_cast<uint32_t>(v);
+  w.y = static_cast<uint32_t>(v >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(lane * 8), 0, 0);
+}
+
+// A lane's id at byte offset soff (wave-uniform) + lane * size of a buffer.
+__device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t soff, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(lane * 4), static_cast<int>(soff), 0);
+}
+
+__device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t soff, uint64_t v) {
+  u32x2 w;
+  w.x = static_cast<uint32_t>(v);
+  w.y = static_cast<uint32_t>(v >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, static_cast<int>(lane * 8), static_cast<int>(soff), 0);
+}
+
 // MurmurHash3's 64-bit finaliser.
 __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
   z ^= z >> 33;
@@ -234,7 +290,7 @@ __device__ __forceinline__ uint64_t block_mask(const GenInst& I, uint64_t rel, u
 //      edges listed;
 //   2. the listed edges finished 64 at a time;
 //   3. the tile stored (or reduced).
-template <typename Acc, bool kReduce, bool kDigest = false>
+template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
@@ -246,21 +302,26 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   // 64, so in pass 1 that is the lane's table for the whole run
   const BucketRecord* __restrict__ tab_lane = tab + (lane & I.table_mask) * I.n_buckets;
   for (uint64_t t0 = wave_blk; t0 < blk_end; t0 += stride * L.tile) {
-    const uint64_t left = (blk_end - t0 + stride - 1) / stride;
-    const uint32_t nb_tile = left < L.tile ? static_cast<uint32_t>(left) : L.tile;
+    // blocks t0 + j * stride below blk_end, at most L.tile (counted without
+    // a 64-bit division: only a wave's last tile is short)
+    uint32_t nb_tile = L.tile;
+    if (blk_end - t0 <= (L.tile - 1) * stride) {
+      nb_tile = 1;
+      while (t0 + nb_tile * stride < blk_end) ++nb_tile;
+    }
 
     // pass 1: first Philox block of every edge of the tile; whole blocks
     // (every block but an instance's first and last) take a copy of the body
     // without lane masks
     uint32_t n_ovf = 0;
-    auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole) {
+    auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole, auto sure) {
       Acc acc;
       acc.clear();
       uint32_t filled = 0;
       uint32_t x0, x1, x2, x3;
       philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1, x0, x1,
                      x2, x3);
-      sample4(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled);
+      sample4<Acc, decltype(sure)::value>(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled);
       res[j * 64 + lane] = acc.pack();
       const bool need = decltype(whole)::value ? filled < I.k : (filled < I.k && ((amask >> lane) & 1ull));
       const uint64_t ovf_mask = __ballot(need);
@@ -273,14 +334,26 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         n_ovf += __popcll(ovf_mask);
       }
     };
-    for (uint32_t j = 0; j < nb_tile; ++j) {
-      const uint64_t rel = t0 + j * stride;                 // block index within the instance
-      const uint64_t base = (I.first_block + rel) << 6;     // wave-uniform
-      const uint64_t amask = block_mask(I, rel, last);
-      if (amask == ~0ull)
-        first_block(j, base, amask, std::true_type{});
-      else
-        first_block(j, base, amask, std::false_type{});
+    // a full tile of whole blocks (every tile but a few at the ends of the
+    // range) runs unrolled, without per-block lane masks
+    const bool prefixed = kGeneral && (I.src_prefix | I.dst_prefix) != 0;
+    const bool whole_tile = nb_tile == kMaxTile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
+                            (t0 + (kMaxTile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
+    const bool sure1 = I.k > static_cast<uint32_t>(kMaxDepthCap);  // a path has at most kMaxDepthCap letters
+    if (whole_tile && sure1) {
+#pragma unroll
+      for (uint32_t j = 0; j < kMaxTile; ++j)
+        first_block(j, (I.first_block + t0 + j * stride) << 6, ~0ull, std::true_type{}, std::true_type{});
+    } else {
+      for (uint32_t j = 0; j < nb_tile; ++j) {
+        const uint64_t rel = t0 + j * stride;                 // block index within the instance
+        const uint64_t base = (I.first_block + rel) << 6;     // wave-uniform
+        const uint64_t amask = block_mask(I, rel, last);
+        if (amask == ~0ull)
+          first_block(j, base, amask, std::true_type{}, std::false_type{});
+        else
+          first_block(j, base, amask, std::false_type{}, std::false_type{});
+      }
     }
     wave_lds_fence();
 
@@ -306,32 +379,25 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     wave_lds_fence();
 
     // pass 3: write the tile out (or fold it into the reduction)
-    auto emit = [&](uint32_t j, uint64_t base) {
+    auto emit = [&](const typename Acc::Packed& v, uint64_t base, auto prefixed) {
       const uint64_t e = base + lane;
       Acc acc;
-      acc.unpack(res[j * 64 + lane]);
+      acc.unpack(v);
       {
         if (kReduce) {
           const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
           bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
         } else {
-          const uint64_t slot = e - I.edge_begin;
-          Id s = static_cast<Id>(acc.src(I.k)) | static_cast<Id>(I.src_prefix);
-          Id d = static_cast<Id>(acc.dst(I.k)) | static_cast<Id>(I.dst_prefix);
-          if (I.epi != 0) {  // uniform
-            if (I.epi & kEpiUndirected) {
-              const Id lo = s < d ? s : d;
-              d = s < d ? d : s;
-              s = lo;
-            }
-            if (I.epi & kEpiScramble) {
-              s = scramble_id(s, I);
-              d = scramble_id(d, I);
-            }
+          Id s = static_cast<Id>(acc.src(I.k));
+          Id d = static_cast<Id>(acc.dst(I.k));
+          if (kGeneral && decltype(prefixed)::value) {  // tiles of a partitioned graph
+            s |= static_cast<Id>(I.src_prefix);
+            d |= static_cast<Id>(I.dst_prefix);
           }
-          static_cast<Id*>(I.out_src)[slot] = s;
-          static_cast<Id*>(I.out_dst)[slot] = d;
+          epilogue<kGeneral>(I, s, d);
+          store_ids(I.out_src, base - I.edge_begin, lane, s);
+          store_ids(I.out_dst, base - I.edge_begin, lane, d);
           if (kDigest) {
             const uint64_t s64 = s, d64 = d;
             xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
@@ -339,14 +405,48 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         }
       }
     };
-    for (uint32_t j = 0; j < nb_tile; ++j) {
-      const uint64_t rel = t0 + j * stride;
-      const uint64_t base = (I.first_block + rel) << 6;
-      const uint64_t amask = block_mask(I, rel, last);
-      if (amask == ~0ull) {
-        emit(j, base);
-      } else if ((amask >> lane) & 1ull) {
-        emit(j, base);
+    // the tile's results are read from LDS first, so the reads overlap
+    typename Acc::Packed vals[kMaxTile];
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxTile; ++j)
+      if (j < nb_tile) vals[j] = res[j * 64 + lane];
+    if (!kReduce && whole_tile && !prefixed) {
+      // one buffer descriptor per output array for the whole tile; block j
+      // sits at a scalar offset from the tile's first block
+      const uint64_t slot0 = ((I.first_block + t0) << 6) - I.edge_begin;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_src) + slot0, 0,
+                                                                           0x7FFFFFFF, kBufferDword3);
+      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_dst) + slot0, 0,
+                                                                           0x7FFFFFFF, kBufferDword3);
+      const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
+#pragma unroll
+      for (uint32_t j = 0; j < kMaxTile; ++j) {
+        Acc acc;
+        acc.unpack(vals[j]);
+        Id sv = static_cast<Id>(acc.src(I.k));
+        Id dv = static_cast<Id>(acc.dst(I.k));
+        epilogue<kGeneral>(I, sv, dv);
+        store_at(rs, lane, j * step, sv);
+        store_at(rd, lane, j * step, dv);
+        if (kDigest) {
+          const uint64_t e = ((I.first_block + t0 + j * stride) << 6) + lane;
+          const uint64_t s64 = sv, d64 = dv;
+          xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
+        }
+      }
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < kMaxTile; ++j) {
+        if (j < nb_tile) {
+          const uint64_t rel = t0 + j * stride;
+          const uint64_t base = (I.first_block + rel) << 6;
+          const uint64_t amask = block_mask(I, rel, last);
+          if (amask == ~0ull && !prefixed) {
+            emit(vals[j], base, std::false_type{});
+          } else if ((amask >> lane) & 1ull) {
+            emit(vals[j], base, std::true_type{});
+          }
+        }
       }
     }
     wave_lds_fence();
@@ -359,7 +459,9 @@ __device__ __forceinline__ void stage_table(const BucketRecord* src_rec, uint32_
   for (uint32_t i = threadIdx.x; i < n_buckets; i += kGenThreads) dst[i] = src[i];
 }
 
-template <typename Acc, bool kLds, bool kReduce>
+// kGeneral: the store may carry id prefixes and the epilogue; without it the
+// launch stores the plain ids and keeps none of their parameters live.
+template <typename Acc, bool kLds, bool kReduce, bool kGeneral>
 __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ unsigned long long s_xor[kWaves];
@@ -377,7 +479,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   Packed* res = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
   uint64_t xsum = 0;
-  run_blocks<Acc, kReduce>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.bins, xsum);
+  run_blocks<Acc, kReduce, false, kGeneral>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.bins,
+                                            xsum);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
@@ -475,7 +578,7 @@ uint64_t persistent_grid(size_t lds_bytes) {
   return static_cast<uint64_t>(limits().cu_count) * per_cu;
 }
 
-template <typename Acc, bool kLds, bool kReduce>
+template <typename Acc, bool kLds, bool kReduce, bool kGeneral>
 hipError_t launch_one(Launch P, hipStream_t s) {
   size_t lds = 0;
   P.L = layout_for<Acc>(P.I.n_buckets * (P.I.table_mask + 1), kLds, &lds);
@@ -485,7 +588,7 @@ hipError_t launch_one(Launch P, hipStream_t s) {
   uint64_t grid = persistent_grid(lds);
   if (grid > wgs_needed) grid = wgs_needed;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
+  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce, kGeneral>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
                      lds, s, P);
   return hipGetLastError();
 }
@@ -585,10 +688,9 @@ __global__ __launch_bounds__(kGenThreads) void kron_kernel(KronLaunch P) {
         if (filled < P.k) {
           const BucketRecord r = tab[x[w] >> P.shift];
           const bool own = x[w] < r.thr_abs;
-          const uint32_t word = own ? r.self_word : r.alias_word;
           const uint32_t L = own ? (r.lens & 0xFFFFu) : (r.lens >> 16);
           const uint32_t take = L < P.k - filled ? L : P.k - filled;
-          uint32_t rv = word >> 16, cv = word & 0xFFFFu;
+          uint32_t rv = own ? (r.rows & 0xFFFFu) : (r.rows >> 16), cv = own ? (r.cols & 0xFFFFu) : (r.cols >> 16);
           if (take < L) {
             const uint32_t dv = static_cast<uint32_t>(s_pow[L - take]);
             rv /= dv;
@@ -663,8 +765,12 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.xor_out = a.xor_out;
   const bool wide = a.k > 32;
   auto gen = [&](const Launch& L) {
-    if (a.lds) return wide ? launch_one<Acc64, true, kReduce>(L, s) : launch_one<Acc32, true, kReduce>(L, s);
-    return wide ? launch_one<Acc64, false, kReduce>(L, s) : launch_one<Acc32, false, kReduce>(L, s);
+    if (!kReduce && L.I.epi != 0) {
+      if (a.lds) return wide ? launch_one<Acc64, true, false, true>(L, s) : launch_one<Acc32, true, false, true>(L, s);
+      return wide ? launch_one<Acc64, false, false, true>(L, s) : launch_one<Acc32, false, false, true>(L, s);
+    }
+    if (a.lds) return wide ? launch_one<Acc64, true, kReduce, false>(L, s) : launch_one<Acc32, true, kReduce, false>(L, s);
+    return wide ? launch_one<Acc64, false, kReduce, false>(L, s) : launch_one<Acc32, false, kReduce, false>(L, s);
   };
   if (!kReduce) return gen(P);
   // reduction: sub-chunks of at most bins_cap edges, each generated into the
@@ -756,10 +862,18 @@ hipError_t prepare_kernels() {
   if (done) return hipSuccess;
   hipError_t e = hipSuccess;
   const hipError_t r[] = {
-      allow_full_lds(&generate_kernel<Acc32, true, false>), allow_full_lds(&generate_kernel<Acc32, false, false>),
-      allow_full_lds(&generate_kernel<Acc64, true, false>), allow_full_lds(&generate_kernel<Acc64, false, false>),
-      allow_full_lds(&generate_kernel<Acc32, true, true>),  allow_full_lds(&generate_kernel<Acc32, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, true, true>),  allow_full_lds(&generate_kernel<Acc64, false, true>),
+      allow_full_lds(&generate_kernel<Acc32, true, false, false>),
+      allow_full_lds(&generate_kernel<Acc32, false, false, false>),
+      allow_full_lds(&generate_kernel<Acc64, true, false, false>),
+      allow_full_lds(&generate_kernel<Acc64, false, false, false>),
+      allow_full_lds(&generate_kernel<Acc32, true, false, true>),
+      allow_full_lds(&generate_kernel<Acc32, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, true, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc32, true, true, false>),
+      allow_full_lds(&generate_kernel<Acc32, false, true, false>),
+      allow_full_lds(&generate_kernel<Acc64, true, true, false>),
+      allow_full_lds(&generate_kernel<Acc64, false, true, false>),
       allow_full_lds(&generate_batch_kernel<Acc32, true, false>),
       allow_full_lds(&generate_batch_kernel<Acc32, false, false>),
       allow_full_lds(&generate_batch_kernel<Acc64, true, false>),

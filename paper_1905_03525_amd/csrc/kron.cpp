@@ -256,8 +256,8 @@ extern "C" int rmat_kron_build_table(const double* P, int K, int k, uint64_t tab
   st.min_len = 0xFFFFFFFFu;
   for (uint64_t i = 0; i < nb; ++i) {
     rec[i].thr_abs = static_cast<uint32_t>(i * C + thr[i]);
-    rec[i].self_word = (row[i] << 16) | col[i];
-    rec[i].alias_word = (row[alias[i]] << 16) | col[alias[i]];
+    rec[i].rows = row[i] | (row[alias[i]] << 16);
+    rec[i].cols = col[i] | (col[alias[i]] << 16);
     rec[i].lens = len[i] | (len[alias[i]] << 16);
     if (i < n) {
       st.min_len = std::min(st.min_len, len[i]);

@@ -17,12 +17,16 @@ constexpr uint64_t kMaxBound = 1ull << 24;
 // Hot-path bucket record, 16 bytes (one ds_read_b128):
 //   x  thr_abs: bucket i keeps its own item for x < i*C + T_i (a full bucket
 //      stores i*C and an alias equal to itself, so the test never matters)
-//   y  own item's path word, z  alias item's path word:
-//      bits 31..16 = row bits left-aligned in 16 bits,
-//      bits 15..0  = column bits left-aligned in 16 bits
-//   w  own length | alias length << 16
+//   y  rows: own item's row value in bits 15..0, the alias item's in 31..16
+//   z  cols: the same for the column values
+//   w  lens: own length in bits 15..0, the alias's in 31..16
+// so each of the three fields the generator needs is one 16-bit half-word
+// select.  For 2 x 2 (R-MAT) tables a value holds the path's bits reversed
+// (the root-most letter in bit 0), which lets the generator append a path
+// with one shift-or at the current fill level; for K x K tables it is the
+// base-K number of the path's digits (root-most digit most significant).
 struct alignas(16) BucketRecord {
-  uint32_t thr_abs, self_word, alias_word, lens;
+  uint32_t thr_abs, rows, cols, lens;
 };
 
 // Device-side results of a table build, read back by the host.

@@ -194,8 +194,10 @@ __device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t 
   return lo;
 }
 
-__device__ __forceinline__ uint32_t path_word(uint32_t len, uint32_t row, uint32_t col) {
-  return ((row << (16 - len)) << 16) | ((col << (16 - len)) & 0xFFFFu);
+// The len low bits of v in reverse order (the first letter of a path, its
+// most significant bit, goes to bit 0).
+__device__ __forceinline__ uint32_t reversed_bits(uint32_t len, uint32_t v) {
+  return len == 0 ? 0u : (__brev(v) >> (32u - len));
 }
 
 __device__ __forceinline__ uint64_t frac_key(double p, uint64_t* floor_out) {
@@ -601,8 +603,8 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
       const uint32_t ls = J.item_len[i], la = J.item_len[a];
       BucketRecord r;
       r.thr_abs = static_cast<uint32_t>(static_cast<uint64_t>(i) * C + (a == i ? 0u : J.thr[i]));
-      r.self_word = path_word(ls, J.item_row[i], J.item_col[i]);
-      r.alias_word = path_word(la, J.item_row[a], J.item_col[a]);
+      r.rows = reversed_bits(ls, J.item_row[i]) | (reversed_bits(la, J.item_row[a]) << 16);
+      r.cols = reversed_bits(ls, J.item_col[i]) | (reversed_bits(la, J.item_col[a]) << 16);
       r.lens = ls | (la << 16);
       J.records[i] = r;
       if (i < n) {
