@@ -162,6 +162,27 @@ __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, ui
   }
 }
 
+// The sampling half of sample4 on records already loaded (k > kMaxDepthCap:
+// the first two samples are always used).
+template <typename Acc>
+__device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
+                                         uint32_t& filled) {
+  auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
+  const bool o0 = x[0] < r[0].thr_abs, o1 = x[1] < r[1].thr_abs, o2 = x[2] < r[2].thr_abs, o3 = x[3] < r[3].thr_abs;
+  acc.append(half(o0, r[0].rows), half(o0, r[0].cols), filled);
+  filled += half(o0, r[0].lens);
+  acc.append(half(o1, r[1].rows), half(o1, r[1].cols), filled);
+  filled += half(o1, r[1].lens);
+  if (filled < k) {
+    acc.append(half(o2, r[2].rows), half(o2, r[2].cols), filled);
+    filled += half(o2, r[2].lens);
+    if (filled < k) {
+      acc.append(half(o3, r[3].rows), half(o3, r[3].cols), filled);
+      filled += half(o3, r[3].lens);
+    }
+  }
+}
+
 using Inst = GenInst;
 
 // LDS layout shared by both kernels: [table | per-wave tile areas].
@@ -341,9 +362,48 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
                             (t0 + (kMaxTile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
     const bool sure1 = I.k > static_cast<uint32_t>(kMaxDepthCap);  // a path has at most kMaxDepthCap letters
     if (whole_tile && sure1) {
+      // software-pipelined: block j's Philox draws and table reads are issued
+      // before block j - 1's samples are consumed, so the reads overlap work
+      auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
+        const uint64_t base = (I.first_block + t0 + j * stride) << 6;
+        philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
+                       x[0], x[1], x[2], x[3]);
 #pragma unroll
-      for (uint32_t j = 0; j < kMaxTile; ++j)
-        first_block(j, (I.first_block + t0 + j * stride) << 6, ~0ull, std::true_type{}, std::true_type{});
+        for (int i = 0; i < 4; ++i) r[i] = tab_lane[x[i] >> I.shift];
+      };
+      auto finish = [&](uint32_t j, const uint32_t (&x)[4], const BucketRecord (&r)[4]) {
+        Acc acc;
+        acc.clear();
+        uint32_t filled = 0;
+        consume4(I.k, x, r, acc, filled);
+        res[j * 64 + lane] = acc.pack();
+        const bool need = filled < I.k;
+        const uint64_t ovf_mask = __ballot(need);
+        if (ovf_mask != 0) {
+          if (need) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
+            ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
+          }
+          n_ovf += __popcll(ovf_mask);
+        }
+      };
+      uint32_t xa[4];
+      BucketRecord ra[4];
+      draw(0, xa, ra);
+#pragma unroll
+      for (uint32_t j = 1; j < kMaxTile; ++j) {
+        uint32_t xb[4];
+        BucketRecord rb[4];
+        draw(j, xb, rb);
+        finish(j - 1, xa, ra);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xa[i] = xb[i];
+          ra[i] = rb[i];
+        }
+      }
+      finish(kMaxTile - 1, xa, ra);
     } else {
       for (uint32_t j = 0; j < nb_tile; ++j) {
         const uint64_t rel = t0 + j * stride;                 // block index within the instance

@@ -95,6 +95,49 @@ __device__ uint32_t block_min_max(uint32_t vmin, uint32_t vmax, uint32_t* s_u32,
   return mn;
 }
 
+// Radix-select step, run by one wave: walks 256 histogram bins from bin 255
+// down to bin 0 and returns the bin in which the running count reaches
+// `need` (bin 0 if it never does), with `need` reduced by the counts of the
+// bins passed.  Lane L owns bins 255 - 4L .. 252 - 4L.
+template <typename Count>
+__device__ uint32_t wave_select_desc(const Count* hist, uint64_t* need) {
+  const int lane = threadIdx.x & 63;
+  uint64_t c[4], own = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c[i] = hist[255 - 4 * lane - i];
+    own += c[i];
+  }
+  uint64_t incl = own;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = shfl_up_u64(incl, d);
+    if (lane >= d) incl += y;
+  }
+  const uint64_t want = *need;
+  const uint64_t hit = __ballot(incl >= want);
+  // the first lane whose range reaches `want`; none: every bin is passed
+  // down to bin 0, which takes the remainder
+  const int f = hit ? __builtin_ctzll(hit) : 63;
+  const uint64_t before = __shfl(static_cast<uint32_t>(incl - own), f, 64) |
+                          (static_cast<uint64_t>(__shfl(static_cast<uint32_t>((incl - own) >> 32), f, 64)) << 32);
+  uint64_t rest = want - before;
+  uint32_t bin = 0;
+  if (lane == f) {
+    int i = 0;
+    for (; i < 3; ++i) {
+      if (rest <= c[i]) break;
+      rest -= c[i];
+    }
+    bin = 255 - 4 * f - i;
+  }
+  bin = __shfl(bin, f, 64);
+  const uint32_t rlo = __shfl(static_cast<uint32_t>(rest), f, 64);
+  const uint32_t rhi = __shfl(static_cast<uint32_t>(rest >> 32), f, 64);
+  *need = (static_cast<uint64_t>(rhi) << 32) | rlo;
+  return bin;
+}
+
 // Probability of a path from its letter counts: 1.0 times a (na times), then
 // b, c, d, rounding after every product.
 __device__ __forceinline__ double path_prob(const double q[4], int na, int nb, int nc, int nd) {
@@ -217,11 +260,12 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
   __shared__ uint64_t s_warp[kWaves];
   __shared__ uint32_t s_u32[2 * kWaves];
   __shared__ uint32_t s_hist[256];
+  __shared__ unsigned long long s_hist64[256];
+  __shared__ uint16_t s_group[kMaxClasses];
   __shared__ uint32_t s_lvl_start[kMaxDepthCap + 2];
   __shared__ Boundary s_bnd;
   __shared__ int s_error;
   __shared__ uint64_t s_sel_prefix, s_sel_need;
-  __shared__ uint64_t s_warp_before;
   __shared__ uint32_t s_binom[kBinomN * kBinomN];
   __shared__ unsigned long long s_len_mass[16];
 
@@ -268,80 +312,86 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
       }
     }
     __syncthreads();
-    // bitonic sort: "before" first
-    for (int size = 2; size <= kMaxClasses; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int t = tid; t < kMaxClasses / 2; t += kBuildThreads) {
-          int i = 2 * t - (t & (stride - 1));
-          int j = i + stride;
-          double pi = s_cls_p[i], pj = s_cls_p[j];
-          int di = class_depth(s_cls_key[i]), dj = class_depth(s_cls_key[j]);
-          bool up = (i & size) == 0;
-          bool swap = up ? class_before(pj, dj, pi, di) : class_before(pi, di, pj, dj);
-          if (swap) {
-            s_cls_p[i] = pj; s_cls_p[j] = pi;
-            uint32_t tk = s_cls_key[i]; s_cls_key[i] = s_cls_key[j]; s_cls_key[j] = tk;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // the group of classes (equal probability and depth) holding the t-th
-    // node: prefix sums of the class sizes in sorted order
+    // The boundary is node n_expand of the order (p descending, depth
+    // ascending, code ascending).  Classes hold whole (p, depth) runs, so a
+    // radix select over the bits of p (descending; a non-negative double's
+    // bit pattern orders like its value), weighted by the classes' node
+    // counts, then over depth, finds the run holding it and its rank there.
     constexpr int kPer = kMaxClasses / kBuildThreads;
-    if (tid == 0) { s_u32[0] = 0xFFFFFFFFu; s_u32[1] = 0xFFFFFFFFu; s_u32[2] = 0; }
-    uint64_t cnt_local[kPer], sum_local = 0;
+    uint64_t cnt_local[kPer], pb_local[kPer], sum_local = 0;
     for (int u = 0; u < kPer; ++u) {
       const int i = tid * kPer + u;
       const uint32_t key = s_cls_key[i];
       cnt_local[u] = i < K ? multinomial(bt, class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3)) : 0;
+      pb_local[u] = static_cast<uint64_t>(__double_as_longlong(s_cls_p[i]));
       sum_local += cnt_local[u];
     }
-    uint64_t total_nodes;
-    uint64_t cum = block_exclusive_scan(sum_local, s_warp, &total_nodes);
-    for (int u = 0; u < kPer; ++u) {  // the class whose range covers node n_expand
-      const int i = tid * kPer + u;
-      if (cum < J.n_expand && J.n_expand <= cum + cnt_local[u]) s_u32[0] = i;
-      cum += cnt_local[u];
-    }
-    __syncthreads();
-    const uint32_t hit = s_u32[0];
-    if (hit != 0xFFFFFFFFu) {  // first and last class of the hit class's group
-      const double hp = s_cls_p[hit];
-      const int hd = class_depth(s_cls_key[hit]);
-      for (int i = tid; i < K; i += kBuildThreads)
-        if (s_cls_p[i] == hp && class_depth(s_cls_key[i]) == hd) {
-          atomicMin(&s_u32[1], static_cast<uint32_t>(i));
-          atomicMax(&s_u32[2], static_cast<uint32_t>(i + 1));
+    const uint64_t total_nodes = block_sum(sum_local, s_warp);
+    const bool all = J.n_expand == 0 || J.n_expand > total_nodes;
+    if (tid == 0) { s_sel_prefix = 0; s_sel_need = J.n_expand; s_u32[0] = 0; }
+    uint64_t prefix = 0, pmask = 0;
+    if (!all) {
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += kBuildThreads) s_hist64[i] = 0;
+        __syncthreads();
+        for (int u = 0; u < kPer; ++u)
+          if (cnt_local[u] != 0 && (pb_local[u] & pmask) == prefix)
+            atomicAdd(&s_hist64[(pb_local[u] >> shift) & 255u], static_cast<unsigned long long>(cnt_local[u]));
+        __syncthreads();
+        if (tid < 64) {
+          uint64_t need = s_sel_need;
+          const uint32_t bin = wave_select_desc(s_hist64, &need);
+          if (tid == 0) {
+            s_sel_need = need;
+            s_sel_prefix = prefix | (static_cast<uint64_t>(bin) << shift);
+          }
         }
-    }
-    __syncthreads();
-    // nodes before the group
-    if (hit != 0xFFFFFFFFu) {
-      cum = block_exclusive_scan(sum_local, s_warp, &total_nodes);
-      for (int u = 0; u < kPer; ++u) {
-        if (tid * kPer + u == static_cast<int>(s_u32[1])) s_warp_before = cum;
-        cum += cnt_local[u];
+        __syncthreads();
+        prefix = s_sel_prefix;
+        pmask |= 255ull << shift;
       }
+      // depth, ascending, among the classes of probability bits `prefix`
+      if (tid < 16) s_hist64[tid] = 0;
+      __syncthreads();
+      for (int u = 0; u < kPer; ++u)
+        if (cnt_local[u] != 0 && pb_local[u] == prefix)
+          atomicAdd(&s_hist64[class_depth(s_cls_key[tid * kPer + u])], static_cast<unsigned long long>(cnt_local[u]));
+      __syncthreads();
+      if (tid == 0) {
+        uint64_t need = s_sel_need;
+        int d = 0;
+        for (; d < 15; ++d) {
+          if (need <= s_hist64[d]) break;
+          need -= s_hist64[d];
+        }
+        s_sel_need = need;
+        s_u32[1] = static_cast<uint32_t>(d);
+      }
+      __syncthreads();
+      // the run's classes, in any order (the rank below only sums over them)
+      const int run_depth = static_cast<int>(s_u32[1]);
+      for (int u = 0; u < kPer; ++u) {
+        const int i = tid * kPer + u;
+        if (cnt_local[u] != 0 && pb_local[u] == prefix && class_depth(s_cls_key[i]) == run_depth)
+          s_group[atomicAdd(&s_u32[0], 1u)] = static_cast<uint16_t>(i);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (tid == 0 && s_error == 0) {
-      const int g0 = hit == 0xFFFFFFFFu ? -1 : static_cast<int>(s_u32[1]);
-      const int g1 = hit == 0xFFFFFFFFu ? -1 : static_cast<int>(s_u32[2]);
-      const uint64_t before = g0 < 0 ? 0 : s_warp_before;
-      if (g0 < 0) {
+      if (all) {
         s_bnd.all = 1;
       } else {
-        uint64_t r = J.n_expand - before - 1;  // rank of the last expanded node in the group
-        const int D = class_depth(s_cls_key[g0]);
+        uint64_t r = s_sel_need - 1;  // rank of the last expanded node in its run
+        const int n_group = static_cast<int>(s_u32[0]);
+        const int D = static_cast<int>(s_u32[1]);
         int used[4] = {0, 0, 0, 0};
         uint32_t code = 0;
         for (int pos = 0; pos < D; ++pos) {
           int chosen = 3;
           for (int x = 0; x < 4; ++x) {
             uint64_t cnt = 0;
-            for (int g = g0; g < g1; ++g) {
-              uint32_t key = s_cls_key[g];
+            for (int g = 0; g < n_group; ++g) {
+              uint32_t key = s_cls_key[s_group[g]];
               int rem[4];
               bool ok = true;
               for (int y = 0; y < 4; ++y) {
@@ -356,7 +406,7 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
           used[chosen]++;
           code = code * 4 + chosen;
         }
-        s_bnd.p = s_cls_p[g0];
+        s_bnd.p = __longlong_as_double(static_cast<long long>(prefix));
         s_bnd.depth = D;
         s_bnd.code = code;
       }
@@ -503,15 +553,13 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
           if ((key & pmask) == prefix) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid < 64) {
           uint64_t need = s_sel_need;
-          int bin = 255;
-          for (; bin > 0; --bin) {
-            if (need <= s_hist[bin]) break;
-            need -= s_hist[bin];
+          const uint32_t bin = wave_select_desc(s_hist, &need);
+          if (tid == 0) {
+            s_sel_need = need;
+            s_sel_prefix = prefix | (static_cast<uint64_t>(bin) << shift);
           }
-          s_sel_need = need;
-          s_sel_prefix = prefix | (static_cast<uint64_t>(bin) << shift);
         }
         pmask |= 255ull << shift;
         __syncthreads();
