@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <map>
 #include <vector>
 #include <new>
 
@@ -281,6 +283,29 @@ extern "C" {
 
 const char* rmat_last_error(void) { return g_err; }
 
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, std::pair<void*, uint64_t>> g_scratch;  // device -> (buffer, bytes); held until exit
+
+// A build scratch buffer of at least `bytes` on `device` (call with
+// g_scratch_mu held); grows by reallocation, never shrinks.
+hipError_t build_scratch(int device, uint64_t bytes, void** out) {
+  auto& slot = g_scratch[device];
+  if (slot.second < bytes) {
+    if (slot.first) (void)hipFree(slot.first);
+    slot = {nullptr, 0};
+    hipError_t e = hipMalloc(&slot.first, bytes);
+    if (e != hipSuccess) {
+      slot.first = nullptr;
+      return e;
+    }
+    slot.second = bytes;
+  }
+  *out = slot.first;
+  return hipSuccess;
+}
+}  // namespace
+
 int rmat_build_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
                      rmat_table_t* out) {
   g_err[0] = '\0';
@@ -302,27 +327,24 @@ int rmat_build_table(double a, double b, double c, double d, int k, uint64_t tab
     return rmat::hip_fail(e, "hipMalloc(table)");
   }
   t->v = rmat::place_table(static_cast<char*>(t->d_mem), S);
-  void* scratch = nullptr;
-  const uint64_t sb = rmat::scratch_bytes(S);
-  e = hipMalloc(&scratch, sb + 256);
-  if (e != hipSuccess) {
-    (void)hipFree(t->d_mem);
-    delete t;
-    return rmat::hip_fail(e, "hipMalloc(build scratch)");
-  }
-  rmat::BuildJob job;
-  rmat::fill_job(&job, q, k, path_mode, S, t->v, static_cast<char*>(scratch));
-  auto* d_job = reinterpret_cast<rmat::BuildJob*>(static_cast<char*>(scratch) + sb);
-
   rmat::BuildStats stats;
-  std::memset(&stats, 0, sizeof(stats));
-  stats.error = -1;
-  e = hipMemcpy(d_job, &job, sizeof(job), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(t->v.stats, &stats, sizeof(stats), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = rmat::launch_table_build(d_job, 1, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(&stats, t->v.stats, sizeof(stats), hipMemcpyDeviceToHost);
-  (void)hipFree(scratch);
+  {
+    // the build's working arrays come from a per-device buffer kept between
+    // builds (builds are synchronous and serialised here)
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    void* scratch = nullptr;
+    e = build_scratch(t->device, rmat::scratch_bytes(S), &scratch);
+    if (e != hipSuccess) {
+      (void)hipFree(t->d_mem);
+      delete t;
+      return rmat::hip_fail(e, "hipMalloc(build scratch)");
+    }
+    rmat::BuildJob job;
+    rmat::fill_job(&job, q, k, path_mode, S, t->v, static_cast<char*>(scratch));
+    e = rmat::launch_table_build_one(job, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&stats, t->v.stats, sizeof(stats), hipMemcpyDeviceToHost);
+  }
   if (e != hipSuccess) {
     (void)hipFree(t->d_mem);
     delete t;

@@ -82,6 +82,7 @@ inline uint64_t build_scratch_bytes(uint64_t n_expand, uint64_t n_buckets) {
 
 // Launchers (defined in the .hip files); return hipSuccess or the launch error.
 hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s);
+hipError_t launch_table_build_one(const BuildJob& job, hipStream_t s);
 
 // One instance of a batched generation (device array).  Block indices are
 // relative to first_block = edge_begin >> 6.

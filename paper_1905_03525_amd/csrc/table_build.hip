@@ -181,6 +181,9 @@ __device__ __forceinline__ uint32_t binom_direct(int n, int r) {
   return c;
 }
 
+// expanded nodes whose per-node arrays (17 bytes each) fit the LDS work area
+constexpr uint32_t kLdsNodes = 2880;
+static_assert(kLdsNodes * 17 <= kMaxClasses * 12, "per-node arrays exceed the LDS work area");
 constexpr int kBinomN = 18;  // rows 0..17: enough for C(D + 3, 3) with D <= 14
 
 // Number of distinct paths with the given letter counts (a multinomial
@@ -250,13 +253,115 @@ __device__ __forceinline__ uint64_t frac_key(double p, uint64_t* floor_out) {
   return static_cast<uint64_t>(__double_as_longlong(x - fl));
 }
 
+// VARIABLE leaves in tree order: level-by-level expansion of the nodes the
+// boundary admits, bottom-up leaf counts, top-down leaf placement.  The
+// per-node arrays are LDS for trees of up to kLdsNodes expanded nodes and the
+// job's global scratch beyond (one body, inlined for either address space).
+// Returns false on an internal error (*s_error set).
+__device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundary& B, const double q[4], int cap,
+                                                uint32_t n, uint32_t* lvl_code, uint8_t* lvl_mask,
+                                                uint32_t* lvl_first, uint32_t* lvl_size, uint32_t* lvl_off,
+                                                uint64_t* s_warp, uint32_t* s_lvl_start, int* s_error) {
+  const int tid = threadIdx.x;
+  // level-by-level expansion
+  if (tid == 0) {
+    lvl_code[0] = 0;
+    s_lvl_start[0] = 0;
+    s_lvl_start[1] = 1;
+  }
+  __syncthreads();
+  int D = 0;
+  for (; D < cap; ++D) {
+    const uint32_t start = s_lvl_start[D], end = s_lvl_start[D + 1];
+    if (start == end) break;
+    uint32_t next = end;
+    for (uint32_t base = start; base < end; base += kBuildThreads) {
+      const uint32_t i = base + tid;
+      uint32_t mask = 0, code = 0;
+      if (i < end) {
+        code = lvl_code[i];
+        int cnt[4];
+        letter_counts(code, D, cnt);
+        for (int x = 0; x < 4; ++x) {
+          cnt[x]++;
+          double p = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+          cnt[x]--;
+          if (node_expanded(B, 1, cap, 0, p, D + 1, code * 4 + x)) mask |= 1u << x;
+        }
+      }
+      uint64_t total;
+      uint32_t pos = next + static_cast<uint32_t>(block_exclusive_scan(__popc(mask), s_warp, &total));
+      if (i < end) {
+        lvl_mask[i] = static_cast<uint8_t>(mask);
+        lvl_first[i] = pos;
+        for (int x = 0; x < 4; ++x)
+          if (mask & (1u << x)) {
+            if (pos < J.n_expand) lvl_code[pos] = code * 4 + x;
+            else *s_error = kBuildItemCount;
+            ++pos;
+          }
+      }
+      next += static_cast<uint32_t>(total);
+    }
+    if (tid == 0) s_lvl_start[D + 2] = next;
+    __syncthreads();
+    if (*s_error) return false;
+  }
+  const int levels = D;  // levels 0..levels-1 are non-empty
+  if (tid == 0 && s_lvl_start[levels] != J.n_expand) *s_error = kBuildItemCount;
+  __syncthreads();
+  if (*s_error) return false;
+  // bottom-up leaf counts
+  for (int L = levels - 1; L >= 0; --L) {
+    for (uint32_t i = s_lvl_start[L] + tid; i < s_lvl_start[L + 1]; i += kBuildThreads) {
+      uint32_t mask = lvl_mask[i], f = lvl_first[i], size = 0;
+      for (int x = 0; x < 4; ++x) size += (mask & (1u << x)) ? lvl_size[f++] : 1u;
+      lvl_size[i] = size;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && lvl_size[0] != n) *s_error = kBuildItemCount;
+  __syncthreads();
+  if (*s_error) return false;
+  // top-down leaf placement
+  if (tid == 0) lvl_off[0] = 0;
+  __syncthreads();
+  for (int L = 0; L < levels; ++L) {
+    for (uint32_t i = s_lvl_start[L] + tid; i < s_lvl_start[L + 1]; i += kBuildThreads) {
+      uint32_t mask = lvl_mask[i], f = lvl_first[i], cur = lvl_off[i], code = lvl_code[i];
+      int cnt[4];
+      letter_counts(code, L, cnt);
+      for (int x = 0; x < 4; ++x) {
+        if (mask & (1u << x)) {
+          lvl_off[f] = cur;
+          cur += lvl_size[f];
+          ++f;
+        } else {
+          uint32_t cc = code * 4 + x, r, c;
+          split_code(cc, L + 1, &r, &c);
+          cnt[x]++;
+          J.item_len[cur] = L + 1;
+          J.item_row[cur] = r;
+          J.item_col[cur] = c;
+          J.item_p[cur] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+          cnt[x]--;
+          ++cur;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 // ------------------------------------------------------------------ kernel --
-__global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJob* __restrict__ jobs) {
-  const BuildJob J = jobs[blockIdx.x];
+__device__ __forceinline__ void build_table(const BuildJob& J) {
   const int tid = threadIdx.x;
 
-  __shared__ double s_cls_p[kMaxClasses];
-  __shared__ uint32_t s_cls_key[kMaxClasses];
+  // phase 1's class arrays, then phase 2's per-node arrays (small trees)
+  __shared__ __align__(16) unsigned char s_work[kMaxClasses * (sizeof(double) + sizeof(uint32_t))];
+  double* const s_cls_p = reinterpret_cast<double*>(s_work);
+  uint32_t* const s_cls_key = reinterpret_cast<uint32_t*>(s_work + kMaxClasses * sizeof(double));
   __shared__ uint64_t s_warp[kWaves];
   __shared__ uint32_t s_u32[2 * kWaves];
   __shared__ uint32_t s_hist[256];
@@ -430,94 +535,19 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJ
       J.item_p[j] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
     }
   } else {
-    // level-by-level expansion
-    if (tid == 0) {
-      J.lvl_code[0] = 0;
-      s_lvl_start[0] = 0;
-      s_lvl_start[1] = 1;
+    bool ok;
+    if (J.n_expand <= kLdsNodes) {
+      uint32_t* code = reinterpret_cast<uint32_t*>(s_work);
+      uint32_t* first = code + kLdsNodes;
+      uint32_t* size = first + kLdsNodes;
+      uint32_t* off = size + kLdsNodes;
+      uint8_t* mask = reinterpret_cast<uint8_t*>(off + kLdsNodes);
+      ok = variable_leaves(J, B, q, cap, n, code, mask, first, size, off, s_warp, s_lvl_start, &s_error);
+    } else {
+      ok = variable_leaves(J, B, q, cap, n, J.lvl_code, J.lvl_mask, J.lvl_first, J.lvl_size, J.lvl_off, s_warp,
+                           s_lvl_start, &s_error);
     }
-    __syncthreads();
-    int D = 0;
-    for (; D < cap; ++D) {
-      const uint32_t start = s_lvl_start[D], end = s_lvl_start[D + 1];
-      if (start == end) break;
-      uint32_t next = end;
-      for (uint32_t base = start; base < end; base += kBuildThreads) {
-        const uint32_t i = base + tid;
-        uint32_t mask = 0, code = 0;
-        if (i < end) {
-          code = J.lvl_code[i];
-          int cnt[4];
-          letter_counts(code, D, cnt);
-          for (int x = 0; x < 4; ++x) {
-            cnt[x]++;
-            double p = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
-            cnt[x]--;
-            if (node_expanded(B, 1, cap, 0, p, D + 1, code * 4 + x)) mask |= 1u << x;
-          }
-        }
-        uint64_t total;
-        uint32_t pos = next + static_cast<uint32_t>(block_exclusive_scan(__popc(mask), s_warp, &total));
-        if (i < end) {
-          J.lvl_mask[i] = static_cast<uint8_t>(mask);
-          J.lvl_first[i] = pos;
-          for (int x = 0; x < 4; ++x)
-            if (mask & (1u << x)) {
-              if (pos < J.n_expand) J.lvl_code[pos] = code * 4 + x;
-              else s_error = kBuildItemCount;
-              ++pos;
-            }
-        }
-        next += static_cast<uint32_t>(total);
-      }
-      if (tid == 0) s_lvl_start[D + 2] = next;
-      __syncthreads();
-      if (s_error) goto finish;
-    }
-    const int levels = D;  // levels 0..levels-1 are non-empty
-    if (tid == 0 && s_lvl_start[levels] != J.n_expand) s_error = kBuildItemCount;
-    __syncthreads();
-    if (s_error) goto finish;
-    // bottom-up leaf counts
-    for (int L = levels - 1; L >= 0; --L) {
-      for (uint32_t i = s_lvl_start[L] + tid; i < s_lvl_start[L + 1]; i += kBuildThreads) {
-        uint32_t mask = J.lvl_mask[i], f = J.lvl_first[i], size = 0;
-        for (int x = 0; x < 4; ++x) size += (mask & (1u << x)) ? J.lvl_size[f++] : 1u;
-        J.lvl_size[i] = size;
-      }
-      __syncthreads();
-    }
-    if (tid == 0 && J.lvl_size[0] != n) s_error = kBuildItemCount;
-    __syncthreads();
-    if (s_error) goto finish;
-    // top-down leaf placement
-    if (tid == 0) J.lvl_off[0] = 0;
-    __syncthreads();
-    for (int L = 0; L < levels; ++L) {
-      for (uint32_t i = s_lvl_start[L] + tid; i < s_lvl_start[L + 1]; i += kBuildThreads) {
-        uint32_t mask = J.lvl_mask[i], f = J.lvl_first[i], cur = J.lvl_off[i], code = J.lvl_code[i];
-        int cnt[4];
-        letter_counts(code, L, cnt);
-        for (int x = 0; x < 4; ++x) {
-          if (mask & (1u << x)) {
-            J.lvl_off[f] = cur;
-            cur += J.lvl_size[f];
-            ++f;
-          } else {
-            uint32_t cc = code * 4 + x, r, c;
-            split_code(cc, L + 1, &r, &c);
-            cnt[x]++;
-            J.item_len[cur] = L + 1;
-            J.item_row[cur] = r;
-            J.item_col[cur] = c;
-            J.item_p[cur] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
-            cnt[x]--;
-            ++cur;
-          }
-        }
-      }
-      __syncthreads();
-    }
+    if (!ok) goto finish;
   }
   for (uint32_t j = n + tid; j < nb; j += kBuildThreads) {
     J.item_len[j] = 0; J.item_row[j] = 0; J.item_col[j] = 0; J.item_p[j] = 0.0;
@@ -681,11 +711,25 @@ finish:
   }
 }
 
+// One workgroup per job, jobs in device memory (batches, table sets).
+__global__ __launch_bounds__(kBuildThreads) void table_build_kernel(const BuildJob* __restrict__ jobs) {
+  const BuildJob J = jobs[blockIdx.x];
+  build_table(J);
+}
+
+// A single job passed by value (no upload before the launch).
+__global__ __launch_bounds__(kBuildThreads) void table_build_one_kernel(BuildJob J) { build_table(J); }
+
 }  // namespace
 
 hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(table_build_kernel, dim3(n_jobs), dim3(kBuildThreads), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_build_one(const BuildJob& job, hipStream_t s) {
+  hipLaunchKernelGGL(table_build_one_kernel, dim3(1), dim3(kBuildThreads), 0, s, job);
   return hipGetLastError();
 }
 

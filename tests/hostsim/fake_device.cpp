@@ -142,6 +142,8 @@ hipError_t launch_table_build(const BuildJob* jobs, int n, hipStream_t) {
   return hipSuccess;
 }
 
+hipError_t launch_table_build_one(const BuildJob& job, hipStream_t s) { return launch_table_build(&job, 1, s); }
+
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
   ++g_launches;
   if (a.n_items == 0) return hipSuccess;
