@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--served-reading", default="A", choices=["A", "B"])
     ap.add_argument("--served-no-plain", action="store_true", help="skip the plain-launch comparison of the stream")
     ap.add_argument("--no-k34", action="store_true", help="skip the k=34 chunked instance")
+    ap.add_argument("--no-sec5", action="store_true",
+                    help="skip the epilogue, perturbed-set and partitioned measurements of the k=26 instance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sampler needs no second one "
@@ -337,44 +339,45 @@ def main():
                      "ops_per_edge": ops_per_edge,
                      "traffic": traffic},
     }
-    # the Sec. 5 epilogue (undirected mirror + id scramble) on the same instance
-    t_epi = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
-    R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
-    ea, eb_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ea.record(stream)
-    R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
-    eb_.record(stream)
-    torch.cuda.synchronize()
-    out["undirected_scrambled_kernel_ms"] = ea.elapsed_time(eb_)
-    out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
-    t_epi.close()
-    # degree smoothing (Sec. 5): 8 perturbed tables of bound 1024 (eps 0.1),
-    # edge e from table e mod 8; the whole set stays LDS-resident
-    t_set = R.rmat_build_perturbed_table(w["a"], w["b"], w["c"], w["d"], k, 1024, R.RMAT_VARIABLE, 8, 0.1, 2019)
-    R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
-    ea.record(stream)
-    R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
-    eb_.record(stream)
-    torch.cuda.synchronize()
-    out["perturbed_set"] = {"tables": 8, "table_bound": 1024, "epsilon": 0.1,
-                            "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
-    t_set.close()
-    # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
-    # tile rows [0, 64) per call, four calls; counting on the host included
-    t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
-    n_part = 0
-    for r0 in range(0, 256, 64):
-        cnt = R.rmat_partition_counts(t_part, w["seed"], m, 8, r0, r0 + 64)
-        n = int(cnt.sum())
-        R.rmat_generate_partition(t_part, w["seed"], m, 8, r0, r0 + 64, src, dst, n)
-        n_part += n
-    part_s = time.perf_counter() - p0
-    assert n_part == m
-    out["partitioned_edges_per_s"] = m / part_s
-    out["partitioned_config"] = {"tile_bits": 8, "row_ranges": 4}
-    t_part.close()
+    if not args.no_sec5:
+        # the Sec. 5 epilogue (undirected mirror + id scramble) on the same instance
+        t_epi = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+        R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
+        ea, eb_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
+        eb_.record(stream)
+        torch.cuda.synchronize()
+        out["undirected_scrambled_kernel_ms"] = ea.elapsed_time(eb_)
+        out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
+        t_epi.close()
+        # degree smoothing (Sec. 5): 8 perturbed tables of bound 1024 (eps 0.1),
+        # edge e from table e mod 8; the whole set stays LDS-resident
+        t_set = R.rmat_build_perturbed_table(w["a"], w["b"], w["c"], w["d"], k, 1024, R.RMAT_VARIABLE, 8, 0.1, 2019)
+        R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
+        ea.record(stream)
+        R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
+        eb_.record(stream)
+        torch.cuda.synchronize()
+        out["perturbed_set"] = {"tables": 8, "table_bound": 1024, "epsilon": 0.1,
+                                "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
+        t_set.close()
+        # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
+        # tile rows [0, 64) per call, four calls; counting on the host included
+        t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        n_part = 0
+        for r0 in range(0, 256, 64):
+            cnt = R.rmat_partition_counts(t_part, w["seed"], m, 8, r0, r0 + 64)
+            n = int(cnt.sum())
+            R.rmat_generate_partition(t_part, w["seed"], m, 8, r0, r0 + 64, src, dst, n)
+            n_part += n
+        part_s = time.perf_counter() - p0
+        assert n_part == m
+        out["partitioned_edges_per_s"] = m / part_s
+        out["partitioned_config"] = {"tile_bits": 8, "row_ranges": 4}
+        t_part.close()
     del src, dst
     torch.cuda.empty_cache()
     if not args.no_batch:

@@ -208,14 +208,38 @@ struct BatchLaunch {
   TileLayout L;
 };
 
+// (x * m + a) mod 2^64 with 32-bit x, m: one v_mad_u64_u32, which runs at
+// the full vector rate on gfx950 where v_mul_lo_u32 does not.  m is
+// wave-uniform (an instance parameter).
+__device__ __forceinline__ uint64_t mad_u64_u32(uint32_t x, uint32_t m, uint64_t a) {
+  uint64_t r, carry;
+  __asm__("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(x), "s"(m), "v"(a));
+  return r;
+}
+
 // The scramble bijection of [0, 2^k): three rounds of an affine map with an
 // odd multiplier followed by an xor-shift, each a bijection mod 2^k.  In
 // 32-bit arithmetic when the ids are (k <= 32: the low k bits agree).
-template <typename Id>
-__device__ __forceinline__ Id scramble_id(Id x, const Inst& I) {
+__device__ __forceinline__ uint32_t scramble_id(uint32_t x, const Inst& I) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    x = (x * static_cast<Id>(I.scr_mul[r]) + static_cast<Id>(I.scr_add[r])) & static_cast<Id>(I.scr_mask);
+    x = static_cast<uint32_t>(mad_u64_u32(x, static_cast<uint32_t>(I.scr_mul[r]), static_cast<uint32_t>(I.scr_add[r]))) &
+        static_cast<uint32_t>(I.scr_mask);
+    x ^= x >> I.scr_shift;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t scramble_id(uint64_t x, const Inst& I) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    // low 64 bits of x * mul + add from 32-bit halves
+    const uint32_t xl = static_cast<uint32_t>(x), xh = static_cast<uint32_t>(x >> 32);
+    const uint32_t ml = static_cast<uint32_t>(I.scr_mul[r]), mh = static_cast<uint32_t>(I.scr_mul[r] >> 32);
+    const uint64_t t = mad_u64_u32(xl, ml, I.scr_add[r]);
+    uint32_t hi = static_cast<uint32_t>(mad_u64_u32(xl, mh, t >> 32));
+    hi = static_cast<uint32_t>(mad_u64_u32(xh, ml, hi));
+    x = ((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(t)) & I.scr_mask;
     x ^= x >> I.scr_shift;
   }
   return x;
@@ -358,10 +382,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     // a full tile of whole blocks (every tile but a few at the ends of the
     // range) runs unrolled, without per-block lane masks
     const bool prefixed = kGeneral && (I.src_prefix | I.dst_prefix) != 0;
-    const bool whole_tile = nb_tile == kMaxTile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
-                            (t0 + (kMaxTile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
+    const bool whole_tile = nb_tile == L.tile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
+                            (t0 + (nb_tile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
     const bool sure1 = I.k > static_cast<uint32_t>(kMaxDepthCap);  // a path has at most kMaxDepthCap letters
-    if (whole_tile && sure1) {
+    if (whole_tile && sure1 && nb_tile == kMaxTile) {
       // software-pipelined: block j's Philox draws and table reads are issued
       // before block j - 1's samples are consumed, so the reads overlap work
       auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
@@ -404,6 +428,16 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         }
       }
       finish(kMaxTile - 1, xa, ra);
+    } else if (whole_tile) {
+      // a full tile of another size (a larger table or an L2 table leaves
+      // less LDS for tiles): whole blocks, rolled
+      for (uint32_t j = 0; j < nb_tile; ++j) {
+        const uint64_t base = (I.first_block + t0 + j * stride) << 6;
+        if (sure1)
+          first_block(j, base, ~0ull, std::true_type{}, std::true_type{});
+        else
+          first_block(j, base, ~0ull, std::true_type{}, std::false_type{});
+      }
     } else {
       for (uint32_t j = 0; j < nb_tile; ++j) {
         const uint64_t rel = t0 + j * stride;                 // block index within the instance
@@ -481,6 +515,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
 #pragma unroll
       for (uint32_t j = 0; j < kMaxTile; ++j) {
+        if (j >= nb_tile) break;
         Acc acc;
         acc.unpack(vals[j]);
         Id sv = static_cast<Id>(acc.src(I.k));
