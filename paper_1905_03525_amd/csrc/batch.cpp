@@ -22,6 +22,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // Instances of one id width and table residency share a generation launch.
 struct Group {
   int wide, lds;
+  int general;  // some instance has epilogue flags
   uint32_t max_buckets;
   uint32_t n_items;
   rmat::GenWorkItem* items;  // device, this group's items in instance order
@@ -150,6 +151,7 @@ int enqueue(rmat_batch* b, hipStream_t s) {
     a.wide = g.wide;
     a.lds = g.lds;
     a.digest = 0;
+    a.general = g.general;
     e = rmat::launch_generate_batch(a, s);
     if (e != hipSuccess) return rmat::hip_fail(e, "batch generation launch");
   }
@@ -287,6 +289,7 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
       Group g;
       g.wide = wide;
       g.lds = lds;
+      g.general = 0;
       g.max_buckets = 0;
       g.items = nullptr;
       g.counter = nullptr;
@@ -297,6 +300,7 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
         if ((x.k > 32) != (wide != 0) || (S.n_buckets <= lds_limit) != (lds != 0)) continue;
         g.max_buckets = std::max<uint32_t>(g.max_buckets, static_cast<uint32_t>(S.n_buckets));
         if (x.m == 0) continue;
+        if (x.flags & (RMAT_UNDIRECTED | RMAT_SCRAMBLE)) g.general = 1;
         const uint64_t first = x.edge_begin >> 6;
         const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - first + 1;
         for (uint64_t f = 0; f < nblk; f += b->work_blocks) {

@@ -591,7 +591,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
 // Persistent kernel over the work items of a batch.  A workgroup claims an
 // item, restages the table only when the instance changes (items are in
 // instance order), and its 16 waves share the item's blocks.
-template <typename Acc, bool kLds, bool kDigest>
+template <typename Acc, bool kLds, bool kDigest, bool kGeneral>
 __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch B) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ uint32_t s_item;
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     cur = W.inst;
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
     uint64_t xsum = 0;
-    run_blocks<Acc, false, kDigest>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0,
+    run_blocks<Acc, false, kDigest, kGeneral>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0,
                                     nullptr, xsum);
     if (kDigest && I.digest != nullptr) {
       const uint64_t x = wave_xor(xsum);
@@ -892,7 +892,7 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   return hipSuccess;
 }
 
-template <typename Acc, bool kLds, bool kDigest>
+template <typename Acc, bool kLds, bool kDigest, bool kGeneral>
 hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   BatchLaunch B;
   B.insts = a.insts;
@@ -905,7 +905,7 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   uint64_t grid = persistent_grid(lds);
   if (grid > a.n_items) grid = a.n_items;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((generate_batch_kernel<Acc, kLds, kDigest>), dim3(static_cast<uint32_t>(grid)),
+  hipLaunchKernelGGL((generate_batch_kernel<Acc, kLds, kDigest, kGeneral>), dim3(static_cast<uint32_t>(grid)),
                      dim3(kGenThreads), lds, s, B);
   return hipGetLastError();
 }
@@ -938,12 +938,14 @@ hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return
 
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s) {
   if (a.n_items == 0) return hipSuccess;
-  if (a.digest) {
-    if (a.wide) return a.lds ? launch_batch<Acc64, true, true>(a, s) : launch_batch<Acc64, false, true>(a, s);
-    return a.lds ? launch_batch<Acc32, true, true>(a, s) : launch_batch<Acc32, false, true>(a, s);
-  }
-  if (a.wide) return a.lds ? launch_batch<Acc64, true, false>(a, s) : launch_batch<Acc64, false, false>(a, s);
-  return a.lds ? launch_batch<Acc32, true, false>(a, s) : launch_batch<Acc32, false, false>(a, s);
+  // digests and the epilogue/prefix store each take their own instantiation
+  auto pick = [&](auto digest, auto general) {
+    constexpr bool kD = decltype(digest)::value, kG = decltype(general)::value;
+    if (a.wide) return a.lds ? launch_batch<Acc64, true, kD, kG>(a, s) : launch_batch<Acc64, false, kD, kG>(a, s);
+    return a.lds ? launch_batch<Acc32, true, kD, kG>(a, s) : launch_batch<Acc32, false, kD, kG>(a, s);
+  };
+  if (a.digest) return a.general ? pick(std::true_type{}, std::true_type{}) : pick(std::true_type{}, std::false_type{});
+  return a.general ? pick(std::false_type{}, std::true_type{}) : pick(std::false_type{}, std::false_type{});
 }
 
 uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds) {
@@ -969,14 +971,22 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_kernel<Acc32, false, true, false>),
       allow_full_lds(&generate_kernel<Acc64, true, true, false>),
       allow_full_lds(&generate_kernel<Acc64, false, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, false, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true, true>),
-      allow_full_lds(&generate_batch_kernel<Acc32, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc32, true, false, false>),
+      allow_full_lds(&generate_batch_kernel<Acc32, true, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc32, true, true, false>),
+      allow_full_lds(&generate_batch_kernel<Acc32, true, true, true>),
+      allow_full_lds(&generate_batch_kernel<Acc32, false, false, false>),
+      allow_full_lds(&generate_batch_kernel<Acc32, false, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc32, false, true, false>),
+      allow_full_lds(&generate_batch_kernel<Acc32, false, true, true>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true, false, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true, true, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, true, true, true>),
+      allow_full_lds(&generate_batch_kernel<Acc64, false, false, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, false, false, true>),
+      allow_full_lds(&generate_batch_kernel<Acc64, false, true, false>),
+      allow_full_lds(&generate_batch_kernel<Acc64, false, true, true>),
       allow_full_lds(&hist_partial_kernel),
       allow_full_lds(&kron_kernel<uint32_t, true>),
       allow_full_lds(&kron_kernel<uint64_t, true>)};

@@ -354,6 +354,7 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     a.wide = info.k > 32;
     a.lds = info.lds_resident != 0;
     a.digest = 0;
+    a.general = 1;  // tiles carry id prefixes
     e = rmat::launch_generate_batch(a, nullptr);
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();

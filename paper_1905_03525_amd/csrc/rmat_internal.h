@@ -136,6 +136,7 @@ struct BatchArgs {
   int wide;                // k > 32 (64-bit ids)
   int lds;                 // tables staged in LDS
   int digest;              // honour GenInst::digest
+  int general;             // some instance has an epilogue or id prefixes
 };
 
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s);

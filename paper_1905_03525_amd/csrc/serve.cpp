@@ -439,6 +439,7 @@ int issue_round(rmat_server* s, bool* launched) {
   std::vector<rmat::GenWorkItem> items[kGroups];
   uint32_t max_buckets[kGroups] = {0, 0, 0, 0};
   bool digest[kGroups] = {false, false, false, false};
+  bool general[kGroups] = {false, false, false, false};
   uint64_t budget = c.tick_blocks;
   const size_t n_act = s->active.size();
   size_t last_served = s->rr;
@@ -481,6 +482,7 @@ int issue_round(rmat_server* s, bool* launched) {
     }
     max_buckets[g] = std::max(max_buckets[g], I.n_buckets);
     if (q->r.flags & RMAT_REQ_DIGEST) digest[g] = true;
+    if (q->r.flags & (RMAT_REQ_UNDIRECTED | RMAT_REQ_SCRAMBLE)) general[g] = true;
     q->next_block += take;
     q->last_round = s->next_round;
     budget -= take;
@@ -536,6 +538,7 @@ int issue_round(rmat_server* s, bool* launched) {
     a.wide = g >> 1;
     a.lds = g & 1;
     a.digest = digest[g] ? 1 : 0;
+    a.general = general[g] ? 1 : 0;
     e = rmat::launch_generate_batch(a, s->stream);
   }
   const uint64_t back = off_insts - off_dig;
