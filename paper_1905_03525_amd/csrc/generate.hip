@@ -209,38 +209,69 @@ struct BatchLaunch {
 };
 
 // (x * m + a) mod 2^64 with 32-bit x, m: one v_mad_u64_u32, which runs at
-// the full vector rate on gfx950 where v_mul_lo_u32 does not.  m is
-// wave-uniform (an instance parameter).
+// the full vector rate on gfx950 where v_mul_lo_u32 does not.
 __device__ __forceinline__ uint64_t mad_u64_u32(uint32_t x, uint32_t m, uint64_t a) {
   uint64_t r, carry;
-  __asm__("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(x), "s"(m), "v"(a));
+  __asm__("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(x), "v"(m), "v"(a));
   return r;
+}
+
+// A wave-uniform value held in a vector register: the epilogue's parameters
+// stay out of the scalar registers, which the tile loop needs.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+  uint32_t r;
+  __asm__("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+__device__ __forceinline__ uint64_t in_vgpr(uint64_t x) {
+  return (static_cast<uint64_t>(in_vgpr(static_cast<uint32_t>(x >> 32))) << 32) | in_vgpr(static_cast<uint32_t>(x));
+}
+
+// The Sec. 5 epilogue of a launch: flags and the scramble's round constants.
+template <typename Id>
+struct Epilogue {
+  uint32_t flags;  // kEpiUndirected | kEpiScramble, wave-uniform
+  Id mul[3], add[3], mask;
+  uint32_t shift;
+};
+
+template <typename Id>
+__device__ __forceinline__ Epilogue<Id> make_epilogue(const Inst& I) {
+  Epilogue<Id> E;
+  E.flags = I.epi;
+  for (int r = 0; r < 3; ++r) {
+    E.mul[r] = in_vgpr(static_cast<Id>(I.scr_mul[r]));
+    E.add[r] = in_vgpr(static_cast<Id>(I.scr_add[r]));
+  }
+  E.mask = in_vgpr(static_cast<Id>(I.scr_mask));
+  E.shift = in_vgpr(I.scr_shift);
+  return E;
 }
 
 // The scramble bijection of [0, 2^k): three rounds of an affine map with an
 // odd multiplier followed by an xor-shift, each a bijection mod 2^k.  In
 // 32-bit arithmetic when the ids are (k <= 32: the low k bits agree).
-__device__ __forceinline__ uint32_t scramble_id(uint32_t x, const Inst& I) {
+__device__ __forceinline__ uint32_t scramble_id(uint32_t x, const Epilogue<uint32_t>& E) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    x = static_cast<uint32_t>(mad_u64_u32(x, static_cast<uint32_t>(I.scr_mul[r]), static_cast<uint32_t>(I.scr_add[r]))) &
-        static_cast<uint32_t>(I.scr_mask);
-    x ^= x >> I.scr_shift;
+    x = static_cast<uint32_t>(mad_u64_u32(x, E.mul[r], E.add[r])) & E.mask;
+    x ^= x >> E.shift;
   }
   return x;
 }
 
-__device__ __forceinline__ uint64_t scramble_id(uint64_t x, const Inst& I) {
+__device__ __forceinline__ uint64_t scramble_id(uint64_t x, const Epilogue<uint64_t>& E) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     // low 64 bits of x * mul + add from 32-bit halves
     const uint32_t xl = static_cast<uint32_t>(x), xh = static_cast<uint32_t>(x >> 32);
-    const uint32_t ml = static_cast<uint32_t>(I.scr_mul[r]), mh = static_cast<uint32_t>(I.scr_mul[r] >> 32);
-    const uint64_t t = mad_u64_u32(xl, ml, I.scr_add[r]);
+    const uint32_t ml = static_cast<uint32_t>(E.mul[r]), mh = static_cast<uint32_t>(E.mul[r] >> 32);
+    const uint64_t t = mad_u64_u32(xl, ml, E.add[r]);
     uint32_t hi = static_cast<uint32_t>(mad_u64_u32(xl, mh, t >> 32));
     hi = static_cast<uint32_t>(mad_u64_u32(xh, ml, hi));
-    x = ((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(t)) & I.scr_mask;
-    x ^= x >> I.scr_shift;
+    x = ((static_cast<uint64_t>(hi) << 32) | static_cast<uint32_t>(t)) & E.mask;
+    x ^= x >> E.shift;
   }
   return x;
 }
@@ -248,16 +279,16 @@ __device__ __forceinline__ uint64_t scramble_id(uint64_t x, const Inst& I) {
 // The Sec. 5 epilogue on one edge, when the launch asks for it (uniform):
 // mirror to row <= column, then relabel both ids.
 template <bool kGeneral, typename Id>
-__device__ __forceinline__ void epilogue(const Inst& I, Id& s, Id& d) {
-  if (kGeneral && I.epi != 0) {
-    if (I.epi & kEpiUndirected) {
+__device__ __forceinline__ void epilogue(const Epilogue<Id>& E, Id& s, Id& d) {
+  if (kGeneral && E.flags != 0) {
+    if (E.flags & kEpiUndirected) {
       const Id lo = s < d ? s : d;
       d = s < d ? d : s;
       s = lo;
     }
-    if (I.epi & kEpiScramble) {
-      s = scramble_id(s, I);
-      d = scramble_id(d, I);
+    if (E.flags & kEpiScramble) {
+      s = scramble_id(s, E);
+      d = scramble_id(d, E);
     }
   }
 }
@@ -346,6 +377,8 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   // edge e reads table e mod P; blocks start at multiples of 64 and P divides
   // 64, so in pass 1 that is the lane's table for the whole run
   const BucketRecord* __restrict__ tab_lane = tab + (lane & I.table_mask) * I.n_buckets;
+  Epilogue<Id> E;
+  if (kGeneral) E = make_epilogue<Id>(I);
   for (uint64_t t0 = wave_blk; t0 < blk_end; t0 += stride * L.tile) {
     // blocks t0 + j * stride below blk_end, at most L.tile (counted without
     // a 64-bit division: only a wave's last tile is short)
@@ -489,7 +522,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
             s |= static_cast<Id>(I.src_prefix);
             d |= static_cast<Id>(I.dst_prefix);
           }
-          epilogue<kGeneral>(I, s, d);
+          epilogue<kGeneral>(E, s, d);
           store_ids(I.out_src, base - I.edge_begin, lane, s);
           store_ids(I.out_dst, base - I.edge_begin, lane, d);
           if (kDigest) {
@@ -513,22 +546,43 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_dst) + slot0, 0,
                                                                            0x7FFFFFFF, kBufferDword3);
       const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
+      // the epilogue's kind is chosen once per tile, so the unrolled stores
+      // carry no per-block branches
+      auto store_tile = [&](auto undirected, auto scrambled) {
 #pragma unroll
-      for (uint32_t j = 0; j < kMaxTile; ++j) {
-        if (j >= nb_tile) break;
-        Acc acc;
-        acc.unpack(vals[j]);
-        Id sv = static_cast<Id>(acc.src(I.k));
-        Id dv = static_cast<Id>(acc.dst(I.k));
-        epilogue<kGeneral>(I, sv, dv);
-        store_at(rs, lane, j * step, sv);
-        store_at(rd, lane, j * step, dv);
-        if (kDigest) {
-          const uint64_t e = ((I.first_block + t0 + j * stride) << 6) + lane;
-          const uint64_t s64 = sv, d64 = dv;
-          xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
+        for (uint32_t j = 0; j < kMaxTile; ++j) {
+          if (j >= nb_tile) break;
+          Acc acc;
+          acc.unpack(vals[j]);
+          Id sv = static_cast<Id>(acc.src(I.k));
+          Id dv = static_cast<Id>(acc.dst(I.k));
+          if (decltype(undirected)::value) {
+            const Id lo = sv < dv ? sv : dv;
+            dv = sv < dv ? dv : sv;
+            sv = lo;
+          }
+          if (decltype(scrambled)::value) {
+            sv = scramble_id(sv, E);
+            dv = scramble_id(dv, E);
+          }
+          store_at(rs, lane, j * step, sv);
+          store_at(rd, lane, j * step, dv);
+          if (kDigest) {
+            const uint64_t e = ((I.first_block + t0 + j * stride) << 6) + lane;
+            const uint64_t s64 = sv, d64 = dv;
+            xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
+          }
         }
-      }
+      };
+      const uint32_t epi = kGeneral ? E.flags : 0u;
+      if (epi == 0)
+        store_tile(std::false_type{}, std::false_type{});
+      else if (epi == kEpiUndirected)
+        store_tile(std::true_type{}, std::false_type{});
+      else if (epi == kEpiScramble)
+        store_tile(std::false_type{}, std::true_type{});
+      else
+        store_tile(std::true_type{}, std::true_type{});
     } else {
 #pragma unroll
       for (uint32_t j = 0; j < kMaxTile; ++j) {
