@@ -334,3 +334,25 @@ def test_epilogue_flags_zero_is_plain_and_bad_flags_rejected(R):
         R.rmat_generate_ex_async(t, 3, 0, 10, 4, 0, a, b)
     assert ei.value.status == R.RMAT_EINVAL
     t.close()
+
+
+def test_concurrent_builds_match_serial(R):
+    """Table builds from several host threads at once (they share the
+    library's per-device build buffer) give the same tables as serial ones."""
+    from concurrent.futures import ThreadPoolExecutor
+    cases = [(_dirichlet(s), 12 + s, 200 + 700 * s, R.RMAT_VARIABLE) for s in range(8)]
+    cases += [(G500, 26, 4096, R.RMAT_VARIABLE), (CFG3, 34, 1 << 16, R.RMAT_VARIABLE), (G500, 20, 4096, R.RMAT_FIXED)]
+
+    def build_export(c):
+        t = R.rmat_build_table(*c[0], c[1], c[2], c[3])
+        g = R.rmat_table_export(t)
+        t.close()
+        return g
+
+    serial = [build_export(c) for c in cases]
+    for _ in range(3):
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            par = list(ex.map(build_export, cases))
+        for a, b in zip(serial, par):
+            for f in a:
+                assert np.array_equal(a[f], b[f]), f
