@@ -132,55 +132,45 @@ struct Acc64 {
   __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
 
-// Up to four samples from one Philox block, stopping at k letters.  A sample
-// x picks bucket x >> (32 - b) and keeps the bucket's own path when x <
-// thr_abs (= bucket * C + T), else takes its alias.  The four bucket records
-// are read before any of them is used, so four LDS reads are in flight.
+// Up to four samples of one Philox block, stopping at k letters, on bucket
+// records already loaded.  A sample x picks bucket x >> (32 - b) and keeps
+// the bucket's own path when x < thr_abs (= bucket * C + T), else takes its
+// alias; each field is the low half-word for the own item, else the high
+// one.  kSure1: the second sample is always used (k > kMaxDepthCap letters
+// cannot come from one path).
 template <typename Acc, bool kSure1 = false>
-__device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
-                                        uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled) {
-  const BucketRecord r0 = tab[x0 >> shift], r1 = tab[x1 >> shift], r2 = tab[x2 >> shift], r3 = tab[x3 >> shift];
-  // keep the reads ahead of the branches below (an operand-only asm, no code)
-  __asm__ volatile("" ::"v"(r1.thr_abs), "v"(r1.rows), "v"(r1.cols), "v"(r1.lens), "v"(r2.thr_abs), "v"(r2.rows),
-                   "v"(r2.cols), "v"(r2.lens), "v"(r3.thr_abs), "v"(r3.rows), "v"(r3.cols), "v"(r3.lens));
-  const bool o0 = x0 < r0.thr_abs, o1 = x1 < r1.thr_abs, o2 = x2 < r2.thr_abs, o3 = x3 < r3.thr_abs;
-  // each field is the low half-word for the bucket's own item, else the high one
-  auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
-  acc.append(half(o0, r0.rows), half(o0, r0.cols), filled);
-  filled += half(o0, r0.lens);
-  if (kSure1 || filled < k) {
-    acc.append(half(o1, r1.rows), half(o1, r1.cols), filled);
-    filled += half(o1, r1.lens);
-    if (filled < k) {
-      acc.append(half(o2, r2.rows), half(o2, r2.cols), filled);
-      filled += half(o2, r2.lens);
-      if (filled < k) {
-        acc.append(half(o3, r3.rows), half(o3, r3.cols), filled);
-        filled += half(o3, r3.lens);
-      }
-    }
-  }
-}
-
-// The sampling half of sample4 on records already loaded (k > kMaxDepthCap:
-// the first two samples are always used).
-template <typename Acc>
 __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
                                          uint32_t& filled) {
   auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
   const bool o0 = x[0] < r[0].thr_abs, o1 = x[1] < r[1].thr_abs, o2 = x[2] < r[2].thr_abs, o3 = x[3] < r[3].thr_abs;
   acc.append(half(o0, r[0].rows), half(o0, r[0].cols), filled);
   filled += half(o0, r[0].lens);
-  acc.append(half(o1, r[1].rows), half(o1, r[1].cols), filled);
-  filled += half(o1, r[1].lens);
-  if (filled < k) {
-    acc.append(half(o2, r[2].rows), half(o2, r[2].cols), filled);
-    filled += half(o2, r[2].lens);
+  if (kSure1 || filled < k) {
+    acc.append(half(o1, r[1].rows), half(o1, r[1].cols), filled);
+    filled += half(o1, r[1].lens);
     if (filled < k) {
-      acc.append(half(o3, r[3].rows), half(o3, r[3].cols), filled);
-      filled += half(o3, r[3].lens);
+      acc.append(half(o2, r[2].rows), half(o2, r[2].cols), filled);
+      filled += half(o2, r[2].lens);
+      if (filled < k) {
+        acc.append(half(o3, r[3].rows), half(o3, r[3].cols), filled);
+        filled += half(o3, r[3].lens);
+      }
     }
   }
+}
+
+// Loads the four bucket records of one Philox block, then samples them.  All
+// four reads are issued before any is used, so they are in flight together.
+template <typename Acc, bool kSure1 = false>
+__device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
+                                        uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled) {
+  const uint32_t x[4] = {x0, x1, x2, x3};
+  const BucketRecord r[4] = {tab[x0 >> shift], tab[x1 >> shift], tab[x2 >> shift], tab[x3 >> shift]};
+  // keep the reads ahead of the branches below (an operand-only asm, no code)
+  __asm__ volatile("" ::"v"(r[1].thr_abs), "v"(r[1].rows), "v"(r[1].cols), "v"(r[1].lens), "v"(r[2].thr_abs),
+                   "v"(r[2].rows), "v"(r[2].cols), "v"(r[2].lens), "v"(r[3].thr_abs), "v"(r[3].rows), "v"(r[3].cols),
+                   "v"(r[3].lens));
+  consume4<Acc, kSure1>(k, x, r, acc, filled);
 }
 
 using Inst = GenInst;
@@ -432,7 +422,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         Acc acc;
         acc.clear();
         uint32_t filled = 0;
-        consume4(I.k, x, r, acc, filled);
+        consume4<Acc, true>(I.k, x, r, acc, filled);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;
         const uint64_t ovf_mask = __ballot(need);
