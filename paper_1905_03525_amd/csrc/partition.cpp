@@ -22,6 +22,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "rmat.h"
@@ -199,31 +201,49 @@ struct Counter {
   uint32_t row_begin, row_end;
   uint64_t* counts;  // (row_end - row_begin) x 2^t, row-major
 
-  void visit(int level, uint32_t r, uint32_t c, uint64_t n) {
-    if (level == t) {
-      counts[(static_cast<uint64_t>(r - row_begin) << t) | c] = n;
-      return;
-    }
-    if (n == 0) return;
-    NodeStream st(seed, r, c, level);
+  struct Node {
+    int level;
+    uint32_t r, c;
+    uint64_t n;
+  };
+
+  // The four children of node (level, r, c) holding n edges, those whose
+  // tile rows meet [row_begin, row_end), in quadrant order.
+  int split(const Node& x, Node out[4]) const {
+    NodeStream st(seed, x.r, x.c, x.level);
     const double bcd = q[1] + q[2] + q[3];
     const double cd = q[2] + q[3];
     uint64_t child[4];
-    child[0] = bin(st, n, q[0]);
-    uint64_t rest = n - child[0];
+    child[0] = bin(st, x.n, q[0]);
+    uint64_t rest = x.n - child[0];
     child[1] = bin(st, rest, bcd > 0.0 ? q[1] / bcd : 0.0);
     rest -= child[1];
     child[2] = bin(st, rest, cd > 0.0 ? q[2] / cd : 0.0);
     child[3] = rest - child[2];
-    const int below = t - level - 1;
+    const int below = t - x.level - 1;
+    int k = 0;
     for (int quad = 0; quad < 4; ++quad) {
-      const uint32_t cr = 2 * r + static_cast<uint32_t>(quad >> 1);
-      const uint32_t cc = 2 * c + static_cast<uint32_t>(quad & 1);
+      const uint32_t cr = 2 * x.r + static_cast<uint32_t>(quad >> 1);
+      const uint32_t cc = 2 * x.c + static_cast<uint32_t>(quad & 1);
       const uint64_t first = static_cast<uint64_t>(cr) << below, end = static_cast<uint64_t>(cr + 1) << below;
       if (end <= row_begin || first >= row_end) continue;
-      visit(level + 1, cr, cc, child[quad]);
+      out[k++] = Node{x.level + 1, cr, cc, child[quad]};
     }
+    return k;
   }
+
+  void visit(const Node& x) {
+    if (x.level == t) {
+      counts[(static_cast<uint64_t>(x.r - row_begin) << t) | x.c] = x.n;
+      return;
+    }
+    if (x.n == 0) return;
+    Node ch[4];
+    const int k = split(x, ch);
+    for (int i = 0; i < k; ++i) visit(ch[i]);
+  }
+
+  void run(uint64_t m) { visit(Node{0, 0, 0, m}); }
 };
 
 constexpr uint64_t kMaxTilesPerCall = 1ull << 18;
@@ -250,6 +270,31 @@ const TableView* table_view_of(const rmat_table* t);
 const double* table_params_of(const rmat_table* t);
 }  // namespace rmat
 
+namespace {
+// The last counts computed, so that generating the tiles right after asking
+// for their counts (the usual order) does not draw the tree twice.  Counts
+// are a function of (a, b, c, d, seed, m, tile_bits, rows) alone, which is
+// the key.
+struct CountCache {
+  std::mutex mu;
+  bool valid = false;
+  double q[4] = {0, 0, 0, 0};
+  uint64_t seed = 0, m = 0;
+  int tbits = 0;
+  uint32_t row_begin = 0, row_end = 0;
+  std::vector<uint64_t> counts;
+};
+CountCache g_count_cache;
+
+// Per-device buffers for a generation's instance and work lists, grown on
+// demand and kept until the process ends.
+std::mutex g_lists_mu;
+std::map<int, std::pair<void*, uint64_t>> g_lists;
+
+int counts_cached(rmat_table_t t, uint64_t seed, uint64_t m, int tbits, uint32_t row_begin, uint32_t row_end,
+                  uint64_t* counts);
+}  // namespace
+
 extern "C" {
 
 int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
@@ -267,7 +312,16 @@ int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bi
   C.row_begin = row_begin;
   C.row_end = row_end;
   C.counts = counts;
-  C.visit(0, 0, 0, m);
+  C.run(m);
+  std::lock_guard<std::mutex> lock(g_count_cache.mu);
+  g_count_cache.valid = true;
+  std::memcpy(g_count_cache.q, C.q, sizeof(C.q));
+  g_count_cache.seed = seed;
+  g_count_cache.m = m;
+  g_count_cache.tbits = tile_bits;
+  g_count_cache.row_begin = row_begin;
+  g_count_cache.row_end = row_end;
+  g_count_cache.counts.assign(counts, counts + (static_cast<uint64_t>(row_end - row_begin) << tile_bits));
   return RMAT_OK;
 }
 
@@ -280,7 +334,7 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   if (rc) return rc;
   const uint64_t n_tiles = static_cast<uint64_t>(row_end - row_begin) << tile_bits;
   std::vector<uint64_t> counts(n_tiles);
-  if ((rc = rmat_partition_counts(t, seed, m, tile_bits, row_begin, row_end, counts.data()))) return rc;
+  if ((rc = counts_cached(t, seed, m, tile_bits, row_begin, row_end, counts.data()))) return rc;
   uint64_t total = 0;
   for (uint64_t x : counts) total += x;
   if (total != n_out)
@@ -336,14 +390,30 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   }
   const uint64_t inst_bytes = (insts.size() * sizeof(rmat::GenInst) + 255) / 256 * 256;
   const uint64_t item_bytes = (items.size() * sizeof(rmat::GenWorkItem) + 255) / 256 * 256;
-  void* d = nullptr;
-  hipError_t e = hipMalloc(&d, inst_bytes + item_bytes + 256);
-  if (e != hipSuccess) return rmat::hip_fail(e, "hipMalloc(partition lists)");
-  char* base = static_cast<char*>(d);
-  e = hipMemcpy(base, insts.data(), insts.size() * sizeof(rmat::GenInst), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(base + inst_bytes, items.data(), items.size() * sizeof(rmat::GenWorkItem), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(base + inst_bytes + item_bytes, 0, 256);
+  const uint64_t bytes = inst_bytes + item_bytes + 256;
+  // [instances | work items | zeroed work counter], assembled on the host and
+  // sent in one copy to a device buffer kept between calls (calls are
+  // synchronous and serialised here)
+  std::vector<char> host(bytes, 0);
+  std::memcpy(host.data(), insts.data(), insts.size() * sizeof(rmat::GenInst));
+  std::memcpy(host.data() + inst_bytes, items.data(), items.size() * sizeof(rmat::GenWorkItem));
+  std::lock_guard<std::mutex> lock(g_lists_mu);
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return rmat::hip_fail(e, "hipGetDevice");
+  auto& slot = g_lists[device];
+  if (slot.second < bytes) {
+    if (slot.first) (void)hipFree(slot.first);
+    slot = {nullptr, 0};
+    e = hipMalloc(&slot.first, bytes);
+    if (e != hipSuccess) {
+      slot.first = nullptr;
+      return rmat::hip_fail(e, "hipMalloc(partition lists)");
+    }
+    slot.second = bytes;
+  }
+  char* base = static_cast<char*>(slot.first);
+  e = hipMemcpy(base, host.data(), bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     rmat::BatchArgs a;
     a.insts = reinterpret_cast<const rmat::GenInst*>(base);
@@ -358,9 +428,26 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     e = rmat::launch_generate_batch(a, nullptr);
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  (void)hipFree(d);
   if (e != hipSuccess) return rmat::hip_fail(e, "partitioned generation");
   return RMAT_OK;
 }
 
 }  // extern "C"
+
+namespace {
+// Counts from the cache when the last count had the same key, else counted
+// afresh (the arguments were checked by the caller).
+int counts_cached(rmat_table_t t, uint64_t seed, uint64_t m, int tbits, uint32_t row_begin, uint32_t row_end,
+                  uint64_t* counts) {
+  {
+    std::lock_guard<std::mutex> lock(g_count_cache.mu);
+    const CountCache& c = g_count_cache;
+    if (c.valid && std::memcmp(c.q, rmat::table_params_of(t), sizeof(c.q)) == 0 && c.seed == seed && c.m == m &&
+        c.tbits == tbits && c.row_begin == row_begin && c.row_end == row_end) {
+      std::memcpy(counts, c.counts.data(), c.counts.size() * sizeof(uint64_t));
+      return RMAT_OK;
+    }
+  }
+  return rmat_partition_counts(t, seed, m, tbits, row_begin, row_end, counts);
+}
+}  // namespace
