@@ -79,3 +79,23 @@ def test_partition_errors(R):
         R.rmat_generate_partition(t, 1, 100, 2, 0, 4, x, x, 16)
     assert ei.value.status == R.RMAT_EINVAL
     t.close()
+
+
+def test_counts_of_another_table_are_not_reused(R):
+    """Counting tiles of one table and then generating those of another
+    (same seed, m, tile bits and rows) gives the second table's graph."""
+    import torch
+    k, tb, m, seed = 20, 4, 200_000, 5
+    a = R.rmat_build_table(*G500, k, 4096, R.RMAT_VARIABLE)
+    b = R.rmat_build_table(*CFG3, k, 4096, R.RMAT_VARIABLE)
+    o = oracle.build_table(*CFG3, k, 4096, oracle.VARIABLE)
+    oc, os_, od = oracle.generate_partition(o, seed, m, tb, 0, 1 << tb)
+    R.rmat_partition_counts(a, seed, m, tb, 0, 1 << tb)       # a's counts are now the library's last ones
+    n = int(oc.sum())
+    src = torch.empty(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty(n, dtype=torch.int32, device="cuda")
+    R.rmat_generate_partition(b, seed, m, tb, 0, 1 << tb, src, dst, n)
+    torch.cuda.synchronize()
+    assert np.array_equal(R.to_numpy_ids(src, k), os_) and np.array_equal(R.to_numpy_ids(dst, k), od)
+    a.close()
+    b.close()
