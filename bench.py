@@ -63,9 +63,21 @@ def samples_per_edge(table_export: dict, k: int):
     return en, eb
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(budget_s: float = 12.0) -> dict:
     """The oracle as it stands, on this host's cores, over the first edges of
-    the same instance in 2^24-edge slices until the time budget is used."""
+    the same instance in 2^24-edge slices until the time budget is used; one
+    2^22-edge slice on one thread beside it."""
     import oracle
     threads = max(1, min(os.cpu_count() or 1, 16))
     w = WORKLOAD
@@ -76,8 +88,12 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
         oracle.generate(t, w["seed"], done, sl, threads=threads)
         done += sl
     el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.generate(t, w["seed"], 0, 1 << 22, threads=1)
+    one = (1 << 22) / (time.perf_counter() - t1)
     return {"value": done / el, "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": f"edges [0, {done}) of the same instance in 2^24-edge slices, {el:.1f} s"}
+            "sample": f"edges [0, {done}) of the same instance in 2^24-edge slices, {el:.1f} s",
+            "one_thread_value": one, "cpu_model": _cpu_model()}
 
 
 def batched_vs_plain(R, reps: int = 3) -> dict:
@@ -331,6 +347,8 @@ def main():
         "generate_kernel_ms": avg_kern_s * 1e3,
         "generate_kernel_hbm_write_gbs": hbm_gbs,
         "generate_kernel_hbm_frac": hbm_gbs / HBM_PEAK_GBS,
+        "write_stream_gbs": None,
+        "generate_kernel_write_stream_frac": None,
         "table_build_ms": build_ms,
         "samples_per_edge": en,
         "philox_blocks_per_edge": eb,
@@ -339,6 +357,16 @@ def main():
                      "ops_per_edge": ops_per_edge,
                      "traffic": traffic},
     }
+    # the measured store-only stream on this device: the achievable write
+    # ceiling the id stores are compared with beside the 8 TB/s spec
+    from paper_1905_03525_amd import microbench
+    del src, dst
+    torch.cuda.empty_cache()
+    ws = microbench.write_bandwidth()
+    out["write_stream_gbs"] = ws
+    out["generate_kernel_write_stream_frac"] = hbm_gbs / ws
+    src = torch.empty(m, dtype=torch.int32, device="cuda")
+    dst = torch.empty(m, dtype=torch.int32, device="cuda")
     if not args.no_sec5:
         # the Sec. 5 epilogue (undirected mirror + id scramble) on the same instance
         t_epi = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
