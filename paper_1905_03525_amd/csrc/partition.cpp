@@ -22,6 +22,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <atomic>
+#include <thread>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -194,6 +197,9 @@ uint64_t bin(NodeStream& st, uint64_t n, double p) {
   return flip ? n - x : x;
 }
 
+constexpr size_t kCountTasks = 256;   // subtrees handed to the counting threads
+constexpr size_t kCountThreads = 16;  // host threads for one count
+
 struct Counter {
   double q[4];
   uint64_t seed;
@@ -243,7 +249,33 @@ struct Counter {
     for (int i = 0; i < k; ++i) visit(ch[i]);
   }
 
-  void run(uint64_t m) { visit(Node{0, 0, 0, m}); }
+  // Every node's draws depend only on the seed and the node, so the subtrees
+  // below a frontier of up to kCountTasks nodes are counted on several host
+  // threads with the same result as one.
+  void run(uint64_t m) {
+    std::vector<Node> frontier{Node{0, 0, 0, m}};
+    while (frontier.size() < kCountTasks && frontier[0].level < t - 1) {
+      std::vector<Node> next;
+      for (const Node& x : frontier) {
+        if (x.n == 0) continue;
+        Node ch[4];
+        const int k = split(x, ch);
+        next.insert(next.end(), ch, ch + k);
+      }
+      if (next.empty()) return;
+      frontier.swap(next);
+    }
+    const size_t hw = std::max(2u, std::thread::hardware_concurrency());
+    const size_t n_threads = std::min<size_t>({frontier.size(), hw, kCountThreads});
+    std::atomic<size_t> next_task{0};
+    auto worker = [&]() {
+      for (size_t i; (i = next_task.fetch_add(1)) < frontier.size();) visit(frontier[i]);
+    };
+    std::vector<std::thread> pool;
+    for (size_t i = 1; i < n_threads; ++i) pool.emplace_back(worker);
+    worker();
+    for (std::thread& th : pool) th.join();
+  }
 };
 
 constexpr uint64_t kMaxTilesPerCall = 1ull << 18;
@@ -286,10 +318,15 @@ struct CountCache {
 };
 CountCache g_count_cache;
 
-// Per-device buffers for a generation's instance and work lists, grown on
-// demand and kept until the process ends.
+// Per-device buffers (device and pinned host) for a generation's instance
+// and work lists, grown on demand and kept until the process ends.
+struct Lists {
+  void* dev = nullptr;   // device copy
+  void* host = nullptr;  // pinned staging
+  uint64_t bytes = 0;
+};
 std::mutex g_lists_mu;
-std::map<int, std::pair<void*, uint64_t>> g_lists;
+std::map<int, Lists> g_lists;
 
 int counts_cached(rmat_table_t t, uint64_t seed, uint64_t m, int tbits, uint32_t row_begin, uint32_t row_end,
                   uint64_t* counts);
@@ -391,29 +428,33 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   const uint64_t inst_bytes = (insts.size() * sizeof(rmat::GenInst) + 255) / 256 * 256;
   const uint64_t item_bytes = (items.size() * sizeof(rmat::GenWorkItem) + 255) / 256 * 256;
   const uint64_t bytes = inst_bytes + item_bytes + 256;
-  // [instances | work items | zeroed work counter], assembled on the host and
-  // sent in one copy to a device buffer kept between calls (calls are
-  // synchronous and serialised here)
-  std::vector<char> host(bytes, 0);
-  std::memcpy(host.data(), insts.data(), insts.size() * sizeof(rmat::GenInst));
-  std::memcpy(host.data() + inst_bytes, items.data(), items.size() * sizeof(rmat::GenWorkItem));
+  // [instances | work items | zeroed work counter], assembled in pinned host
+  // memory and sent in one copy to a device buffer; both are kept between
+  // calls (calls are synchronous and serialised here)
   std::lock_guard<std::mutex> lock(g_lists_mu);
   int device = 0;
   hipError_t e = hipGetDevice(&device);
   if (e != hipSuccess) return rmat::hip_fail(e, "hipGetDevice");
-  auto& slot = g_lists[device];
-  if (slot.second < bytes) {
-    if (slot.first) (void)hipFree(slot.first);
-    slot = {nullptr, 0};
-    e = hipMalloc(&slot.first, bytes);
+  Lists& L = g_lists[device];
+  if (L.bytes < bytes) {
+    if (L.dev) (void)hipFree(L.dev);
+    if (L.host) (void)hipHostFree(L.host);
+    L = Lists{};
+    e = hipMalloc(&L.dev, bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&L.host, bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
-      slot.first = nullptr;
-      return rmat::hip_fail(e, "hipMalloc(partition lists)");
+      if (L.dev) (void)hipFree(L.dev);
+      L = Lists{};
+      return rmat::hip_fail(e, "allocation of the partition lists");
     }
-    slot.second = bytes;
+    L.bytes = bytes;
   }
-  char* base = static_cast<char*>(slot.first);
-  e = hipMemcpy(base, host.data(), bytes, hipMemcpyHostToDevice);
+  char* host = static_cast<char*>(L.host);
+  std::memcpy(host, insts.data(), insts.size() * sizeof(rmat::GenInst));
+  std::memcpy(host + inst_bytes, items.data(), items.size() * sizeof(rmat::GenWorkItem));
+  std::memset(host + inst_bytes + item_bytes, 0, 256);
+  char* base = static_cast<char*>(L.dev);
+  e = hipMemcpy(base, host, bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     rmat::BatchArgs a;
     a.insts = reinterpret_cast<const rmat::GenInst*>(base);
