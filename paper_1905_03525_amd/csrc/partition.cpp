@@ -388,6 +388,8 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   const uint32_t work_blocks = 2048;
   std::vector<rmat::GenInst> insts;
   std::vector<rmat::GenWorkItem> items;
+  insts.reserve(n_tiles);
+  items.reserve(n_tiles + total / (64ull * work_blocks));
   uint64_t off = 0;
   for (uint64_t i = 0; i < n_tiles; ++i) {
     const uint64_t n = counts[i];
