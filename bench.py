@@ -390,6 +390,18 @@ def main():
         out["perturbed_set"] = {"tables": 8, "table_bound": 1024, "epsilon": 0.1,
                                 "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
         t_set.close()
+        # a 3 x 3 stochastic Kronecker initiator (Sec. 5) with 3^17 = 1.29e8
+        # nodes (uint32 ids), a 4096-bound table, the same 2^30 edges
+        P3 = [0.3, 0.1, 0.05, 0.1, 0.2, 0.05, 0.05, 0.05, 0.1]
+        t_kron = R.rmat_kron_build_table(P3, 3, 17, 4096, R.RMAT_VARIABLE)
+        R.rmat_generate_async(t_kron, w["seed"], 0, m, src, dst, stream)
+        ea.record(stream)
+        R.rmat_generate_async(t_kron, w["seed"], 0, m, src, dst, stream)
+        eb_.record(stream)
+        torch.cuda.synchronize()
+        out["kronecker_3x3"] = {"k": 17, "nodes": 3 ** 17, "table_bound": 4096,
+                                "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
+        t_kron.close()
         # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
         # tile rows [0, 64) per call, four calls; counting on the host included
         t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)

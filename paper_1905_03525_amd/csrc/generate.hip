@@ -806,8 +806,10 @@ struct KronLaunch {
 template <typename Id, bool kLds>
 __global__ __launch_bounds__(kGenThreads) void kron_kernel(KronLaunch P) {
   extern __shared__ __align__(16) unsigned char s_mem[];
-  __shared__ uint64_t s_pow[16];
-  if (threadIdx.x < 16) s_pow[threadIdx.x] = P.pow[threadIdx.x];
+  // K^0 .. K^15 in the id width: with 32-bit ids K^k <= 2^32, so every
+  // partial id (K^filled at most) fits 32-bit arithmetic
+  __shared__ Id s_pow[16];
+  if (threadIdx.x < 16) s_pow[threadIdx.x] = static_cast<Id>(P.pow[threadIdx.x]);
   const BucketRecord* tab = P.records;
   if (kLds) {
     stage_table(P.records, P.n_buckets, s_mem);
@@ -817,7 +819,7 @@ __global__ __launch_bounds__(kGenThreads) void kron_kernel(KronLaunch P) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P.m; i += stride) {
     const uint64_t e = P.edge_begin + i;
-    uint64_t row = 0, col = 0;
+    Id row = 0, col = 0;
     uint32_t filled = 0;
     for (uint32_t j = 0; filled < P.k; ++j) {
       uint32_t x[4] = {static_cast<uint32_t>(e), static_cast<uint32_t>(e >> 32), j, 0u};
@@ -835,15 +837,15 @@ __global__ __launch_bounds__(kGenThreads) void kron_kernel(KronLaunch P) {
             rv /= dv;
             cv /= dv;
           }
-          const uint64_t mul = s_pow[take];
+          const Id mul = s_pow[take];
           row = row * mul + rv;
           col = col * mul + cv;
           filled += take;
         }
       }
     }
-    static_cast<Id*>(P.out_src)[i] = static_cast<Id>(row);
-    static_cast<Id*>(P.out_dst)[i] = static_cast<Id>(col);
+    static_cast<Id*>(P.out_src)[i] = row;
+    static_cast<Id*>(P.out_dst)[i] = col;
   }
 }
 
