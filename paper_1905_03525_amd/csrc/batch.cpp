@@ -368,6 +368,7 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
     d.out_dst = x.out_dst;
     d.digest = nullptr;
     d.ctr3 = 0;
+    d.kron_k = 2;
     d.src_prefix = d.dst_prefix = 0;
     d.epi = static_cast<uint32_t>(x.flags);
     if (d.epi) rmat::scramble_params(x.scramble_key, x.k, &d);

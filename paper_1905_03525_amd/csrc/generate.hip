@@ -97,17 +97,27 @@ __device__ __forceinline__ void philox10_first(uint32_t e_lo, uint32_t e_hi, uin
   }
 }
 
+// (x * m + a) mod 2^64 with 32-bit x, m: one v_mad_u64_u32, which runs at
+// the full vector rate on gfx950 where v_mul_lo_u32 does not.
+__device__ __forceinline__ uint64_t mad_u64_u32(uint32_t x, uint32_t m, uint64_t a) {
+  uint64_t r, carry;
+  __asm__("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(x), "v"(m), "v"(a));
+  return r;
+}
+
 // Row/column accumulators, filled from bit 0 up: a path of L letters,
 // stored bit-reversed, is shifted to the current fill level and OR-ed in
 // (one v_lshl_or_b32 per half); letters past the register's width fall off
 // the top.  The id is the first k letters, the first one most significant:
 // the bit reversal of the accumulator, shifted down to k bits.
 struct Acc32 {
+  static constexpr bool kKron = false;
   using Id = uint32_t;
   using Packed = uint2;
   uint32_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
-  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t filled) {
+  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t, uint32_t filled, uint32_t,
+                                         const uint64_t*) {
     row |= rowv << filled;
     col |= colv << filled;
   }
@@ -118,17 +128,49 @@ struct Acc32 {
 };
 
 struct Acc64 {
+  static constexpr bool kKron = false;
   using Id = uint64_t;
   using Packed = ulonglong2;
   uint64_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
-  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t filled) {
+  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t, uint32_t filled, uint32_t,
+                                         const uint64_t*) {
     row |= static_cast<uint64_t>(rowv) << filled;
     col |= static_cast<uint64_t>(colv) << filled;
   }
   __device__ __forceinline__ uint64_t src(uint32_t k) const { return __builtin_bitreverse64(row) >> (64 - k); }
   __device__ __forceinline__ uint64_t dst(uint32_t k) const { return __builtin_bitreverse64(col) >> (64 - k); }
   __device__ __forceinline__ Packed pack() const { return make_ulonglong2(row, col); }
+  __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
+};
+
+// Base-K accumulators for K x K initiators: a path of L digit pairs holds
+// its row and column digits as base-K numbers (root-most digit most
+// significant); the first min(L, k - filled) digits are appended by
+// id = id * K^take + value / K^(L - take).  kpow[i] = K^i (i <= 15).  Ids
+// stay below K^k, so 32-bit ids (K^k <= 2^32) take 32-bit arithmetic.
+template <typename IdT>
+struct KronAcc {
+  static constexpr bool kKron = true;
+  using Id = IdT;
+  using Packed = typename std::conditional<sizeof(Id) == 4, uint2, ulonglong2>::type;
+  Id row, col;
+  __device__ __forceinline__ void clear() { row = 0; col = 0; }
+  __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t len, uint32_t filled, uint32_t k,
+                                         const uint64_t* kpow) {
+    const uint32_t take = len < k - filled ? len : k - filled;
+    if (take < len) {  // the edge's last path, cut to the digits still needed
+      const uint32_t d = static_cast<uint32_t>(kpow[len - take]);
+      rowv /= d;
+      colv /= d;
+    }
+    const Id mul = static_cast<Id>(kpow[take]);
+    row = row * mul + rowv;
+    col = col * mul + colv;
+  }
+  __device__ __forceinline__ Id src(uint32_t) const { return row; }
+  __device__ __forceinline__ Id dst(uint32_t) const { return col; }
+  __device__ __forceinline__ Packed pack() const { return Packed{row, col}; }
   __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
 
@@ -140,21 +182,20 @@ struct Acc64 {
 // cannot come from one path).
 template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
-                                         uint32_t& filled) {
+                                         uint32_t& filled, const uint64_t* kpow) {
   auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
   const bool o0 = x[0] < r[0].thr_abs, o1 = x[1] < r[1].thr_abs, o2 = x[2] < r[2].thr_abs, o3 = x[3] < r[3].thr_abs;
-  acc.append(half(o0, r[0].rows), half(o0, r[0].cols), filled);
-  filled += half(o0, r[0].lens);
+  auto take = [&](bool o, const BucketRecord& q) {
+    const uint32_t len = half(o, q.lens);
+    acc.append(half(o, q.rows), half(o, q.cols), len, filled, k, kpow);
+    filled += len;
+  };
+  take(o0, r[0]);
   if (kSure1 || filled < k) {
-    acc.append(half(o1, r[1].rows), half(o1, r[1].cols), filled);
-    filled += half(o1, r[1].lens);
+    take(o1, r[1]);
     if (filled < k) {
-      acc.append(half(o2, r[2].rows), half(o2, r[2].cols), filled);
-      filled += half(o2, r[2].lens);
-      if (filled < k) {
-        acc.append(half(o3, r[3].rows), half(o3, r[3].cols), filled);
-        filled += half(o3, r[3].lens);
-      }
+      take(o2, r[2]);
+      if (filled < k) take(o3, r[3]);
     }
   }
 }
@@ -163,14 +204,15 @@ __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], con
 // four reads are issued before any is used, so they are in flight together.
 template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
-                                        uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled) {
+                                        uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled,
+                                        const uint64_t* kpow) {
   const uint32_t x[4] = {x0, x1, x2, x3};
   const BucketRecord r[4] = {tab[x0 >> shift], tab[x1 >> shift], tab[x2 >> shift], tab[x3 >> shift]};
   // keep the reads ahead of the branches below (an operand-only asm, no code)
   __asm__ volatile("" ::"v"(r[1].thr_abs), "v"(r[1].rows), "v"(r[1].cols), "v"(r[1].lens), "v"(r[2].thr_abs),
                    "v"(r[2].rows), "v"(r[2].cols), "v"(r[2].lens), "v"(r[3].thr_abs), "v"(r[3].rows), "v"(r[3].cols),
                    "v"(r[3].lens));
-  consume4<Acc, kSure1>(k, x, r, acc, filled);
+  consume4<Acc, kSure1>(k, x, r, acc, filled, kpow);
 }
 
 using Inst = GenInst;
@@ -197,14 +239,6 @@ struct BatchLaunch {
   unsigned int* counter;  // reset to 0 by the batch's table-build launch
   TileLayout L;
 };
-
-// (x * m + a) mod 2^64 with 32-bit x, m: one v_mad_u64_u32, which runs at
-// the full vector rate on gfx950 where v_mul_lo_u32 does not.
-__device__ __forceinline__ uint64_t mad_u64_u32(uint32_t x, uint32_t m, uint64_t a) {
-  uint64_t r, carry;
-  __asm__("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(x), "v"(m), "v"(a));
-  return r;
-}
 
 // A wave-uniform value held in a vector register: the epilogue's parameters
 // stay out of the scalar registers, which the tile loop needs.
@@ -360,7 +394,7 @@ template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
-                                           uint16_t* bins, uint64_t& xsum) {
+                                           uint16_t* bins, uint64_t& xsum, const uint64_t* kpow = nullptr) {
   using Id = typename Acc::Id;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
@@ -389,7 +423,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       uint32_t x0, x1, x2, x3;
       philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1, x0, x1,
                      x2, x3);
-      sample4<Acc, decltype(sure)::value>(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled);
+      sample4<Acc, decltype(sure)::value>(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
       res[j * 64 + lane] = acc.pack();
       const bool need = decltype(whole)::value ? filled < I.k : (filled < I.k && ((amask >> lane) & 1ull));
       const uint64_t ovf_mask = __ballot(need);
@@ -422,7 +456,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         Acc acc;
         acc.clear();
         uint32_t filled = 0;
-        consume4<Acc, true>(I.k, x, r, acc, filled);
+        consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;
         const uint64_t ovf_mask = __ballot(need);
@@ -488,7 +522,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         for (uint32_t jj = 1; filled < I.k; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
-          sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled);
+          sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
         }
         res[idx] = acc.pack();
       }
@@ -605,6 +639,16 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ unsigned long long s_xor[kWaves];
   using Packed = typename Acc::Packed;
+  const uint64_t* kpow = nullptr;
+  if constexpr (Acc::kKron) {
+    __shared__ uint64_t s_kpow[16];  // K^0 .. K^15
+    if (threadIdx.x == 0) {
+      uint64_t x = 1;
+      for (int i = 0; i < 16; ++i, x *= P.I.kron_k) s_kpow[i] = x;
+    }
+    __syncthreads();
+    kpow = s_kpow;
+  }
   const BucketRecord* tab = P.I.records;
   if (kLds) {
     stage_table(P.I.records, P.I.n_buckets * (P.I.table_mask + 1), s_mem);
@@ -619,7 +663,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
   uint64_t xsum = 0;
   run_blocks<Acc, kReduce, false, kGeneral>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.bins,
-                                            xsum);
+                                            xsum, kpow);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
@@ -791,94 +835,9 @@ uint32_t hist_groups(uint64_t n) {
   return static_cast<uint32_t>(want < 1 ? 1 : (want > cus ? cus : want));
 }
 
-// K x K Kronecker tables (K > 2): one lane per edge, base-K digits,
-// row = row K^take + floor(rowval / K^(L - take)).  A secondary path: the
-// table is staged in LDS when it fits; no tile compaction.
-struct KronLaunch {
-  const BucketRecord* records;
-  uint32_t n_buckets, shift, k, key0, key1;
-  uint64_t edge_begin, m;
-  void* out_src;
-  void* out_dst;
-  uint64_t pow[16];  // K^0 .. K^15
-};
-
-template <typename Id, bool kLds>
-__global__ __launch_bounds__(kGenThreads) void kron_kernel(KronLaunch P) {
-  extern __shared__ __align__(16) unsigned char s_mem[];
-  // K^0 .. K^15 in the id width: with 32-bit ids K^k <= 2^32, so every
-  // partial id (K^filled at most) fits 32-bit arithmetic
-  __shared__ Id s_pow[16];
-  if (threadIdx.x < 16) s_pow[threadIdx.x] = static_cast<Id>(P.pow[threadIdx.x]);
-  const BucketRecord* tab = P.records;
-  if (kLds) {
-    stage_table(P.records, P.n_buckets, s_mem);
-    tab = reinterpret_cast<const BucketRecord*>(s_mem);
-  }
-  __syncthreads();
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < P.m; i += stride) {
-    const uint64_t e = P.edge_begin + i;
-    Id row = 0, col = 0;
-    uint32_t filled = 0;
-    for (uint32_t j = 0; filled < P.k; ++j) {
-      uint32_t x[4] = {static_cast<uint32_t>(e), static_cast<uint32_t>(e >> 32), j, 0u};
-      philox10(x[0], x[1], x[2], x[3], P.key0, P.key1);
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        if (filled < P.k) {
-          const BucketRecord r = tab[x[w] >> P.shift];
-          const bool own = x[w] < r.thr_abs;
-          const uint32_t L = own ? (r.lens & 0xFFFFu) : (r.lens >> 16);
-          const uint32_t take = L < P.k - filled ? L : P.k - filled;
-          uint32_t rv = own ? (r.rows & 0xFFFFu) : (r.rows >> 16), cv = own ? (r.cols & 0xFFFFu) : (r.cols >> 16);
-          if (take < L) {
-            const uint32_t dv = static_cast<uint32_t>(s_pow[L - take]);
-            rv /= dv;
-            cv /= dv;
-          }
-          const Id mul = s_pow[take];
-          row = row * mul + rv;
-          col = col * mul + cv;
-          filled += take;
-        }
-      }
-    }
-    static_cast<Id*>(P.out_src)[i] = row;
-    static_cast<Id*>(P.out_dst)[i] = col;
-  }
-}
-
-template <typename Id, bool kLds>
-hipError_t launch_kron(const GenerateArgs& a, hipStream_t s) {
-  KronLaunch P;
-  P.records = a.records;
-  P.n_buckets = a.n_buckets;
-  P.shift = 32u - static_cast<uint32_t>(a.bucket_bits);
-  P.k = static_cast<uint32_t>(a.k);
-  P.key0 = static_cast<uint32_t>(a.seed);
-  P.key1 = static_cast<uint32_t>(a.seed >> 32);
-  P.edge_begin = a.edge_begin;
-  P.m = a.m;
-  P.out_src = a.out_src;
-  P.out_dst = a.out_dst;
-  P.pow[0] = 1;
-  for (int i = 1; i < 16; ++i) P.pow[i] = P.pow[i - 1] * a.kron_k;
-  const size_t lds = kLds ? static_cast<size_t>(a.n_buckets) * sizeof(BucketRecord) : 0;
-  uint64_t grid = (a.m + kGenThreads - 1) / kGenThreads;
-  const uint64_t cap = static_cast<uint64_t>(limits().cu_count) * (kLds ? 1 : 2);
-  if (grid > cap) grid = cap;
-  hipLaunchKernelGGL((kron_kernel<Id, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads), lds, s, P);
-  return hipGetLastError();
-}
-
 template <bool kReduce>
 hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   if (a.m == 0) return hipSuccess;
-  if (!kReduce && a.kron_k > 2) {
-    if (a.id_bytes == 4) return a.lds ? launch_kron<uint32_t, true>(a, s) : launch_kron<uint32_t, false>(a, s);
-    return a.lds ? launch_kron<uint64_t, true>(a, s) : launch_kron<uint64_t, false>(a, s);
-  }
   Launch P;
   P.I.records = a.records;
   P.I.n_buckets = a.n_buckets;
@@ -895,6 +854,7 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.I.out_dst = a.out_dst;
   P.I.digest = nullptr;
   P.I.ctr3 = 0;
+  P.I.kron_k = static_cast<uint32_t>(a.kron_k);
   P.I.src_prefix = P.I.dst_prefix = 0;
   P.I.epi = 0;
   if (!kReduce && a.epi) {
@@ -906,6 +866,13 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.xor_out = a.xor_out;
   const bool wide = a.k > 32;
   auto gen = [&](const Launch& L) {
+    if (!kReduce && a.kron_k > 2) {  // base-K digits; no epilogue, reduction or sets for these tables
+      if (a.id_bytes == 4)
+        return a.lds ? launch_one<KronAcc<uint32_t>, true, false, false>(L, s)
+                     : launch_one<KronAcc<uint32_t>, false, false, false>(L, s);
+      return a.lds ? launch_one<KronAcc<uint64_t>, true, false, false>(L, s)
+                   : launch_one<KronAcc<uint64_t>, false, false, false>(L, s);
+    }
     if (!kReduce && L.I.epi != 0) {
       if (a.lds) return wide ? launch_one<Acc64, true, false, true>(L, s) : launch_one<Acc32, true, false, true>(L, s);
       return wide ? launch_one<Acc64, false, false, true>(L, s) : launch_one<Acc32, false, false, true>(L, s);
@@ -1034,8 +1001,8 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_batch_kernel<Acc64, false, true, false>),
       allow_full_lds(&generate_batch_kernel<Acc64, false, true, true>),
       allow_full_lds(&hist_partial_kernel),
-      allow_full_lds(&kron_kernel<uint32_t, true>),
-      allow_full_lds(&kron_kernel<uint64_t, true>)};
+      allow_full_lds(&generate_kernel<KronAcc<uint32_t>, true, false, false>),
+      allow_full_lds(&generate_kernel<KronAcc<uint64_t>, true, false, false>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

@@ -413,6 +413,7 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     I.out_dst = static_cast<char*>(out_dst) + off * idb;
     I.digest = nullptr;
     I.ctr3 = 1u + ((r << tile_bits) | c);
+    I.kron_k = 2;
     I.src_prefix = static_cast<uint64_t>(r) << kk;
     I.dst_prefix = static_cast<uint64_t>(c) << kk;
     I.epi = 0;

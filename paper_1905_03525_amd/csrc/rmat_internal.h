@@ -100,10 +100,11 @@ struct GenInst {
   // if set (launches with digests enabled), XOR-ed with the XOR over the
   // generated edges of fmix64(e ^ fmix64(src ^ rotl64(dst, 32)))
   unsigned long long* digest;
+  uint32_t ctr3;                  // fourth Philox counter word: 0, or 1 + tile id (partitioned generation)
+  uint32_t kron_k;                // K of the K x K initiator (2: R-MAT letters, bit concatenation)
+  uint64_t src_prefix, dst_prefix;  // OR-ed into the ids (a tile's row and column offsets)
   // epilogue applied to each edge before it is stored (Sec. 5): bit 0 mirrors
   // an edge with src > dst, bit 1 relabels both ids by the scramble
-  uint32_t ctr3;                  // fourth Philox counter word: 0, or 1 + tile id (partitioned generation)
-  uint64_t src_prefix, dst_prefix;  // OR-ed into the ids (a tile's row and column offsets)
   uint32_t epi;
   uint32_t scr_shift;             // ceil(k / 2)
   uint64_t scr_mask;              // 2^k - 1

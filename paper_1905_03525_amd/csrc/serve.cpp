@@ -467,6 +467,7 @@ int issue_round(rmat_server* s, bool* launched) {
     I.out_dst = q->out_dst;
     I.digest = nullptr;  // set below once the packet layout is known
     I.ctr3 = 0;
+    I.kron_k = 2;
     I.src_prefix = I.dst_prefix = 0;
     I.epi = ((q->r.flags & RMAT_REQ_UNDIRECTED) ? rmat::kEpiUndirected : 0u) |
             ((q->r.flags & RMAT_REQ_SCRAMBLE) ? rmat::kEpiScramble : 0u);
