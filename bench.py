@@ -13,7 +13,7 @@ reduced on the device (`k34`), and the CPU oracle on a bounded sample
 (`cpu_baseline`).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-batch]
-                    [--served-window S] [--served-reading A|B]
+                    [--served-window S] [--served-reading A|B] [--served-pool P]
 """
 from __future__ import annotations
 
@@ -151,17 +151,19 @@ def batched_vs_plain(R, reps: int = 3) -> dict:
             "bounds_histogram": {str(v): bounds.count(v) for v in sorted(set(bounds))}}
 
 
-def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0, plain: bool = True) -> dict:
+def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0, plain: bool = True,
+                    pool: int = 0) -> dict:
     """The served workload: a Poisson stream of R-MAT requests (k per
     `reading`, edge factor 8 or 16, Dirichlet(4,2,2,1) parameters, table bound
     4096) at `rate` requests/s; the first `window_s` seconds of arrivals go
     through the request server (200 GB output arena, device table cache,
     continuous batching), outputs released as each request completes.  The
     same requests are then generated one after another by plain
-    rmat_build_table + rmat_generate_async calls."""
+    rmat_build_table + rmat_generate_async calls.  pool > 0: parameters from
+    that many pre-drawn sets, so the table cache can hit."""
     import torch
     from paper_1905_03525_amd import workloads
-    reqs = workloads.served_requests(rate=rate, duration=window_s, arrival_seed=2019, reading=reading)
+    reqs = workloads.served_requests(rate=rate, duration=window_s, arrival_seed=2019, reading=reading, pool=pool)
     for p in reqs:
         p["flags"] = R.RMAT_REQ_DISCARD
     total = sum(p["m"] for p in reqs)
@@ -176,7 +178,8 @@ def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0
     lat = sorted(c["t_done"] - c["t_submit"] for c in out)
     wait = sorted(c["t_admit"] - c["t_submit"] for c in out)
     pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))] * 1e3  # noqa: E731
-    res = {"workload": f"served_poisson{rate:g}_k12-28{reading}_ef8-16_var4096", "reading": reading,
+    pooled = f"_pool{pool}" if pool else ""
+    res = {"workload": f"served_poisson{rate:g}_k12-28{reading}_ef8-16_var4096{pooled}", "reading": reading,
            "window_s": window_s, "requests": len(reqs), "total_edges": total, "wall_s": wall,
            "edges_per_s": total / wall, "hbm_write_gbs": 8 * total / wall / 1e9,
            "p50_latency_ms": pct(lat, 0.5), "p99_latency_ms": pct(lat, 0.99), "p50_wait_ms": pct(wait, 0.5),
@@ -265,6 +268,8 @@ def main():
                     help="seconds of the 2000 requests/s stream to serve (0: skip; the full stream is 60)")
     ap.add_argument("--served-reading", default="A", choices=["A", "B"])
     ap.add_argument("--served-no-plain", action="store_true", help="skip the plain-launch comparison of the stream")
+    ap.add_argument("--served-pool", type=int, default=0,
+                    help="also run the stream window with parameters from this many pre-drawn sets (cache hits)")
     ap.add_argument("--no-k34", action="store_true", help="skip the k=34 chunked instance")
     ap.add_argument("--no-sec5", action="store_true",
                     help="skip the epilogue, perturbed-set and partitioned measurements of the k=26 instance")
@@ -428,6 +433,9 @@ def main():
         out["k34"] = k34_chunked(R)
     if args.served_window > 0:
         out["served"] = served_vs_plain(R, args.served_window, args.served_reading, plain=not args.served_no_plain)
+        if args.served_pool > 0:
+            out["served_pooled"] = served_vs_plain(R, args.served_window, args.served_reading,
+                                                   plain=not args.served_no_plain, pool=args.served_pool)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -12,7 +12,10 @@ default_rng(arrival_seed)) at `rate` requests/s for `duration` s; request r
 draws from default_rng(r) its k (reading "A": an integer uniform in
 [12, 28], i.e. n log-uniform; reading "B": ln k uniform on [ln 12, ln 28],
 rounded), an edge factor from {8, 16} and (a, b, c, d) from
-Dirichlet(4, 2, 2, 1); its seed is r.
+Dirichlet(4, 2, 2, 1); its seed is r.  With a parameter pool of P sets
+(drawn in order from default_rng(arrival_seed + 1)), request r instead
+takes set j, j uniform in [0, P) drawn from default_rng(r) after its edge
+factor, so that requests repeat tables.
 """
 from __future__ import annotations
 
@@ -54,9 +57,15 @@ def request_k(rng: np.random.Generator, reading: str, k_min: int = 12, k_max: in
 
 
 def served_requests(rate: float = 2000.0, duration: float = 60.0, arrival_seed: int = 2019, reading: str = "A",
-                    k_min: int = 12, k_max: int = 28, edge_factors=(8, 16), table_bound: int = 4096) -> list:
+                    k_min: int = 12, k_max: int = 28, edge_factors=(8, 16), table_bound: int = 4096,
+                    pool: int = 0) -> list:
     """Request dicts in arrival order: id, t_arrival (s), a, b, c, d, k,
-    path_mode, table_bound, seed, edge_begin=0, m."""
+    path_mode, table_bound, seed, edge_begin=0, m.  pool > 0 draws the
+    parameters from that many pre-drawn sets."""
+    if pool < 0:
+        raise ValueError("pool must be >= 0")
+    prng = np.random.default_rng(arrival_seed + 1)
+    sets = [dirichlet_q(prng) for _ in range(pool)]
     gaps = np.random.default_rng(arrival_seed)
     t, out, r = 0.0, [], 0
     while True:
@@ -66,7 +75,7 @@ def served_requests(rate: float = 2000.0, duration: float = 60.0, arrival_seed: 
         rng = np.random.default_rng(r)
         k = request_k(rng, reading, k_min, k_max)
         ef = int(rng.choice(edge_factors))
-        a, b, c, d = dirichlet_q(rng)
+        a, b, c, d = sets[int(rng.integers(pool))] if pool else dirichlet_q(rng)
         out.append(dict(id=r, t_arrival=t, a=a, b=b, c=c, d=d, k=k, path_mode=RMAT_VARIABLE,
                         table_bound=table_bound, seed=r, edge_begin=0, m=ef << k))
         r += 1
