@@ -412,16 +412,20 @@ def main():
         t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
         torch.cuda.synchronize()
         p0 = time.perf_counter()
-        n_part = 0
+        n_part, count_s = 0, 0.0
         for r0 in range(0, 256, 64):
+            c0 = time.perf_counter()
             cnt = R.rmat_partition_counts(t_part, w["seed"], m, 8, r0, r0 + 64)
+            count_s += time.perf_counter() - c0
             n = int(cnt.sum())
             R.rmat_generate_partition(t_part, w["seed"], m, 8, r0, r0 + 64, src, dst, n)
             n_part += n
         part_s = time.perf_counter() - p0
         assert n_part == m
         out["partitioned_edges_per_s"] = m / part_s
-        out["partitioned_config"] = {"tile_bits": 8, "row_ranges": 4}
+        out["partitioned_config"] = {"tile_bits": 8, "row_ranges": 4, "total_ms": part_s * 1e3,
+                                     "host_count_ms": count_s * 1e3,
+                                     "generate_calls_ms": (part_s - count_s) * 1e3}
         t_part.close()
     del src, dst
     torch.cuda.empty_cache()

@@ -561,9 +561,11 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
 #pragma unroll
     for (uint32_t j = 0; j < kMaxTile; ++j)
       if (j < nb_tile) vals[j] = res[j * 64 + lane];
-    if (!kReduce && whole_tile && !prefixed) {
+    const uint32_t epi = kGeneral ? E.flags : 0u;
+    if (!kReduce && whole_tile && (!prefixed || epi == 0)) {
       // one buffer descriptor per output array for the whole tile; block j
-      // sits at a scalar offset from the tile's first block
+      // sits at a scalar offset from the tile's first block (a tile of a
+      // partitioned graph ORs in its id prefixes and has no epilogue)
       const uint64_t slot0 = ((I.first_block + t0) << 6) - I.edge_begin;
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_src) + slot0, 0,
                                                                            0x7FFFFFFF, kBufferDword3);
@@ -572,7 +574,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
       // the epilogue's kind is chosen once per tile, so the unrolled stores
       // carry no per-block branches
-      auto store_tile = [&](auto undirected, auto scrambled) {
+      auto store_tile = [&](auto undirected, auto scrambled, auto with_prefix) {
 #pragma unroll
         for (uint32_t j = 0; j < kMaxTile; ++j) {
           if (j >= nb_tile) break;
@@ -580,6 +582,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           acc.unpack(vals[j]);
           Id sv = static_cast<Id>(acc.src(I.k));
           Id dv = static_cast<Id>(acc.dst(I.k));
+          if (decltype(with_prefix)::value) {
+            sv |= static_cast<Id>(I.src_prefix);
+            dv |= static_cast<Id>(I.dst_prefix);
+          }
           if (decltype(undirected)::value) {
             const Id lo = sv < dv ? sv : dv;
             dv = sv < dv ? dv : sv;
@@ -598,15 +604,16 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           }
         }
       };
-      const uint32_t epi = kGeneral ? E.flags : 0u;
-      if (epi == 0)
-        store_tile(std::false_type{}, std::false_type{});
+      if (prefixed)
+        store_tile(std::false_type{}, std::false_type{}, std::true_type{});
+      else if (epi == 0)
+        store_tile(std::false_type{}, std::false_type{}, std::false_type{});
       else if (epi == kEpiUndirected)
-        store_tile(std::true_type{}, std::false_type{});
+        store_tile(std::true_type{}, std::false_type{}, std::false_type{});
       else if (epi == kEpiScramble)
-        store_tile(std::false_type{}, std::true_type{});
+        store_tile(std::false_type{}, std::true_type{}, std::false_type{});
       else
-        store_tile(std::true_type{}, std::true_type{});
+        store_tile(std::true_type{}, std::true_type{}, std::false_type{});
     } else {
 #pragma unroll
       for (uint32_t j = 0; j < kMaxTile; ++j) {
@@ -677,8 +684,10 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
 }
 
 // Persistent kernel over the work items of a batch.  A workgroup claims an
-// item, restages the table only when the instance changes (items are in
-// instance order), and its 16 waves share the item's blocks.
+// item, restages the table only when the item's table differs from the one
+// in LDS (items are in instance order; the tiles of a partitioned graph and
+// requests served from one cached table share it), and its 16 waves share
+// the item's blocks.
 template <typename Acc, bool kLds, bool kDigest, bool kGeneral>
 __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch B) {
   extern __shared__ __align__(16) unsigned char s_mem[];
@@ -687,7 +696,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
   const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   Packed* res = reinterpret_cast<Packed*>(s_mem + B.L.lds_table + wave_in_wg * B.L.wave_bytes);
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + B.L.tile * 64);
-  uint32_t cur = 0xFFFFFFFFu;
+  const BucketRecord* cur = nullptr;  // table in LDS and its buckets
+  uint32_t cur_buckets = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(B.counter, 1u);
     __syncthreads();
@@ -696,11 +706,28 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     if (item >= B.n_items) break;
     const GenWorkItem W = B.items[item];
     const Inst I = B.insts[W.inst];
-    if (kLds && W.inst != cur) {
-      stage_table(I.records, I.n_buckets * (I.table_mask + 1), s_mem);
+    const uint32_t buckets = I.n_buckets * (I.table_mask + 1);
+    if (kLds && (I.records != cur || buckets != cur_buckets)) {
+      stage_table(I.records, buckets, s_mem);
       __syncthreads();
+      cur = I.records;
+      cur_buckets = buckets;
     }
-    cur = W.inst;
+    if (W.n_inst > 1) {
+      // a run of small instances on this table: each wave takes whole
+      // instances (no workgroup step between them)
+      for (uint32_t j = wave_in_wg; j < W.n_inst; j += kWaves) {
+        const Inst Ij = B.insts[W.inst + j];
+        const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : Ij.records;
+        uint64_t xsum = 0;
+        run_blocks<Acc, false, kDigest, kGeneral>(Ij, tab, B.L, 0, Ij.n_blocks, 1, res, ovf, 0, nullptr, xsum);
+        if (kDigest && Ij.digest != nullptr) {
+          const uint64_t x = wave_xor(xsum);
+          if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(Ij.digest, x);
+        }
+      }
+      continue;
+    }
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
     uint64_t xsum = 0;
     run_blocks<Acc, false, kDigest, kGeneral>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0,

@@ -382,11 +382,18 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   const uintptr_t idb = info.id_bytes;
   if ((reinterpret_cast<uintptr_t>(out_src) | reinterpret_cast<uintptr_t>(out_dst)) % idb)
     return set_error(RMAT_EINVAL, "output pointers must be %u-byte aligned", (unsigned)idb);
-  // one instance per non-empty tile, outputs back to back in row-major order
+  // one instance per non-empty tile, outputs back to back in row-major
+  // order.  A tile of more than kSmallTile blocks is cut into work items of
+  // up to work_blocks blocks that a workgroup's waves share; the smaller tiles
+  // follow the others in the instance list and are packed into items of up
+  // to kPackInsts instances (kPackBlocks blocks), one wave per instance.
   const rmat::TableView& V = *rmat::table_view_of(t);
   const int kk = info.k - tile_bits;
   const uint32_t work_blocks = 2048;
-  std::vector<rmat::GenInst> insts;
+  constexpr uint64_t kSmallTile = 8;
+  constexpr uint32_t kPackInsts = 256;
+  constexpr uint64_t kPackBlocks = 1024;
+  std::vector<rmat::GenInst> insts, small;
   std::vector<rmat::GenWorkItem> items;
   insts.reserve(n_tiles);
   items.reserve(n_tiles + total / (64ull * work_blocks));
@@ -417,6 +424,11 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     I.src_prefix = static_cast<uint64_t>(r) << kk;
     I.dst_prefix = static_cast<uint64_t>(c) << kk;
     I.epi = 0;
+    off += n;
+    if (I.n_blocks <= kSmallTile) {
+      small.push_back(I);
+      continue;
+    }
     const uint32_t ii = static_cast<uint32_t>(insts.size());
     insts.push_back(I);
     for (uint64_t f = 0; f < I.n_blocks; f += work_blocks) {
@@ -426,7 +438,21 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
       w.n_blocks = static_cast<uint32_t>(I.n_blocks - f < work_blocks ? I.n_blocks - f : work_blocks);
       items.push_back(w);
     }
-    off += n;
+  }
+  const size_t s0 = insts.size();
+  insts.insert(insts.end(), small.begin(), small.end());
+  for (size_t i = 0; i < small.size();) {
+    uint32_t n = 0;
+    uint64_t blocks = 0;
+    while (i + n < small.size() && n < kPackInsts && blocks + small[i + n].n_blocks <= kPackBlocks)
+      blocks += small[i + n++].n_blocks;
+    rmat::GenWorkItem w;  // n == 1 is an ordinary item over the whole instance
+    w.inst = static_cast<uint32_t>(s0 + i);
+    w.first = 0;
+    w.n_blocks = static_cast<uint32_t>(blocks);
+    w.n_inst = n;
+    items.push_back(w);
+    i += n;
   }
   const uint64_t inst_bytes = (insts.size() * sizeof(rmat::GenInst) + 255) / 256 * 256;
   const uint64_t item_bytes = (items.size() * sizeof(rmat::GenWorkItem) + 255) / 256 * 256;

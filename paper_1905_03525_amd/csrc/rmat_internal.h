@@ -125,7 +125,10 @@ uint64_t splitmix64(uint64_t& state);
 struct GenWorkItem {
   uint32_t inst;
   uint32_t n_blocks;
-  uint64_t first;  // first block, relative to the instance's first block
+  uint64_t first;        // first block, relative to the instance's first block
+  uint32_t n_inst = 1;   // > 1: instances inst .. inst + n_inst - 1, all on one table, each
+                         // generated whole by one wave (first and n_blocks unused)
+  uint32_t reserved = 0;
 };
 
 struct BatchArgs {

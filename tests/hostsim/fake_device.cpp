@@ -148,13 +148,12 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
   ++g_launches;
   if (a.n_items == 0) return hipSuccess;
   if (*a.counter != 0) fail("work counter not zero at launch");
-  for (uint32_t it = 0; it < a.n_items; ++it) {
-    const GenWorkItem& W = a.items[it];
-    const GenInst& I = a.insts[W.inst];
+  // one instance's blocks [first, first + n_blocks)
+  auto run = [&](const GenInst& I, uint64_t first, uint64_t n_blocks) {
     uint64_t tag[2];
     std::memcpy(tag, I.records, sizeof(tag));
     if (tag[1] != I.n_buckets) fail("instance table of another size");
-    if (W.n_blocks == 0 || W.first + W.n_blocks > I.n_blocks) fail("work item outside its instance");
+    if (n_blocks == 0 || first + n_blocks > I.n_blocks) fail("work item outside its instance");
     if ((I.k > 32) != (a.wide != 0)) fail("id width of the launch");
     if ((I.n_buckets <= lds_table_limit()) != (a.lds != 0)) fail("table residency of the launch");
     if (I.n_buckets > a.max_buckets) fail("table larger than the launch's LDS layout");
@@ -163,7 +162,7 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
     std::vector<uint32_t>& cov = g_cov[seed];
     if (cov.size() != I.m) cov.assign(I.m, 0);
     const uint64_t last = I.edge_begin + (I.m - 1);
-    for (uint64_t b = W.first; b < W.first + W.n_blocks; ++b) {
+    for (uint64_t b = first; b < first + n_blocks; ++b) {
       const uint64_t base = (I.first_block + b) << 6;
       for (uint64_t l = 0; l < 64; ++l) {
         const uint64_t e = base + l;
@@ -171,6 +170,18 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
         ++cov[e - I.edge_begin];
         if (a.digest && I.digest) *I.digest ^= sim::edge_word(e, seed, tag[0]);
       }
+    }
+  };
+  for (uint32_t it = 0; it < a.n_items; ++it) {
+    const GenWorkItem& W = a.items[it];
+    if (W.n_inst > 1) {  // whole instances on the first one's table
+      for (uint32_t j = 0; j < W.n_inst; ++j) {
+        const GenInst& I = a.insts[W.inst + j];
+        if (I.records != a.insts[W.inst].records) fail("packed instances on different tables");
+        run(I, 0, I.n_blocks);
+      }
+    } else {
+      run(a.insts[W.inst], W.first, W.n_blocks);
     }
   }
   *a.counter = a.n_items;

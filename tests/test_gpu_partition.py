@@ -33,6 +33,7 @@ CASES = [
     ((0.25, 0.25, 0.25, 0.25), 16, 1000, oracle.VARIABLE, 1, 100_000, 8, (0, 3)),
     (G500, 2, 100, oracle.VARIABLE, 4, 10_000, 1, None),                 # one letter left per tile
     (G500, 33, 4096, oracle.VARIABLE, 2, 70_000, 1, (1, 2)),
+    (G500, 24, 4096, oracle.VARIABLE, 5, 1 << 22, 10, (0, 4)),          # tiles of 1 to 8 blocks packed per wave
 ]
 
 
