@@ -410,6 +410,9 @@ def main():
         # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
         # tile rows [0, 64) per call, four calls; counting on the host included
         t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+        for r0 in range(0, 256, 64):  # warm-up pass (list buffers, code objects); counted again below
+            n = int(R.rmat_partition_counts(t_part, w["seed"], m, 8, r0, r0 + 64).sum())
+            R.rmat_generate_partition(t_part, w["seed"], m, 8, r0, r0 + 64, src, dst, n)
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         n_part, count_s = 0, 0.0

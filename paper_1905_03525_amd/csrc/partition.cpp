@@ -385,19 +385,75 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   // one instance per non-empty tile, outputs back to back in row-major
   // order.  A tile of more than kSmallTile blocks is cut into work items of
   // up to work_blocks blocks that a workgroup's waves share; the smaller tiles
-  // follow the others in the instance list and are packed into items of up
-  // to kPackInsts instances (kPackBlocks blocks), one wave per instance.
+  // follow the others in the instance list and are packed, in row-major
+  // order, into items of up to kPackInsts instances (kPackBlocks blocks), one
+  // wave per instance.  The lists are sized in a first pass and written
+  // straight into pinned memory in a second.
   const rmat::TableView& V = *rmat::table_view_of(t);
   const int kk = info.k - tile_bits;
-  const uint32_t work_blocks = 2048;
+  const uint64_t work_blocks = 2048;
   constexpr uint64_t kSmallTile = 8;
   constexpr uint32_t kPackInsts = 256;
   constexpr uint64_t kPackBlocks = 1024;
-  std::vector<rmat::GenInst> insts, small;
-  std::vector<rmat::GenWorkItem> items;
-  insts.reserve(n_tiles);
-  items.reserve(n_tiles + total / (64ull * work_blocks));
+  // a small tile of nb blocks opens a new pack when the current one is full
+  auto opens_pack = [&](uint32_t pack_n, uint64_t pack_blocks, uint64_t nb) {
+    return pack_n == 0 || pack_n == kPackInsts || pack_blocks + nb > kPackBlocks;
+  };
+  uint64_t n_big = 0, n_small = 0, n_big_items = 0, n_packs = 0;
+  {
+    uint32_t pack_n = 0;
+    uint64_t pack_blocks = 0;
+    for (uint64_t i = 0; i < n_tiles; ++i) {
+      if (counts[i] == 0) continue;
+      const uint64_t nb = (counts[i] + 63) / 64;
+      if (nb > kSmallTile) {
+        ++n_big;
+        n_big_items += (nb + work_blocks - 1) / work_blocks;
+        continue;
+      }
+      ++n_small;
+      if (opens_pack(pack_n, pack_blocks, nb)) {
+        ++n_packs;
+        pack_n = 0;
+        pack_blocks = 0;
+      }
+      ++pack_n;
+      pack_blocks += nb;
+    }
+  }
+  const uint64_t n_items = n_big_items + n_packs;
+  const uint64_t inst_bytes = ((n_big + n_small) * sizeof(rmat::GenInst) + 255) / 256 * 256;
+  const uint64_t item_bytes = (n_items * sizeof(rmat::GenWorkItem) + 255) / 256 * 256;
+  const uint64_t bytes = inst_bytes + item_bytes + 256;
+  // [instances | work items | zeroed work counter] in pinned host memory, sent
+  // in one copy to a device buffer; both are kept between calls (calls are
+  // synchronous and serialised here)
+  std::lock_guard<std::mutex> lock(g_lists_mu);
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return rmat::hip_fail(e, "hipGetDevice");
+  Lists& L = g_lists[device];
+  if (L.bytes < bytes) {
+    if (L.dev) (void)hipFree(L.dev);
+    if (L.host) (void)hipHostFree(L.host);
+    L = Lists{};
+    e = hipMalloc(&L.dev, bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&L.host, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      if (L.dev) (void)hipFree(L.dev);
+      L = Lists{};
+      return rmat::hip_fail(e, "allocation of the partition lists");
+    }
+    L.bytes = bytes;
+  }
+  char* host = static_cast<char*>(L.host);
+  auto* h_inst = reinterpret_cast<rmat::GenInst*>(host);
+  auto* h_item = reinterpret_cast<rmat::GenWorkItem*>(host + inst_bytes);
+  uint64_t next_big = 0, next_small = n_big, next_big_item = 0, next_pack = n_big_items;
+  uint32_t pack_n = 0;
+  uint64_t pack_blocks = 0;
   uint64_t off = 0;
+  const char* overrun = "partition lists: filling outgrew the sizing pass";
   for (uint64_t i = 0; i < n_tiles; ++i) {
     const uint64_t n = counts[i];
     if (n == 0) continue;
@@ -425,62 +481,41 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     I.dst_prefix = static_cast<uint64_t>(c) << kk;
     I.epi = 0;
     off += n;
-    if (I.n_blocks <= kSmallTile) {
-      small.push_back(I);
+    if (I.n_blocks > kSmallTile) {
+      if (next_big >= n_big) return set_error(RMAT_EDEVICE, "%s", overrun);
+      const uint64_t ii = next_big++;
+      h_inst[ii] = I;
+      for (uint64_t f = 0; f < I.n_blocks; f += work_blocks) {
+        if (next_big_item >= n_big_items) return set_error(RMAT_EDEVICE, "%s", overrun);
+        rmat::GenWorkItem w;
+        w.inst = static_cast<uint32_t>(ii);
+        w.first = f;
+        w.n_blocks = static_cast<uint32_t>(I.n_blocks - f < work_blocks ? I.n_blocks - f : work_blocks);
+        h_item[next_big_item++] = w;
+      }
       continue;
     }
-    const uint32_t ii = static_cast<uint32_t>(insts.size());
-    insts.push_back(I);
-    for (uint64_t f = 0; f < I.n_blocks; f += work_blocks) {
-      rmat::GenWorkItem w;
-      w.inst = ii;
-      w.first = f;
-      w.n_blocks = static_cast<uint32_t>(I.n_blocks - f < work_blocks ? I.n_blocks - f : work_blocks);
-      items.push_back(w);
+    if (next_small >= n_big + n_small) return set_error(RMAT_EDEVICE, "%s", overrun);
+    const uint64_t ii = next_small++;
+    h_inst[ii] = I;
+    if (opens_pack(pack_n, pack_blocks, I.n_blocks)) {
+      if (next_pack >= n_items) return set_error(RMAT_EDEVICE, "%s", overrun);
+      rmat::GenWorkItem w;  // a pack of one instance is an ordinary item over it
+      w.inst = static_cast<uint32_t>(ii);
+      w.first = 0;
+      w.n_blocks = 0;
+      w.n_inst = 0;
+      h_item[next_pack++] = w;
+      pack_n = 0;
+      pack_blocks = 0;
     }
+    rmat::GenWorkItem& w = h_item[next_pack - 1];
+    w.n_inst = ++pack_n;
+    pack_blocks += I.n_blocks;
+    w.n_blocks = static_cast<uint32_t>(pack_blocks);
   }
-  const size_t s0 = insts.size();
-  insts.insert(insts.end(), small.begin(), small.end());
-  for (size_t i = 0; i < small.size();) {
-    uint32_t n = 0;
-    uint64_t blocks = 0;
-    while (i + n < small.size() && n < kPackInsts && blocks + small[i + n].n_blocks <= kPackBlocks)
-      blocks += small[i + n++].n_blocks;
-    rmat::GenWorkItem w;  // n == 1 is an ordinary item over the whole instance
-    w.inst = static_cast<uint32_t>(s0 + i);
-    w.first = 0;
-    w.n_blocks = static_cast<uint32_t>(blocks);
-    w.n_inst = n;
-    items.push_back(w);
-    i += n;
-  }
-  const uint64_t inst_bytes = (insts.size() * sizeof(rmat::GenInst) + 255) / 256 * 256;
-  const uint64_t item_bytes = (items.size() * sizeof(rmat::GenWorkItem) + 255) / 256 * 256;
-  const uint64_t bytes = inst_bytes + item_bytes + 256;
-  // [instances | work items | zeroed work counter], assembled in pinned host
-  // memory and sent in one copy to a device buffer; both are kept between
-  // calls (calls are synchronous and serialised here)
-  std::lock_guard<std::mutex> lock(g_lists_mu);
-  int device = 0;
-  hipError_t e = hipGetDevice(&device);
-  if (e != hipSuccess) return rmat::hip_fail(e, "hipGetDevice");
-  Lists& L = g_lists[device];
-  if (L.bytes < bytes) {
-    if (L.dev) (void)hipFree(L.dev);
-    if (L.host) (void)hipHostFree(L.host);
-    L = Lists{};
-    e = hipMalloc(&L.dev, bytes);
-    if (e == hipSuccess) e = hipHostMalloc(&L.host, bytes, hipHostMallocDefault);
-    if (e != hipSuccess) {
-      if (L.dev) (void)hipFree(L.dev);
-      L = Lists{};
-      return rmat::hip_fail(e, "allocation of the partition lists");
-    }
-    L.bytes = bytes;
-  }
-  char* host = static_cast<char*>(L.host);
-  std::memcpy(host, insts.data(), insts.size() * sizeof(rmat::GenInst));
-  std::memcpy(host + inst_bytes, items.data(), items.size() * sizeof(rmat::GenWorkItem));
+  if (next_big != n_big || next_small != n_big + n_small || next_big_item != n_big_items || next_pack != n_items)
+    return set_error(RMAT_EDEVICE, "partition lists: sizing and filling disagree");
   std::memset(host + inst_bytes + item_bytes, 0, 256);
   char* base = static_cast<char*>(L.dev);
   e = hipMemcpy(base, host, bytes, hipMemcpyHostToDevice);
@@ -488,7 +523,7 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
     rmat::BatchArgs a;
     a.insts = reinterpret_cast<const rmat::GenInst*>(base);
     a.items = reinterpret_cast<const rmat::GenWorkItem*>(base + inst_bytes);
-    a.n_items = static_cast<uint32_t>(items.size());
+    a.n_items = static_cast<uint32_t>(n_items);
     a.counter = reinterpret_cast<unsigned int*>(base + inst_bytes + item_bytes);
     a.max_buckets = static_cast<uint32_t>(info.n_buckets);
     a.wide = info.k > 32;

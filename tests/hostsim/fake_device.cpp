@@ -23,6 +23,8 @@ double g_ready_p = 0.5;
 int g_fail = 0;
 std::map<uint64_t, std::vector<uint32_t>> g_cov;  // request seed -> per-edge write count
 uint64_t g_launches = 0;
+bool g_whole_cover = false;   // partitioned launches: every instance covered once
+uint64_t g_cover_insts = 0;   // instances the last such launch covered
 
 void fail(const char* what) {
   std::fprintf(stderr, "fake device: %s\n", what);
@@ -43,6 +45,11 @@ void sim_seed(uint64_t s, double ready_p) {
   g_ready_p = ready_p;
 }
 int sim_failed() { return g_fail; }
+// Partitioned-graph mode: each batch launch must cover every block of every
+// instance it lists exactly once (instances 0 .. n-1); tiles may be narrower
+// than the launch's ids (their prefixes widen them).
+void sim_whole_cover(int on) { g_whole_cover = on != 0; }
+uint64_t sim_cover_insts() { return g_cover_insts; }
 uint64_t sim_launches() { return g_launches; }
 // 0 if every edge of the request with this seed was generated exactly once,
 // else -1; forgets the request.
@@ -154,7 +161,7 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
     std::memcpy(tag, I.records, sizeof(tag));
     if (tag[1] != I.n_buckets) fail("instance table of another size");
     if (n_blocks == 0 || first + n_blocks > I.n_blocks) fail("work item outside its instance");
-    if ((I.k > 32) != (a.wide != 0)) fail("id width of the launch");
+    if (g_whole_cover ? (I.k > 32 && !a.wide) : ((I.k > 32) != (a.wide != 0))) fail("id width of the launch");
     if ((I.n_buckets <= lds_table_limit()) != (a.lds != 0)) fail("table residency of the launch");
     if (I.n_buckets > a.max_buckets) fail("table larger than the launch's LDS layout");
     if (I.first_block != I.edge_begin >> 6) fail("first block");
@@ -172,17 +179,38 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
       }
     }
   };
+  std::map<uint32_t, std::vector<uint32_t>> blocks;  // instance -> per-block visits
+  auto visit = [&](uint32_t inst, uint64_t first, uint64_t n) {
+    if (!g_whole_cover) return;
+    std::vector<uint32_t>& v = blocks[inst];
+    if (v.empty()) v.assign(a.insts[inst].n_blocks, 0);
+    for (uint64_t b = first; b < first + n && b < v.size(); ++b) ++v[b];
+  };
   for (uint32_t it = 0; it < a.n_items; ++it) {
     const GenWorkItem& W = a.items[it];
     if (W.n_inst > 1) {  // whole instances on the first one's table
+      uint64_t sum = 0;
       for (uint32_t j = 0; j < W.n_inst; ++j) {
         const GenInst& I = a.insts[W.inst + j];
         if (I.records != a.insts[W.inst].records) fail("packed instances on different tables");
         run(I, 0, I.n_blocks);
+        visit(W.inst + j, 0, I.n_blocks);
+        sum += I.n_blocks;
       }
+      if (sum != W.n_blocks) fail("packed item's block count");
     } else {
       run(a.insts[W.inst], W.first, W.n_blocks);
+      visit(W.inst, W.first, W.n_blocks);
     }
+  }
+  if (g_whole_cover) {
+    uint32_t expect = 0;
+    for (const auto& kv : blocks) {
+      if (kv.first != expect++) fail("an instance without work items");
+      for (uint32_t c : kv.second)
+        if (c != 1) fail("a block of an instance not covered exactly once");
+    }
+    g_cover_insts = blocks.size();
   }
   *a.counter = a.n_items;
   return hipSuccess;

@@ -33,6 +33,9 @@ def lib(tmp_path_factory):
     L.rmat_build_table.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, u64, ctypes.c_int, ctypes.POINTER(vp)]
     L.rmat_partition_counts.argtypes = [vp, u64, u64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, vp]
     L.rmat_free_table.argtypes = [vp]
+    L.rmat_generate_partition.argtypes = [vp, u64, u64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, vp, vp, u64]
+    L.sim_whole_cover.argtypes = [ctypes.c_int]
+    L.sim_cover_insts.restype = u64
     L.rmat_last_error.restype = ctypes.c_char_p
     return L
 
@@ -65,3 +68,37 @@ def test_library_counts_equal_oracle(lib, q, k, bound, seed, m, tb, rows):
     assert np.array_equal(got, want)
     if rows is None:
         assert int(got.sum()) == m
+
+
+LIST_CASES = [
+    # q, k, bound, seed, m, tile_bits, rows: big tiles cut into several items,
+    # small ones packed (pack limits by instance count and by blocks), 64-bit ids
+    ((0.57, 0.19, 0.19, 0.05), 26, 4096, 7, 1 << 30, 6, None),
+    ((0.57, 0.19, 0.19, 0.05), 24, 4096, 5, 1 << 22, 10, (0, 4)),
+    ((0.25, 0.25, 0.25, 0.25), 20, 1000, 3, 1 << 22, 8, (0, 16)),   # tiles of 64 edges: 256 per pack
+    ((0.25, 0.25, 0.25, 0.25), 22, 1000, 4, 450 << 16, 8, (7, 9)),  # tiles of 7-8 blocks: packs end by blocks
+    ((0.45, 0.22, 0.22, 0.11), 34, 1 << 16, 3, 1 << 30, 8, (17, 20)),
+]
+
+
+@pytest.mark.parametrize("q,k,bound,seed,m,tb,rows", LIST_CASES)
+def test_generation_lists_cover_every_tile_once(lib, q, k, bound, seed, m, tb, rows):
+    """The work lists of a partitioned generation (through the fake device):
+    every block of every non-empty tile in exactly one work item, packed
+    items on one table with their block counts, one instance per tile."""
+    r0, r1 = rows if rows else (0, 1 << tb)
+    h = ctypes.c_void_p()
+    assert lib.rmat_build_table(*q, k, bound, 1, ctypes.byref(h)) == 0, lib.rmat_last_error()
+    counts = np.zeros((r1 - r0, 1 << tb), np.uint64)
+    assert lib.rmat_partition_counts(h, seed, m, tb, r0, r1, counts.ctypes.data_as(ctypes.c_void_p)) == 0
+    out = np.zeros(2, np.uint64)   # the fake device writes no ids
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    lib.sim_whole_cover(1)
+    try:
+        rc = lib.rmat_generate_partition(h, seed, m, tb, r0, r1, p, p, int(counts.sum()))
+        assert rc == 0, lib.rmat_last_error()
+        assert lib.sim_failed() == 0
+        assert lib.sim_cover_insts() == int((counts > 0).sum())
+    finally:
+        lib.sim_whole_cover(0)
+        lib.rmat_free_table(h)
