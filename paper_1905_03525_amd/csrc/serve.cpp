@@ -589,11 +589,11 @@ int rmat_server_create(const rmat_server_config* cfg_in, rmat_server_t* out) {
   if (cfg_in) c = *cfg_in;
   if (!c.hbm_budget_bytes) c.hbm_budget_bytes = 200000000000ull;
   if (!c.max_table_bound) c.max_table_bound = 8192;
-  if (!c.tick_blocks) c.tick_blocks = 1ull << 23;
-  if (!c.request_quantum) c.request_quantum = 1ull << 20;
+  if (!c.tick_blocks) c.tick_blocks = 1ull << 24;
+  if (!c.request_quantum) c.request_quantum = 1ull << 21;
   if (!c.max_active) c.max_active = 256;
   if (!c.table_slots) c.table_slots = std::max<uint32_t>(1024, c.max_active);
-  if (!c.work_blocks) c.work_blocks = 512;
+  if (!c.work_blocks) c.work_blocks = 2048;
   if (!c.max_inflight) c.max_inflight = 2;
   if (!c.max_builds) c.max_builds = 256;
   if (c.table_slots < c.max_active) return set_error(RMAT_EINVAL, "table_slots must be at least max_active");
