@@ -105,6 +105,16 @@ __device__ __forceinline__ uint64_t mad_u64_u32(uint32_t x, uint32_t m, uint64_t
   return r;
 }
 
+// Powers of a K x K initiator's K for the base-K accumulators: pow[i] = K^i
+// (i <= 15) and magic[i] = floor(2^32 / K^i) + 1, with which the high word of
+// x * magic[i] is floor(x / K^i) for every x < 2^16 when 2 <= K^i <= 2^16
+// (the error x * (magic[i] - 2^32 / K^i) / 2^32 < 2^-16 <= 1 / K^i cannot
+// carry the quotient past the next integer).
+struct KronPow {
+  uint64_t pow[16];
+  uint32_t magic[16];
+};
+
 // Row/column accumulators, filled from bit 0 up: a path of L letters,
 // stored bit-reversed, is shifted to the current fill level and OR-ed in
 // (one v_lshl_or_b32 per half); letters past the register's width fall off
@@ -117,7 +127,7 @@ struct Acc32 {
   uint32_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t, uint32_t filled, uint32_t,
-                                         const uint64_t*) {
+                                         const KronPow*) {
     row |= rowv << filled;
     col |= colv << filled;
   }
@@ -134,7 +144,7 @@ struct Acc64 {
   uint64_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t, uint32_t filled, uint32_t,
-                                         const uint64_t*) {
+                                         const KronPow*) {
     row |= static_cast<uint64_t>(rowv) << filled;
     col |= static_cast<uint64_t>(colv) << filled;
   }
@@ -147,8 +157,10 @@ struct Acc64 {
 // Base-K accumulators for K x K initiators: a path of L digit pairs holds
 // its row and column digits as base-K numbers (root-most digit most
 // significant); the first min(L, k - filled) digits are appended by
-// id = id * K^take + value / K^(L - take).  kpow[i] = K^i (i <= 15).  Ids
-// stay below K^k, so 32-bit ids (K^k <= 2^32) take 32-bit arithmetic.
+// id = id * K^take + value / K^(L - take).  Path values are below 2^15 and
+// the divisor K^(L - take) is at least K, so the quotient is a multiply-high
+// by KronPow::magic.  Ids stay below K^k, so 32-bit ids (K^k <= 2^32) take
+// one 32 x 32 + 32 multiply-add each (its low word, exact).
 template <typename IdT>
 struct KronAcc {
   static constexpr bool kKron = true;
@@ -157,16 +169,22 @@ struct KronAcc {
   Id row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t len, uint32_t filled, uint32_t k,
-                                         const uint64_t* kpow) {
+                                         const KronPow* kpow) {
     const uint32_t take = len < k - filled ? len : k - filled;
     if (take < len) {  // the edge's last path, cut to the digits still needed
-      const uint32_t d = static_cast<uint32_t>(kpow[len - take]);
-      rowv /= d;
-      colv /= d;
+      const uint32_t mg = kpow->magic[len - take];
+      rowv = static_cast<uint32_t>(mad_u64_u32(rowv, mg, 0) >> 32);
+      colv = static_cast<uint32_t>(mad_u64_u32(colv, mg, 0) >> 32);
     }
-    const Id mul = static_cast<Id>(kpow[take]);
-    row = row * mul + rowv;
-    col = col * mul + colv;
+    if constexpr (sizeof(Id) == 4) {
+      const uint32_t mul = static_cast<uint32_t>(kpow->pow[take]);
+      row = static_cast<uint32_t>(mad_u64_u32(row, mul, rowv));
+      col = static_cast<uint32_t>(mad_u64_u32(col, mul, colv));
+    } else {
+      const Id mul = static_cast<Id>(kpow->pow[take]);
+      row = row * mul + rowv;
+      col = col * mul + colv;
+    }
   }
   __device__ __forceinline__ Id src(uint32_t) const { return row; }
   __device__ __forceinline__ Id dst(uint32_t) const { return col; }
@@ -182,7 +200,7 @@ struct KronAcc {
 // cannot come from one path).
 template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
-                                         uint32_t& filled, const uint64_t* kpow) {
+                                         uint32_t& filled, const KronPow* kpow) {
   auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
   const bool o0 = x[0] < r[0].thr_abs, o1 = x[1] < r[1].thr_abs, o2 = x[2] < r[2].thr_abs, o3 = x[3] < r[3].thr_abs;
   auto take = [&](bool o, const BucketRecord& q) {
@@ -205,7 +223,7 @@ __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], con
 template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
                                         uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled,
-                                        const uint64_t* kpow) {
+                                        const KronPow* kpow) {
   const uint32_t x[4] = {x0, x1, x2, x3};
   const BucketRecord r[4] = {tab[x0 >> shift], tab[x1 >> shift], tab[x2 >> shift], tab[x3 >> shift]};
   // keep the reads ahead of the branches below (an operand-only asm, no code)
@@ -394,7 +412,7 @@ template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
-                                           uint16_t* bins, uint64_t& xsum, const uint64_t* kpow = nullptr) {
+                                           uint16_t* bins, uint64_t& xsum, const KronPow* kpow = nullptr) {
   using Id = typename Acc::Id;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
@@ -646,15 +664,18 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ unsigned long long s_xor[kWaves];
   using Packed = typename Acc::Packed;
-  const uint64_t* kpow = nullptr;
+  const KronPow* kpow = nullptr;
   if constexpr (Acc::kKron) {
-    __shared__ uint64_t s_kpow[16];  // K^0 .. K^15
+    __shared__ KronPow s_kpow;
     if (threadIdx.x == 0) {
       uint64_t x = 1;
-      for (int i = 0; i < 16; ++i, x *= P.I.kron_k) s_kpow[i] = x;
+      for (int i = 0; i < 16; ++i, x *= P.I.kron_k) {
+        s_kpow.pow[i] = x;
+        s_kpow.magic[i] = static_cast<uint32_t>((1ull << 32) / x + 1);  // used for 2 <= x < 2^15 only
+      }
     }
     __syncthreads();
-    kpow = s_kpow;
+    kpow = &s_kpow;
   }
   const BucketRecord* tab = P.I.records;
   if (kLds) {
