@@ -227,6 +227,36 @@ int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed,
                                void* d_hist, void* d_xor, void* stream);
 
 /*
+ * Out-degrees of the generated graph (the out-degree histogram of a huge
+ * instance read literally: one counter per node).  Generates the same edges
+ * as rmat_generate, stores none of them, and adds 1 to d_degree[src] for each
+ * edge in [edge_begin, edge_begin + m):
+ *  d_degree  device array of 2^k uint32 counters (4-byte aligned), owned
+ *            and zeroed by the caller; chunks accumulate; a counter wraps
+ *            modulo 2^32.
+ * R-MAT tables and perturbed sets; a K x K Kronecker table is rejected
+ * (RMAT_EINVAL).  No workspace; asynchronous on `stream`; calls on different
+ * streams may overlap (the increments are atomic).  Errors as for
+ * rmat_generate_async.
+ */
+int rmat_generate_degrees_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, void* d_degree,
+                                void* stream);
+
+/*
+ * Degree distribution of n_nodes out-degree counters: d_hist[min(d, max_degree)]
+ * += 1 for every counter d of d_degree[0 .. n_nodes).
+ *  d_degree  device array of n_nodes uint32 (16-byte aligned), read only;
+ *  d_hist    device array of max_degree + 1 uint64, zeroed by the caller
+ *            (calls accumulate), the last bin counting every degree
+ *            >= max_degree.
+ * n_nodes <= 2^40, max_degree < 2^31.  Asynchronous on `stream`.  Errors:
+ * RMAT_EINVAL (NULL or misaligned pointers, sizes out of range),
+ * RMAT_EDEVICE.
+ */
+int rmat_degree_distribution_async(const void* d_degree, uint64_t n_nodes, uint32_t max_degree, void* d_hist,
+                                   void* stream);
+
+/*
  * Partitioned, communication-free generation (Sec. 5): the adjacency matrix
  * is cut into 2^t x 2^t tiles (t = tile_bits, 1 <= t <= min(k - 1, 15)); the
  * m edges (m <= 2^53) are divided over the tiles top-down through the

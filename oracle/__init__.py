@@ -239,6 +239,31 @@ def generate_reduce(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int
 
 
 # ---------------------------------------------------------------------------
+# out-degrees: the workload's out-degree histogram read literally (one
+# counter per node, reading R23), built from the edges of generate()
+
+def out_degrees(t: Table, seed: int, edge_begin: int, m: int, threads: int = 8,
+                slice_edges: int = 1 << 24) -> np.ndarray:
+    """Out-degree of each of the 2^k nodes over edges [edge_begin, edge_begin + m):
+    how many of those edges have it as source (uint64)."""
+    if t.K != 2:
+        raise OracleError(-1, "out_degrees (R-MAT tables only)")
+    n = 1 << t.k
+    deg = np.zeros(n, np.uint64)
+    for off in range(0, m, slice_edges):
+        src, _ = generate(t, seed, edge_begin + off, min(slice_edges, m - off), threads=threads)
+        deg += np.bincount(src.astype(np.int64), minlength=n).astype(np.uint64)
+    return deg
+
+
+def degree_distribution(deg: np.ndarray, max_degree: int) -> np.ndarray:
+    """Number of nodes of each out-degree 0 .. max_degree, the last bin counting
+    every degree >= max_degree (uint64)."""
+    clipped = np.minimum(deg.astype(np.uint64), np.uint64(max_degree)).astype(np.int64)
+    return np.bincount(clipped, minlength=max_degree + 1).astype(np.uint64)
+
+
+# ---------------------------------------------------------------------------
 # partitioned generation (Sec. 5, reading R20)
 
 def binomial(seed: int, r: int, c: int, level: int, n: int, p: float) -> int:

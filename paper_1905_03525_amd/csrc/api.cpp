@@ -576,4 +576,51 @@ int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed, uint64_t edge_begi
   return generate_common(t, seed, edge_begin, m, nullptr, nullptr, stream, true, hist_bits, d_hist, d_xor);
 }
 
+int rmat_generate_degrees_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, void* d_degree,
+                                void* stream) {
+  g_err[0] = '\0';
+  if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (t->info.initiator_k > 2) return set_error(RMAT_EINVAL, "out-degrees are for R-MAT tables (K = 2)");
+  if (m == 0) return RMAT_OK;
+  if (edge_begin + (m - 1) < edge_begin) return set_error(RMAT_ERANGE, "edge_begin + m exceeds 2^64");
+  if (!d_degree || reinterpret_cast<uintptr_t>(d_degree) % 4)
+    return set_error(RMAT_EINVAL, "d_degree must be a non-NULL, 4-byte aligned device pointer");
+  rmat::GenerateArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.records = t->v.records;
+  a.n_buckets = static_cast<uint32_t>(t->info.n_buckets);
+  a.bucket_bits = t->info.bucket_bits;
+  a.k = t->info.k;
+  a.lds = t->info.lds_resident;
+  a.seed = seed;
+  a.edge_begin = edge_begin;
+  a.m = m;
+  a.kron_k = 2;
+  a.id_bytes = t->info.id_bytes;
+  a.n_tables = t->info.n_tables;
+  a.degree = static_cast<uint32_t*>(d_degree);
+  hipError_t e = rmat::launch_generate_degrees(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return rmat::hip_fail(e, "generate_degrees launch");
+  return RMAT_OK;
+}
+
+int rmat_degree_distribution_async(const void* d_degree, uint64_t n_nodes, uint32_t max_degree, void* d_hist,
+                                   void* stream) {
+  g_err[0] = '\0';
+  if (n_nodes > (1ull << 40)) return set_error(RMAT_EINVAL, "n_nodes above 2^40");
+  if (max_degree >= (1u << 31)) return set_error(RMAT_EINVAL, "max_degree must be below 2^31");
+  if (!d_hist || reinterpret_cast<uintptr_t>(d_hist) % 8)
+    return set_error(RMAT_EINVAL, "d_hist must be a non-NULL, 8-byte aligned device pointer");
+  if (n_nodes == 0) return RMAT_OK;
+  if (!d_degree || reinterpret_cast<uintptr_t>(d_degree) % 16)
+    return set_error(RMAT_EINVAL, "d_degree must be a non-NULL, 16-byte aligned device pointer");
+  int rc = rmat::check_device();
+  if (rc) return rc;
+  hipError_t e = rmat::launch_degree_distribution(static_cast<const uint32_t*>(d_degree), n_nodes, max_degree,
+                                                  static_cast<unsigned long long*>(d_hist),
+                                                  static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return rmat::hip_fail(e, "degree_distribution launch");
+  return RMAT_OK;
+}
+
 }  // extern "C"

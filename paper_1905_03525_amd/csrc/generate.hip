@@ -248,6 +248,7 @@ struct Launch {
   uint32_t hist_shift;
   uint16_t* bins;  // reduction: source prefix of edge e at bins[e - I.edge_begin]
   unsigned long long* xor_out;
+  uint32_t* degree;  // out-degree counters, one per node (degree launches)
 };
 
 struct BatchLaunch {
@@ -408,11 +409,12 @@ __device__ __forceinline__ uint64_t block_mask(const GenInst& I, uint64_t rel, u
 //      edges listed;
 //   2. the listed edges finished 64 at a time;
 //   3. the tile stored (or reduced).
-template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true>
+template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
-                                           uint16_t* bins, uint64_t& xsum, const KronPow* kpow = nullptr) {
+                                           uint16_t* bins, uint64_t& xsum, const KronPow* kpow = nullptr,
+                                           uint32_t* degree = nullptr) {
   using Id = typename Acc::Id;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
@@ -557,6 +559,9 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
           bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
           xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
+        } else if (kDegree) {  // one more edge out of its source
+          const uint64_t s = acc.src(I.k);
+          atomicAdd(degree + s, 1u);
         } else {
           Id s = static_cast<Id>(acc.src(I.k));
           Id d = static_cast<Id>(acc.dst(I.k));
@@ -580,7 +585,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     for (uint32_t j = 0; j < kMaxTile; ++j)
       if (j < nb_tile) vals[j] = res[j * 64 + lane];
     const uint32_t epi = kGeneral ? E.flags : 0u;
-    if (!kReduce && whole_tile && (!prefixed || epi == 0)) {
+    if (!kReduce && !kDegree && whole_tile && (!prefixed || epi == 0)) {
       // one buffer descriptor per output array for the whole tile; block j
       // sits at a scalar offset from the tile's first block (a tile of a
       // partitioned graph ORs in its id prefixes and has no epilogue)
@@ -659,7 +664,7 @@ __device__ __forceinline__ void stage_table(const BucketRecord* src_rec, uint32_
 
 // kGeneral: the store may carry id prefixes and the epilogue; without it the
 // launch stores the plain ids and keeps none of their parameters live.
-template <typename Acc, bool kLds, bool kReduce, bool kGeneral>
+template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false>
 __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ unsigned long long s_xor[kWaves];
@@ -690,8 +695,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   Packed* res = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
   uint64_t xsum = 0;
-  run_blocks<Acc, kReduce, false, kGeneral>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf, P.hist_shift, P.bins,
-                                            xsum, kpow);
+  run_blocks<Acc, kReduce, false, kGeneral, kDegree>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf,
+                                                     P.hist_shift, P.bins, xsum, kpow, P.degree);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
@@ -809,7 +814,7 @@ uint64_t persistent_grid(size_t lds_bytes) {
   return static_cast<uint64_t>(limits().cu_count) * per_cu;
 }
 
-template <typename Acc, bool kLds, bool kReduce, bool kGeneral>
+template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false>
 hipError_t launch_one(Launch P, hipStream_t s) {
   size_t lds = 0;
   P.L = layout_for<Acc>(P.I.n_buckets * (P.I.table_mask + 1), kLds, &lds);
@@ -819,9 +824,59 @@ hipError_t launch_one(Launch P, hipStream_t s) {
   uint64_t grid = persistent_grid(lds);
   if (grid > wgs_needed) grid = wgs_needed;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce, kGeneral>), dim3(static_cast<uint32_t>(grid)), dim3(kGenThreads),
-                     lds, s, P);
+  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce, kGeneral, kDegree>), dim3(static_cast<uint32_t>(grid)),
+                     dim3(kGenThreads), lds, s, P);
   return hipGetLastError();
+}
+
+// Distribution of out-degrees: each workgroup reads a grid-stride share of
+// the counters 16 bytes at a time, keeps degrees 0..3 (most nodes of an
+// R-MAT graph) in registers, counts degrees below lds_bins in LDS and larger
+// ones with global atomics, then adds its counts to the caller's histogram.
+// A degree above max_degree counts as max_degree.  Per-workgroup counts stay
+// below 2^32 while n < 2^40.
+constexpr uint32_t kDegThreads = 512;
+constexpr uint32_t kDegLdsBins = 8192;  // 32 KB of counters
+
+__global__ __launch_bounds__(kDegThreads) void degree_hist_kernel(const uint32_t* __restrict__ degree, uint64_t n,
+                                                                   uint32_t max_degree, uint32_t lds_bins,
+                                                                   unsigned long long* __restrict__ hist) {
+  extern __shared__ uint32_t s_bins[];
+  for (uint32_t i = threadIdx.x; i < lds_bins; i += kDegThreads) s_bins[i] = 0;
+  __syncthreads();
+  uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  auto count = [&](uint32_t v) {
+    const uint32_t b = v < max_degree ? v : max_degree;
+    c0 += b == 0;
+    c1 += b == 1;
+    c2 += b == 2;
+    c3 += b == 3;
+    if (b >= 4) {
+      if (b < lds_bins)
+        atomicAdd(s_bins + b, 1u);
+      else
+        atomicAdd(hist + b, 1ull);
+    }
+  };
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDegThreads;
+  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * kDegThreads + threadIdx.x;
+  const uint64_t n4 = n / 4;
+  const uint4* d4 = reinterpret_cast<const uint4*>(degree);
+  for (uint64_t i = first; i < n4; i += stride) {
+    const uint4 v = d4[i];
+    count(v.x);
+    count(v.y);
+    count(v.z);
+    count(v.w);
+  }
+  for (uint64_t i = 4 * n4 + first; i < n; i += stride) count(degree[i]);
+  // bins 0..3 exist (b <= max_degree) only up to max_degree; lds_bins > min(3, max_degree)
+  const uint32_t cs[4] = {c0, c1, c2, c3};
+  for (uint32_t b = 0; b < 4 && b <= max_degree; ++b)
+    if (cs[b]) atomicAdd(s_bins + b, cs[b]);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < lds_bins; i += kDegThreads)
+    if (s_bins[i]) atomicAdd(hist + i, static_cast<unsigned long long>(s_bins[i]));
 }
 
 // Histogram of 16-bit bin values: each workgroup counts its slice of the
@@ -883,9 +938,8 @@ uint32_t hist_groups(uint64_t n) {
   return static_cast<uint32_t>(want < 1 ? 1 : (want > cus ? cus : want));
 }
 
-template <bool kReduce>
-hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
-  if (a.m == 0) return hipSuccess;
+// One launch's instance over the call's whole edge range.
+Launch make_launch(const GenerateArgs& a) {
   Launch P;
   P.I.records = a.records;
   P.I.n_buckets = a.n_buckets;
@@ -905,13 +959,21 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
   P.I.kron_k = static_cast<uint32_t>(a.kron_k);
   P.I.src_prefix = P.I.dst_prefix = 0;
   P.I.epi = 0;
+  P.hist_shift = static_cast<uint32_t>(a.k - a.hist_bits);
+  P.bins = a.bins;
+  P.xor_out = a.xor_out;
+  P.degree = a.degree;
+  return P;
+}
+
+template <bool kReduce>
+hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
+  if (a.m == 0) return hipSuccess;
+  Launch P = make_launch(a);
   if (!kReduce && a.epi) {
     P.I.epi = a.epi;
     scramble_params(a.scramble_key, a.k, &P.I);
   }
-  P.hist_shift = static_cast<uint32_t>(a.k - a.hist_bits);
-  P.bins = a.bins;
-  P.xor_out = a.xor_out;
   const bool wide = a.k > 32;
   auto gen = [&](const Launch& L) {
     if (!kReduce && a.kron_k > 2) {  // base-K digits; no epilogue, reduction or sets for these tables
@@ -995,6 +1057,27 @@ uint64_t reduce_partials_bytes() {
 }
 
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispatch<false>(a, s); }
+
+hipError_t launch_generate_degrees(const GenerateArgs& a, hipStream_t s) {
+  if (a.m == 0) return hipSuccess;
+  const Launch P = make_launch(a);
+  if (a.k > 32)
+    return a.lds ? launch_one<Acc64, true, false, false, true>(P, s) : launch_one<Acc64, false, false, false, true>(P, s);
+  return a.lds ? launch_one<Acc32, true, false, false, true>(P, s) : launch_one<Acc32, false, false, false, true>(P, s);
+}
+
+hipError_t launch_degree_distribution(const uint32_t* degree, uint64_t n, uint32_t max_degree,
+                                      unsigned long long* hist, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t lds_bins = max_degree + 1 < kDegLdsBins ? max_degree + 1 : kDegLdsBins;
+  const uint64_t per_group = static_cast<uint64_t>(kDegThreads) * 64;  // 64 counters per thread at least
+  uint64_t groups = (n + per_group - 1) / per_group;
+  const uint64_t cap = 4ull * static_cast<uint64_t>(limits().cu_count);
+  if (groups > cap) groups = cap;
+  hipLaunchKernelGGL(degree_hist_kernel, dim3(static_cast<uint32_t>(groups)), dim3(kDegThreads),
+                     lds_bins * sizeof(uint32_t), s, degree, n, max_degree, lds_bins, hist);
+  return hipGetLastError();
+}
 hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s) { return dispatch<true>(a, s); }
 
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s) {
@@ -1032,6 +1115,10 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_kernel<Acc32, false, true, false>),
       allow_full_lds(&generate_kernel<Acc64, true, true, false>),
       allow_full_lds(&generate_kernel<Acc64, false, true, false>),
+      allow_full_lds(&generate_kernel<Acc32, true, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc32, false, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, true, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, false, false, false, true>),
       allow_full_lds(&generate_batch_kernel<Acc32, true, false, false>),
       allow_full_lds(&generate_batch_kernel<Acc32, true, false, true>),
       allow_full_lds(&generate_batch_kernel<Acc32, true, true, false>),

@@ -176,6 +176,8 @@ struct GenerateArgs {
   uint16_t* bins;
   uint64_t bins_cap;
   uint32_t* partials;
+  // degree variant: counter `degree[src]` incremented once per edge
+  uint32_t* degree;
 };
 
 // Largest sub-chunk of a reduction (edges) and the workspace it needs.
@@ -183,6 +185,10 @@ constexpr uint64_t kReduceChunk = 1ull << 28;
 uint64_t reduce_partials_bytes();
 
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s);
+hipError_t launch_generate_degrees(const GenerateArgs& a, hipStream_t s);
+// hist[min(degree[i], max_degree)] += 1 for i < n (degree 16-byte aligned).
+hipError_t launch_degree_distribution(const uint32_t* degree, uint64_t n, uint32_t max_degree,
+                                      unsigned long long* hist, hipStream_t s);
 hipError_t launch_generate_reduce(const GenerateArgs& a, hipStream_t s);
 
 // Largest table (in buckets) that generation stages in LDS.

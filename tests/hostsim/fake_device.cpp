@@ -218,6 +218,10 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
 
 hipError_t launch_generate(const GenerateArgs&, hipStream_t) { return hipSuccess; }
 hipError_t launch_generate_reduce(const GenerateArgs&, hipStream_t) { return hipSuccess; }
+hipError_t launch_generate_degrees(const GenerateArgs&, hipStream_t) { return hipSuccess; }
+hipError_t launch_degree_distribution(const uint32_t*, uint64_t, uint32_t, unsigned long long*, hipStream_t) {
+  return hipSuccess;
+}
 hipError_t prepare_kernels() { return hipSuccess; }
 uint32_t lds_table_limit() { return 8192; }
 uint32_t tile_blocks(uint32_t, int, int) { return 8; }
