@@ -257,6 +257,42 @@ def k34_chunked(R) -> dict:
                          "reduce_achieved": reduce_rate * en, "reduce_frac": reduce_rate * en / ceiling}}
 
 
+def k34_degrees(R) -> dict:
+    """The k = 34 instance read literally: the out-degree of each of the 2^34
+    nodes (2^34 uint32 counters, 64 GiB) over all 2^34 edges, generated in 16
+    chunks of 2^30 edges with one atomic increment per edge, then the degree
+    distribution (degrees 0 .. 2^20, the last bin clipped), both timed by HIP
+    events; checked by its sums (2^34 nodes, 2^34 edges)."""
+    import numpy as np
+    import torch
+    t = R.rmat_build_table(0.45, 0.22, 0.22, 0.11, 34, 1 << 16, R.RMAT_VARIABLE)
+    deg = torch.zeros(1 << 34, dtype=torch.int32, device="cuda")
+    max_degree = 1 << 20
+    hist = torch.zeros(max_degree + 1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    a.record(stream)
+    for ch in range(16):
+        R.rmat_generate_degrees_async(t, 3, ch << 30, 1 << 30, deg, stream)
+    b.record(stream)
+    R.rmat_degree_distribution_async(deg, 1 << 34, max_degree, hist, stream)
+    c.record(stream)
+    torch.cuda.synchronize()
+    gen_s, dist_s = a.elapsed_time(b) / 1e3, b.elapsed_time(c) / 1e3
+    h = hist.cpu().numpy().view(np.uint64)
+    assert int(h.sum()) == 1 << 34 and int(h[-1]) == 0
+    assert int((np.arange(max_degree + 1, dtype=np.uint64) * h).sum()) == 1 << 34
+    nz = np.nonzero(h)[0]
+    t.close()
+    del deg, hist
+    torch.cuda.empty_cache()
+    return {"workload": "rmat_k34_m2^34_var65536_outdegrees", "counters_gib": 64,
+            "generate_ms": gen_s * 1e3, "edges_per_s": (1 << 34) / gen_s,
+            "distribution_ms": dist_s * 1e3, "distribution_read_gbs": 4 * (1 << 34) / dist_s / 1e9,
+            "isolated_nodes": int(h[0]), "max_degree": int(nz[-1]), "degree_1_nodes": int(h[1])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,6 +474,7 @@ def main():
         out["batched"] = bt
     if not args.no_k34:
         out["k34"] = k34_chunked(R)
+        out["k34_degrees"] = k34_degrees(R)
     if args.served_window > 0:
         out["served"] = served_vs_plain(R, args.served_window, args.served_reading, plain=not args.served_no_plain)
         if args.served_pool > 0:
