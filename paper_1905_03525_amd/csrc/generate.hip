@@ -1,7 +1,9 @@
 // generate.hip -- the hot path: per-edge Philox draws, alias lookups in an
 // LDS-resident (or L2-resident) bucket table, and bit concatenation (Sec. 2,
-// the sampling loop), plus the variant that reduces edges on the device
-// instead of storing them.
+// the sampling loop), plus the variants that reduce edges on the device
+// instead of storing them (a source-prefix histogram with a checksum, or an
+// out-degree counter per node), the persistent kernel of batches, partitioned
+// tiles and served requests, and the base-K accumulators of K x K initiators.
 //
 // Work split.  The absolute edge index space is cut into 64-edge blocks
 // aligned to multiples of 64, so the high counter word e >> 32 is uniform
