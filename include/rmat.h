@@ -335,7 +335,8 @@ typedef struct rmat_autotune_report {
  * Validates every instance (as rmat_build_table and rmat_generate would),
  * sizes and allocates all tables, their build scratch and the work list, and
  * uploads them.  Nothing is built yet.  work_blocks: 64-edge blocks per work
- * item (0: 2048).  The instance array is copied; outputs must stay valid for
+ * item (0: 2048); the work list holds at most 2^28 items (RMAT_EINVAL
+ * beyond).  The instance array is copied; outputs must stay valid for
  * every run.  Errors: RMAT_EINVAL (naming the instance), RMAT_ERANGE,
  * RMAT_ENOMEM, RMAT_EDEVICE.
  */

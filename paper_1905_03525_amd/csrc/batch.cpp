@@ -260,6 +260,9 @@ int calibrate(double* ns) {
 
 }  // namespace
 
+// Largest work list of one batch (24 bytes per item on the host and the device).
+constexpr uint64_t kMaxWorkItems = 1ull << 28;
+
 extern "C" {
 
 int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rmat_batch_t* out) {
@@ -280,9 +283,23 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
     destroy(b);
     return rc;
   }
+  // the work list is bounded before it is built (it grows with m)
+  uint64_t n_work = 0;
+  for (int i = 0; i < n; ++i) {
+    const rmat_instance& x = b->inst[i];
+    if (x.m == 0) continue;
+    const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - (x.edge_begin >> 6) + 1;
+    n_work += (nblk + b->work_blocks - 1) / b->work_blocks;
+    if (n_work > kMaxWorkItems) {
+      destroy(b);
+      return set_error(RMAT_EINVAL, "the batch needs more than %llu work items of %u blocks (instance %d)",
+                       static_cast<unsigned long long>(kMaxWorkItems), b->work_blocks, i);
+    }
+  }
   // groups by id width and table residency; work items in instance order
   const uint32_t lds_limit = rmat::lds_table_limit();
   std::vector<rmat::GenWorkItem> items;
+  items.reserve(n_work);
   std::vector<uint32_t> group_first;
   for (int wide = 0; wide < 2; ++wide)
     for (int lds = 1; lds >= 0; --lds) {

@@ -176,3 +176,23 @@ def test_batch_workload_512_full(R):
     for p in insts:
         p["out_src"] = p["out_dst"] = None
     torch.cuda.empty_cache()
+
+
+def test_batch_rejections(R):
+    """Inputs refused before any device work: a work list beyond 2^28 items
+    (m = 2^60 would otherwise grow it without bound), unknown flags, NULL
+    outputs, edge ranges past 2^64; the outputs are never touched."""
+    import torch
+    buf = torch.full((16,), -1, dtype=torch.int32, device="cuda")
+    base = dict(a=G500[0], b=G500[1], c=G500[2], d=G500[3], k=26, table_bound=4096, path_mode=R.RMAT_VARIABLE,
+                seed=1, edge_begin=0, m=16, out_src=buf, out_dst=buf)
+    for change, status in (({"m": 1 << 60}, R.RMAT_EINVAL), ({"gen_flags": 4}, R.RMAT_EINVAL),
+                           ({"out_src": None}, R.RMAT_EINVAL), ({"edge_begin": 2**64 - 8}, R.RMAT_ERANGE)):
+        with pytest.raises(R.RmatError) as ei:
+            R.rmat_batch_create([dict(base, **change)], 2048)
+        assert ei.value.status == status, change
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_batch_create([dict(base, m=1 << 60)], 1)
+    assert "work items" in str(ei.value)
+    torch.cuda.synchronize()
+    assert int((buf != -1).sum().item()) == 0
