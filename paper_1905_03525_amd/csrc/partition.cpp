@@ -27,6 +27,7 @@
 #include <thread>
 #include <map>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "rmat.h"
@@ -272,7 +273,14 @@ struct Counter {
       for (size_t i; (i = next_task.fetch_add(1)) < frontier.size();) visit(frontier[i]);
     };
     std::vector<std::thread> pool;
-    for (size_t i = 1; i < n_threads; ++i) pool.emplace_back(worker);
+    pool.reserve(n_threads);
+    for (size_t i = 1; i < n_threads; ++i) {
+      try {
+        pool.emplace_back(worker);
+      } catch (...) {  // no more threads: the ones running take the rest, same counts
+        break;
+      }
+    }
     worker();
     for (std::thread& th : pool) th.join();
   }
@@ -349,8 +357,18 @@ int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bi
   C.row_begin = row_begin;
   C.row_end = row_end;
   C.counts = counts;
-  C.run(m);
+  try {
+    C.run(m);
+  } catch (const std::bad_alloc&) {
+    return set_error(RMAT_ENOMEM, "host allocation while counting");
+  }
   std::lock_guard<std::mutex> lock(g_count_cache.mu);
+  g_count_cache.valid = false;
+  try {
+    g_count_cache.counts.assign(counts, counts + (static_cast<uint64_t>(row_end - row_begin) << tile_bits));
+  } catch (const std::bad_alloc&) {
+    return RMAT_OK;  // the counts are in `counts`; only the cache for the next generation is lost
+  }
   g_count_cache.valid = true;
   std::memcpy(g_count_cache.q, C.q, sizeof(C.q));
   g_count_cache.seed = seed;
@@ -358,7 +376,6 @@ int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bi
   g_count_cache.tbits = tile_bits;
   g_count_cache.row_begin = row_begin;
   g_count_cache.row_end = row_end;
-  g_count_cache.counts.assign(counts, counts + (static_cast<uint64_t>(row_end - row_begin) << tile_bits));
   return RMAT_OK;
 }
 
