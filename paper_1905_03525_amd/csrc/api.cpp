@@ -306,8 +306,8 @@ hipError_t build_scratch(int device, uint64_t bytes, void** out) {
 }
 }  // namespace
 
-int rmat_build_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
-                     rmat_table_t* out) {
+static int rmat_build_table_body(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                                 rmat_table_t* out) {
   g_err[0] = '\0';
   if (!out) return set_error(RMAT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -363,8 +363,14 @@ int rmat_build_table(double a, double b, double c, double d, int k, uint64_t tab
   return RMAT_OK;
 }
 
-int rmat_build_perturbed_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
-                               int n_tables, double epsilon, uint64_t perturb_seed, rmat_table_t* out) {
+int rmat_build_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                     rmat_table_t* out) {
+  RMAT_GUARD("rmat_build_table", rmat_build_table_body(a, b, c, d, k, table_bound, path_mode, out));
+}
+
+static int rmat_build_perturbed_table_body(double a, double b, double c, double d, int k, uint64_t table_bound,
+                                           int path_mode, int n_tables, double epsilon, uint64_t perturb_seed,
+                                           rmat_table_t* out) {
   g_err[0] = '\0';
   if (!out) return set_error(RMAT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -453,6 +459,12 @@ int rmat_build_perturbed_table(double a, double b, double c, double d, int k, ui
   std::memcpy(t->q, q0, sizeof(t->q));
   *out = t;
   return RMAT_OK;
+}
+
+int rmat_build_perturbed_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                               int n_tables, double epsilon, uint64_t perturb_seed, rmat_table_t* out) {
+  RMAT_GUARD("rmat_build_perturbed_table", rmat_build_perturbed_table_body(a, b, c, d, k, table_bound, path_mode,
+                                                                           n_tables, epsilon, perturb_seed, out));
 }
 
 int rmat_table_export_member(rmat_table_t t, int i, void* host_buf, size_t nbytes) {

@@ -265,7 +265,7 @@ constexpr uint64_t kMaxWorkItems = 1ull << 28;
 
 extern "C" {
 
-int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rmat_batch_t* out) {
+static int rmat_batch_create_body(const rmat_instance* inst, int n, uint32_t work_blocks, rmat_batch_t* out) {
   rmat::clear_error();
   if (!out) return set_error(RMAT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -408,6 +408,10 @@ int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rm
   return RMAT_OK;
 }
 
+int rmat_batch_create(const rmat_instance* inst, int n, uint32_t work_blocks, rmat_batch_t* out) {
+  RMAT_GUARD("rmat_batch_create", rmat_batch_create_body(inst, n, work_blocks, out));
+}
+
 int rmat_batch_enqueue(rmat_batch_t b, void* stream) {
   rmat::clear_error();
   if (!b) return set_error(RMAT_EINVAL, "NULL batch");
@@ -497,7 +501,7 @@ int rmat_batch_free(rmat_batch_t b) {
   return RMAT_OK;
 }
 
-int rmat_batch_autotune(rmat_instance* inst, int n, rmat_autotune_report* report) {
+static int rmat_batch_autotune_body(rmat_instance* inst, int n, rmat_autotune_report* report) {
   rmat::clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   if (!inst || n <= 0) return set_error(RMAT_EINVAL, "empty instance list");
@@ -605,6 +609,10 @@ int rmat_batch_autotune(rmat_instance* inst, int n, rmat_autotune_report* report
     report->reserved = 0;
   }
   return RMAT_OK;
+}
+
+int rmat_batch_autotune(rmat_instance* inst, int n, rmat_autotune_report* report) {
+  RMAT_GUARD("rmat_batch_autotune", rmat_batch_autotune_body(inst, n, report));
 }
 
 }  // extern "C"

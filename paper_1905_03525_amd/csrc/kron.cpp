@@ -66,8 +66,8 @@ int depth_cap(int K, int k) {
 
 }  // namespace
 
-extern "C" int rmat_kron_build_table(const double* P, int K, int k, uint64_t table_bound, int path_mode,
-                                     rmat_table_t* out) {
+static int rmat_kron_build_table_body(const double* P, int K, int k, uint64_t table_bound, int path_mode,
+                                      rmat_table_t* out) {
   rmat::clear_error();
   if (!out) return set_error(RMAT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -297,4 +297,9 @@ extern "C" int rmat_kron_build_table(const double* P, int K, int k, uint64_t tab
   rc = rmat::adopt_table(info, q4, K, V, d_mem, out);
   if (rc) (void)hipFree(d_mem);
   return rc;
+}
+
+extern "C" int rmat_kron_build_table(const double* P, int K, int k, uint64_t table_bound, int path_mode,
+                                     rmat_table_t* out) {
+  RMAT_GUARD("rmat_kron_build_table", rmat_kron_build_table_body(P, K, k, table_bound, path_mode, out));
 }

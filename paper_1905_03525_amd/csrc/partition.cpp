@@ -342,8 +342,8 @@ int counts_cached(rmat_table_t t, uint64_t seed, uint64_t m, int tbits, uint32_t
 
 extern "C" {
 
-int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
-                          uint32_t row_end, uint64_t* counts) {
+static int rmat_partition_counts_body(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                                      uint32_t row_end, uint64_t* counts) {
   rmat::clear_error();
   if (!t || !counts) return set_error(RMAT_EINVAL, "NULL table or counts");
   const rmat_info& info = *rmat::table_info_of(t);
@@ -379,8 +379,13 @@ int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bi
   return RMAT_OK;
 }
 
-int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
-                            uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out) {
+int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                          uint32_t row_end, uint64_t* counts) {
+  RMAT_GUARD("rmat_partition_counts", rmat_partition_counts_body(t, seed, m, tile_bits, row_begin, row_end, counts));
+}
+
+static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                                        uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out) {
   rmat::clear_error();
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
   const rmat_info& info = *rmat::table_info_of(t);
@@ -552,6 +557,12 @@ int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return rmat::hip_fail(e, "partitioned generation");
   return RMAT_OK;
+}
+
+int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                            uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out) {
+  RMAT_GUARD("rmat_generate_partition", rmat_generate_partition_body(t, seed, m, tile_bits, row_begin, row_end,
+                                                                     out_src, out_dst, n_out));
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
+
 #include "rmat.h"
 
 namespace rmat {
@@ -235,3 +237,15 @@ int set_error(int code, const char* fmt, ...);
 int check_launch(const char* what);
 
 }  // namespace rmat
+
+// The body of an exported function whose host allocations grow with its
+// arguments: an exception never crosses the C ABI; a failed host allocation
+// is RMAT_ENOMEM, anything else RMAT_EDEVICE.
+#define RMAT_GUARD(name, call)                                                      \
+  try {                                                                             \
+    return call;                                                                    \
+  } catch (const std::bad_alloc&) {                                                 \
+    return rmat::set_error(RMAT_ENOMEM, "%s: host allocation failed", name);       \
+  } catch (...) {                                                                   \
+    return rmat::set_error(RMAT_EDEVICE, "%s: unexpected host error", name);      \
+  }

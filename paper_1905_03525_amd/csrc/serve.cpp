@@ -580,7 +580,7 @@ bool busy(const rmat_server* s) { return !s->pending.empty() || !s->active.empty
 
 extern "C" {
 
-int rmat_server_create(const rmat_server_config* cfg_in, rmat_server_t* out) {
+static int rmat_server_create_body(const rmat_server_config* cfg_in, rmat_server_t* out) {
   rmat::clear_error();
   if (!out) return set_error(RMAT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -651,7 +651,11 @@ int rmat_server_create(const rmat_server_config* cfg_in, rmat_server_t* out) {
   return RMAT_OK;
 }
 
-int rmat_server_submit(rmat_server_t s, const rmat_request* r, double t_arrival, uint64_t* ticket) {
+int rmat_server_create(const rmat_server_config* cfg_in, rmat_server_t* out) {
+  RMAT_GUARD("rmat_server_create", rmat_server_create_body(cfg_in, out));
+}
+
+static int rmat_server_submit_body(rmat_server_t s, const rmat_request* r, double t_arrival, uint64_t* ticket) {
   rmat::clear_error();
   if (!s || !r) return set_error(RMAT_EINVAL, "NULL server or request");
   rmat::Shape S;
@@ -669,7 +673,11 @@ int rmat_server_submit(rmat_server_t s, const rmat_request* r, double t_arrival,
   return RMAT_OK;
 }
 
-int rmat_server_step(rmat_server_t s, int* is_busy) {
+int rmat_server_submit(rmat_server_t s, const rmat_request* r, double t_arrival, uint64_t* ticket) {
+  RMAT_GUARD("rmat_server_submit", rmat_server_submit_body(s, r, t_arrival, ticket));
+}
+
+static int rmat_server_step_body(rmat_server_t s, int* is_busy) {
   rmat::clear_error();
   if (!s) return set_error(RMAT_EINVAL, "NULL server");
   bool progressed = false;
@@ -678,7 +686,11 @@ int rmat_server_step(rmat_server_t s, int* is_busy) {
   return rc;
 }
 
-int rmat_server_drain(rmat_server_t s) {
+int rmat_server_step(rmat_server_t s, int* is_busy) {
+  RMAT_GUARD("rmat_server_step", rmat_server_step_body(s, is_busy));
+}
+
+static int rmat_server_drain_body(rmat_server_t s) {
   rmat::clear_error();
   if (!s) return set_error(RMAT_EINVAL, "NULL server");
   while (busy(s)) {
@@ -695,6 +707,10 @@ int rmat_server_drain(rmat_server_t s) {
     }
   }
   return RMAT_OK;
+}
+
+int rmat_server_drain(rmat_server_t s) {
+  RMAT_GUARD("rmat_server_drain", rmat_server_drain_body(s));
 }
 
 int rmat_server_poll(rmat_server_t s, rmat_completion* out, int max, int* n) {
@@ -719,8 +735,8 @@ int rmat_server_release(rmat_server_t s, uint64_t ticket) {
   return RMAT_OK;
 }
 
-int rmat_server_run_trace(rmat_server_t s, const rmat_request* reqs, const double* t_arrival, int n,
-                          rmat_completion* out, rmat_progress_fn progress, void* user) {
+static int rmat_server_run_trace_body(rmat_server_t s, const rmat_request* reqs, const double* t_arrival, int n,
+                                      rmat_completion* out, rmat_progress_fn progress, void* user) {
   rmat::clear_error();
   if (!s || n < 0 || (n > 0 && (!reqs || !t_arrival || !out))) return set_error(RMAT_EINVAL, "NULL argument");
   for (int i = 0; i < n; ++i) {
@@ -767,6 +783,11 @@ int rmat_server_run_trace(rmat_server_t s, const rmat_request* reqs, const doubl
     if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
   return RMAT_OK;
+}
+
+int rmat_server_run_trace(rmat_server_t s, const rmat_request* reqs, const double* t_arrival, int n,
+                          rmat_completion* out, rmat_progress_fn progress, void* user) {
+  RMAT_GUARD("rmat_server_run_trace", rmat_server_run_trace_body(s, reqs, t_arrival, n, out, progress, user));
 }
 
 int rmat_server_get_stats(rmat_server_t s, rmat_server_stats* out) {
