@@ -235,6 +235,27 @@ __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, ui
   consume4<Acc, kSure1>(k, x, r, acc, filled, kpow);
 }
 
+// The samples of one Philox block with each bucket record loaded only when
+// the edge still needs letters (same samples, same order as sample4).  For a
+// table read from L2, where the continuation of an edge usually needs one or
+// two of the block's four samples, this saves the unused random reads.
+template <typename Acc>
+__device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k,
+                                            uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc,
+                                            uint32_t& filled, const KronPow* kpow) {
+  const uint32_t x[4] = {x0, x1, x2, x3};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (filled >= k) break;
+    const BucketRecord q = tab[x[i] >> shift];
+    const bool own = x[i] < q.thr_abs;
+    const uint32_t len = own ? (q.lens & 0xFFFFu) : (q.lens >> 16);
+    acc.append(own ? (q.rows & 0xFFFFu) : (q.rows >> 16), own ? (q.cols & 0xFFFFu) : (q.cols >> 16), len, filled, k,
+               kpow);
+    filled += len;
+  }
+}
+
 using Inst = GenInst;
 
 // LDS layout shared by both kernels: [table | per-wave tile areas].
@@ -411,7 +432,8 @@ __device__ __forceinline__ uint64_t block_mask(const GenInst& I, uint64_t rel, u
 //      edges listed;
 //   2. the listed edges finished 64 at a time;
 //   3. the tile stored (or reduced).
-template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false>
+template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
+          bool kLazy = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
@@ -544,7 +566,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         for (uint32_t jj = 1; filled < I.k; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
-          sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+          if (kLazy)
+            sample_lazy(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+          else
+            sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
         }
         res[idx] = acc.pack();
       }
@@ -697,7 +722,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   Packed* res = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
   uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
   uint64_t xsum = 0;
-  run_blocks<Acc, kReduce, false, kGeneral, kDegree>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf,
+  run_blocks<Acc, kReduce, false, kGeneral, kDegree, !kLds>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf,
                                                      P.hist_shift, P.bins, xsum, kpow, P.degree);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
@@ -748,7 +773,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
         const Inst Ij = B.insts[W.inst + j];
         const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : Ij.records;
         uint64_t xsum = 0;
-        run_blocks<Acc, false, kDigest, kGeneral>(Ij, tab, B.L, 0, Ij.n_blocks, 1, res, ovf, 0, nullptr, xsum);
+        run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(Ij, tab, B.L, 0, Ij.n_blocks, 1, res, ovf, 0, nullptr,
+                                                               xsum);
         if (kDigest && Ij.digest != nullptr) {
           const uint64_t x = wave_xor(xsum);
           if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(Ij.digest, x);
@@ -758,7 +784,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     }
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
     uint64_t xsum = 0;
-    run_blocks<Acc, false, kDigest, kGeneral>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks, kWaves, res, ovf, 0,
+    run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks,
+                                                          kWaves, res, ovf, 0,
                                     nullptr, xsum);
     if (kDigest && I.digest != nullptr) {
       const uint64_t x = wave_xor(xsum);
