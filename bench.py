@@ -34,6 +34,8 @@ BYTES_PER_EDGE = 8  # two uint32 ids written per edge
 INT_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_PHILOX_BLOCK = 40  # 20 products 32x32->64 + 20 three-input XORs (10 rounds)
 OPS_PER_SAMPLE = 11        # shift, compare, 2 selects, row/col split (2), 2 shifts, 2 ORs, add
+OPS_EPILOGUE = 27          # mirror (compare + 2 selects) + per id 3 rounds of (multiply-add, mask, shift, xor)
+OPS_KRON_CUT = 2           # K x K: the last path's two digit values divided by K^i (one multiply-high each)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "generate_k26_ef16_traffic.txt")
 
 
@@ -61,6 +63,14 @@ def samples_per_edge(table_export: dict, k: int):
         eb += ((n + 3) // 4) * done
         state = nxt
     return en, eb
+
+
+def alu_roofline(kernel_ms: float, m: int, ops_per_edge: float) -> dict:
+    """Integer-ALU roofline of one generation kernel: algorithmic ops per edge
+    times the edges of the launch over its duration, against the VALU peak."""
+    achieved = ops_per_edge * m / (kernel_ms / 1e3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK_OPS / 1e12, "unit": "Tops/s",
+            "frac": achieved / INT_PEAK_OPS, "ops_per_edge": ops_per_edge}
 
 
 def _cpu_model() -> str:
@@ -418,6 +428,7 @@ def main():
         eb_.record(stream)
         torch.cuda.synchronize()
         out["undirected_scrambled_kernel_ms"] = ea.elapsed_time(eb_)
+        out["undirected_scrambled_roofline"] = alu_roofline(ea.elapsed_time(eb_), m, ops_per_edge + OPS_EPILOGUE)
         out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
         t_epi.close()
         # degree smoothing (Sec. 5): 8 perturbed tables of bound 1024 (eps 0.1),
@@ -428,8 +439,14 @@ def main():
         R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
         eb_.record(stream)
         torch.cuda.synchronize()
+        laws = [samples_per_edge(R.rmat_table_export_member(t_set, i), k) for i in range(8)]
+        en_set = sum(x[0] for x in laws) / 8  # edge e uses member e mod 8
+        eb_set = sum(x[1] for x in laws) / 8
         out["perturbed_set"] = {"tables": 8, "table_bound": 1024, "epsilon": 0.1,
-                                "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
+                                "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3),
+                                "samples_per_edge": en_set, "philox_blocks_per_edge": eb_set,
+                                "roofline": alu_roofline(ea.elapsed_time(eb_), m, eb_set * OPS_PER_PHILOX_BLOCK +
+                                                         en_set * OPS_PER_SAMPLE)}
         t_set.close()
         # a 3 x 3 stochastic Kronecker initiator (Sec. 5) with 3^17 = 1.29e8
         # nodes (uint32 ids), a 4096-bound table, the same 2^30 edges
@@ -440,8 +457,12 @@ def main():
         R.rmat_generate_async(t_kron, w["seed"], 0, m, src, dst, stream)
         eb_.record(stream)
         torch.cuda.synchronize()
+        en_k, eb_k = samples_per_edge(R.rmat_table_export(t_kron), 17)  # letters are digit pairs
         out["kronecker_3x3"] = {"k": 17, "nodes": 3 ** 17, "table_bound": 4096,
-                                "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3)}
+                                "kernel_ms": ea.elapsed_time(eb_), "edges_per_s": m / (ea.elapsed_time(eb_) / 1e3),
+                                "samples_per_edge": en_k, "philox_blocks_per_edge": eb_k,
+                                "roofline": alu_roofline(ea.elapsed_time(eb_), m, eb_k * OPS_PER_PHILOX_BLOCK +
+                                                         en_k * OPS_PER_SAMPLE + OPS_KRON_CUT)}
         t_kron.close()
         # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
         # tile rows [0, 64) per call, four calls; counting on the host included
