@@ -433,7 +433,7 @@ __device__ __forceinline__ uint64_t block_mask(const GenInst& I, uint64_t rel, u
 //   2. the listed edges finished 64 at a time;
 //   3. the tile stored (or reduced).
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
-          bool kLazy = false>
+          bool kLazy = false, bool kShortPipe = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
@@ -529,6 +529,50 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         }
       }
       finish(kMaxTile - 1, xa, ra);
+    } else if (kShortPipe && whole_tile && sure1) {
+      // a shorter full tile with the tables in LDS (a batch holding a larger
+      // table leaves less LDS for tiles): the same pipeline, rolled.  The
+      // single-instance kernel leaves it out: there it measured no faster
+      // and its presence changes the code of the 8-block path
+      auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
+        const uint64_t base = (I.first_block + t0 + j * stride) << 6;
+        philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
+                       x[0], x[1], x[2], x[3]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = tab_lane[x[i] >> I.shift];
+      };
+      auto finish = [&](uint32_t j, const uint32_t (&x)[4], const BucketRecord (&r)[4]) {
+        Acc acc;
+        acc.clear();
+        uint32_t filled = 0;
+        consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        res[j * 64 + lane] = acc.pack();
+        const bool need = filled < I.k;
+        const uint64_t ovf_mask = __ballot(need);
+        if (ovf_mask != 0) {
+          if (need) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
+            ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
+          }
+          n_ovf += __popcll(ovf_mask);
+        }
+      };
+      uint32_t xa[4];
+      BucketRecord ra[4];
+      draw(0, xa, ra);
+      for (uint32_t j = 1; j < nb_tile; ++j) {
+        uint32_t xb[4];
+        BucketRecord rb[4];
+        draw(j, xb, rb);
+        finish(j - 1, xa, ra);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xa[i] = xb[i];
+          ra[i] = rb[i];
+        }
+      }
+      finish(nb_tile - 1, xa, ra);
     } else if (whole_tile) {
       // a full tile of another size (a larger table or an L2 table leaves
       // less LDS for tiles): whole blocks, rolled
@@ -773,8 +817,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
         const Inst Ij = B.insts[W.inst + j];
         const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : Ij.records;
         uint64_t xsum = 0;
-        run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(Ij, tab, B.L, 0, Ij.n_blocks, 1, res, ovf, 0, nullptr,
-                                                               xsum);
+        run_blocks<Acc, false, kDigest, kGeneral, false, !kLds, kLds>(Ij, tab, B.L, 0, Ij.n_blocks, 1, res, ovf, 0,
+                                                                     nullptr, xsum);
         if (kDigest && Ij.digest != nullptr) {
           const uint64_t x = wave_xor(xsum);
           if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(Ij.digest, x);
@@ -784,9 +828,9 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     }
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
     uint64_t xsum = 0;
-    run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks,
-                                                          kWaves, res, ovf, 0,
-                                    nullptr, xsum);
+    run_blocks<Acc, false, kDigest, kGeneral, false, !kLds, kLds>(I, tab, B.L, W.first + wave_in_wg,
+                                                                W.first + W.n_blocks, kWaves, res, ovf, 0,
+                                                                nullptr, xsum);
     if (kDigest && I.digest != nullptr) {
       const uint64_t x = wave_xor(xsum);
       if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(I.digest, x);
