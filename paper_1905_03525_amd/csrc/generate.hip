@@ -33,6 +33,10 @@ namespace {
 constexpr int kGenThreads = 1024;  // 16 waves share one LDS copy of the table
 constexpr int kWaves = kGenThreads / 64;
 constexpr uint32_t kMaxTile = 8;
+// Every path of a built table has at least one letter and ids have at most
+// 64, so an edge uses at most 64 samples: 16 Philox blocks.  The
+// continuation loop stops there whatever the table holds.
+constexpr uint32_t kMaxBlocksPerEdge = 16;
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
 
@@ -607,7 +611,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         const uint64_t e = ((I.first_block + t0 + (idx >> 6) * stride) << 6) + (idx & 63u);
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
         const BucketRecord* __restrict__ tab_e = tab + ((idx & 63u) & I.table_mask) * I.n_buckets;
-        for (uint32_t jj = 1; filled < I.k; ++jj) {
+        for (uint32_t jj = 1; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
           if (kLazy)

@@ -247,7 +247,7 @@ void complete(rmat_server* s, Req* q, int32_t status) {
   c.t_submit = q->t_submit;
   c.t_admit = q->t_admit;
   c.t_done = now(s);
-  c.digest = (q->r.flags & RMAT_REQ_DIGEST) ? q->digest : 0;
+  c.digest = (status == RMAT_OK && (q->r.flags & RMAT_REQ_DIGEST)) ? q->digest : 0;
   if (q->r.m > 0) {
     Slot& sl = s->slots[q->slot];
     if (--sl.refs == 0) {
@@ -261,7 +261,7 @@ void complete(rmat_server* s, Req* q, int32_t status) {
     }
   }
   if (q->arena) {
-    if (q->r.flags & RMAT_REQ_DISCARD) {
+    if ((q->r.flags & RMAT_REQ_DISCARD) || status != RMAT_OK) {  // nothing to deliver
       s->arena.release(q->arena, q->arena_bytes);
     } else {
       s->delivered[q->ticket] = {q->arena, q->arena_bytes};
@@ -274,8 +274,10 @@ void complete(rmat_server* s, Req* q, int32_t status) {
   }
   s->completions.push_back(c);
   ++s->st.completed;
-  if (status != RMAT_OK) ++s->st.failed;
-  s->st.edges_done += q->r.m;
+  if (status != RMAT_OK)
+    ++s->st.failed;
+  else
+    s->st.edges_done += q->r.m;
   delete q;
 }
 
@@ -308,12 +310,34 @@ int retire(rmat_server* s) {
       }
     }
     for (size_t i = 0; i < R.inst_req.size(); ++i) R.inst_req[i]->digest ^= dig[i];
+    auto status_of = [](int32_t err) {
+      return err == 0 ? RMAT_OK : (err == rmat::kBuildResidual ? RMAT_EINVAL : RMAT_EDEVICE);
+    };
     for (size_t i = 0; i < R.inst_req.size(); ++i) {
       Req* q = R.inst_req[i];
       if (q->last_round != R.id || q->next_block != q->n_blocks) continue;
       const int32_t err = s->slots[q->slot].error;
       remove_active(s, q);
-      complete(s, q, err == 0 ? RMAT_OK : (err == rmat::kBuildResidual ? RMAT_EINVAL : RMAT_EDEVICE));
+      complete(s, q, status_of(err));
+    }
+    // A request whose table failed to build gets no further blocks.  It
+    // completes now unless a round still in flight holds some of its blocks
+    // (round ids grow, so that is a last_round above this round's); such a
+    // request completes when that round retires, by the loop above.
+    for (size_t i = 0; i < s->active.size();) {
+      Req* q = s->active[i];
+      const int32_t err = s->slots[q->slot].error;
+      if (err == 0) {
+        ++i;
+        continue;
+      }
+      q->next_block = q->n_blocks;
+      if (q->last_round > R.id) {
+        ++i;
+        continue;
+      }
+      remove_active(s, q);
+      complete(s, q, status_of(err));
     }
     R.busy = false;
     R.inst_req.clear();

@@ -705,6 +705,16 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
 
 finish:
   __syncthreads();
+  if (s_error != 0 && J.records) {
+    // A failed build still leaves a table a generation can run on: every
+    // bucket holds two empty paths of the longest length, so each sample
+    // adds kMaxDepthCap letters and every edge ends within five samples.  A
+    // batch or a served round that launches generation right after the
+    // build (before the host sees the status) therefore terminates; its
+    // output is meaningless and the status reports the failure.
+    const uint32_t len2 = static_cast<uint32_t>(kMaxDepthCap) * 0x10001u;
+    for (uint32_t i = tid; i < nb; i += kBuildThreads) J.records[i] = BucketRecord{0xFFFFFFFFu, 0u, 0u, len2};
+  }
   if (tid == 0) {
     J.stats->error = s_error;
     J.stats->n_items = n;

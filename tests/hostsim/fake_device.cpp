@@ -51,14 +51,15 @@ int sim_failed() { return g_fail; }
 void sim_whole_cover(int on) { g_whole_cover = on != 0; }
 uint64_t sim_cover_insts() { return g_cover_insts; }
 uint64_t sim_launches() { return g_launches; }
-// 0 if every edge of the request with this seed was generated exactly once,
-// else -1; forgets the request.
-int sim_take_coverage(uint64_t seed, uint64_t m) {
+// 0 if every edge of the request with this seed was generated exactly once
+// (partial: at most once, for a request cut short by a failed build), else
+// -1; forgets the request.
+int sim_take_coverage(uint64_t seed, uint64_t m, int partial) {
   auto it = g_cov.find(seed);
-  if (m == 0) return it == g_cov.end() ? 0 : -1;
+  if (m == 0 || (partial && it == g_cov.end())) return it == g_cov.end() ? 0 : -1;
   if (it == g_cov.end() || it->second.size() != m) return -1;
   for (uint32_t c : it->second)
-    if (c != 1) return -1;
+    if (c > 1 || (c == 0 && !partial)) return -1;
   g_cov.erase(it);
   return 0;
 }

@@ -196,3 +196,33 @@ def test_batch_rejections(R):
     assert "work items" in str(ei.value)
     torch.cuda.synchronize()
     assert int((buf != -1).sum().item()) == 0
+
+
+def test_batch_with_failing_build_terminates_and_reports(R):
+    """An instance whose parameters admit no fixed-point table (inside the
+    validation tolerance, refused by the oracle) is built and generated in
+    the same launch as the others: the launch ends, rmat_batch_check reports
+    RMAT_EINVAL and names the instance, and the other instances equal their
+    plain launches."""
+    import torch
+    bad = (0.57, 0.19, 0.19, 0.05 - 9e-10)
+    insts = [dict(a=G500[0], b=G500[1], c=G500[2], d=G500[3], k=20, table_bound=4096, path_mode=R.RMAT_VARIABLE,
+                  seed=5, edge_begin=0, m=1 << 18),
+             dict(a=bad[0], b=bad[1], c=bad[2], d=bad[3], k=26, table_bound=5, path_mode=R.RMAT_VARIABLE,
+                  seed=6, edge_begin=0, m=1 << 20),
+             dict(a=bad[0], b=bad[1], c=bad[2], d=bad[3], k=40, table_bound=5, path_mode=R.RMAT_VARIABLE,
+                  seed=7, edge_begin=0, m=1 << 16),
+             dict(a=CFG3[0], b=CFG3[1], c=CFG3[2], d=CFG3[3], k=30, table_bound=1 << 15, path_mode=R.RMAT_VARIABLE,
+                  seed=8, edge_begin=3, m=100_000)]
+    _alloc(R, insts)
+    with R.rmat_batch_create(insts, 64) as b:
+        R.rmat_batch_enqueue(b, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        with pytest.raises(R.RmatError) as ei:
+            R.rmat_batch_check(b)
+        assert ei.value.status == R.RMAT_EINVAL and "instance 1" in str(ei.value)
+        for i in (0, 3):
+            p = insts[i]
+            t, s, d = _plain(R, p)
+            assert torch.equal(s, p["out_src"]) and torch.equal(d, p["out_dst"]), f"instance {i}"
+            t.close()

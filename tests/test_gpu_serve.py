@@ -216,3 +216,52 @@ def test_server_errors(R):
         assert R.rmat_server_get_stats(s)["submitted"] == 0
     with pytest.raises(R.RmatError):
         R.rmat_server_create(table_slots=4, max_active=8)
+
+
+# Parameters inside the validation tolerance (|a+b+c+d-1| <= 1e-9) whose
+# largest-remainder residual falls outside [0, n] for a 4-path table: the
+# oracle refuses them, and so does the device build.
+FAILING = (0.57, 0.19, 0.19, 0.05 - 9e-10)
+
+
+def test_failing_parameters_refused_by_oracle_and_build(R):
+    with pytest.raises(oracle.OracleError):
+        oracle.build_table(*FAILING, 26, 5, oracle.VARIABLE)
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_build_table(*FAILING, 26, 5, R.RMAT_VARIABLE)
+    assert ei.value.status == R.RMAT_EINVAL
+
+
+def test_served_failed_build_completes_with_einval(R):
+    """A request whose table fails to build completes with RMAT_EINVAL (no
+    digest, no arena outputs), also when it spans several rounds and when a
+    second request joins the failing slot while its build is in flight; the
+    requests around them complete with their oracle digests."""
+    good = [dict(a=G500[0], b=G500[1], c=G500[2], d=G500[3], k=20, path_mode=1, table_bound=4096, seed=50 + i,
+                 edge_begin=0, m=1 << 18, flags=1) for i in range(2)]
+    bad = [dict(a=FAILING[0], b=FAILING[1], c=FAILING[2], d=FAILING[3], k=26, path_mode=1, table_bound=5,
+                seed=60 + i, edge_begin=0, m=1 << 22, flags=1) for i in range(2)]
+    reqs = [good[0], bad[0], bad[1], good[1]]
+    with R.rmat_server_create(hbm_budget_bytes=1 << 28, max_table_bound=4096, tick_blocks=1 << 12,
+                              request_quantum=1 << 10, max_active=4, work_blocks=64) as s:
+        tickets = [R.rmat_server_submit(s, p) for p in reqs]
+        R.rmat_server_drain(s)
+        done = {c["ticket"]: c for c in R.rmat_server_poll(s, 100)}
+        st = R.rmat_server_get_stats(s)
+        assert st["completed"] == 4 and st["failed"] == 2 and st["active"] == 0 and st["pending"] == 0
+        for p, t in zip(reqs, tickets):
+            c = done[t]
+            if p in bad:
+                assert c["status"] == R.RMAT_EINVAL and c["digest"] == 0 and c["out_src"] is None
+            else:
+                assert c["status"] == 0
+                o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+                _, ox = oracle.generate_reduce(o, p["seed"], p["edge_begin"], p["m"], 0, threads=8)
+                assert c["digest"] == ox
+                R.rmat_server_release(s, t)
+        assert R.rmat_server_get_stats(s)["arena_bytes"] == 0
+        # the failed slot is not cached: the same parameters fail again
+        t = R.rmat_server_submit(s, bad[0])
+        R.rmat_server_drain(s)
+        (c,) = R.rmat_server_poll(s)
+        assert c["ticket"] == t and c["status"] == R.RMAT_EINVAL and c["table_hit"] == 0
