@@ -227,6 +227,26 @@ int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed,
                                void* d_hist, void* d_xor, void* stream);
 
 /*
+ * rmat_generate_reduce_async for callers that cannot allocate device memory
+ * (code under stream or graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and the same results, bit for bit, but the
+ * workspace is a fixed array in the library's device data (48 MiB per GPU
+ * the library runs on, held until the process ends) instead of one the
+ * table allocates.  The edges are reduced in sub-chunks of 2^23 (bins of 2
+ * bytes per edge, then the counts of at most 128 workgroups per 2^15-bin
+ * window), so no m or hist_bits that rmat_generate_reduce_async accepts is
+ * too large.  The call allocates nothing and makes no memset; it only
+ * launches kernels on `stream` (the first call on a device also looks up the
+ * array's address there).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on the device race (issue them on one stream), and
+ * only d_hist and d_xor carry results between calls.  Errors as for
+ * rmat_generate_reduce_async.
+ */
+int rmat_generate_reduce_noalloc_async(rmat_table_t t, uint64_t seed,
+                                       uint64_t edge_begin, uint64_t m, int hist_bits,
+                                       void* d_hist, void* d_xor, void* stream);
+
+/*
  * Out-degrees of the generated graph (the out-degree histogram of a huge
  * instance read literally: one counter per node).  Generates the same edges
  * as rmat_generate, stores none of them, and adds 1 to d_degree[src] for each

@@ -501,7 +501,7 @@ int rmat_table_export(rmat_table_t t, void* host_buf, size_t nbytes) {
 
 static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, void* out_src,
                            void* out_dst, void* stream, bool reduce, int hist_bits, void* d_hist, void* d_xor,
-                           int flags = 0, uint64_t scramble_key = 0) {
+                           int flags = 0, uint64_t scramble_key = 0, bool static_workspace = false) {
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
   if (t->info.initiator_k > 2 && (reduce || flags))
     return set_error(RMAT_EINVAL, "a K x K Kronecker table supports plain generation only");
@@ -515,6 +515,14 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
     if (hist_bits < 0 || hist_bits > hmax)
       return set_error(RMAT_EINVAL, "hist_bits %d outside 0..%d", hist_bits, hmax);
     if (!d_hist || !d_xor) return set_error(RMAT_EINVAL, "NULL histogram or checksum pointer");
+    a.hist_bits = hist_bits;
+    a.hist = static_cast<unsigned long long*>(d_hist);
+    a.xor_out = static_cast<unsigned long long*>(d_xor);
+  }
+  if (reduce && static_workspace) {
+    hipError_t e = rmat::static_reduce_workspace(&a);
+    if (e != hipSuccess) return rmat::hip_fail(e, "hipGetSymbolAddress(reduction workspace)");
+  } else if (reduce) {
     // workspace: bins for one sub-chunk, grown on demand (a larger one replaces it)
     const uint64_t want = std::min<uint64_t>(rmat::kReduceChunk, (m + (1u << 20) - 1) & ~static_cast<uint64_t>((1u << 20) - 1));
     if (t->reduce_edges < want) {
@@ -527,9 +535,6 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
       if (e != hipSuccess) return rmat::hip_fail(e, "hipMalloc(reduction workspace)");
       t->reduce_edges = want;
     }
-    a.hist_bits = hist_bits;
-    a.hist = static_cast<unsigned long long*>(d_hist);
-    a.xor_out = static_cast<unsigned long long*>(d_xor);
     a.bins = static_cast<uint16_t*>(t->d_reduce);
     a.bins_cap = t->reduce_edges;
     a.partials = reinterpret_cast<uint32_t*>(static_cast<char*>(t->d_reduce) + t->reduce_edges * sizeof(uint16_t));
@@ -586,6 +591,13 @@ int rmat_generate_reduce_async(rmat_table_t t, uint64_t seed, uint64_t edge_begi
                                void* d_hist, void* d_xor, void* stream) {
   g_err[0] = '\0';
   return generate_common(t, seed, edge_begin, m, nullptr, nullptr, stream, true, hist_bits, d_hist, d_xor);
+}
+
+int rmat_generate_reduce_noalloc_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, int hist_bits,
+                                       void* d_hist, void* d_xor, void* stream) {
+  g_err[0] = '\0';
+  return generate_common(t, seed, edge_begin, m, nullptr, nullptr, stream, true, hist_bits, d_hist, d_xor, 0, 0,
+                         true);
 }
 
 int rmat_generate_degrees_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin, uint64_t m, void* d_degree,

@@ -23,6 +23,7 @@
 // a full tile of whole blocks -- all but a few tiles at the ends of a range --
 // takes an unrolled copy with no per-block lane masks or loop control, and
 // stores through one buffer descriptor per output array.
+#include <mutex>
 #include <type_traits>
 
 #include "rmat_internal.h"
@@ -1081,7 +1082,8 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
     L.I.n_blocks = ((L.I.edge_begin + (len - 1)) >> 6) - L.I.first_block + 1;
     hipError_t e = gen(L);
     if (e != hipSuccess) return e;
-    const uint32_t G = hist_groups(len);
+    uint32_t G = hist_groups(len);
+    if (a.max_hist_groups && G > a.max_hist_groups) G = a.max_hist_groups;
     hipLaunchKernelGGL(hist_partial_kernel, dim3(G), dim3(kHistThreads), kHistWindow * sizeof(uint32_t), s, a.bins,
                        len, n_windows, a.partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1131,6 +1133,44 @@ uint32_t lds_table_limit() {
 
 uint64_t reduce_partials_bytes() {
   return 2ull * static_cast<uint64_t>(limits().cu_count) * kHistWindow * sizeof(uint32_t);
+}
+
+// Workspace of the allocation-free reduction, one copy per device for the
+// life of the process: 16-bit bins of one sub-chunk, then up to two windows
+// of kStaticHistGroups partial rows (hist_bits <= 16).  Every byte a call
+// reads is written earlier in the same call (the bins of a sub-chunk by its
+// generation, each partial row by the counting kernel), so nothing needs
+// clearing between calls.
+constexpr uint64_t kStaticBinsBytes = kStaticReduceChunk * sizeof(uint16_t);
+constexpr uint64_t kStaticScratchBytes =
+    kStaticBinsBytes + 2ull * kStaticHistGroups * kHistWindow * sizeof(uint32_t);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_reduce_workspace(GenerateArgs* a) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+      // the device address of this device's copy; host code uses only it
+      void* d = nullptr;
+      e = hipGetSymbolAddress(&d, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      ptr[dev] = d;
+    }
+    p = ptr[dev];
+  }
+  a->bins = static_cast<uint16_t*>(p);
+  a->bins_cap = kStaticReduceChunk;
+  a->partials = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + kStaticBinsBytes);
+  a->max_hist_groups = kStaticHistGroups;
+  return hipSuccess;
 }
 
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispatch<false>(a, s); }

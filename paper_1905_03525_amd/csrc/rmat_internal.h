@@ -178,6 +178,7 @@ struct GenerateArgs {
   uint16_t* bins;
   uint64_t bins_cap;
   uint32_t* partials;
+  uint32_t max_hist_groups; // rows of `partials` per window (0: one per CU)
   // degree variant: counter `degree[src]` incremented once per edge
   uint32_t* degree;
 };
@@ -185,6 +186,16 @@ struct GenerateArgs {
 // Largest sub-chunk of a reduction (edges) and the workspace it needs.
 constexpr uint64_t kReduceChunk = 1ull << 28;
 uint64_t reduce_partials_bytes();
+
+// The fixed workspace of the allocation-free reduction: a file-scope device
+// array in generate.hip holding the bins of one sub-chunk of
+// kStaticReduceChunk edges and the partial counts of kStaticHistGroups
+// workgroups.  Fills `a`'s workspace fields with this device's copy; the
+// array's address is looked up once per device (hipGetSymbolAddress) on the
+// first call with that device current.
+constexpr uint64_t kStaticReduceChunk = 1ull << 23;
+constexpr uint32_t kStaticHistGroups = 128;
+hipError_t static_reduce_workspace(GenerateArgs* a);
 
 hipError_t launch_generate(const GenerateArgs& a, hipStream_t s);
 hipError_t launch_generate_degrees(const GenerateArgs& a, hipStream_t s);

@@ -28,7 +28,8 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
 
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
 EXPORTED = ["rmat_build_table", "rmat_kron_build_table", "rmat_build_perturbed_table", "rmat_table_export_member", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
-            "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async", "rmat_generate_degrees_async",
+            "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async",
+            "rmat_generate_reduce_noalloc_async", "rmat_generate_degrees_async",
             "rmat_degree_distribution_async", "rmat_batch_create", "rmat_batch_enqueue",
             "rmat_partition_counts", "rmat_generate_partition", "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
             "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
@@ -133,6 +134,7 @@ def load() -> ctypes.CDLL:
     L.rmat_generate.argtypes = [vp, u64, u64, u64, vp, vp]
     L.rmat_generate_async.argtypes = [vp, u64, u64, u64, vp, vp, vp]
     L.rmat_generate_reduce_async.argtypes = [vp, u64, u64, u64, c_int, vp, vp, vp]
+    L.rmat_generate_reduce_noalloc_async.argtypes = [vp, u64, u64, u64, c_int, vp, vp, vp]
     L.rmat_generate_ex_async.argtypes = [vp, u64, u64, u64, c_int, u64, vp, vp, vp]
     L.rmat_generate_degrees_async.argtypes = [vp, u64, u64, u64, vp, vp]
     L.rmat_degree_distribution_async.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
@@ -322,6 +324,12 @@ def rmat_generate_reduce_async(t: Table, seed: int, edge_begin: int, m: int, his
                                stream=None):
     _check(load().rmat_generate_reduce_async(t.handle, seed, edge_begin, m, hist_bits, _ptr(d_hist), _ptr(d_xor),
                                              _stream(stream)), "rmat_generate_reduce_async")
+
+
+def rmat_generate_reduce_noalloc_async(t: Table, seed: int, edge_begin: int, m: int, hist_bits: int, d_hist, d_xor,
+                                       stream=None):
+    _check(load().rmat_generate_reduce_noalloc_async(t.handle, seed, edge_begin, m, hist_bits, _ptr(d_hist),
+                                                     _ptr(d_xor), _stream(stream)), "rmat_generate_reduce_noalloc_async")
 
 
 def rmat_generate_degrees_async(t: Table, seed: int, edge_begin: int, m: int, d_degree, stream=None):

@@ -227,5 +227,6 @@ hipError_t prepare_kernels() { return hipSuccess; }
 uint32_t lds_table_limit() { return 8192; }
 uint32_t tile_blocks(uint32_t, int, int) { return 8; }
 uint64_t reduce_partials_bytes() { return 1u << 20; }
+hipError_t static_reduce_workspace(GenerateArgs*) { return hipErrorInvalidValue; }
 
 }  // namespace rmat
