@@ -419,7 +419,7 @@ def main():
     src = torch.empty(m, dtype=torch.int32, device="cuda")
     dst = torch.empty(m, dtype=torch.int32, device="cuda")
     if not args.no_sec5:
-        # the Sec. 5 epilogue (undirected mirror + id scramble) on the same instance
+        # the Sec. 3 epilogue (undirected mirror + id scramble) on the same instance
         t_epi = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
         R.rmat_generate_ex_async(t_epi, w["seed"], 0, m, 3, 0x5EED, src, dst, stream)
         ea, eb_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -431,7 +431,7 @@ def main():
         out["undirected_scrambled_roofline"] = alu_roofline(ea.elapsed_time(eb_), m, ops_per_edge + OPS_EPILOGUE)
         out["undirected_scrambled_edges_per_s"] = m / (ea.elapsed_time(eb_) / 1e3)
         t_epi.close()
-        # degree smoothing (Sec. 5): 8 perturbed tables of bound 1024 (eps 0.1),
+        # degree smoothing (Sec. 3): 8 perturbed tables of bound 1024 (eps 0.1),
         # edge e from table e mod 8; the whole set stays LDS-resident
         t_set = R.rmat_build_perturbed_table(w["a"], w["b"], w["c"], w["d"], k, 1024, R.RMAT_VARIABLE, 8, 0.1, 2019)
         R.rmat_generate_async(t_set, w["seed"], 0, m, src, dst, stream)
@@ -448,7 +448,7 @@ def main():
                                 "roofline": alu_roofline(ea.elapsed_time(eb_), m, eb_set * OPS_PER_PHILOX_BLOCK +
                                                          en_set * OPS_PER_SAMPLE)}
         t_set.close()
-        # a 3 x 3 stochastic Kronecker initiator (Sec. 5) with 3^17 = 1.29e8
+        # a 3 x 3 stochastic Kronecker initiator (Sec. 3) with 3^17 = 1.29e8
         # nodes (uint32 ids), a 4096-bound table, the same 2^30 edges
         P3 = [0.3, 0.1, 0.05, 0.1, 0.2, 0.05, 0.05, 0.05, 0.1]
         t_kron = R.rmat_kron_build_table(P3, 3, 17, 4096, R.RMAT_VARIABLE)
@@ -464,7 +464,7 @@ def main():
                                 "roofline": alu_roofline(ea.elapsed_time(eb_), m, eb_k * OPS_PER_PHILOX_BLOCK +
                                                          en_k * OPS_PER_SAMPLE + OPS_KRON_CUT)}
         t_kron.close()
-        # partitioned generation (Sec. 5) of the same instance: 2^8 x 2^8 tiles,
+        # partitioned generation (Sec. 3) of the same instance: 2^8 x 2^8 tiles,
         # tile rows [0, 64) per call, four calls; counting on the host included
         t_part = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
         for r0 in range(0, 256, 64):  # warm-up pass (list buffers, code objects); counted again below

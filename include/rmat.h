@@ -106,7 +106,7 @@ int rmat_build_table(double a, double b, double c, double d, int k,
                      uint64_t table_bound, int path_mode, rmat_table_t* out);
 
 /*
- * Table of a K x K stochastic Kronecker initiator (Sec. 5 generalizations):
+ * Table of a K x K stochastic Kronecker initiator (Sec. 3 generalizations):
  * P holds K^2 probabilities, row-major (cell (i, j) = letter K i + j: row
  * digit i, column digit j), each >= 0, summing to 1 within 1e-9; 2 <= K <= 16;
  * the graph has K^k nodes (K^k <= 2^64) with base-K ids of k digits, the
@@ -127,7 +127,7 @@ int rmat_build_table(double a, double b, double c, double d, int k,
 int rmat_kron_build_table(const double* P, int K, int k, uint64_t table_bound, int path_mode, rmat_table_t* out);
 
 /*
- * A set of P perturbed tables for degree smoothing (Sec. 5, in place of
+ * A set of P perturbed tables for degree smoothing (Sec. 3, in place of
  * per-step parameter noise): table i is rmat_build_table of (a, b, c, d)
  * with each entry x scaled by 1 + epsilon (2 u - 1) and the four then
  * normalised (divided by their sum), u the 53-bit uniforms (high 53 bits)
@@ -187,7 +187,7 @@ int rmat_generate_async(rmat_table_t t, uint64_t seed, uint64_t edge_begin,
                         uint64_t m, void* out_src, void* out_dst, void* stream);
 
 /*
- * Generalizations of Sec. 5 applied to each edge before it is stored (the
+ * Generalizations of Sec. 3 applied to each edge before it is stored (the
  * same edges as rmat_generate_async otherwise):
  *  RMAT_UNDIRECTED  an undirected graph: an edge in the lower-left triangle
  *                   (src > dst) is mirrored to the upper right, i.e. its ids
@@ -277,7 +277,7 @@ int rmat_degree_distribution_async(const void* d_degree, uint64_t n_nodes, uint3
                                    void* stream);
 
 /*
- * Partitioned, communication-free generation (Sec. 5): the adjacency matrix
+ * Partitioned, communication-free generation (Sec. 3): the adjacency matrix
  * is cut into 2^t x 2^t tiles (t = tile_bits, 1 <= t <= min(k - 1, 15)); the
  * m edges (m <= 2^53) are divided over the tiles top-down through the
  * quadrant tree, and a call only visits the subtrees that meet tile rows

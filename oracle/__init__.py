@@ -213,7 +213,7 @@ def generate(t: Table, seed: int, edge_begin: int, m: int, threads: int = 1,
              width: int | None = None, samples: bool = False, flags: int = 0, scramble_key: int = 0):
     """Edges [edge_begin, edge_begin + m) as (src, dst[, samples per edge]).
     flags: UNDIRECTED (mirror to the upper triangle) and/or SCRAMBLE (relabel
-    ids by the keyed bijection), Sec. 5 generalizations, reading R19."""
+    ids by the keyed bijection), Sec. 3 generalizations, reading R19."""
     if width is None:
         width = 4 if t.K ** t.k <= 2 ** 32 else 8
     dt = np.uint32 if width == 4 else np.uint64
@@ -264,7 +264,7 @@ def degree_distribution(deg: np.ndarray, max_degree: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# partitioned generation (Sec. 5, reading R20)
+# partitioned generation (Sec. 3, reading R20)
 
 def binomial(seed: int, r: int, c: int, level: int, n: int, p: float) -> int:
     """Bin(n, p) drawn from the uniform stream of tree node (level, r, c)."""
@@ -300,7 +300,7 @@ def generate_partition(t: Table, seed: int, m: int, tbits: int, row_begin: int =
 
 
 # ---------------------------------------------------------------------------
-# perturbed tables (Sec. 5, reading R22)
+# perturbed tables (Sec. 3, reading R22)
 
 def perturbed_params(a, b, c, d, n_tables: int, eps: float, seed: int) -> np.ndarray:
     """(n_tables, 4) parameter sets: each entry scaled by 1 + eps (2u - 1),

@@ -53,7 +53,7 @@
  *      bit of the k-bit row and column ids.
  *  R12 letters left over after the k-th are discarded (each edge has its own
  *      counter stream), instead of being carried over to the next edge.
- *  R19 Sec. 5 (Generalizations) epilogue, optional per call: an undirected
+ *  R19 Sec. 3 (Generalizations) epilogue, optional per call: an undirected
  *      graph mirrors each edge of the lower-left triangle (row > column) to
  *      the upper right, i.e. swaps its ids; the scramble relabels every id by
  *      one keyed bijection pi of [0, 2^k), applied after the mirror.  pi is
@@ -61,12 +61,12 @@
  *      with M_r (odd) and C_r the outputs of SplitMix64 [Steele, Lea, Flood,
  *      OOPSLA'14] seeded with the scramble key, drawn in the order M_0, C_0,
  *      M_1, C_1, M_2, C_2 (M_r with its lowest bit set).
- *  R22 Sec. 5 perturbed tables: P tables (P a power of two <= 64) built from
+ *  R22 Sec. 3 perturbed tables: P tables (P a power of two <= 64) built from
  *      (a, b, c, d) with each entry x multiplied by 1 + eps (2 u - 1) and then
  *      normalised, u the 53-bit uniforms of SplitMix64 seeded with the
  *      perturbation seed, drawn table by table, entries in the order a, b,
  *      c, d; edge e is drawn from table e mod P.
- *  R20 Sec. 5 partitioned generation: the adjacency matrix is cut into
+ *  R20 Sec. 3 partitioned generation: the adjacency matrix is cut into
  *      2^t x 2^t tiles; the m edges are split over them top-down, each node
  *      of the quadrant tree splitting its count n into (n_a, n_b, n_c, n_d)
  *      by n_a = Bin(n, a), n_b = Bin(n - n_a, b / (b + c + d)),
@@ -501,7 +501,7 @@ static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t 
 }
 
 /* ------------------------------------------------------------------------
- * Epilogue of Sec. 5 (reading R19): mirror to the upper triangle, scramble.
+ * Epilogue of Sec. 3 (reading R19): mirror to the upper triangle, scramble.
  * ---------------------------------------------------------------------- */
 #define ORC_UNDIRECTED 1
 #define ORC_SCRAMBLE 2
@@ -718,7 +718,7 @@ int orc_generate_reduce(const orc_table* t, uint64_t seed, uint64_t edge_begin,
  * Flat accessors for the ctypes wrapper.
  * ---------------------------------------------------------------------- */
 /* ------------------------------------------------------------------------
- * Partitioned generation (Sec. 5, reading R20).
+ * Partitioned generation (Sec. 3, reading R20).
  * ---------------------------------------------------------------------- */
 typedef struct {
   uint32_t key[2], ctr[4];
@@ -930,7 +930,7 @@ int orc_generate_partition(const orc_table* t, uint64_t seed, uint64_t m, int tb
 }
 
 /* ------------------------------------------------------------------------
- * K x K stochastic Kronecker initiators (Sec. 5, reading R21): the same
+ * K x K stochastic Kronecker initiators (Sec. 3, reading R21): the same
  * table over the K^2 cells of the initiator.  Letter x = K i + j is cell
  * (i, j): row digit i, column digit j; ids are base-K numbers of k digits.
  * ---------------------------------------------------------------------- */
@@ -1149,7 +1149,7 @@ int orc_kron_build_table(const double* P, int K, int k, uint64_t bound, int mode
 }
 
 /* ------------------------------------------------------------------------
- * Perturbed tables (Sec. 5, reading R22).
+ * Perturbed tables (Sec. 3, reading R22).
  * ---------------------------------------------------------------------- */
 int orc_perturbed_params(double a, double b, double c, double d, int n_tables, double eps,
                          uint64_t seed, double* out /* n_tables x 4 */) {

@@ -299,7 +299,7 @@ __device__ __forceinline__ uint64_t in_vgpr(uint64_t x) {
   return (static_cast<uint64_t>(in_vgpr(static_cast<uint32_t>(x >> 32))) << 32) | in_vgpr(static_cast<uint32_t>(x));
 }
 
-// The Sec. 5 epilogue of a launch: flags and the scramble's round constants.
+// The Sec. 3 epilogue of a launch: flags and the scramble's round constants.
 template <typename Id>
 struct Epilogue {
   uint32_t flags;  // kEpiUndirected | kEpiScramble, wave-uniform
@@ -347,7 +347,7 @@ __device__ __forceinline__ uint64_t scramble_id(uint64_t x, const Epilogue<uint6
   return x;
 }
 
-// The Sec. 5 epilogue on one edge, when the launch asks for it (uniform):
+// The Sec. 3 epilogue on one edge, when the launch asks for it (uniform):
 // mirror to row <= column, then relabel both ids.
 template <bool kGeneral, typename Id>
 __device__ __forceinline__ void epilogue(const Epilogue<Id>& E, Id& s, Id& d) {

@@ -1,4 +1,4 @@
-// kron.cpp -- tables for K x K stochastic Kronecker initiators (Sec. 5).
+// kron.cpp -- tables for K x K stochastic Kronecker initiators (Sec. 3).
 //
 // The letters are the K^2 cells of the initiator, cell (i, j) being letter
 // K i + j (row digit i, column digit j); node ids are k-digit base-K numbers.

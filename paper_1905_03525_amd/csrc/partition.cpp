@@ -1,4 +1,4 @@
-// partition.cpp -- partitioned, communication-free generation (Sec. 5): the
+// partition.cpp -- partitioned, communication-free generation (Sec. 3): the
 // adjacency matrix is cut into 2^t x 2^t tiles, the m edges are divided over
 // the tiles top-down through the quadrant tree (only into the subtrees that
 // meet the requested tile rows), and every tile's edges are generated on the

@@ -105,7 +105,7 @@ struct GenInst {
   uint32_t ctr3;                  // fourth Philox counter word: 0, or 1 + tile id (partitioned generation)
   uint32_t kron_k;                // K of the K x K initiator (2: R-MAT letters, bit concatenation)
   uint64_t src_prefix, dst_prefix;  // OR-ed into the ids (a tile's row and column offsets)
-  // epilogue applied to each edge before it is stored (Sec. 5): bit 0 mirrors
+  // epilogue applied to each edge before it is stored (Sec. 3): bit 0 mirrors
   // an edge with src > dst, bit 1 relabels both ids by the scramble
   uint32_t epi;
   uint32_t scr_shift;             // ceil(k / 2)

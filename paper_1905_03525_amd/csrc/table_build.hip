@@ -12,7 +12,7 @@
 //     the t-th node is found from at most 3060 letter-count classes (depth
 //     < 15) sorted in LDS, plus a walk over the digits of the codes inside
 //     the last, partly expanded class group.  Expansion is then a test
-//     against that boundary node.  (Sec. 5, Parallelization, notes the same
+//     against that boundary node.  (Sec. 3, Parallelization, notes the same
 //     idea: expand every entry above a probability threshold.)
 //  2. The tree is expanded level by level with block-wide prefix sums;
 //     subtree leaf counts (bottom-up) and leaf offsets (top-down) place every
@@ -25,7 +25,7 @@
 //     the lights' cumulative deficit before i, and a heavy whose cumulative
 //     excess E falls short of the total deficit keeps C + E - D(i) where
 //     D(i) is the first cumulative deficit above E, aliasing the next heavy.
-//     Sec. 5 cites a parallel construction of the same kind [HubSan19].
+//     Sec. 3 cites a parallel construction of the same kind [HubSan19].
 #include "rmat_internal.h"
 
 namespace rmat {

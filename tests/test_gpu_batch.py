@@ -69,7 +69,7 @@ def _mixed():
     ]
     out = [dict(a=x[0][0], b=x[0][1], c=x[0][2], d=x[0][3], k=x[1], table_bound=x[2], path_mode=x[3], seed=x[4],
                 edge_begin=x[5], m=x[6]) for x in rows]
-    # Sec. 5 epilogues on some instances
+    # Sec. 3 epilogues on some instances
     for i, (fl, key) in {1: (3, 0xBEEF), 2: (2, 7), 3: (1, 0), 8: (3, 2**64 - 1)}.items():
         out[i]["gen_flags"], out[i]["scramble_key"] = fl, key
     return out

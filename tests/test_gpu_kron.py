@@ -1,4 +1,4 @@
-"""K x K stochastic Kronecker tables (Sec. 5) through the C ABI against the
+"""K x K stochastic Kronecker tables (Sec. 3) through the C ABI against the
 oracle: tables bit for bit, edges bit for bit (base-K ids), K = 2 equal to
 the R-MAT path, and the unsupported combinations rejected."""
 from __future__ import annotations

@@ -304,7 +304,7 @@ EPILOGUE_CASES = [
 
 @pytest.mark.parametrize("q,k,bound,mode,seed,e0,m,flags,key", EPILOGUE_CASES)
 def test_epilogue_parity(R, q, k, bound, mode, seed, e0, m, flags, key):
-    """Sec. 5 generalizations: undirected mirror and id scramble, bit-exact."""
+    """Sec. 3 generalizations: undirected mirror and id scramble, bit-exact."""
     import torch
     t = R.rmat_build_table(*q, k, bound, mode)
     src = torch.empty(m, dtype=R.id_dtype(k), device="cuda")

@@ -1,4 +1,4 @@
-"""Partitioned generation (Sec. 5) through the C ABI against the oracle:
+"""Partitioned generation (Sec. 3) through the C ABI against the oracle:
 tile counts and every edge of every tile, bit-exact; disjoint row ranges
 generated separately add up to the whole graph."""
 from __future__ import annotations

@@ -1,4 +1,4 @@
-"""Perturbed-table degree smoothing (Sec. 5) through the C ABI against the
+"""Perturbed-table degree smoothing (Sec. 3) through the C ABI against the
 oracle: every member table bit for bit, edge e from member e mod P bit for
 bit (with and without the undirected / scramble epilogue), the reduction of
 a set, no perturbation equal to the plain table, and the rejected inputs."""

@@ -145,7 +145,7 @@ def test_served_into_caller_outputs_equals_plain(R):
 
 
 def test_served_epilogues_match_oracle(R):
-    """Requests with the Sec. 5 epilogues (undirected, scramble) served in a
+    """Requests with the Sec. 3 epilogues (undirected, scramble) served in a
     mix equal the oracle with the same flags."""
     import torch
     reqs = _requests(12, seed=13)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's K x K stochastic Kronecker tables (Sec. 5, reading
+"""Pins of the oracle's K x K stochastic Kronecker tables (Sec. 3, reading
 R21) against what the mathematics fixes: K = 2 is R-MAT itself (the pinned
 R-MAT oracle, bit for bit); path probabilities are exact products of the
 initiator's entries; a variable table is a complete K^2-ary prefix code; its

@@ -1,4 +1,4 @@
-"""Pins of the oracle's partitioned generator (Sec. 5, reading R20) against
+"""Pins of the oracle's partitioned generator (Sec. 3, reading R20) against
 what probability fixes: the binomial law of every split (exact pmf from
 scipy), the multinomial law of a node's four-way split (enumerated), the
 R-MAT law of the whole partitioned graph (closed-form cell probabilities),

@@ -1,4 +1,4 @@
-"""Pins of the oracle's perturbed tables (Sec. 5, reading R22): with no
+"""Pins of the oracle's perturbed tables (Sec. 3, reading R22): with no
 perturbation they are the base table and the plain stream; every parameter
 set is a normalised perturbation within the stated band; edge e is exactly
 the plain edge of table e mod P; the whole stream follows the mixture of

@@ -438,7 +438,7 @@ def test_invalid_inputs_rejected(args):
 
 
 # ---------------------------------------------------------------------------
-# Sec. 5 generalizations: undirected mirror and id scramble (reading R19)
+# Sec. 3 generalizations: undirected mirror and id scramble (reading R19)
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 7, 10, 16])
 @pytest.mark.parametrize("key", [0, 1, 0x0123456789ABCDEF, 2**64 - 1])
@@ -461,7 +461,7 @@ def test_scramble_depends_on_key_and_k():
 @pytest.mark.parametrize("k,bound,e0,m", [(12, 256, 0, 5000), (26, 4096, 2**32 - 100, 3000), (64, 2000, 2**64 - 500, 500),
                                           (33, 1000, 7, 2000)])
 def test_undirected_mirrors_the_lower_triangle(k, bound, e0, m):
-    """Sec. 5: an undirected graph mirrors edges of the lower-left triangle
+    """Sec. 3: an undirected graph mirrors edges of the lower-left triangle
     (row > column) to the upper right: (min, max) of the directed edge."""
     t = oracle.build_table(0.57, 0.19, 0.19, 0.05, k, bound, oracle.VARIABLE)
     s, d = oracle.generate(t, 3, e0, m)

@@ -1,4 +1,4 @@
-"""The library's host-side tile counting (partitioned generation, Sec. 5)
+"""The library's host-side tile counting (partitioned generation, Sec. 3)
 compiled with g++ against the fake device of tests/hostsim and compared,
 count for count, with the oracle: both take every integer decision of the
 binomial draws from the same sequence of floating-point operations."""
