@@ -118,7 +118,9 @@ int rmat_build_table(double a, double b, double c, double d, int k,
  * path is longer than min(k, the largest L with K^L <= 2^15).  A sample
  * appends base-K digits: row = row K^take + floor(rowval / K^(L - take)).
  * K = 2 is rmat_build_table(P[0], P[1], P[2], P[3], ...).  For K > 2 the
- * table is built on the host and copied to the device; rmat_generate and
+ * table is built on the device by one workgroup (the boundary path found by
+ * bisection over its probability, then the shared weight, alias and record
+ * steps), synchronously; rmat_generate and
  * rmat_generate_async work on it (ids uint32 if K^k <= 2^32, else uint64),
  * rmat_table_export exports it (row / col arrays hold digit values), and the
  * epilogue flags, the reduction, partitioned generation and batches reject

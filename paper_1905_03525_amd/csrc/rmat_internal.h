@@ -75,6 +75,15 @@ struct BuildJob {
   uint32_t* heavy_idx;
   uint64_t* light_cum;     // inclusive prefix sums of light deficits C - w
   uint64_t* heavy_cum;     // inclusive prefix sums of heavy excesses w - C
+  // K x K Kronecker tables (kron_K > 2; 0 or 2: an R-MAT table): the K^2
+  // letter probabilities, the digit width of packed codes (root-most digit
+  // most significant), the expanded nodes' codes level by level and two node
+  // buffers of bfs_cap codes for the boundary search
+  int32_t kron_K, letters, digit_bits, pad_;
+  const double* qk;
+  uint64_t* kcode;
+  uint64_t* bfs[2];
+  uint64_t bfs_cap;
 };
 
 // Scratch bytes a build needs beyond the table itself.
@@ -85,6 +94,8 @@ inline uint64_t build_scratch_bytes(uint64_t n_expand, uint64_t n_buckets) {
 // Launchers (defined in the .hip files); return hipSuccess or the launch error.
 hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s);
 hipError_t launch_table_build_one(const BuildJob& job, hipStream_t s);
+// One K x K Kronecker table (job.kron_K > 2), one workgroup.
+hipError_t launch_kron_table_build(const BuildJob& job, hipStream_t s);
 
 // One instance of a batched generation (device array).  Block indices are
 // relative to first_block = edge_begin >> 6.

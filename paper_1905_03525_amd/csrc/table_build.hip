@@ -354,6 +354,580 @@ __device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundar
   return true;
 }
 
+// Phases 3 to 5, the same for every table: fixed-point weights by largest
+// remainders, the alias table in closed form, the hot-path records and the
+// statistics.  Returns false on an internal error (*S.error set).
+struct BuildShared {
+  uint64_t* warp;
+  uint32_t* u32;
+  uint32_t* hist;
+  uint64_t* sel_prefix;
+  uint64_t* sel_need;
+  unsigned long long* len_mass;
+  int* error;
+};
+
+__device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_t n, uint32_t nb, uint64_t C,
+                                                      const BuildShared& S) {
+  const int tid = threadIdx.x;
+  // digit values of K x K paths are stored as they are; R-MAT bit strings
+  // reversed (the root-most letter in bit 0), for the shift-or append
+  const bool reverse = J.kron_K <= 2;
+  // ---- 3. weights by largest remainders -------------------------------------
+  {
+    uint64_t part = 0;
+    for (uint32_t j = tid; j < n; j += kBuildThreads) {
+      uint64_t fl;
+      frac_key(J.item_p[j], &fl);
+      part += fl;
+    }
+    const uint64_t sum = block_sum(part, S.warp);
+    const int64_t R = static_cast<int64_t>(1ull << 32) - static_cast<int64_t>(sum);
+    if (R < 0 || R > static_cast<int64_t>(n)) {
+      if (tid == 0) *S.error = kBuildResidual;
+      __syncthreads();
+      return false;
+    }
+    // radix select of the R-th largest fractional part (its bit pattern)
+    if (tid == 0) { *S.sel_prefix = 0; *S.sel_need = static_cast<uint64_t>(R); }
+    __syncthreads();
+    if (R > 0) {
+      uint64_t pmask = 0;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += kBuildThreads) S.hist[i] = 0;
+        __syncthreads();
+        const uint64_t prefix = *S.sel_prefix;
+        for (uint32_t j = tid; j < n; j += kBuildThreads) {
+          uint64_t fl, key = frac_key(J.item_p[j], &fl);
+          if ((key & pmask) == prefix) atomicAdd(&S.hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid < 64) {
+          uint64_t need = *S.sel_need;
+          const uint32_t bin = wave_select_desc(S.hist, &need);
+          if (tid == 0) {
+            *S.sel_need = need;
+            *S.sel_prefix = prefix | (static_cast<uint64_t>(bin) << shift);
+          }
+        }
+        pmask |= 255ull << shift;
+        __syncthreads();
+      }
+    }
+    const uint64_t tau = *S.sel_prefix, take_ties = (R > 0) ? *S.sel_need : 0;
+    // items above tau round up; ties at tau round up in index order
+    uint64_t tie_base = 0;
+    for (uint32_t base = 0; base < n; base += kBuildThreads) {
+      const uint32_t j = base + tid;
+      uint64_t fl = 0, key = 0;
+      bool tie = false;
+      if (j < n) {
+        key = frac_key(J.item_p[j], &fl);
+        tie = (R > 0) && key == tau;
+      }
+      uint64_t total;
+      uint64_t rank = tie_base + block_exclusive_scan(tie ? 1u : 0u, S.warp, &total);
+      if (j < n) {
+        bool up = (R > 0) && (key > tau || (tie && rank < take_ties));
+        J.item_w[j] = fl + (up ? 1u : 0u);
+      }
+      tie_base += total;
+    }
+    for (uint32_t j = n + tid; j < nb; j += kBuildThreads) J.item_w[j] = 0;
+    if (tid == 0) J.stats->residual = static_cast<uint64_t>(R);
+    __syncthreads();
+  }
+
+  // ---- 4. alias table ----------------------------------------------------------
+  {
+    uint64_t nl = 0, dsum = 0, esum = 0;
+    for (uint32_t base = 0; base < nb; base += kBuildThreads) {
+      const uint32_t j = base + tid;
+      uint64_t w = 0;
+      bool light = false, valid = j < nb;
+      if (valid) { w = J.item_w[j]; light = w < C; }
+      uint64_t t_l, t_d, t_e;
+      uint64_t lrank = nl + block_exclusive_scan(valid && light ? 1u : 0u, S.warp, &t_l);
+      uint64_t dpre = dsum + block_exclusive_scan(valid && light ? C - w : 0u, S.warp, &t_d);
+      uint64_t epre = esum + block_exclusive_scan(valid && !light ? w - C : 0u, S.warp, &t_e);
+      if (valid) {
+        if (light) {
+          J.light_idx[lrank] = j;
+          J.light_cum[lrank] = dpre + (C - w);
+        } else {
+          uint64_t hrank = j - lrank;
+          J.heavy_idx[hrank] = j;
+          J.heavy_cum[hrank] = epre + (w - C);
+        }
+      }
+      nl += t_l; dsum += t_d; esum += t_e;
+    }
+    __syncthreads();
+    const uint32_t n_light = static_cast<uint32_t>(nl), n_heavy = nb - n_light;
+    if (dsum != esum || n_heavy == 0) {
+      if (tid == 0) *S.error = kBuildAlias;
+      __syncthreads();
+      return false;
+    }
+    for (uint32_t li = tid; li < n_light; li += kBuildThreads) {
+      const uint32_t j = J.light_idx[li];
+      const uint64_t prev = li > 0 ? J.light_cum[li - 1] : 0;
+      const uint32_t h = lower_bound_u64(J.heavy_cum, n_heavy, prev);
+      J.thr[j] = static_cast<uint32_t>(J.item_w[j]);
+      J.alias[j] = J.heavy_idx[h < n_heavy ? h : n_heavy - 1];
+    }
+    for (uint32_t hi = tid; hi < n_heavy; hi += kBuildThreads) {
+      const uint32_t j = J.heavy_idx[hi];
+      const uint64_t E = J.heavy_cum[hi];
+      if (E < dsum && hi + 1 < n_heavy) {
+        const uint32_t i = upper_bound_u64(J.light_cum, n_light, E);
+        J.thr[j] = static_cast<uint32_t>(C + E - J.light_cum[i < n_light ? i : n_light - 1]);
+        J.alias[j] = J.heavy_idx[hi + 1];
+      } else {
+        J.thr[j] = static_cast<uint32_t>(C);
+        J.alias[j] = j;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 5. hot-path records and statistics --------------------------------------
+  {
+    uint64_t wl = 0;
+    uint32_t mn = 0xFFFFFFFFu, mx = 0;
+    for (uint32_t i = tid; i < nb; i += kBuildThreads) {
+      const uint32_t a = J.alias[i];
+      const uint32_t ls = J.item_len[i], la = J.item_len[a];
+      BucketRecord r;
+      r.thr_abs = static_cast<uint32_t>(static_cast<uint64_t>(i) * C + (a == i ? 0u : J.thr[i]));
+      if (reverse) {
+        r.rows = reversed_bits(ls, J.item_row[i]) | (reversed_bits(la, J.item_row[a]) << 16);
+        r.cols = reversed_bits(ls, J.item_col[i]) | (reversed_bits(la, J.item_col[a]) << 16);
+      } else {
+        r.rows = J.item_row[i] | (J.item_row[a] << 16);
+        r.cols = J.item_col[i] | (J.item_col[a] << 16);
+      }
+      r.lens = ls | (la << 16);
+      J.records[i] = r;
+      if (i < n) {
+        wl += J.item_w[i] * ls;
+        mn = min(mn, ls);
+        mx = max(mx, ls);
+        atomicAdd(&S.len_mass[ls & 15u], static_cast<unsigned long long>(J.item_w[i]));
+      }
+    }
+    const uint64_t sum_wl = block_sum(wl, S.warp);
+    uint32_t vmax;
+    const uint32_t vmin = block_min_max(mn, mx, S.u32, &vmax);
+    if (tid == 0) {
+      J.stats->sum_wl = sum_wl;
+      J.stats->min_len = vmin;
+      J.stats->max_len = vmax;
+    }
+    if (tid < 16) J.stats->len_mass[tid] = S.len_mass[tid];
+  }
+  return true;
+}
+
+// End of a build: on failure every bucket gets a record that still ends each
+// edge (see below); then the status and the item count.
+__device__ __forceinline__ void finish_build(const BuildJob& J, uint32_t n, uint32_t nb, int error) {
+  const int tid = threadIdx.x;
+  if (error != 0 && J.records) {
+    // A failed build still leaves a table a generation can run on: every
+    // bucket holds two empty paths of the longest length, so each sample
+    // adds kMaxDepthCap letters and every edge ends within five samples.  A
+    // batch or a served round that launches generation right after the
+    // build (before the host sees the status) therefore terminates; its
+    // output is meaningless and the status reports the failure.
+    const uint32_t len2 = static_cast<uint32_t>(kMaxDepthCap) * 0x10001u;
+    for (uint32_t i = tid; i < nb; i += kBuildThreads) J.records[i] = BucketRecord{0xFFFFFFFFu, 0u, 0u, len2};
+  }
+  if (tid == 0) {
+    J.stats->error = error;
+    J.stats->n_items = n;
+  }
+}
+
+
+// ------------------------------------------------------ K x K initiators --
+// The table of a K x K initiator is the R-MAT table over K^2 letters (letter
+// K i + j is cell (i, j)): the same queue order and canonical products, with
+// paths capped at the largest L with K^L <= 2^15, so that each path's row
+// and column digits fit 15 bits as base-K values.  Phases 3 to 5 are shared
+// with R-MAT tables; phases 1 and 2 work on packed codes (digit_bits bits
+// per letter, the root-most letter most significant).  Letter-count classes
+// do not scale to K^2 letters (C(D + K^2 - 1, D) of them), so the boundary
+// node is found by bisection over its probability instead: the expandable
+// nodes of probability >= tau form a subtree (a child is never more
+// probable than its parent), counted level by level up to t; the largest
+// tau with at least t of them is the boundary's probability, and the
+// boundary is the r-th node of that probability in (depth, code) order,
+// which a level-order walk meets in exactly that order.
+
+constexpr int kKronMaxDigits = 9;  // K >= 3: K^L <= 2^15 gives L <= 9
+
+struct KronCtx {
+  const double* q;  // the K^2 letter probabilities (LDS)
+  uint32_t L;       // letters
+  uint32_t dbits;   // bits per letter in a packed code
+  uint32_t K;
+  int cap;
+};
+
+struct KronBoundary {
+  double p;
+  int depth;
+  int all;  // every expandable node is expanded
+  uint64_t code;
+};
+
+// Canonical probability of a path: its letters sorted ascending, multiplied
+// into 1.0 one at a time with rounding after each product (the same as
+// multiplying P_x n_x times for x = 0, 1, ...).
+__device__ __forceinline__ double kron_prob(const KronCtx& X, uint64_t code, int depth) {
+  const uint32_t mask = (1u << X.dbits) - 1u;
+  uint32_t d[kKronMaxDigits];
+#pragma unroll
+  for (int i = 0; i < kKronMaxDigits; ++i)
+    d[i] = i < depth ? static_cast<uint32_t>(code >> (X.dbits * i)) & mask : 0xFFFFFFFFu;
+  // odd-even transposition sort: n rounds sort n values
+#pragma unroll
+  for (int r = 0; r < kKronMaxDigits; ++r)
+#pragma unroll
+    for (int i = r & 1; i + 1 < kKronMaxDigits; i += 2) {
+      const uint32_t lo = min(d[i], d[i + 1]), hi = max(d[i], d[i + 1]);
+      d[i] = lo;
+      d[i + 1] = hi;
+    }
+  double p = 1.0;
+#pragma unroll
+  for (int i = 0; i < kKronMaxDigits; ++i)
+    if (i < depth) p = __dmul_rn(p, X.q[d[i]]);
+  return p;
+}
+
+__device__ __forceinline__ uint64_t prob_bits(double p) { return static_cast<uint64_t>(__double_as_longlong(p)); }
+
+// Row and column digit values of a path (root-most digit most significant).
+__device__ __forceinline__ void kron_rowcol(const KronCtx& X, uint64_t code, int depth, uint32_t* row, uint32_t* col) {
+  const uint32_t mask = (1u << X.dbits) - 1u;
+  uint32_t r = 0, c = 0;
+  for (int pos = depth - 1; pos >= 0; --pos) {
+    const uint32_t x = static_cast<uint32_t>(code >> (X.dbits * pos)) & mask;
+    r = r * X.K + x / X.K;
+    c = c * X.K + x % X.K;
+  }
+  *row = r;
+  *col = c;
+}
+
+__device__ __forceinline__ bool kron_expanded(const KronBoundary& B, int cap, double p, int depth, uint64_t code) {
+  if (depth >= cap) return false;
+  if (B.all) return true;
+  if (p != B.p) return p > B.p;
+  if (depth != B.depth) return depth < B.depth;
+  return code <= B.code;
+}
+
+// Number of expandable nodes (depth < cap) of probability >= tau (bit
+// pattern), counted level by level and stopped once it reaches `limit`:
+// returns min(count, limit).  Each level's nodes are kept (in code order) in
+// one of two buffers of cap_buf codes.
+__device__ uint64_t kron_count_ge(const KronCtx& X, uint64_t tau, uint64_t limit, uint64_t* buf0, uint64_t* buf1,
+                                  uint64_t cap_buf, uint64_t* s_warp) {
+  const int tid = threadIdx.x;
+  uint64_t count = 1;  // the root, probability 1 >= tau
+  if (count >= limit) return limit;
+  uint64_t* cur = buf0;
+  uint64_t* nxt = buf1;
+  __syncthreads();  // a previous walk's last stores into the buffers are done
+  if (tid == 0) cur[0] = 0;
+  __syncthreads();
+  uint32_t len = 1;
+  for (int D = 0; D + 1 < X.cap && len > 0; ++D) {
+    const uint32_t pairs = len * X.L;
+    uint64_t next = 0;
+    for (uint32_t base = 0; base < pairs; base += kBuildThreads) {
+      const uint32_t pr = base + tid;
+      bool pass = false;
+      uint64_t child = 0;
+      if (pr < pairs) {
+        const uint32_t i = pr / X.L, x = pr - i * X.L;
+        child = (cur[i] << X.dbits) | x;
+        pass = prob_bits(kron_prob(X, child, D + 1)) >= tau;
+      }
+      uint64_t total;
+      const uint64_t pos = next + block_exclusive_scan(pass ? 1u : 0u, s_warp, &total);
+      if (pass && pos < cap_buf) nxt[pos] = child;
+      next += total;
+      if (count + next >= limit) return limit;  // uniform
+    }
+    __syncthreads();
+    count += next;
+    uint64_t* t = cur;
+    cur = nxt;
+    nxt = t;
+    len = static_cast<uint32_t>(next);
+  }
+  return count;
+}
+
+// Boundary of a VARIABLE table: the n_expand-th expandable node in the queue
+// order (probability descending, depth ascending, code ascending).  Written
+// to *s_bnd by the thread that meets it; error kBuildItemCount if the walk
+// ends without it.
+__device__ void kron_boundary(const BuildJob& J, const KronCtx& X, KronBoundary* s_bnd, uint64_t* s_warp,
+                              int* s_error) {
+  const int tid = threadIdx.x;
+  const uint64_t t = J.n_expand;
+  uint64_t all_nodes = 0, lp = 1;
+  for (int D = 0; D < X.cap; ++D, lp *= X.L) all_nodes += lp;
+  if (tid == 0) {
+    s_bnd->p = 0.0;
+    s_bnd->depth = 0;
+    s_bnd->code = 0;
+    s_bnd->all = t >= all_nodes ? 1 : 0;
+  }
+  __syncthreads();
+  if (t >= all_nodes) return;
+  uint64_t* buf0 = J.bfs[0];
+  uint64_t* buf1 = J.bfs[1];
+  const uint64_t one = prob_bits(1.0);
+  // the largest tau with at least t nodes of probability >= tau: such a
+  // node exists (the count drops past it), and it is the t-th node's
+  uint64_t lo = 0, hi = one + 1, c_hi = 0;
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    const uint64_t c = kron_count_ge(X, mid, t, buf0, buf1, J.bfs_cap, s_warp);
+    if (c >= t) {
+      lo = mid;
+    } else {
+      hi = mid;
+      c_hi = c;  // exact: below the limit
+    }
+  }
+  const uint64_t tau = lo;
+  const uint64_t r = t - c_hi;  // rank of the boundary among the nodes of probability tau
+  // level-order walk over the nodes of probability >= tau, counting those of
+  // probability exactly tau; children are generated in code order
+  uint64_t ties = (one == tau) ? 1 : 0;
+  if (ties >= r) {
+    if (tid == 0) {
+      s_bnd->p = 1.0;
+      s_bnd->depth = 0;
+      s_bnd->code = 0;
+    }
+    __syncthreads();
+    return;
+  }
+  uint64_t* cur = buf0;
+  uint64_t* nxt = buf1;
+  __syncthreads();
+  if (tid == 0) cur[0] = 0;
+  __syncthreads();
+  uint32_t len = 1;
+  for (int D = 0; D + 1 < X.cap && len > 0; ++D) {
+    const uint32_t pairs = len * X.L;
+    uint64_t next = 0;
+    for (uint32_t base = 0; base < pairs; base += kBuildThreads) {
+      const uint32_t pr = base + tid;
+      bool pass = false, tie = false;
+      uint64_t child = 0;
+      double p = 0.0;
+      if (pr < pairs) {
+        const uint32_t i = pr / X.L, x = pr - i * X.L;
+        child = (cur[i] << X.dbits) | x;
+        p = kron_prob(X, child, D + 1);
+        pass = prob_bits(p) >= tau;
+        tie = prob_bits(p) == tau;
+      }
+      // one scan for both counts: passes in the low word, ties in the high
+      uint64_t total;
+      const uint64_t both = block_exclusive_scan((pass ? 1ull : 0ull) | (tie ? 1ull << 32 : 0ull), s_warp, &total);
+      const uint64_t pos = next + (both & 0xFFFFFFFFull);
+      if (pass && pos < J.bfs_cap) nxt[pos] = child;
+      next += total & 0xFFFFFFFFull;
+      const uint64_t tie_total = total >> 32;
+      if (ties + tie_total >= r) {
+        if (tie && ties + (both >> 32) + 1 == r) {
+          s_bnd->p = p;
+          s_bnd->depth = D + 1;
+          s_bnd->code = child;
+        }
+        __syncthreads();
+        return;
+      }
+      ties += tie_total;
+    }
+    __syncthreads();
+    uint64_t* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    len = static_cast<uint32_t>(next);
+  }
+  if (tid == 0) *s_error = kBuildItemCount;
+  __syncthreads();
+}
+
+// VARIABLE leaves of a K x K table in tree order: the nodes the boundary
+// admits, level by level (one thread per (node, letter) pair), subtree leaf
+// counts bottom-up, leaf placement top-down.  A node's expanded children are
+// stored from lvl_first[node] in letter order, so the number of them is the
+// distance to the next node's first child.  Returns false on an internal
+// error (*s_error set).
+__device__ bool kron_variable_leaves(const BuildJob& J, const KronCtx& X, const KronBoundary& B, uint32_t n,
+                                     uint64_t* s_warp, uint32_t* s_lvl_start, int* s_error) {
+  const int tid = threadIdx.x;
+  uint64_t* code = J.kcode;
+  uint32_t* first = J.lvl_first;
+  uint32_t* size = J.lvl_size;
+  uint32_t* off = J.lvl_off;
+  if (tid == 0) {
+    code[0] = 0;
+    s_lvl_start[0] = 0;
+    s_lvl_start[1] = 1;
+  }
+  __syncthreads();
+  int D = 0;
+  for (; D < X.cap; ++D) {
+    const uint32_t start = s_lvl_start[D], end = s_lvl_start[D + 1];
+    if (start == end) break;
+    const uint32_t pairs = (end - start) * X.L;
+    uint32_t next = end;
+    for (uint32_t base = 0; base < pairs; base += kBuildThreads) {
+      const uint32_t pr = base + tid;
+      bool pass = false;
+      uint64_t child = 0;
+      uint32_t i = 0, x = 0;
+      if (pr < pairs) {
+        i = start + pr / X.L;
+        x = pr % X.L;
+        child = (code[i] << X.dbits) | x;
+        if (D + 1 < X.cap) pass = kron_expanded(B, X.cap, kron_prob(X, child, D + 1), D + 1, child);
+      }
+      uint64_t total;
+      const uint32_t pos = next + static_cast<uint32_t>(block_exclusive_scan(pass ? 1u : 0u, s_warp, &total));
+      if (pr < pairs && x == 0) first[i] = pos;
+      if (pass) {
+        if (pos < J.n_expand) code[pos] = child;
+        else *s_error = kBuildItemCount;
+      }
+      next += static_cast<uint32_t>(total);
+    }
+    if (tid == 0) s_lvl_start[D + 2] = next;
+    __syncthreads();
+    if (*s_error) return false;
+  }
+  const int levels = D;
+  if (tid == 0 && s_lvl_start[levels] != J.n_expand) *s_error = kBuildItemCount;
+  __syncthreads();
+  if (*s_error) return false;
+  // bottom-up leaf counts
+  for (int Lv = levels - 1; Lv >= 0; --Lv) {
+    const uint32_t end = s_lvl_start[Lv + 1];
+    for (uint32_t i = s_lvl_start[Lv] + tid; i < end; i += kBuildThreads) {
+      const uint32_t f = first[i], e = i + 1 < end ? first[i + 1] : s_lvl_start[Lv + 2];
+      uint32_t sz = X.L - (e - f);
+      for (uint32_t j = f; j < e; ++j) sz += size[j];
+      size[i] = sz;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && size[0] != n) *s_error = kBuildItemCount;
+  __syncthreads();
+  if (*s_error) return false;
+  // top-down placement
+  if (tid == 0) off[0] = 0;
+  __syncthreads();
+  for (int Lv = 0; Lv < levels; ++Lv) {
+    for (uint32_t i = s_lvl_start[Lv] + tid; i < s_lvl_start[Lv + 1]; i += kBuildThreads) {
+      const uint64_t c0 = code[i];
+      uint32_t f = first[i], cur = off[i];
+      for (uint32_t x = 0; x < X.L; ++x) {
+        const uint64_t child = (c0 << X.dbits) | x;
+        const double p = kron_prob(X, child, Lv + 1);
+        if (kron_expanded(B, X.cap, p, Lv + 1, child)) {
+          off[f] = cur;
+          cur += size[f];
+          ++f;
+        } else {
+          uint32_t r, c;
+          kron_rowcol(X, child, Lv + 1, &r, &c);
+          J.item_len[cur] = Lv + 1;
+          J.item_row[cur] = r;
+          J.item_col[cur] = c;
+          J.item_p[cur] = p;
+          ++cur;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBuildThreads) void kron_table_build_kernel(BuildJob J) {
+  const int tid = threadIdx.x;
+  __shared__ double s_q[256];
+  __shared__ uint64_t s_warp[kWaves];
+  __shared__ uint32_t s_u32[2 * kWaves];
+  __shared__ uint32_t s_hist[256];
+  __shared__ int s_error;
+  __shared__ uint64_t s_sel_prefix, s_sel_need;
+  __shared__ unsigned long long s_len_mass[16];
+  __shared__ uint32_t s_lvl_start[kKronMaxDigits + 2];
+  __shared__ KronBoundary s_kb;
+
+  const uint32_t n = J.n_items;
+  const uint32_t nb = static_cast<uint32_t>(J.n_buckets);
+  const uint64_t C = J.capacity;
+  if (tid == 0) s_error = 0;
+  if (tid < 16) s_len_mass[tid] = 0ull;
+  for (int x = tid; x < J.letters; x += kBuildThreads) s_q[x] = J.qk[x];
+  __syncthreads();
+  const KronCtx X{s_q, static_cast<uint32_t>(J.letters), static_cast<uint32_t>(J.digit_bits),
+                  static_cast<uint32_t>(J.kron_K), J.cap};
+
+  if (J.mode == 0) {  // FIXED: all paths of length l, in code order
+    const int ell = J.fixed_len;
+    for (uint32_t j = tid; j < n; j += kBuildThreads) {
+      uint64_t code = 0;
+      uint32_t v = j;
+      for (int pos = 0; pos < ell; ++pos) {
+        code |= static_cast<uint64_t>(v % X.L) << (X.dbits * pos);
+        v /= X.L;
+      }
+      uint32_t r, c;
+      kron_rowcol(X, code, ell, &r, &c);
+      J.item_len[j] = ell;
+      J.item_row[j] = r;
+      J.item_col[j] = c;
+      J.item_p[j] = kron_prob(X, code, ell);
+    }
+  } else {
+    kron_boundary(J, X, &s_kb, s_warp, &s_error);
+    __syncthreads();
+    if (s_error) goto finish;
+    {
+      const KronBoundary B = s_kb;
+      if (!kron_variable_leaves(J, X, B, n, s_warp, s_lvl_start, &s_error)) goto finish;
+    }
+  }
+  for (uint32_t j = n + tid; j < nb; j += kBuildThreads) {
+    J.item_len[j] = 0; J.item_row[j] = 0; J.item_col[j] = 0; J.item_p[j] = 0.0;
+  }
+  __syncthreads();
+  {
+    const BuildShared S{s_warp, s_u32, s_hist, &s_sel_prefix, &s_sel_need, s_len_mass, &s_error};
+    weights_alias_records(J, n, nb, C, S);
+  }
+
+finish:
+  __syncthreads();
+  finish_build(J, n, nb, s_error);
+}
+
 // ------------------------------------------------------------------ kernel --
 __device__ __forceinline__ void build_table(const BuildJob& J) {
   const int tid = threadIdx.x;
@@ -554,171 +1128,14 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
   }
   __syncthreads();
 
-  // ---- 3. weights by largest remainders -------------------------------------
   {
-    uint64_t part = 0;
-    for (uint32_t j = tid; j < n; j += kBuildThreads) {
-      uint64_t fl;
-      frac_key(J.item_p[j], &fl);
-      part += fl;
-    }
-    const uint64_t sum = block_sum(part, s_warp);
-    const int64_t R = static_cast<int64_t>(1ull << 32) - static_cast<int64_t>(sum);
-    if (R < 0 || R > static_cast<int64_t>(n)) {
-      if (tid == 0) s_error = kBuildResidual;
-      __syncthreads();
-      goto finish;
-    }
-    // radix select of the R-th largest fractional part (its bit pattern)
-    if (tid == 0) { s_sel_prefix = 0; s_sel_need = static_cast<uint64_t>(R); }
-    __syncthreads();
-    if (R > 0) {
-      uint64_t pmask = 0;
-      for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int i = tid; i < 256; i += kBuildThreads) s_hist[i] = 0;
-        __syncthreads();
-        const uint64_t prefix = s_sel_prefix;
-        for (uint32_t j = tid; j < n; j += kBuildThreads) {
-          uint64_t fl, key = frac_key(J.item_p[j], &fl);
-          if ((key & pmask) == prefix) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        if (tid < 64) {
-          uint64_t need = s_sel_need;
-          const uint32_t bin = wave_select_desc(s_hist, &need);
-          if (tid == 0) {
-            s_sel_need = need;
-            s_sel_prefix = prefix | (static_cast<uint64_t>(bin) << shift);
-          }
-        }
-        pmask |= 255ull << shift;
-        __syncthreads();
-      }
-    }
-    const uint64_t tau = s_sel_prefix, take_ties = (R > 0) ? s_sel_need : 0;
-    // items above tau round up; ties at tau round up in index order
-    uint64_t tie_base = 0;
-    for (uint32_t base = 0; base < n; base += kBuildThreads) {
-      const uint32_t j = base + tid;
-      uint64_t fl = 0, key = 0;
-      bool tie = false;
-      if (j < n) {
-        key = frac_key(J.item_p[j], &fl);
-        tie = (R > 0) && key == tau;
-      }
-      uint64_t total;
-      uint64_t rank = tie_base + block_exclusive_scan(tie ? 1u : 0u, s_warp, &total);
-      if (j < n) {
-        bool up = (R > 0) && (key > tau || (tie && rank < take_ties));
-        J.item_w[j] = fl + (up ? 1u : 0u);
-      }
-      tie_base += total;
-    }
-    for (uint32_t j = n + tid; j < nb; j += kBuildThreads) J.item_w[j] = 0;
-    if (tid == 0) J.stats->residual = static_cast<uint64_t>(R);
-    __syncthreads();
-  }
-
-  // ---- 4. alias table ----------------------------------------------------------
-  {
-    uint64_t nl = 0, dsum = 0, esum = 0;
-    for (uint32_t base = 0; base < nb; base += kBuildThreads) {
-      const uint32_t j = base + tid;
-      uint64_t w = 0;
-      bool light = false, valid = j < nb;
-      if (valid) { w = J.item_w[j]; light = w < C; }
-      uint64_t t_l, t_d, t_e;
-      uint64_t lrank = nl + block_exclusive_scan(valid && light ? 1u : 0u, s_warp, &t_l);
-      uint64_t dpre = dsum + block_exclusive_scan(valid && light ? C - w : 0u, s_warp, &t_d);
-      uint64_t epre = esum + block_exclusive_scan(valid && !light ? w - C : 0u, s_warp, &t_e);
-      if (valid) {
-        if (light) {
-          J.light_idx[lrank] = j;
-          J.light_cum[lrank] = dpre + (C - w);
-        } else {
-          uint64_t hrank = j - lrank;
-          J.heavy_idx[hrank] = j;
-          J.heavy_cum[hrank] = epre + (w - C);
-        }
-      }
-      nl += t_l; dsum += t_d; esum += t_e;
-    }
-    __syncthreads();
-    const uint32_t n_light = static_cast<uint32_t>(nl), n_heavy = nb - n_light;
-    if (dsum != esum || n_heavy == 0) {
-      if (tid == 0) s_error = kBuildAlias;
-      __syncthreads();
-      goto finish;
-    }
-    for (uint32_t li = tid; li < n_light; li += kBuildThreads) {
-      const uint32_t j = J.light_idx[li];
-      const uint64_t prev = li > 0 ? J.light_cum[li - 1] : 0;
-      const uint32_t h = lower_bound_u64(J.heavy_cum, n_heavy, prev);
-      J.thr[j] = static_cast<uint32_t>(J.item_w[j]);
-      J.alias[j] = J.heavy_idx[h < n_heavy ? h : n_heavy - 1];
-    }
-    for (uint32_t hi = tid; hi < n_heavy; hi += kBuildThreads) {
-      const uint32_t j = J.heavy_idx[hi];
-      const uint64_t E = J.heavy_cum[hi];
-      if (E < dsum && hi + 1 < n_heavy) {
-        const uint32_t i = upper_bound_u64(J.light_cum, n_light, E);
-        J.thr[j] = static_cast<uint32_t>(C + E - J.light_cum[i < n_light ? i : n_light - 1]);
-        J.alias[j] = J.heavy_idx[hi + 1];
-      } else {
-        J.thr[j] = static_cast<uint32_t>(C);
-        J.alias[j] = j;
-      }
-    }
-    __syncthreads();
-  }
-
-  // ---- 5. hot-path records and statistics --------------------------------------
-  {
-    uint64_t wl = 0;
-    uint32_t mn = 0xFFFFFFFFu, mx = 0;
-    for (uint32_t i = tid; i < nb; i += kBuildThreads) {
-      const uint32_t a = J.alias[i];
-      const uint32_t ls = J.item_len[i], la = J.item_len[a];
-      BucketRecord r;
-      r.thr_abs = static_cast<uint32_t>(static_cast<uint64_t>(i) * C + (a == i ? 0u : J.thr[i]));
-      r.rows = reversed_bits(ls, J.item_row[i]) | (reversed_bits(la, J.item_row[a]) << 16);
-      r.cols = reversed_bits(ls, J.item_col[i]) | (reversed_bits(la, J.item_col[a]) << 16);
-      r.lens = ls | (la << 16);
-      J.records[i] = r;
-      if (i < n) {
-        wl += J.item_w[i] * ls;
-        mn = min(mn, ls);
-        mx = max(mx, ls);
-        atomicAdd(&s_len_mass[ls & 15u], static_cast<unsigned long long>(J.item_w[i]));
-      }
-    }
-    const uint64_t sum_wl = block_sum(wl, s_warp);
-    uint32_t vmax;
-    const uint32_t vmin = block_min_max(mn, mx, s_u32, &vmax);
-    if (tid == 0) {
-      J.stats->sum_wl = sum_wl;
-      J.stats->min_len = vmin;
-      J.stats->max_len = vmax;
-    }
-    if (tid < 16) J.stats->len_mass[tid] = s_len_mass[tid];
+    const BuildShared S{s_warp, s_u32, s_hist, &s_sel_prefix, &s_sel_need, s_len_mass, &s_error};
+    weights_alias_records(J, n, nb, C, S);
   }
 
 finish:
   __syncthreads();
-  if (s_error != 0 && J.records) {
-    // A failed build still leaves a table a generation can run on: every
-    // bucket holds two empty paths of the longest length, so each sample
-    // adds kMaxDepthCap letters and every edge ends within five samples.  A
-    // batch or a served round that launches generation right after the
-    // build (before the host sees the status) therefore terminates; its
-    // output is meaningless and the status reports the failure.
-    const uint32_t len2 = static_cast<uint32_t>(kMaxDepthCap) * 0x10001u;
-    for (uint32_t i = tid; i < nb; i += kBuildThreads) J.records[i] = BucketRecord{0xFFFFFFFFu, 0u, 0u, len2};
-  }
-  if (tid == 0) {
-    J.stats->error = s_error;
-    J.stats->n_items = n;
-  }
+  finish_build(J, n, nb, s_error);
 }
 
 // One workgroup per job, jobs in device memory (batches, table sets).
@@ -735,6 +1152,11 @@ __global__ __launch_bounds__(kBuildThreads) void table_build_one_kernel(BuildJob
 hipError_t launch_table_build(const BuildJob* d_jobs, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(table_build_kernel, dim3(n_jobs), dim3(kBuildThreads), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_kron_table_build(const BuildJob& job, hipStream_t s) {
+  hipLaunchKernelGGL(kron_table_build_kernel, dim3(1), dim3(kBuildThreads), 0, s, job);
   return hipGetLastError();
 }
 

@@ -37,6 +37,12 @@ TABLES = [
     (_dirichlet(16, 2), 16, 16, 300, oracle.VARIABLE),
     (P3, 3, 30, 20_000, oracle.VARIABLE),        # 32768 buckets: read from global memory
     (_dirichlet(3, 3), 3, 40, 5000, oracle.VARIABLE),
+    (P3, 3, 30, 60_000, oracle.VARIABLE),        # 59993 paths, 65536 buckets
+    ([1 / 9] * 9, 3, 12, 4000, oracle.VARIABLE),  # every path of a depth ties: the boundary inside a level
+    ([0.5, 0, 0, 0, 0.5, 0, 0, 0, 0], 3, 12, 8000, oracle.VARIABLE),  # boundary among probability-0 paths
+    ([1.0] + [0.0] * 8, 3, 10, 200, oracle.VARIABLE),  # one letter of probability 1
+    (_dirichlet(16, 4), 16, 2, 1 << 20, oracle.VARIABLE),  # every expandable path expanded (256^2 leaves)
+    (_dirichlet(5, 5), 5, 9, 25 ** 3, oracle.FIXED),
 ]
 
 
