@@ -27,6 +27,7 @@ struct rmat_table {
   uint64_t reduce_edges = 0;   // bins it holds
   double q[4];                 // a, b, c, d as given
   std::vector<rmat::TableView> members;  // a perturbed set's tables (empty for one table)
+  double p_second = 0.0;       // probability that an edge needs more than four samples
 };
 
 namespace rmat {
@@ -214,8 +215,23 @@ void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const S
   I->n_tables = 1;
 }
 
+double p_second_block(const BuildStats& st, int k) {
+  // distribution of the total length of four samples (each path 1..15 letters)
+  double pl[16], d[61] = {1.0};
+  for (int L = 0; L < 16; ++L) pl[L] = static_cast<double>(st.len_mass[L]) / 4294967296.0;
+  for (int s = 0; s < 4; ++s) {
+    double nd[61] = {0.0};
+    for (int v = 0; v <= 15 * s; ++v)
+      for (int L = 1; L < 16; ++L) nd[v + L] += d[v] * pl[L];
+    std::memcpy(d, nd, sizeof(d));
+  }
+  double p = 0.0;
+  for (int v = 0; v < k && v <= 60; ++v) p += d[v];
+  return p;
+}
+
 int adopt_table(const rmat_info& info, const double q[4], int kron_K, const TableView& view, void* d_mem,
-                rmat_table_t* out) {
+                double p_second, rmat_table_t* out) {
   rmat_table* t = new (std::nothrow) rmat_table();
   if (!t) return set_error(RMAT_ENOMEM, "host allocation of the table handle failed");
   if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
@@ -223,6 +239,7 @@ int adopt_table(const rmat_info& info, const double q[4], int kron_K, const Tabl
   t->info.initiator_k = static_cast<uint32_t>(kron_K);
   t->v = view;
   t->d_mem = d_mem;
+  t->p_second = p_second;
   std::memcpy(t->q, q, sizeof(t->q));
   if (kron_K > 2) {
     t->info.id_bytes = 4;  // K^k <= 2^32 ?
@@ -358,6 +375,7 @@ static int rmat_build_table_body(double a, double b, double c, double d, int k, 
   }
 
   rmat::fill_info(&t->info, k, path_mode, table_bound, S, stats, tb);
+  t->p_second = rmat::p_second_block(stats, k);
   std::memcpy(t->q, q, sizeof(t->q));
   *out = t;
   return RMAT_OK;
@@ -456,6 +474,7 @@ static int rmat_build_perturbed_table_body(double a, double b, double c, double 
   t->d_mem = d_mem;
   t->v = views[0];
   t->members = views;
+  for (int i = 0; i < n_tables; ++i) t->p_second += rmat::p_second_block(stats[i], k) / n_tables;  // edge e: member e mod P
   std::memcpy(t->q, q0, sizeof(t->q));
   *out = t;
   return RMAT_OK;
@@ -559,6 +578,9 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
   a.kron_k = t->info.initiator_k;
   a.id_bytes = t->info.id_bytes;
   a.n_tables = t->info.n_tables;
+  a.first_blocks = rmat::first_blocks_for(
+      t->p_second, rmat::tile_blocks(static_cast<uint32_t>(t->info.n_buckets * t->info.n_tables), t->info.id_bytes == 8,
+                                     t->info.lds_resident));
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = reduce ? rmat::launch_generate_reduce(a, s) : rmat::launch_generate(a, s);
   if (e != hipSuccess) return rmat::hip_fail(e, reduce ? "generate_reduce launch" : "generate launch");
@@ -622,6 +644,9 @@ int rmat_generate_degrees_async(rmat_table_t t, uint64_t seed, uint64_t edge_beg
   a.kron_k = 2;
   a.id_bytes = t->info.id_bytes;
   a.n_tables = t->info.n_tables;
+  a.first_blocks = rmat::first_blocks_for(
+      t->p_second, rmat::tile_blocks(static_cast<uint32_t>(t->info.n_buckets * t->info.n_tables), t->info.id_bytes == 8,
+                                     t->info.lds_resident));
   a.degree = static_cast<uint32_t*>(d_degree);
   hipError_t e = rmat::launch_generate_degrees(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return rmat::hip_fail(e, "generate_degrees launch");

@@ -465,6 +465,20 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     // (every block but an instance's first and last) take a copy of the body
     // without lane masks
     uint32_t n_ovf = 0;
+    // counter block 1 of the lanes still short of k letters, in this pass
+    // when the table's edges mostly need it (the same samples, in the same
+    // order, as the continuation pass would draw)
+    auto second_block = [&](uint64_t base, Acc& acc, uint32_t& filled) {
+      if (I.first_blocks == 2 && filled < I.k) {
+        uint32_t y0 = static_cast<uint32_t>(base) + lane, y1 = static_cast<uint32_t>(base >> 32), y2 = 1u,
+                 y3 = I.ctr3;
+        philox10(y0, y1, y2, y3, I.key0, I.key1);
+        if (kLazy)
+          sample_lazy(tab_lane, I.shift, I.k, y0, y1, y2, y3, acc, filled, kpow);
+        else
+          sample4(tab_lane, I.shift, I.k, y0, y1, y2, y3, acc, filled, kpow);
+      }
+    };
     auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole, auto sure) {
       Acc acc;
       acc.clear();
@@ -473,6 +487,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1, x0, x1,
                      x2, x3);
       sample4<Acc, decltype(sure)::value>(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+      second_block(base, acc, filled);
       res[j * 64 + lane] = acc.pack();
       const bool need = decltype(whole)::value ? filled < I.k : (filled < I.k && ((amask >> lane) & 1ull));
       const uint64_t ovf_mask = __ballot(need);
@@ -506,6 +521,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         acc.clear();
         uint32_t filled = 0;
         consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        second_block((I.first_block + t0 + j * stride) << 6, acc, filled);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;
         const uint64_t ovf_mask = __ballot(need);
@@ -551,6 +567,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         acc.clear();
         uint32_t filled = 0;
         consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        second_block((I.first_block + t0 + j * stride) << 6, acc, filled);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;
         const uint64_t ovf_mask = __ballot(need);
@@ -612,7 +629,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         const uint64_t e = ((I.first_block + t0 + (idx >> 6) * stride) << 6) + (idx & 63u);
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
         const BucketRecord* __restrict__ tab_e = tab + ((idx & 63u) & I.table_mask) * I.n_buckets;
-        for (uint32_t jj = 1; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
+        for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
           if (kLazy)
@@ -1034,6 +1051,7 @@ Launch make_launch(const GenerateArgs& a) {
   P.I.out_dst = a.out_dst;
   P.I.digest = nullptr;
   P.I.ctr3 = 0;
+  P.I.first_blocks = a.first_blocks == 2 ? 2u : 1u;
   P.I.kron_k = static_cast<uint32_t>(a.kron_k);
   P.I.src_prefix = P.I.dst_prefix = 0;
   P.I.epi = 0;

@@ -23,7 +23,7 @@
 
 namespace rmat {
 int adopt_table(const rmat_info& info, const double q[4], int kron_K, const TableView& host, void* d_mem,
-                rmat_table_t* out);
+                double p_second, rmat_table_t* out);
 }  // namespace rmat
 
 namespace {
@@ -155,7 +155,7 @@ static int rmat_kron_build_table_body(const double* P, int K, int k, uint64_t ta
   }
   rmat_info info;
   rmat::fill_info(&info, k, path_mode, table_bound, S, st, tb);
-  rc = rmat::adopt_table(info, q4, K, V, d_mem, out);
+  rc = rmat::adopt_table(info, q4, K, V, d_mem, rmat::p_second_block(st, k), out);
   if (rc) (void)hipFree(d_mem);
   return rc;
 }

@@ -481,8 +481,7 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
     if (n == 0) continue;
     const uint32_t r = row_begin + static_cast<uint32_t>(i >> tile_bits);
     const uint32_t c = static_cast<uint32_t>(i & ((1u << tile_bits) - 1));
-    rmat::GenInst I;
-    std::memset(&I, 0, sizeof(I));
+    rmat::GenInst I{};  // zero, one first-pass counter block
     I.records = V.records;
     I.n_buckets = static_cast<uint32_t>(info.n_buckets);
     I.table_mask = 0;

@@ -114,6 +114,9 @@ struct GenInst {
   // generated edges of fmix64(e ^ fmix64(src ^ rotl64(dst, 32)))
   unsigned long long* digest;
   uint32_t ctr3;                  // fourth Philox counter word: 0, or 1 + tile id (partitioned generation)
+  // 2: the first pass draws counter blocks 0 and 1 of every edge (tables
+  // whose edges mostly need more than four samples); otherwise block 0 only
+  uint32_t first_blocks = 1;
   uint32_t kron_k;                // K of the K x K initiator (2: R-MAT letters, bit concatenation)
   uint64_t src_prefix, dst_prefix;  // OR-ed into the ids (a tile's row and column offsets)
   // epilogue applied to each edge before it is stored (Sec. 3): bit 0 mirrors
@@ -180,6 +183,7 @@ struct GenerateArgs {
   uint32_t kron_k;          // 2: R-MAT bit strings; K > 2: base-K digit values (Kronecker table)
   uint32_t id_bytes;
   uint32_t n_tables;        // perturbed set size (1: a single table)
+  uint32_t first_blocks;    // GenInst::first_blocks
   // reduction variant: the edges are generated in sub-chunks of at most
   // bins_cap edges into `bins` (16-bit source prefixes), counted per
   // workgroup into `partials` (reduce_partials_bytes()) and merged into hist
@@ -248,6 +252,17 @@ int export_table(const TableView& V, uint64_t n_buckets, void* host_buf, size_t 
 void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const Shape& S, const BuildStats& stats,
                uint64_t device_bytes);
 // Clears the calling thread's error message (every entry point starts so).
+// Probability that an edge needs more than four samples (four path lengths,
+// drawn from the table's length law, sum to fewer than k letters).
+double p_second_block(const BuildStats& st, int k);
+// Counter blocks the first generation pass draws for every edge: 2 when most
+// edges need a second block and the tiles are shorter than 8 blocks (the
+// continuation pass then holds only the few edges that need more than eight
+// samples), else 1.  Full 8-block tiles keep one: their continuation pass
+// runs nearly full waves and the first pass's software pipeline stays as it
+// is (a 3 x 3 Kronecker table measured 1% slower with two).
+inline uint32_t first_blocks_for(double p_second, uint32_t tile) { return p_second >= 0.5 && tile < 8 ? 2u : 1u; }
+
 void clear_error();
 int check_device();
 int hip_fail(hipError_t e, const char* what);

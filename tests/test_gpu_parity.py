@@ -101,6 +101,11 @@ EDGE_CASES = [
     ((0.25, 0.25, 0.25, 0.25), 26, 5000, oracle.VARIABLE, 19, 0, 40_000),
     ((1.0, 0.0, 0.0, 0.0), 26, 300, oracle.VARIABLE, 20, 0, 1000),
     (G500, 28, 1 << 20, oracle.VARIABLE, 21, 0, 100_000),   # global-memory (L2) table
+    # most edges need more than four samples: the first pass draws counter
+    # blocks 0 and 1, the continuation pass starts at block 2
+    (G500, 26, 16, oracle.VARIABLE, 22, 5, 70_000),         # about 13 samples per edge
+    (G500, 30, 4, oracle.FIXED, 23, 2**32 - 64 * 50, 64 * 100),  # one letter per path: 30 samples
+    (CFG3, 64, 1 << 16, oracle.VARIABLE, 24, 3, 60_000),    # L2 table, records loaded lazily
 ]
 
 
