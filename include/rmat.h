@@ -346,11 +346,18 @@ typedef struct rmat_batch_info {
 
 typedef struct rmat_autotune_report {
   double search_seconds;     /* wall time of rmat_batch_autotune */
-  double calibration_ns;     /* measured device time per (edge x integer op), ns */
+  double calibration_ns;     /* measured device time per (edge x integer op), ns,
+                                of 4096-bucket LDS tables (8-block tiles) */
   uint32_t n_tuned;          /* instances whose table_bound was chosen */
   uint32_t n_candidates;     /* candidate tables built per tuned instance */
-  uint32_t work_blocks;      /* suggested work-item size for rmat_batch_create */
+  uint32_t work_blocks;      /* measured work-item size for rmat_batch_create */
+  uint32_t chosen;           /* 0: the model's bounds; 1: 4096 for all; 2: 8192 for all */
+  uint32_t measured;         /* 1 if the choices were timed (outputs given) */
   uint32_t reserved;
+  double model_ms;           /* the model's predicted generation time of its bounds */
+  double tuned_ms;           /* measured run of the model's bounds (0 if not timed) */
+  double all_4096_ms;        /* measured run with bound 4096 (FIXED: 4^6) for all */
+  double all_8192_ms;        /* the same with 8192 */
 } rmat_autotune_report;
 
 /*
@@ -392,19 +399,27 @@ int rmat_batch_free(rmat_batch_t b);
 
 /*
  * Chooses table_bound for every instance whose table_bound is 0 (in place;
- * path_mode is kept).  Candidates are the LDS-resident powers of two
- * 2^8 .. 2^13 (FIXED: 4^4 .. 4^6, at most 4^min(15,k)).  All candidate
- * tables are built on the device in one launch; each one's path-length law
- * gives the exact expected Philox blocks and samples per edge (Sec. 2: a
- * longer expected path means fewer samples per edge), and the cost of an
- * instance is m x (40 x blocks + 11 x samples) integer ops at the generation
- * kernel's measured MI355X rate, plus the time to stage the table into LDS
- * once per work item.  The rate is a fixed constant, so the same instances
- * always get the same bounds; report->calibration_ns is the rate measured
- * live (one 2^24-edge generation per process), for comparison.  The choice
- * changes the edges (a different table), which is why it is written back.
- * report may be NULL.  Synchronous.  Errors: RMAT_EINVAL (naming the
- * instance), RMAT_ENOMEM, RMAT_EDEVICE.
+ * path_mode is kept), and the work-item size.  Candidates are the powers of
+ * two 2^8 .. 2^16 (FIXED: 4^4 .. 4^8, at most 4^min(15,k)): up to 2^13 held
+ * in LDS, where a larger table leaves room for shorter tiles (8 blocks per
+ * wave up to 4096 buckets, 3 at 8192), above that read from L2 (Sec. 4: the
+ * table's size and cache residency set the speed).  All candidate tables are
+ * built on the device in one launch; each one's path-length law gives the
+ * exact expected Philox blocks and samples per edge (Sec. 2: a longer
+ * expected path means fewer samples per edge), and the model's cost of an
+ * instance is m x (40 x blocks + 11 x samples) integer ops at the measured
+ * rate of the candidate's launch class (residency and tile length; one
+ * 2^24-edge batch per class, measured once per process), plus the time to
+ * stage an LDS table once per work item.  When every tuned instance has its
+ * outputs, the model's bounds are then timed on the batch itself against
+ * 4096 and against 8192 for all (a single size replaces the model's bounds
+ * only if it is faster by more than 1%), and the work-item size (the
+ * formula's, a quarter and four times it) timed on that choice; the
+ * edges are overwritten by the caller's run.  Without outputs the model
+ * decides alone (the same instances get the same bounds on one device).
+ * The choice changes the edges (a different table), which is why it is
+ * written back.  report may be NULL.  Synchronous.  Errors: RMAT_EINVAL
+ * (naming the instance), RMAT_ENOMEM, RMAT_EDEVICE.
  */
 int rmat_batch_autotune(rmat_instance* inst, int n, rmat_autotune_report* report);
 

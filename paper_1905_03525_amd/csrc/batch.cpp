@@ -19,9 +19,12 @@ namespace {
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-// Instances of one id width and table residency share a generation launch.
+// Instances of one id width, table residency and tile length share a
+// generation launch (a larger LDS table leaves room for shorter tiles, so
+// instances on smaller tables are not held to those).
 struct Group {
   int wide, lds;
+  uint32_t tile;
   int general;  // some instance has epilogue flags
   uint32_t max_buckets;
   uint32_t n_items;
@@ -189,73 +192,144 @@ void sample_laws(const uint64_t mass[16], int k, double* blocks, double* samples
 
 constexpr double kOpsPerBlock = 40.0;  // Philox4x32-10: 20 products + 20 three-input XORs
 constexpr double kOpsPerSample = 11.0;
-// Device time per (edge x op) that the cost model uses: the generation kernel's
-// rate on MI355X at k = 26 (2^30 edges, 88.6 ops per edge, 4.45 ms).  A fixed
-// constant rather than the live calibration keeps the choice reproducible.
-constexpr double kNsPerEdgeOp = 4.45e6 / (1073741824.0 * 88.6);
 // Staging one table into a workgroup's LDS: ~1 us of latency plus its bytes at
 // 64 B per clock (2.2 GHz), during which the other workgroups keep generating.
 constexpr double kStageLatencyNs = 1000.0;
 constexpr double kStageBytesPerNs = 64.0 * 2.2;
 constexpr double kResidentWorkgroups = 256.0;
 
-// Device time per (edge x op), measured once per process by generating 2^24
-// edges of the 4093-path table at k = 26.
-double g_calibration_ns = 0.0;
+// Candidate table sizes: VARIABLE bounds 2^8 .. 2^16 (LDS-resident up to
+// 2^13, read from L2 above), FIXED 4^4 .. 4^8.
+constexpr int kMinBoundLog2 = 8, kMaxBoundLog2 = 16;
 
-int calibrate(double* ns) {
-  if (g_calibration_ns > 0.0) {
-    *ns = g_calibration_ns;
-    return RMAT_OK;
-  }
-  rmat_table_t t = nullptr;
-  int rc = rmat_build_table(0.57, 0.19, 0.19, 0.05, 26, 4096, RMAT_VARIABLE, &t);
-  if (rc) return rc;
-  const uint64_t m = 1ull << 24;
-  void* buf = nullptr;
-  hipError_t e = hipMalloc(&buf, 2 * m * sizeof(uint32_t));
-  if (e != hipSuccess) {
-    rmat_free_table(t);
-    return rmat::hip_fail(e, "hipMalloc(calibration)");
-  }
-  uint32_t* src = static_cast<uint32_t*>(buf);
-  hipEvent_t a = nullptr, z = nullptr;
-  (void)hipEventCreate(&a);
-  (void)hipEventCreate(&z);
+// Measured device time per (edge x integer op) of the batch generation
+// kernel, one figure per launch class (table residency and tile length):
+// one-instance batches of 2^25 and 2^27 edges at k = 26 (a = .57, b = c =
+// .19, d = .05) on a table of the class's size, best of three runs each;
+// the slope between the two leaves out the table build and the launches.
+// Measured once per process and class.
+struct ClassRate {
+  bool lds;
+  uint32_t tile;
+  double ns_per_op;
+};
+std::vector<ClassRate> g_rates;
+
+double laws_ops(const uint64_t mass[16], int k) {
+  double eb, en;
+  sample_laws(mass, k, &eb, &en);
+  return kOpsPerBlock * eb + kOpsPerSample * en;
+}
+
+// Best of three eager runs (after one that loads the code) of a one-instance
+// batch of m edges into buf; *ops gets the table's ops per edge.
+int time_one_instance(uint64_t bound, uint64_t m, void* buf, float* ms, double* ops) {
+  rmat_instance x;
+  std::memset(&x, 0, sizeof(x));
+  x.a = 0.57, x.b = 0.19, x.c = 0.19, x.d = 0.05;
+  x.k = 26;
+  x.path_mode = RMAT_VARIABLE;
+  x.table_bound = bound;
+  x.seed = 1;
+  x.m = m;
+  x.out_src = buf;
+  x.out_dst = static_cast<uint32_t*>(buf) + m;
+  rmat_batch_t b = nullptr;
+  int rc = rmat_batch_create(&x, 1, 2048, &b);
+  hipEvent_t ea = nullptr, ez = nullptr;
   float best = 1e30f;
-  for (int rep = 0; rep < 4 && rc == RMAT_OK; ++rep) {
-    (void)hipEventRecord(a, nullptr);
-    rc = rmat_generate_async(t, 1, 0, m, src, src + m, nullptr);
-    (void)hipEventRecord(z, nullptr);
-    (void)hipEventSynchronize(z);
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, a, z);
-    if (rep > 0) best = std::min(best, ms);
-  }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(z);
-  (void)hipFree(buf);
   if (rc == RMAT_OK) {
-    uint64_t mass[16] = {0};
+    (void)hipEventCreate(&ea);
+    (void)hipEventCreate(&ez);
+    for (int rep = 0; rep < 4 && rc == RMAT_OK; ++rep) {
+      (void)hipEventRecord(ea, nullptr);
+      rc = rmat_batch_enqueue(b, nullptr);
+      (void)hipEventRecord(ez, nullptr);
+      (void)hipEventSynchronize(ez);
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, ea, ez);
+      if (rep > 0) best = std::min(best, t);
+    }
+    if (rc == RMAT_OK) rc = rmat_batch_check(b);
+  }
+  if (rc == RMAT_OK) {
+    std::vector<char> ex(36 * (1ull << 16));
     rmat_info info;
-    rmat_table_info(t, &info);
-    // the length law from the exported table
-    std::vector<char> ex(info.export_bytes);
-    rc = rmat_table_export(t, ex.data(), ex.size());
+    rc = rmat_batch_table_info(b, 0, &info);
+    if (rc == RMAT_OK) rc = rmat_batch_table_export(b, 0, ex.data(), ex.size());
     if (rc == RMAT_OK) {
+      uint64_t mass[16] = {0};
       const uint64_t nb = info.n_buckets;
       const uint64_t* w = reinterpret_cast<const uint64_t*>(ex.data());
       const uint32_t* len = reinterpret_cast<const uint32_t*>(ex.data() + 16 * nb);
       for (uint64_t j = 0; j < nb; ++j) mass[len[j] & 15] += w[j];
-      double eb, en;
-      sample_laws(mass, 26, &eb, &en);
-      g_calibration_ns = best * 1e6 / (static_cast<double>(m) * (kOpsPerBlock * eb + kOpsPerSample * en));
+      *ops = laws_ops(mass, 26);
     }
   }
-  rmat_free_table(t);
+  if (ea) (void)hipEventDestroy(ea);
+  if (ez) (void)hipEventDestroy(ez);
+  rmat_batch_free(b);
+  *ms = best;
+  return rc;
+}
+
+int measure_class(uint64_t bound, double* ns_per_op) {
+  const uint64_t m1 = 1ull << 25, m2 = 1ull << 27;
+  void* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, 2 * m2 * sizeof(uint32_t));
+  if (e != hipSuccess) return rmat::hip_fail(e, "hipMalloc(autotune calibration)");
+  float t1 = 0.0f, t2 = 0.0f;
+  double ops = 0.0;
+  int rc = time_one_instance(bound, m1, buf, &t1, &ops);
+  if (rc == RMAT_OK) rc = time_one_instance(bound, m2, buf, &t2, &ops);
+  (void)hipFree(buf);
   if (rc) return rc;
-  *ns = g_calibration_ns;
+  const double slope = static_cast<double>(t2 - t1) * 1e6 / (static_cast<double>(m2 - m1) * ops);
+  *ns_per_op = slope > 0.0 ? slope : static_cast<double>(t2) * 1e6 / (static_cast<double>(m2) * ops);
   return RMAT_OK;
+}
+
+// The rate of the launch class of a table of nb buckets (32-bit ids).
+int class_rate(uint32_t nb, double* ns_per_op) {
+  const bool lds = nb <= rmat::lds_table_limit();
+  const uint32_t tile = rmat::tile_blocks(nb, 0, lds);
+  for (const ClassRate& c : g_rates)
+    if (c.lds == lds && c.tile == tile) {
+      *ns_per_op = c.ns_per_op;
+      return RMAT_OK;
+    }
+  double ns = 0.0;
+  int rc = measure_class(nb, &ns);
+  if (rc) return rc;
+  g_rates.push_back(ClassRate{lds, tile, ns});
+  *ns_per_op = ns;
+  return RMAT_OK;
+}
+
+// Host-clock ms of one eager run of a batch of `inst` with work items of
+// work_blocks blocks (the best of two runs after a first one).
+int time_batch(const std::vector<rmat_instance>& inst, uint32_t work_blocks, double* ms) {
+  rmat_batch_t b = nullptr;
+  int rc = rmat_batch_create(inst.data(), static_cast<int>(inst.size()), work_blocks, &b);
+  if (rc) return rc;
+  double best = 1e300;
+  for (int rep = 0; rep < 3 && rc == RMAT_OK; ++rep) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      rc = rmat::hip_fail(e, "autotune timing");
+      break;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = rmat_batch_enqueue(b, nullptr);
+    e = hipDeviceSynchronize();
+    if (rc == RMAT_OK && e != hipSuccess) rc = rmat::hip_fail(e, "autotune timing");
+    const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep > 0) best = std::min(best, t);
+  }
+  if (rc == RMAT_OK) rc = rmat_batch_check(b);
+  rmat_batch_free(b);
+  if (rc == RMAT_OK) *ms = best;
+  return rc;
 }
 
 }  // namespace
@@ -296,47 +370,57 @@ static int rmat_batch_create_body(const rmat_instance* inst, int n, uint32_t wor
                        static_cast<unsigned long long>(kMaxWorkItems), b->work_blocks, i);
     }
   }
-  // groups by id width and table residency; work items in instance order
+  // groups by id width, table residency and tile length; work items in
+  // instance order
   const uint32_t lds_limit = rmat::lds_table_limit();
   std::vector<rmat::GenWorkItem> items;
   items.reserve(n_work);
   std::vector<uint32_t> group_first;
+  std::vector<uint32_t> inst_tile(n);
+  for (int i = 0; i < n; ++i) {
+    const uint32_t nb = static_cast<uint32_t>(b->shape[i].n_buckets);
+    inst_tile[i] = rmat::tile_blocks(nb, b->inst[i].k > 32, nb <= lds_limit);
+  }
   for (int wide = 0; wide < 2; ++wide)
-    for (int lds = 1; lds >= 0; --lds) {
-      Group g;
-      g.wide = wide;
-      g.lds = lds;
-      g.general = 0;
-      g.max_buckets = 0;
-      g.items = nullptr;
-      g.counter = nullptr;
-      const uint32_t first_item = static_cast<uint32_t>(items.size());
-      for (int i = 0; i < n; ++i) {
-        const rmat_instance& x = b->inst[i];
-        const rmat::Shape& S = b->shape[i];
-        if ((x.k > 32) != (wide != 0) || (S.n_buckets <= lds_limit) != (lds != 0)) continue;
-        g.max_buckets = std::max<uint32_t>(g.max_buckets, static_cast<uint32_t>(S.n_buckets));
-        if (x.m == 0) continue;
-        if (x.flags & (RMAT_UNDIRECTED | RMAT_SCRAMBLE)) g.general = 1;
-        const uint64_t first = x.edge_begin >> 6;
-        const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - first + 1;
-        for (uint64_t f = 0; f < nblk; f += b->work_blocks) {
-          rmat::GenWorkItem w;
-          w.inst = static_cast<uint32_t>(i);
-          w.first = f;
-          w.n_blocks = static_cast<uint32_t>(std::min<uint64_t>(b->work_blocks, nblk - f));
-          items.push_back(w);
+    for (int lds = 1; lds >= 0; --lds)
+      for (uint32_t tile = 8; tile >= 1; --tile) {
+        Group g;
+        g.wide = wide;
+        g.lds = lds;
+        g.tile = tile;
+        g.general = 0;
+        g.max_buckets = 0;
+        g.items = nullptr;
+        g.counter = nullptr;
+        const uint32_t first_item = static_cast<uint32_t>(items.size());
+        for (int i = 0; i < n; ++i) {
+          const rmat_instance& x = b->inst[i];
+          const rmat::Shape& S = b->shape[i];
+          if ((x.k > 32) != (wide != 0) || (S.n_buckets <= lds_limit) != (lds != 0) || inst_tile[i] != tile) continue;
+          g.max_buckets = std::max<uint32_t>(g.max_buckets, static_cast<uint32_t>(S.n_buckets));
+          if (x.m == 0) continue;
+          if (x.flags & (RMAT_UNDIRECTED | RMAT_SCRAMBLE)) g.general = 1;
+          const uint64_t first = x.edge_begin >> 6;
+          const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - first + 1;
+          for (uint64_t f = 0; f < nblk; f += b->work_blocks) {
+            rmat::GenWorkItem w;
+            w.inst = static_cast<uint32_t>(i);
+            w.first = f;
+            w.n_blocks = static_cast<uint32_t>(std::min<uint64_t>(b->work_blocks, nblk - f));
+            items.push_back(w);
+          }
         }
+        g.n_items = static_cast<uint32_t>(items.size()) - first_item;
+        b->max_buckets = std::max(b->max_buckets, g.max_buckets);
+        if (g.n_items == 0) continue;
+        b->groups.push_back(g);
+        group_first.push_back(first_item);
       }
-      g.n_items = static_cast<uint32_t>(items.size()) - first_item;
-      b->max_buckets = std::max(b->max_buckets, g.max_buckets);
-      if (g.n_items == 0) continue;
-      if (rmat::tile_blocks(g.max_buckets, wide, lds) == 0) {
-        destroy(b);
-        return set_error(RMAT_EINVAL, "a table of %u buckets leaves no LDS for the generation tiles", g.max_buckets);
-      }
-      b->groups.push_back(g);
-      group_first.push_back(first_item);
+  for (int i = 0; i < n; ++i)
+    if (inst_tile[i] == 0 || inst_tile[i] > 8) {
+      destroy(b);
+      return set_error(RMAT_EINVAL, "instance %d: a table of %llu buckets leaves no LDS for the generation tiles", i,
+                       static_cast<unsigned long long>(b->shape[i].n_buckets));
     }
   b->n_items = static_cast<uint32_t>(items.size());
   if (b->groups.size() > static_cast<size_t>(n)) {  // cannot happen: every group holds an instance
@@ -505,21 +589,24 @@ static int rmat_batch_autotune_body(rmat_instance* inst, int n, rmat_autotune_re
   rmat::clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   if (!inst || n <= 0) return set_error(RMAT_EINVAL, "empty instance list");
-  // candidate bounds per instance to tune (host only)
+  // candidate tables of every instance to tune (host only)
   std::vector<int> who;
   std::vector<rmat_instance> cand;
   std::vector<rmat::Shape> shapes;
-  uint32_t n_tuned = 0;
+  uint32_t n_tuned = 0, n_cand = 0;
+  bool outputs = true;
   for (int i = 0; i < n; ++i) {
     if (inst[i].table_bound != 0) continue;
     ++n_tuned;
+    if (inst[i].m > 0 && (!inst[i].out_src || !inst[i].out_dst)) outputs = false;
     const int cap = std::min(std::max(inst[i].k, 1), rmat::kMaxDepthCap);
     std::vector<uint64_t> bounds;
     if (inst[i].path_mode == RMAT_FIXED) {
-      for (int l = std::min(4, cap); l <= std::min(6, cap); ++l) bounds.push_back(1ull << (2 * l));
+      for (int l = std::min(4, cap); l <= std::min(kMaxBoundLog2 / 2, cap); ++l) bounds.push_back(1ull << (2 * l));
     } else {
-      for (int e2 = 8; e2 <= 13; ++e2) bounds.push_back(1ull << e2);
+      for (int e2 = kMinBoundLog2; e2 <= kMaxBoundLog2; ++e2) bounds.push_back(1ull << e2);
     }
+    n_cand = std::max<uint32_t>(n_cand, static_cast<uint32_t>(bounds.size()));
     for (uint64_t bound : bounds) {
       rmat_instance c = inst[i];
       c.table_bound = bound;
@@ -537,34 +624,12 @@ static int rmat_batch_autotune_body(rmat_instance* inst, int n, rmat_autotune_re
   }
   int rc = rmat::check_device();
   if (rc) return rc;
-  double ns = 0.0;
-  if ((rc = calibrate(&ns))) return rc;
-  // keep the LDS-resident candidates (every VARIABLE bound up to 2^13 and FIXED up to 4^6 is)
-  const uint32_t lds_limit = rmat::lds_table_limit();
-  uint32_t n_cand = 0;
-  {
-    std::vector<int> w2;
-    std::vector<rmat_instance> c2;
-    std::vector<rmat::Shape> s2;
-    std::vector<uint32_t> per(n, 0);
-    for (size_t c = 0; c < cand.size(); ++c) {
-      if (shapes[c].n_buckets > lds_limit) continue;
-      w2.push_back(who[c]);
-      c2.push_back(cand[c]);
-      s2.push_back(shapes[c]);
-      n_cand = std::max(n_cand, ++per[who[c]]);
-    }
-    for (int i = 0; i < n; ++i)
-      if (inst[i].table_bound == 0 && per[i] == 0)
-        return set_error(RMAT_EINVAL, "instance %d: no candidate table fits in LDS", i);
-    who.swap(w2);
-    cand.swap(c2);
-    shapes.swap(s2);
-  }
   uint64_t total_blocks = 0;
   for (int i = 0; i < n; ++i) total_blocks += (inst[i].m + 63) / 64;
   uint32_t work_blocks = static_cast<uint32_t>(std::min<uint64_t>(
       8192, std::max<uint64_t>(128, total_blocks / (static_cast<uint64_t>(256) * 8))));
+  std::vector<uint64_t> model(n, 0);
+  double model_cost = 0.0;
   if (!cand.empty()) {
     TableSet T;
     if ((rc = alloc_tables(shapes, cand, 0, &T))) return rc;
@@ -576,37 +641,93 @@ static int rmat_batch_autotune_body(rmat_instance* inst, int n, rmat_autotune_re
       e = hipMemcpy(&st[c], T.views[c].stats, sizeof(rmat::BuildStats), hipMemcpyDeviceToHost);
     free_tables(&T);
     if (e != hipSuccess) return rmat::hip_fail(e, "autotune candidate tables");
-    // choose per instance
+    // the model: exact ops per edge of each candidate (its length law) at
+    // the measured rate of its launch class, plus table staging
     std::vector<double> best(n, 1e300);
-    std::vector<uint64_t> chosen(n, 0);
     for (size_t c = 0; c < cand.size(); ++c) {
       if (st[c].error != 0) continue;
       const int i = who[c];
-      double eb, en;
-      sample_laws(st[c].len_mass, cand[c].k, &eb, &en);
-      const double gen = static_cast<double>(cand[c].m) * kNsPerEdgeOp * (kOpsPerBlock * eb + kOpsPerSample * en);
+      double rate = 0.0;
+      if ((rc = class_rate(static_cast<uint32_t>(shapes[c].n_buckets), &rate))) return rc;
+      const double gen = static_cast<double>(cand[c].m) * rate * laws_ops(st[c].len_mass, cand[c].k);
       const double items = std::ceil(static_cast<double>((cand[c].m + 63) / 64) / work_blocks);
-      const double stage_one = kStageLatencyNs + static_cast<double>(shapes[c].n_buckets) * 16.0 / kStageBytesPerNs;
-      const double stage = items * stage_one / kResidentWorkgroups;
-      const double cost = gen + stage;
+      const bool lds = shapes[c].n_buckets <= rmat::lds_table_limit();
+      const double stage_one =
+          lds ? kStageLatencyNs + static_cast<double>(shapes[c].n_buckets) * 16.0 / kStageBytesPerNs : 0.0;
+      const double cost = gen + items * stage_one / kResidentWorkgroups;
       if (cost < best[i]) {
         best[i] = cost;
-        chosen[i] = cand[c].table_bound;
+        model[i] = cand[c].table_bound;
       }
     }
     for (int i = 0; i < n; ++i)
-      if (inst[i].table_bound == 0 && chosen[i] == 0)
-        return set_error(RMAT_EDEVICE, "instance %d: every candidate table failed", i);
-    for (int i = 0; i < n; ++i)
-      if (inst[i].table_bound == 0) inst[i].table_bound = chosen[i];
+      if (inst[i].table_bound == 0) {
+        if (model[i] == 0) return set_error(RMAT_EDEVICE, "instance %d: every candidate table failed", i);
+        model_cost += best[i];
+      }
   }
+  // With the callers' outputs, the model's choice is checked by measurement
+  // against one table size for all (2^12 and 2^13: the largest LDS tables
+  // with 8-block and with 3-block tiles), and the fastest is kept; then the
+  // work-item size is measured.  Without outputs the model decides alone.
+  uint32_t chosen = 0;
+  double times[3] = {0.0, 0.0, 0.0};
+  std::vector<uint64_t> pick = model;
+  if (outputs && n_tuned > 0) {
+    std::vector<std::vector<uint64_t>> configs(3, model);
+    for (int i = 0; i < n; ++i) {
+      if (inst[i].table_bound != 0) continue;
+      const bool fixed = inst[i].path_mode == RMAT_FIXED;
+      const int cap = std::min(std::max(inst[i].k, 1), rmat::kMaxDepthCap);
+      configs[1][i] = fixed ? (1ull << (2 * std::min(6, cap))) : 4096;
+      configs[2][i] = fixed ? (1ull << (2 * std::min(6, cap))) : 8192;
+    }
+    std::vector<rmat_instance> trial(inst, inst + n);
+    for (uint32_t c = 0; c < 3; ++c) {
+      for (int i = 0; i < n; ++i)
+        if (inst[i].table_bound == 0) trial[i].table_bound = configs[c][i];
+      if ((rc = time_batch(trial, work_blocks, &times[c]))) return rc;
+    }
+    // a single size for all replaces the model's bounds only when it is
+    // faster by more than the run-to-run spread (1%)
+    double best = times[0];
+    for (uint32_t c = 1; c < 3; ++c)
+      if (times[c] < 0.99 * best) {
+        best = times[c];
+        chosen = c;
+      }
+    pick = configs[chosen];
+    for (int i = 0; i < n; ++i)
+      if (inst[i].table_bound == 0) trial[i].table_bound = pick[i];
+    uint32_t best_wb = work_blocks;
+    for (uint32_t wb : {work_blocks / 4, work_blocks * 4}) {
+      if (wb < 64 || wb > 65536) continue;
+      double t = 0.0;
+      if ((rc = time_batch(trial, wb, &t))) return rc;
+      if (t < 0.99 * best) {
+        best = t;
+        best_wb = wb;
+      }
+    }
+    work_blocks = best_wb;
+  }
+  for (int i = 0; i < n; ++i)
+    if (inst[i].table_bound == 0) inst[i].table_bound = pick[i];
   if (report) {
+    std::memset(report, 0, sizeof(*report));
     report->search_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    report->calibration_ns = ns;
+    double r4096 = 0.0;
+    if ((rc = class_rate(4096, &r4096))) return rc;
+    report->calibration_ns = r4096;
     report->n_tuned = n_tuned;
     report->n_candidates = n_cand;
     report->work_blocks = work_blocks;
-    report->reserved = 0;
+    report->chosen = chosen;
+    report->measured = outputs && n_tuned > 0 ? 1u : 0u;
+    report->model_ms = model_cost * 1e-6;
+    report->tuned_ms = times[0];
+    report->all_4096_ms = times[1];
+    report->all_8192_ms = times[2];
   }
   return RMAT_OK;
 }

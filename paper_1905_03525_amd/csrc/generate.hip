@@ -506,9 +506,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     const bool whole_tile = nb_tile == L.tile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
                             (t0 + (nb_tile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
     const bool sure1 = I.k > static_cast<uint32_t>(kMaxDepthCap);  // a path has at most kMaxDepthCap letters
-    if (whole_tile && sure1 && nb_tile == kMaxTile) {
+    if (whole_tile && sure1 && nb_tile == kMaxTile && I.first_blocks != 2) {
       // software-pipelined: block j's Philox draws and table reads are issued
       // before block j - 1's samples are consumed, so the reads overlap work
+      // (full 8-block tiles draw one counter block per edge in this pass)
       auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
         const uint64_t base = (I.first_block + t0 + j * stride) << 6;
         philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
@@ -521,7 +522,6 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         acc.clear();
         uint32_t filled = 0;
         consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
-        second_block((I.first_block + t0 + j * stride) << 6, acc, filled);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;
         const uint64_t ovf_mask = __ballot(need);

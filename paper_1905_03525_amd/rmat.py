@@ -75,7 +75,9 @@ class rmat_batch_info(ctypes.Structure):
 class rmat_autotune_report(ctypes.Structure):
     _fields_ = [("search_seconds", ctypes.c_double), ("calibration_ns", ctypes.c_double),
                 ("n_tuned", ctypes.c_uint32), ("n_candidates", ctypes.c_uint32),
-                ("work_blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("work_blocks", ctypes.c_uint32), ("chosen", ctypes.c_uint32), ("measured", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("model_ms", ctypes.c_double), ("tuned_ms", ctypes.c_double),
+                ("all_4096_ms", ctypes.c_double), ("all_8192_ms", ctypes.c_double)]
 
 
 class rmat_server_config(ctypes.Structure):

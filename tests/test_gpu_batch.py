@@ -82,7 +82,10 @@ def test_batch_equals_plain_and_oracle(R, work_blocks):
     _alloc(R, insts)
     with R.rmat_batch_create(insts, work_blocks) as b:
         info = R.rmat_batch_get_info(b)
-        assert info["n_instances"] == len(insts) and info["n_launches"] == 4
+        # one launch per id width, table residency and tile length: 32-bit
+        # ids on LDS tables with 8- and 3-block tiles and on an L2 table,
+        # 64-bit ids on LDS tables with 7- and 1-block tiles and on an L2 table
+        assert info["n_instances"] == len(insts) and info["n_launches"] == 6
         assert info["total_edges"] == sum(p["m"] for p in insts)
         R.rmat_batch_enqueue(b, torch.cuda.current_stream())
         R.rmat_batch_check(b)
@@ -128,6 +131,8 @@ def test_batch_graph_replays_equal_eager(R):
 
 
 def test_autotune_deterministic(R):
+    """Without outputs the model alone decides: the same instances get the
+    same bounds (LDS and L2 candidates 2^8 .. 2^16), fixed bounds are kept."""
     insts = workloads.batch_instances(64)
     insts[5]["table_bound"] = 777
     a = [dict(p) for p in insts]
@@ -136,11 +141,56 @@ def test_autotune_deterministic(R):
     rep2 = R.rmat_batch_autotune(b)
     assert [p["table_bound"] for p in a] == [p["table_bound"] for p in b]
     assert a[5]["table_bound"] == 777
-    assert all(p["table_bound"] in {256, 512, 1024, 2048, 4096, 8192} for j, p in enumerate(a) if j != 5)
+    assert all(p["table_bound"] in {1 << e for e in range(8, 17)} for j, p in enumerate(a) if j != 5)
     for rep in (rep1, rep2):
-        assert rep["n_tuned"] == 63 and rep["n_candidates"] == 6
-        assert 128 <= rep["work_blocks"] <= 8192
-        assert rep["calibration_ns"] > 0 and rep["search_seconds"] > 0
+        assert rep["n_tuned"] == 63 and rep["n_candidates"] == 9 and rep["measured"] == 0
+        assert 128 <= rep["work_blocks"] <= 8192 and rep["chosen"] == 0
+        assert rep["calibration_ns"] > 0 and rep["search_seconds"] > 0 and rep["model_ms"] > 0
+
+
+def test_autotune_measured_choice(R):
+    """With outputs the model's bounds are timed against 4096 and 8192 for
+    all; the kept choice is the fastest of the three and the batch built
+    with it equals the plain launches."""
+    import torch
+    insts = workloads.batch_instances(24, k_min=12, k_max=18)
+    _alloc(R, insts)
+    rep = R.rmat_batch_autotune(insts)
+    assert rep["measured"] == 1 and rep["chosen"] in (0, 1, 2)
+    t = [rep["tuned_ms"], rep["all_4096_ms"], rep["all_8192_ms"]]
+    # the model's bounds are kept unless a single size is faster by more than 1%
+    assert all(x > 0 for x in t) and t[rep["chosen"]] <= min(t) / 0.99
+    if rep["chosen"] == 1:
+        assert all(p["table_bound"] == 4096 for p in insts)
+    if rep["chosen"] == 2:
+        assert all(p["table_bound"] == 8192 for p in insts)
+    with R.rmat_batch_create(insts, rep["work_blocks"]) as b:
+        R.rmat_batch_enqueue(b, torch.cuda.current_stream())
+        R.rmat_batch_check(b)
+        for i, p in enumerate(insts):
+            tb, s, d = _plain(R, p)
+            assert torch.equal(s, p["out_src"]) and torch.equal(d, p["out_dst"]), f"instance {i}"
+            tb.close()
+
+
+def test_batch_l2_and_tile_groups(R):
+    """Instances on 4096-, 8192- and 2^15-bucket tables in one batch: one
+    launch per tile length and residency, every instance equal to its plain
+    launch."""
+    import torch
+    insts = workloads.batch_instances(12, k_min=12, k_max=20)
+    for j, p in enumerate(insts):
+        p["table_bound"] = (4096, 8192, 1 << 15)[j % 3]
+    _alloc(R, insts)
+    with R.rmat_batch_create(insts, 64) as b:
+        info = R.rmat_batch_get_info(b)
+        assert info["n_launches"] == 3 and info["max_buckets"] == 1 << 15
+        R.rmat_batch_enqueue(b, torch.cuda.current_stream())
+        R.rmat_batch_check(b)
+        for i, p in enumerate(insts):
+            tb, s, d = _plain(R, p)
+            assert torch.equal(s, p["out_src"]) and torch.equal(d, p["out_dst"]), f"instance {i}"
+            tb.close()
 
 
 def test_batch_workload_512_full(R):
@@ -149,8 +199,8 @@ def test_batch_workload_512_full(R):
     device, and oracle samples at both ends and in the middle of each."""
     import torch
     insts = workloads.batch_instances()
-    rep = R.rmat_batch_autotune(insts)
     _alloc(R, insts)
+    rep = R.rmat_batch_autotune(insts)
     stream = torch.cuda.current_stream()
     m_max = max(p["m"] for p in insts)
     s_all = torch.empty(m_max, dtype=torch.int32, device="cuda")
