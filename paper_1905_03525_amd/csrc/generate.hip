@@ -225,6 +225,40 @@ __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], con
   }
 }
 
+// The four samples of a first block with no branches, for the
+// bit-concatenating accumulators of the pipelined passes: every path is
+// appended whatever the fill level, since letters past k are dropped when the
+// id is read.  The first three start at most 2 * kMaxDepthCap < 32
+// positions up.  The fourth may start past the register's width: 64-bit ids
+// still hold it; for 32-bit ids its shift is clamped to 31, which lands at
+// or above bit k only while k < 32 (the callers take this path for k < 32).
+// filled ends as the sum of the four lengths, so filled < k exactly when
+// consume4 would also have used all four.
+template <typename Acc>
+__device__ __forceinline__ void consume4_flat(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
+                                              uint32_t& filled) {
+  static_assert(!Acc::kKron, "base-K accumulators cut their last path to the digits needed");
+  static_assert(2 * kMaxDepthCap < 32, "the first three paths must start inside a 32-bit register");
+  auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
+  const bool o0 = x[0] < r[0].thr_abs, o1 = x[1] < r[1].thr_abs, o2 = x[2] < r[2].thr_abs, o3 = x[3] < r[3].thr_abs;
+  auto take = [&](bool o, const BucketRecord& q) {
+    const uint32_t len = half(o, q.lens);
+    acc.append(half(o, q.rows), half(o, q.cols), len, filled, k, nullptr);
+    filled += len;
+  };
+  take(o0, r[0]);
+  take(o1, r[1]);
+  take(o2, r[2]);
+  if constexpr (sizeof(typename Acc::Id) == 8) {
+    take(o3, r[3]);
+  } else {
+    const uint32_t sh = filled < 31u ? filled : 31u;
+    acc.row |= half(o3, r[3].rows) << sh;
+    acc.col |= half(o3, r[3].cols) << sh;
+    filled += half(o3, r[3].lens);
+  }
+}
+
 // Loads the four bucket records of one Philox block, then samples them.  All
 // four reads are issued before any is used, so they are in flight together.
 template <typename Acc, bool kSure1 = false>
@@ -506,7 +540,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     const bool whole_tile = nb_tile == L.tile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
                             (t0 + (nb_tile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
     const bool sure1 = I.k > static_cast<uint32_t>(kMaxDepthCap);  // a path has at most kMaxDepthCap letters
-    if (whole_tile && sure1 && nb_tile == kMaxTile && I.first_blocks != 2) {
+    // the pipelined passes consume a block without branches (consume4_flat):
+    // exact for 64-bit ids and base-K accumulators, for 32-bit ids when k < 32
+    const bool pipe_ok = sure1 && (Acc::kKron || sizeof(typename Acc::Id) == 8 || I.k < 32u);
+    if (whole_tile && pipe_ok && nb_tile == kMaxTile && I.first_blocks != 2) {
       // software-pipelined: block j's Philox draws and table reads are issued
       // before block j - 1's samples are consumed, so the reads overlap work
       // (full 8-block tiles draw one counter block per edge in this pass)
@@ -521,7 +558,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         Acc acc;
         acc.clear();
         uint32_t filled = 0;
-        consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        if constexpr (Acc::kKron)
+          consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        else
+          consume4_flat<Acc>(I.k, x, r, acc, filled);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;
         const uint64_t ovf_mask = __ballot(need);
@@ -550,7 +590,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         }
       }
       finish(kMaxTile - 1, xa, ra);
-    } else if (kShortPipe && whole_tile && sure1) {
+    } else if (kShortPipe && whole_tile && pipe_ok) {
       // a shorter full tile with the tables in LDS (a batch holding a larger
       // table leaves less LDS for tiles): the same pipeline, rolled.  The
       // single-instance kernel leaves it out: there it measured no faster
@@ -566,7 +606,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         Acc acc;
         acc.clear();
         uint32_t filled = 0;
-        consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        if constexpr (Acc::kKron)
+          consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+        else
+          consume4_flat<Acc>(I.k, x, r, acc, filled);
         second_block((I.first_block + t0 + j * stride) << 6, acc, filled);
         res[j * 64 + lane] = acc.pack();
         const bool need = filled < I.k;

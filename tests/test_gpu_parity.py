@@ -106,6 +106,11 @@ EDGE_CASES = [
     (G500, 26, 16, oracle.VARIABLE, 22, 5, 70_000),         # about 13 samples per edge
     (G500, 30, 4, oracle.FIXED, 23, 2**32 - 64 * 50, 64 * 100),  # one letter per path: 30 samples
     (CFG3, 64, 1 << 16, oracle.VARIABLE, 24, 3, 60_000),    # L2 table, records loaded lazily
+    # whole 8-block tiles near the 32-bit width: the fourth path of a first
+    # block often starts at or past bit k (k = 32 takes the rolled path)
+    (G500, 31, 4096, oracle.VARIABLE, 25, 0, 300_000),
+    (G500, 32, 4096, oracle.VARIABLE, 26, 0, 300_000),
+    (G500, 33, 4096, oracle.VARIABLE, 27, 0, 300_000),
 ]
 
 
