@@ -338,7 +338,7 @@ typedef struct rmat_batch_info {
   uint32_t n_launches;    /* generation launches per run (one per id width / table residency) */
   uint32_t n_work_items;  /* runs of blocks claimed by workgroups */
   uint32_t work_blocks;   /* 64-edge blocks per work item */
-  uint32_t tile_blocks;   /* blocks per wave tile in the generation kernel */
+  uint32_t tile_blocks;   /* blocks per wave tile in the generation kernel (8) */
   uint32_t max_buckets;   /* largest table */
   uint64_t total_edges;
   uint64_t device_bytes;  /* tables, build scratch and work lists held by the batch */
@@ -347,7 +347,7 @@ typedef struct rmat_batch_info {
 typedef struct rmat_autotune_report {
   double search_seconds;     /* wall time of rmat_batch_autotune */
   double calibration_ns;     /* measured device time per (edge x integer op), ns,
-                                of 4096-bucket LDS tables (8-block tiles) */
+                                of 4096-bucket LDS tables */
   uint32_t n_tuned;          /* instances whose table_bound was chosen */
   uint32_t n_candidates;     /* candidate tables built per tuned instance */
   uint32_t work_blocks;      /* measured work-item size for rmat_batch_create */
@@ -401,14 +401,13 @@ int rmat_batch_free(rmat_batch_t b);
  * Chooses table_bound for every instance whose table_bound is 0 (in place;
  * path_mode is kept), and the work-item size.  Candidates are the powers of
  * two 2^8 .. 2^16 (FIXED: 4^4 .. 4^8, at most 4^min(15,k)): up to 2^13 held
- * in LDS, where a larger table leaves room for shorter tiles (8 blocks per
- * wave up to 4096 buckets, 3 at 8192), above that read from L2 (Sec. 4: the
- * table's size and cache residency set the speed).  All candidate tables are
+ * in LDS, above that read from L2 (Sec. 4: the table's size and cache
+ * residency set the speed).  All candidate tables are
  * built on the device in one launch; each one's path-length law gives the
  * exact expected Philox blocks and samples per edge (Sec. 2: a longer
  * expected path means fewer samples per edge), and the model's cost of an
  * instance is m x (40 x blocks + 11 x samples) integer ops at the measured
- * rate of the candidate's launch class (residency and tile length; one
+ * rate of the candidate's launch class (table residency; one
  * 2^24-edge batch per class, measured once per process), plus the time to
  * stage an LDS table once per work item.  When every tuned instance has its
  * outputs, the model's bounds are then timed on the batch itself against

@@ -578,9 +578,7 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
   a.kron_k = t->info.initiator_k;
   a.id_bytes = t->info.id_bytes;
   a.n_tables = t->info.n_tables;
-  a.first_blocks = rmat::first_blocks_for(
-      t->p_second, rmat::tile_blocks(static_cast<uint32_t>(t->info.n_buckets * t->info.n_tables), t->info.id_bytes == 8,
-                                     t->info.lds_resident));
+  a.first_blocks = rmat::first_blocks_for(t->p_second);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = reduce ? rmat::launch_generate_reduce(a, s) : rmat::launch_generate(a, s);
   if (e != hipSuccess) return rmat::hip_fail(e, reduce ? "generate_reduce launch" : "generate launch");
@@ -644,9 +642,7 @@ int rmat_generate_degrees_async(rmat_table_t t, uint64_t seed, uint64_t edge_beg
   a.kron_k = 2;
   a.id_bytes = t->info.id_bytes;
   a.n_tables = t->info.n_tables;
-  a.first_blocks = rmat::first_blocks_for(
-      t->p_second, rmat::tile_blocks(static_cast<uint32_t>(t->info.n_buckets * t->info.n_tables), t->info.id_bytes == 8,
-                                     t->info.lds_resident));
+  a.first_blocks = 1;  // the counting kernel draws one counter block in its first pass
   a.degree = static_cast<uint32_t*>(d_degree);
   hipError_t e = rmat::launch_generate_degrees(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return rmat::hip_fail(e, "generate_degrees launch");

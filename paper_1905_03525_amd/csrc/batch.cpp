@@ -19,12 +19,9 @@ namespace {
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-// Instances of one id width, table residency and tile length share a
-// generation launch (a larger LDS table leaves room for shorter tiles, so
-// instances on smaller tables are not held to those).
+// Instances of one id width and table residency share a generation launch.
 struct Group {
   int wide, lds;
-  uint32_t tile;
   int general;  // some instance has epilogue flags
   uint32_t max_buckets;
   uint32_t n_items;
@@ -203,14 +200,13 @@ constexpr double kResidentWorkgroups = 256.0;
 constexpr int kMinBoundLog2 = 8, kMaxBoundLog2 = 16;
 
 // Measured device time per (edge x integer op) of the batch generation
-// kernel, one figure per launch class (table residency and tile length):
+// kernel, one figure per launch class (table residency):
 // one-instance batches of 2^25 and 2^27 edges at k = 26 (a = .57, b = c =
 // .19, d = .05) on a table of the class's size, best of three runs each;
 // the slope between the two leaves out the table build and the launches.
 // Measured once per process and class.
 struct ClassRate {
   bool lds;
-  uint32_t tile;
   double ns_per_op;
 };
 std::vector<ClassRate> g_rates;
@@ -292,16 +288,15 @@ int measure_class(uint64_t bound, double* ns_per_op) {
 // The rate of the launch class of a table of nb buckets (32-bit ids).
 int class_rate(uint32_t nb, double* ns_per_op) {
   const bool lds = nb <= rmat::lds_table_limit();
-  const uint32_t tile = rmat::tile_blocks(nb, 0, lds);
   for (const ClassRate& c : g_rates)
-    if (c.lds == lds && c.tile == tile) {
+    if (c.lds == lds) {
       *ns_per_op = c.ns_per_op;
       return RMAT_OK;
     }
   double ns = 0.0;
   int rc = measure_class(nb, &ns);
   if (rc) return rc;
-  g_rates.push_back(ClassRate{lds, tile, ns});
+  g_rates.push_back(ClassRate{lds, ns});
   *ns_per_op = ns;
   return RMAT_OK;
 }
@@ -370,57 +365,51 @@ static int rmat_batch_create_body(const rmat_instance* inst, int n, uint32_t wor
                        static_cast<unsigned long long>(kMaxWorkItems), b->work_blocks, i);
     }
   }
-  // groups by id width, table residency and tile length; work items in
-  // instance order
+  // groups by id width and table residency; work items in instance order
   const uint32_t lds_limit = rmat::lds_table_limit();
+  for (int i = 0; i < n; ++i) {
+    const uint32_t nb = static_cast<uint32_t>(b->shape[i].n_buckets);
+    if (rmat::tile_blocks(nb, b->inst[i].k > 32, nb <= lds_limit) == 0) {
+      destroy(b);
+      return set_error(RMAT_EINVAL, "instance %d: a table of %u buckets leaves no LDS for the generation queues", i,
+                       nb);
+    }
+  }
   std::vector<rmat::GenWorkItem> items;
   items.reserve(n_work);
   std::vector<uint32_t> group_first;
-  std::vector<uint32_t> inst_tile(n);
-  for (int i = 0; i < n; ++i) {
-    const uint32_t nb = static_cast<uint32_t>(b->shape[i].n_buckets);
-    inst_tile[i] = rmat::tile_blocks(nb, b->inst[i].k > 32, nb <= lds_limit);
-  }
   for (int wide = 0; wide < 2; ++wide)
-    for (int lds = 1; lds >= 0; --lds)
-      for (uint32_t tile = 8; tile >= 1; --tile) {
-        Group g;
-        g.wide = wide;
-        g.lds = lds;
-        g.tile = tile;
-        g.general = 0;
-        g.max_buckets = 0;
-        g.items = nullptr;
-        g.counter = nullptr;
-        const uint32_t first_item = static_cast<uint32_t>(items.size());
-        for (int i = 0; i < n; ++i) {
-          const rmat_instance& x = b->inst[i];
-          const rmat::Shape& S = b->shape[i];
-          if ((x.k > 32) != (wide != 0) || (S.n_buckets <= lds_limit) != (lds != 0) || inst_tile[i] != tile) continue;
-          g.max_buckets = std::max<uint32_t>(g.max_buckets, static_cast<uint32_t>(S.n_buckets));
-          if (x.m == 0) continue;
-          if (x.flags & (RMAT_UNDIRECTED | RMAT_SCRAMBLE)) g.general = 1;
-          const uint64_t first = x.edge_begin >> 6;
-          const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - first + 1;
-          for (uint64_t f = 0; f < nblk; f += b->work_blocks) {
-            rmat::GenWorkItem w;
-            w.inst = static_cast<uint32_t>(i);
-            w.first = f;
-            w.n_blocks = static_cast<uint32_t>(std::min<uint64_t>(b->work_blocks, nblk - f));
-            items.push_back(w);
-          }
+    for (int lds = 1; lds >= 0; --lds) {
+      Group g;
+      g.wide = wide;
+      g.lds = lds;
+      g.general = 0;
+      g.max_buckets = 0;
+      g.items = nullptr;
+      g.counter = nullptr;
+      const uint32_t first_item = static_cast<uint32_t>(items.size());
+      for (int i = 0; i < n; ++i) {
+        const rmat_instance& x = b->inst[i];
+        const rmat::Shape& S = b->shape[i];
+        if ((x.k > 32) != (wide != 0) || (S.n_buckets <= lds_limit) != (lds != 0)) continue;
+        g.max_buckets = std::max<uint32_t>(g.max_buckets, static_cast<uint32_t>(S.n_buckets));
+        if (x.m == 0) continue;
+        if (x.flags & (RMAT_UNDIRECTED | RMAT_SCRAMBLE)) g.general = 1;
+        const uint64_t first = x.edge_begin >> 6;
+        const uint64_t nblk = ((x.edge_begin + (x.m - 1)) >> 6) - first + 1;
+        for (uint64_t f = 0; f < nblk; f += b->work_blocks) {
+          rmat::GenWorkItem w;
+          w.inst = static_cast<uint32_t>(i);
+          w.first = f;
+          w.n_blocks = static_cast<uint32_t>(std::min<uint64_t>(b->work_blocks, nblk - f));
+          items.push_back(w);
         }
-        g.n_items = static_cast<uint32_t>(items.size()) - first_item;
-        b->max_buckets = std::max(b->max_buckets, g.max_buckets);
-        if (g.n_items == 0) continue;
-        b->groups.push_back(g);
-        group_first.push_back(first_item);
       }
-  for (int i = 0; i < n; ++i)
-    if (inst_tile[i] == 0 || inst_tile[i] > 8) {
-      destroy(b);
-      return set_error(RMAT_EINVAL, "instance %d: a table of %llu buckets leaves no LDS for the generation tiles", i,
-                       static_cast<unsigned long long>(b->shape[i].n_buckets));
+      g.n_items = static_cast<uint32_t>(items.size()) - first_item;
+      b->max_buckets = std::max(b->max_buckets, g.max_buckets);
+      if (g.n_items == 0) continue;
+      b->groups.push_back(g);
+      group_first.push_back(first_item);
     }
   b->n_items = static_cast<uint32_t>(items.size());
   if (b->groups.size() > static_cast<size_t>(n)) {  // cannot happen: every group holds an instance
@@ -668,7 +657,7 @@ static int rmat_batch_autotune_body(rmat_instance* inst, int n, rmat_autotune_re
   }
   // With the callers' outputs, the model's choice is checked by measurement
   // against one table size for all (2^12 and 2^13: the largest LDS tables
-  // with 8-block and with 3-block tiles), and the fastest is kept; then the
+  // with two workgroups per CU and with one), and the fastest is kept; then the
   // work-item size is measured.  Without outputs the model decides alone.
   uint32_t chosen = 0;
   double times[3] = {0.0, 0.0, 0.0};

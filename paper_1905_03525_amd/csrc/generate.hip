@@ -8,30 +8,30 @@
 // Work split.  The absolute edge index space is cut into 64-edge blocks
 // aligned to multiples of 64, so the high counter word e >> 32 is uniform
 // across a wave and every store instruction covers 64 consecutive slots.  A
-// wave takes its blocks in tiles of up to 8 (wave, wave + W, wave + 2W, ...
-// for W waves in the grid) and runs each tile in three passes over a private
-// LDS area:
-//   1. every edge of the tile draws its first Philox block (4 samples); the
-//      row/column bits go to the LDS area, and edges still short of k
-//      letters (11% of them at k = 26 with the 4093-path table) are appended
-//      to a compact list;
-//   2. the listed edges continue 64 at a time with counter blocks 1, 2, ...,
-//      so a second Philox block is only paid for edges that need it;
-//   3. the tile is written out block by block, 64 consecutive ids per store,
-//      every cache line written once and whole.
-// The kernel is bound by instruction issue (vector and scalar together), so
-// a full tile of whole blocks -- all but a few tiles at the ends of a range --
-// takes an unrolled copy with no per-block lane masks or loop control, and
-// stores through one buffer descriptor per output array.
+// wave takes its blocks in tiles of 8 (wave, wave + W, wave + 2W, ... for W
+// waves in the grid).  Every edge of a tile draws its first Philox block (4
+// samples; two blocks when the table's edges mostly need more); an edge
+// with k letters is stored at once from registers, 64 consecutive ids per
+// store, and the others (11% at k = 26 with the 4093-path table) join a
+// small per-wave LDS queue, which continues them 64 at a time with counter
+// blocks 1, 2, ... as soon as it holds a full wave's worth, so a further
+// Philox block is only paid for edges that need it.  The queue's 128
+// entries leave the LDS to the table: two 12-wave workgroups share a CU
+// where one 64 KiB table copy each fits.  The kernel is bound by
+// instruction issue under the chip's power limit, so a full tile of whole
+// blocks -- all but a few tiles at the ends of a range -- takes an unrolled,
+// software-pipelined copy with no per-block lane masks or loop control,
+// whose ids go out through one buffer descriptor per output array.
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "rmat_internal.h"
 
 namespace rmat {
 namespace {
 
-constexpr int kGenThreads = 1024;  // 16 waves share one LDS copy of the table
+constexpr int kGenThreads = 1024;  // the largest workgroup: 16 waves share one LDS copy of the table
 constexpr int kWaves = kGenThreads / 64;
 constexpr uint32_t kMaxTile = 8;
 // Every path of a built table has at least one letter and ids have at most
@@ -297,11 +297,12 @@ __device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ tab
 
 using Inst = GenInst;
 
-// LDS layout shared by both kernels: [table | per-wave tile areas].
+// LDS layout shared by both kernels: [table | per-wave queues].
 struct TileLayout {
   uint32_t tile;        // blocks per tile
   uint32_t lds_table;   // LDS bytes holding the table (0: read from global memory)
-  uint32_t wave_bytes;  // LDS bytes of one wave's tile area
+  uint32_t wave_bytes;  // LDS bytes of one wave's queue
+  uint32_t waves;       // waves per workgroup
 };
 
 struct Launch {
@@ -465,27 +466,66 @@ __device__ __forceinline__ uint64_t block_mask(const GenInst& I, uint64_t rel, u
   return mask;
 }
 
+// Per-wave LDS queue of the edges still short of k letters after their
+// first counter block: entry i holds (slot << 6 | filled), slot = j * 64 +
+// lane within the tile, and the partial accumulator.  A full wave's worth
+// (64 entries) is finished as soon as it is there, so the queue holds at
+// most 63 + 64 entries.
+constexpr uint32_t kQueueCap = 128;
+
+template <typename Acc>
+constexpr uint32_t queue_bytes() {
+  return kQueueCap * static_cast<uint32_t>(sizeof(typename Acc::Packed) + sizeof(uint16_t));
+}
+
 // Blocks t0 + j*stride of one instance for one wave, t0 = wave_blk,
-// wave_blk + stride*tile, ... below blk_end, in tiles of L.tile blocks:
-//   1. first Philox block of every edge into the wave's LDS area, unfinished
-//      edges listed;
-//   2. the listed edges finished 64 at a time;
-//   3. the tile stored (or reduced).
+// wave_blk + stride*tile, ... below blk_end, in tiles of L.tile blocks.
+// Each edge's first counter block is drawn in block order; an edge with k
+// letters is stored (or reduced) at once, from registers, and the others
+// join the wave's queue, which is finished 64 edges at a time (counter
+// blocks 1, 2, ...) and emptied at the end of the tile.
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
-          bool kLazy = false, bool kShortPipe = false>
+          bool kLazy = false, bool kTwo = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
-                                           typename Acc::Packed* res, uint16_t* ovf, uint32_t hist_shift,
+                                           typename Acc::Packed* qacc, uint16_t* qent, uint32_t hist_shift,
                                            uint16_t* bins, uint64_t& xsum, const KronPow* kpow = nullptr,
                                            uint32_t* degree = nullptr) {
   using Id = typename Acc::Id;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
   // edge e reads table e mod P; blocks start at multiples of 64 and P divides
-  // 64, so in pass 1 that is the lane's table for the whole run
+  // 64, so in the first pass that is the lane's table for the whole run
   const BucketRecord* __restrict__ tab_lane = tab + (lane & I.table_mask) * I.n_buckets;
   Epilogue<Id> E;
   if (kGeneral) E = make_epilogue<Id>(I);
+  const Id src_prefix = static_cast<Id>(kGeneral ? I.src_prefix : 0);
+  const Id dst_prefix = static_cast<Id>(kGeneral ? I.dst_prefix : 0);
+
+  // the ids of a finished edge e: reduced, counted, or handed to put(s, d)
+  auto finish_edge = [&](const Acc& acc, uint64_t e, auto put) {
+    if (kReduce) {
+      const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
+      bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
+      xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
+    } else if (kDegree) {  // one more edge out of its source
+      atomicAdd(degree + acc.src(I.k), 1u);
+    } else {
+      Id s = static_cast<Id>(acc.src(I.k));
+      Id d = static_cast<Id>(acc.dst(I.k));
+      if (kGeneral) {  // tiles of a partitioned graph carry id prefixes
+        s |= src_prefix;
+        d |= dst_prefix;
+      }
+      epilogue<kGeneral>(E, s, d);
+      put(s, d);
+      if (kDigest) {
+        const uint64_t s64 = s, d64 = d;
+        xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
+      }
+    }
+  };
+
   for (uint64_t t0 = wave_blk; t0 < blk_end; t0 += stride * L.tile) {
     // blocks t0 + j * stride below blk_end, at most L.tile (counted without
     // a 64-bit division: only a wave's last tile is short)
@@ -494,14 +534,84 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       nb_tile = 1;
       while (t0 + nb_tile * stride < blk_end) ++nb_tile;
     }
+    // a full tile of whole blocks (every tile but a few at the ends of the
+    // range) runs without per-block lane masks and stores through one buffer
+    // descriptor per output array, block j at a scalar offset
+    const bool whole_tile = nb_tile == L.tile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
+                            (t0 + (nb_tile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
+    const uint64_t slot0 = ((I.first_block + t0) << 6) - I.edge_begin;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_src) + slot0, 0, 0x7FFFFFFF, kBufferDword3);
+    const __amdgpu_buffer_rsrc_t rd =
+        __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_dst) + slot0, 0, 0x7FFFFFFF, kBufferDword3);
+    const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
 
-    // pass 1: first Philox block of every edge of the tile; whole blocks
-    // (every block but an instance's first and last) take a copy of the body
-    // without lane masks
-    uint32_t n_ovf = 0;
-    // counter block 1 of the lanes still short of k letters, in this pass
-    // when the table's edges mostly need it (the same samples, in the same
-    // order, as the continuation pass would draw)
+    // the queued edges [q0, q0 + cnt), one per lane, finished from counter
+    // block 1 (2 when the first pass drew two) and stored
+    auto drain = [&](uint32_t q0, uint32_t cnt) {
+      wave_lds_fence();
+      if (lane < cnt) {
+        const uint32_t entry = qent[q0 + lane];
+        Acc acc;
+        acc.unpack(qacc[q0 + lane]);
+        const uint32_t slot = entry >> 6;
+        uint32_t filled = entry & 63u;
+        const uint64_t e = ((I.first_block + t0 + (slot >> 6) * stride) << 6) + (slot & 63u);
+        const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
+        const BucketRecord* __restrict__ tab_e = tab + ((slot & 63u) & I.table_mask) * I.n_buckets;
+        for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
+          uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
+          philox10(x0, x1, x2, x3, I.key0, I.key1);
+          if (kLazy)
+            sample_lazy(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+          else
+            sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+        }
+        finish_edge(acc, e, [&](Id s, Id d) {
+          static_cast<Id*>(I.out_src)[e - I.edge_begin] = s;
+          static_cast<Id*>(I.out_dst)[e - I.edge_begin] = d;
+        });
+      }
+      wave_lds_fence();
+    };
+
+    // block j of the tile after its first counter block: finished lanes are
+    // emitted, the others queued; a full wave of queued edges is drained
+    uint32_t n_q = 0;
+    // soff: block j's byte offset from the tile's first block (whole tiles)
+    auto settle = [&](uint32_t j, uint64_t base, const Acc& acc, uint32_t filled, bool active, uint32_t soff,
+                      auto desc) {
+      const bool need = active && filled < I.k;
+      const uint64_t qmask = __ballot(need);
+      if (active && !need) {
+        finish_edge(acc, base + lane, [&](Id s, Id d) {
+          if constexpr (decltype(desc)::value) {
+            store_at(rs, lane, soff, s);
+            store_at(rd, lane, soff, d);
+          } else {
+            store_ids(I.out_src, base - I.edge_begin, lane, s);
+            store_ids(I.out_dst, base - I.edge_begin, lane, d);
+          }
+        });
+      }
+      if (qmask != 0) {
+        if (need) {
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qmask >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qmask), 0u));
+          qent[n_q + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
+          qacc[n_q + rank] = acc.pack();
+        }
+        n_q += __popcll(qmask);
+        if (n_q >= 64) {
+          n_q -= 64;
+          drain(n_q, 64);
+        }
+      }
+    };
+
+    // counter block 1 of the lanes still short of k letters, in the first
+    // pass when the table's edges mostly need it (the same samples, in the
+    // same order, as the queue's drain would draw)
     auto second_block = [&](uint64_t base, Acc& acc, uint32_t& filled) {
       if (I.first_blocks == 2 && filled < I.k) {
         uint32_t y0 = static_cast<uint32_t>(base) + lane, y1 = static_cast<uint32_t>(base >> 32), y2 = 1u,
@@ -513,7 +623,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           sample4(tab_lane, I.shift, I.k, y0, y1, y2, y3, acc, filled, kpow);
       }
     };
-    auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole, auto sure) {
+    auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole, auto sure, auto desc) {
       Acc acc;
       acc.clear();
       uint32_t filled = 0;
@@ -522,57 +632,43 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
                      x2, x3);
       sample4<Acc, decltype(sure)::value>(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
       second_block(base, acc, filled);
-      res[j * 64 + lane] = acc.pack();
-      const bool need = decltype(whole)::value ? filled < I.k : (filled < I.k && ((amask >> lane) & 1ull));
-      const uint64_t ovf_mask = __ballot(need);
-      if (ovf_mask != 0) {
-        if (need) {
-          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-              static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
-          ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
-        }
-        n_ovf += __popcll(ovf_mask);
-      }
+      settle(j, base, acc, filled, decltype(whole)::value || ((amask >> lane) & 1ull), j * step, desc);
     };
-    // a full tile of whole blocks (every tile but a few at the ends of the
-    // range) runs unrolled, without per-block lane masks
-    const bool prefixed = kGeneral && (I.src_prefix | I.dst_prefix) != 0;
-    const bool whole_tile = nb_tile == L.tile && stride < (1u << 16) && (t0 != 0 || (I.edge_begin & 63u) == 0) &&
-                            (t0 + (nb_tile - 1) * stride != I.n_blocks - 1 || (last & 63u) == 63u);
     const bool sure1 = I.k > static_cast<uint32_t>(kMaxDepthCap);  // a path has at most kMaxDepthCap letters
     // the pipelined passes consume a block without branches (consume4_flat):
     // exact for 64-bit ids and base-K accumulators, for 32-bit ids when k < 32
     const bool pipe_ok = sure1 && (Acc::kKron || sizeof(typename Acc::Id) == 8 || I.k < 32u);
-    if (whole_tile && pipe_ok && nb_tile == kMaxTile && I.first_blocks != 2) {
-      // software-pipelined: block j's Philox draws and table reads are issued
-      // before block j - 1's samples are consumed, so the reads overlap work
-      // (full 8-block tiles draw one counter block per edge in this pass)
-      auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
-        const uint64_t base = (I.first_block + t0 + j * stride) << 6;
-        philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
-                       x[0], x[1], x[2], x[3]);
+    // block j's Philox draws and table reads, issued before block j - 1 is
+    // consumed so that the reads overlap work
+    auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
+      const uint64_t base = (I.first_block + t0 + j * stride) << 6;
+      philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
+                     x[0], x[1], x[2], x[3]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) r[i] = tab_lane[x[i] >> I.shift];
-      };
+      for (int i = 0; i < 4; ++i) r[i] = tab_lane[x[i] >> I.shift];
+    };
+    auto consume = [&](const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc, uint32_t& filled) {
+      if constexpr (Acc::kKron)
+        consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
+      else
+        consume4_flat<Acc>(I.k, x, r, acc, filled);
+    };
+    if (whole_tile && pipe_ok && nb_tile == kMaxTile && (kTwo || I.first_blocks != 2)) {
+      // software-pipelined, unrolled; the copy with kTwo also draws counter
+      // block 1 in this pass for the lanes that need it (a separate copy:
+      // its presence slows the one-block code)
+      // a running store offset (the products j * step, kept for all blocks,
+      // would crowd the scalar registers)
+      uint32_t soff = 0;
       auto finish = [&](uint32_t j, const uint32_t (&x)[4], const BucketRecord (&r)[4]) {
         Acc acc;
         acc.clear();
         uint32_t filled = 0;
-        if constexpr (Acc::kKron)
-          consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
-        else
-          consume4_flat<Acc>(I.k, x, r, acc, filled);
-        res[j * 64 + lane] = acc.pack();
-        const bool need = filled < I.k;
-        const uint64_t ovf_mask = __ballot(need);
-        if (ovf_mask != 0) {
-          if (need) {
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
-            ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
-          }
-          n_ovf += __popcll(ovf_mask);
-        }
+        consume(x, r, acc, filled);
+        const uint64_t base = (I.first_block + t0 + j * stride) << 6;
+        if constexpr (kTwo) second_block(base, acc, filled);
+        settle(j, base, acc, filled, true, soff, std::true_type{});
+        soff += step;
       };
       uint32_t xa[4];
       BucketRecord ra[4];
@@ -590,217 +686,39 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         }
       }
       finish(kMaxTile - 1, xa, ra);
-    } else if (kShortPipe && whole_tile && pipe_ok) {
-      // a shorter full tile with the tables in LDS (a batch holding a larger
-      // table leaves less LDS for tiles): the same pipeline, rolled.  The
-      // single-instance kernel leaves it out: there it measured no faster
-      // and its presence changes the code of the 8-block path
-      auto draw = [&](uint32_t j, uint32_t (&x)[4], BucketRecord (&r)[4]) {
-        const uint64_t base = (I.first_block + t0 + j * stride) << 6;
-        philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
-                       x[0], x[1], x[2], x[3]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) r[i] = tab_lane[x[i] >> I.shift];
-      };
-      auto finish = [&](uint32_t j, const uint32_t (&x)[4], const BucketRecord (&r)[4]) {
-        Acc acc;
-        acc.clear();
-        uint32_t filled = 0;
-        if constexpr (Acc::kKron)
-          consume4<Acc, true>(I.k, x, r, acc, filled, kpow);
-        else
-          consume4_flat<Acc>(I.k, x, r, acc, filled);
-        second_block((I.first_block + t0 + j * stride) << 6, acc, filled);
-        res[j * 64 + lane] = acc.pack();
-        const bool need = filled < I.k;
-        const uint64_t ovf_mask = __ballot(need);
-        if (ovf_mask != 0) {
-          if (need) {
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                static_cast<uint32_t>(ovf_mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(ovf_mask), 0u));
-            ovf[n_ovf + rank] = static_cast<uint16_t>(((j * 64 + lane) << 6) | filled);
-          }
-          n_ovf += __popcll(ovf_mask);
-        }
-      };
-      uint32_t xa[4];
-      BucketRecord ra[4];
-      draw(0, xa, ra);
-      for (uint32_t j = 1; j < nb_tile; ++j) {
-        uint32_t xb[4];
-        BucketRecord rb[4];
-        draw(j, xb, rb);
-        finish(j - 1, xa, ra);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          xa[i] = xb[i];
-          ra[i] = rb[i];
-        }
-      }
-      finish(nb_tile - 1, xa, ra);
     } else if (whole_tile) {
-      // a full tile of another size (a larger table or an L2 table leaves
-      // less LDS for tiles): whole blocks, rolled
+      // other full tiles of whole blocks, rolled
       for (uint32_t j = 0; j < nb_tile; ++j) {
         const uint64_t base = (I.first_block + t0 + j * stride) << 6;
         if (sure1)
-          first_block(j, base, ~0ull, std::true_type{}, std::true_type{});
+          first_block(j, base, ~0ull, std::true_type{}, std::true_type{}, std::true_type{});
         else
-          first_block(j, base, ~0ull, std::true_type{}, std::false_type{});
+          first_block(j, base, ~0ull, std::true_type{}, std::false_type{}, std::true_type{});
       }
     } else {
       for (uint32_t j = 0; j < nb_tile; ++j) {
-        const uint64_t rel = t0 + j * stride;                 // block index within the instance
-        const uint64_t base = (I.first_block + rel) << 6;     // wave-uniform
+        const uint64_t rel = t0 + j * stride;              // block index within the instance
+        const uint64_t base = (I.first_block + rel) << 6;  // wave-uniform
         const uint64_t amask = block_mask(I, rel, last);
         if (amask == ~0ull)
-          first_block(j, base, amask, std::true_type{}, std::false_type{});
+          first_block(j, base, amask, std::true_type{}, std::false_type{}, std::false_type{});
         else
-          first_block(j, base, amask, std::false_type{}, std::false_type{});
+          first_block(j, base, amask, std::false_type{}, std::false_type{}, std::false_type{});
       }
     }
-    wave_lds_fence();
-
-    // pass 2: the unfinished edges, 64 at a time, counter blocks 1, 2, ...
-    for (uint32_t q = 0; q < n_ovf; q += 64) {
-      if (q + lane < n_ovf) {
-        const uint32_t entry = ovf[q + lane];
-        const uint32_t idx = entry >> 6;
-        uint32_t filled = entry & 63u;
-        Acc acc;
-        acc.unpack(res[idx]);
-        const uint64_t e = ((I.first_block + t0 + (idx >> 6) * stride) << 6) + (idx & 63u);
-        const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
-        const BucketRecord* __restrict__ tab_e = tab + ((idx & 63u) & I.table_mask) * I.n_buckets;
-        for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
-          uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
-          philox10(x0, x1, x2, x3, I.key0, I.key1);
-          if (kLazy)
-            sample_lazy(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
-          else
-            sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
-        }
-        res[idx] = acc.pack();
-      }
-    }
-    wave_lds_fence();
-
-    // pass 3: write the tile out (or fold it into the reduction)
-    auto emit = [&](const typename Acc::Packed& v, uint64_t base, auto prefixed) {
-      const uint64_t e = base + lane;
-      Acc acc;
-      acc.unpack(v);
-      {
-        if (kReduce) {
-          const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
-          bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
-          xsum ^= fmix64(e ^ fmix64(s ^ ((d << 32) | (d >> 32))));
-        } else if (kDegree) {  // one more edge out of its source
-          const uint64_t s = acc.src(I.k);
-          atomicAdd(degree + s, 1u);
-        } else {
-          Id s = static_cast<Id>(acc.src(I.k));
-          Id d = static_cast<Id>(acc.dst(I.k));
-          if (kGeneral && decltype(prefixed)::value) {  // tiles of a partitioned graph
-            s |= static_cast<Id>(I.src_prefix);
-            d |= static_cast<Id>(I.dst_prefix);
-          }
-          epilogue<kGeneral>(E, s, d);
-          store_ids(I.out_src, base - I.edge_begin, lane, s);
-          store_ids(I.out_dst, base - I.edge_begin, lane, d);
-          if (kDigest) {
-            const uint64_t s64 = s, d64 = d;
-            xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
-          }
-        }
-      }
-    };
-    // the tile's results are read from LDS first, so the reads overlap
-    typename Acc::Packed vals[kMaxTile];
-#pragma unroll
-    for (uint32_t j = 0; j < kMaxTile; ++j)
-      if (j < nb_tile) vals[j] = res[j * 64 + lane];
-    const uint32_t epi = kGeneral ? E.flags : 0u;
-    if (!kReduce && !kDegree && whole_tile && (!prefixed || epi == 0)) {
-      // one buffer descriptor per output array for the whole tile; block j
-      // sits at a scalar offset from the tile's first block (a tile of a
-      // partitioned graph ORs in its id prefixes and has no epilogue)
-      const uint64_t slot0 = ((I.first_block + t0) << 6) - I.edge_begin;
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_src) + slot0, 0,
-                                                                           0x7FFFFFFF, kBufferDword3);
-      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(static_cast<Id*>(I.out_dst) + slot0, 0,
-                                                                           0x7FFFFFFF, kBufferDword3);
-      const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
-      // the epilogue's kind is chosen once per tile, so the unrolled stores
-      // carry no per-block branches
-      auto store_tile = [&](auto undirected, auto scrambled, auto with_prefix) {
-#pragma unroll
-        for (uint32_t j = 0; j < kMaxTile; ++j) {
-          if (j >= nb_tile) break;
-          Acc acc;
-          acc.unpack(vals[j]);
-          Id sv = static_cast<Id>(acc.src(I.k));
-          Id dv = static_cast<Id>(acc.dst(I.k));
-          if (decltype(with_prefix)::value) {
-            sv |= static_cast<Id>(I.src_prefix);
-            dv |= static_cast<Id>(I.dst_prefix);
-          }
-          if (decltype(undirected)::value) {
-            const Id lo = sv < dv ? sv : dv;
-            dv = sv < dv ? dv : sv;
-            sv = lo;
-          }
-          if (decltype(scrambled)::value) {
-            sv = scramble_id(sv, E);
-            dv = scramble_id(dv, E);
-          }
-          store_at(rs, lane, j * step, sv);
-          store_at(rd, lane, j * step, dv);
-          if (kDigest) {
-            const uint64_t e = ((I.first_block + t0 + j * stride) << 6) + lane;
-            const uint64_t s64 = sv, d64 = dv;
-            xsum ^= fmix64(e ^ fmix64(s64 ^ ((d64 << 32) | (d64 >> 32))));
-          }
-        }
-      };
-      if (prefixed)
-        store_tile(std::false_type{}, std::false_type{}, std::true_type{});
-      else if (epi == 0)
-        store_tile(std::false_type{}, std::false_type{}, std::false_type{});
-      else if (epi == kEpiUndirected)
-        store_tile(std::true_type{}, std::false_type{}, std::false_type{});
-      else if (epi == kEpiScramble)
-        store_tile(std::false_type{}, std::true_type{}, std::false_type{});
-      else
-        store_tile(std::true_type{}, std::true_type{}, std::false_type{});
-    } else {
-#pragma unroll
-      for (uint32_t j = 0; j < kMaxTile; ++j) {
-        if (j < nb_tile) {
-          const uint64_t rel = t0 + j * stride;
-          const uint64_t base = (I.first_block + rel) << 6;
-          const uint64_t amask = block_mask(I, rel, last);
-          if (amask == ~0ull && !prefixed) {
-            emit(vals[j], base, std::false_type{});
-          } else if ((amask >> lane) & 1ull) {
-            emit(vals[j], base, std::true_type{});
-          }
-        }
-      }
-    }
-    wave_lds_fence();
+    if (n_q != 0) drain(0, n_q);
   }
 }
 
 __device__ __forceinline__ void stage_table(const BucketRecord* src_rec, uint32_t n_buckets, unsigned char* s_mem) {
   const uint4* src = reinterpret_cast<const uint4*>(src_rec);
   uint4* dst = reinterpret_cast<uint4*>(s_mem);
-  for (uint32_t i = threadIdx.x; i < n_buckets; i += kGenThreads) dst[i] = src[i];
+  for (uint32_t i = threadIdx.x; i < n_buckets; i += blockDim.x) dst[i] = src[i];
 }
 
 // kGeneral: the store may carry id prefixes and the epilogue; without it the
 // launch stores the plain ids and keeps none of their parameters live.
-template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false>
+template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false, bool kTwo = false>
 __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ unsigned long long s_xor[kWaves];
@@ -826,20 +744,20 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   }
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * kWaves + wave_in_wg;
-  const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * kWaves;
-  Packed* res = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
-  uint16_t* ovf = reinterpret_cast<uint16_t*>(res + P.L.tile * 64);
+  const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * P.L.waves + wave_in_wg;
+  const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * P.L.waves;
+  Packed* qacc = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
+  uint16_t* qent = reinterpret_cast<uint16_t*>(qacc + kQueueCap);
   uint64_t xsum = 0;
-  run_blocks<Acc, kReduce, false, kGeneral, kDegree, !kLds>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, res, ovf,
-                                                     P.hist_shift, P.bins, xsum, kpow, P.degree);
+  run_blocks<Acc, kReduce, false, kGeneral, kDegree, !kLds, kTwo>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, qacc,
+                                                            qent, P.hist_shift, P.bins, xsum, kpow, P.degree);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long t = 0;
-      for (int w = 0; w < kWaves; ++w) t ^= s_xor[w];
+      for (uint32_t w = 0; w < P.L.waves; ++w) t ^= s_xor[w];
       atomicXor(P.xor_out, t);
     }
   }
@@ -848,16 +766,16 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
 // Persistent kernel over the work items of a batch.  A workgroup claims an
 // item, restages the table only when the item's table differs from the one
 // in LDS (items are in instance order; the tiles of a partitioned graph and
-// requests served from one cached table share it), and its 16 waves share
-// the item's blocks.
+// requests served from one cached table share it), and its waves share the
+// item's blocks.
 template <typename Acc, bool kLds, bool kDigest, bool kGeneral>
 __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch B) {
   extern __shared__ __align__(16) unsigned char s_mem[];
   __shared__ uint32_t s_item;
   using Packed = typename Acc::Packed;
   const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  Packed* res = reinterpret_cast<Packed*>(s_mem + B.L.lds_table + wave_in_wg * B.L.wave_bytes);
-  uint16_t* ovf = reinterpret_cast<uint16_t*>(res + B.L.tile * 64);
+  Packed* qacc = reinterpret_cast<Packed*>(s_mem + B.L.lds_table + wave_in_wg * B.L.wave_bytes);
+  uint16_t* qent = reinterpret_cast<uint16_t*>(qacc + kQueueCap);
   const BucketRecord* cur = nullptr;  // table in LDS and its buckets
   uint32_t cur_buckets = 0;
   for (;;) {
@@ -878,12 +796,12 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     if (W.n_inst > 1) {
       // a run of small instances on this table: each wave takes whole
       // instances (no workgroup step between them)
-      for (uint32_t j = wave_in_wg; j < W.n_inst; j += kWaves) {
+      for (uint32_t j = wave_in_wg; j < W.n_inst; j += B.L.waves) {
         const Inst Ij = B.insts[W.inst + j];
         const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : Ij.records;
         uint64_t xsum = 0;
-        run_blocks<Acc, false, kDigest, kGeneral, false, !kLds, kLds>(Ij, tab, B.L, 0, Ij.n_blocks, 1, res, ovf, 0,
-                                                                     nullptr, xsum);
+        run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(Ij, tab, B.L, 0, Ij.n_blocks, 1, qacc, qent, 0,
+                                                               nullptr, xsum);
         if (kDigest && Ij.digest != nullptr) {
           const uint64_t x = wave_xor(xsum);
           if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(Ij.digest, x);
@@ -893,9 +811,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     }
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
     uint64_t xsum = 0;
-    run_blocks<Acc, false, kDigest, kGeneral, false, !kLds, kLds>(I, tab, B.L, W.first + wave_in_wg,
-                                                                W.first + W.n_blocks, kWaves, res, ovf, 0,
-                                                                nullptr, xsum);
+    run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(I, tab, B.L, W.first + wave_in_wg, W.first + W.n_blocks,
+                                                           B.L.waves, qacc, qent, 0, nullptr, xsum);
     if (kDigest && I.digest != nullptr) {
       const uint64_t x = wave_xor(xsum);
       if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(I.digest, x);
@@ -923,47 +840,82 @@ const DeviceLimits& limits() {
   return g_limits;
 }
 
-// Tile size and LDS bytes for a table of `buckets` (staged when lds).
+// Waves per workgroup a launch may take, most first: one workgroup of 16
+// shares a table copy among the most waves, two of 12 fit twice a 64 KiB
+// table's LDS with more waves per CU where registers allow.
+constexpr uint32_t kWaveChoices[] = {16, 12, 8};
+constexpr uint32_t kMinWaves = 8;
+
+bool fits_lds(size_t bytes) { return bytes + 1024 <= static_cast<size_t>(limits().lds_per_block); }  // + static LDS
+
+// Workgroups of kernel fn resident per CU at `waves` waves and `bytes` of
+// dynamic LDS, from the runtime's occupancy calculator (cached; -1 if the
+// query failed).
+int resident_groups(const void* fn, uint32_t waves, size_t bytes) {
+  struct Entry {
+    const void* fn;
+    uint32_t waves;
+    size_t bytes;
+    int n;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& c : cache)
+      if (c.fn == fn && c.waves == waves && c.bytes == bytes) return c.n;
+  }
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, static_cast<int>(waves * 64), bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    n = -1;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  cache.push_back(Entry{fn, waves, bytes, n});
+  return n;
+}
+
+// Layout of a launch of kernel fn over a table of `buckets` (staged when
+// lds): the waves per workgroup that keep the most waves resident per CU,
+// its LDS bytes and resident workgroups.  tile = 0 when no layout fits.
 template <typename Acc>
-TileLayout layout_for(uint32_t buckets, bool lds, size_t* lds_bytes) {
-  const DeviceLimits& D = limits();
+TileLayout layout_for(const void* fn, uint32_t buckets, bool lds, size_t* lds_bytes, uint32_t* per_cu) {
   TileLayout L;
   L.lds_table = lds ? buckets * static_cast<uint32_t>(sizeof(BucketRecord)) : 0;
-  const uint32_t per_block_bytes = 64 * sizeof(typename Acc::Packed) + 64 * sizeof(uint16_t);
-  const uint32_t budget = static_cast<uint32_t>(D.lds_per_block) - 1024;  // room for static LDS
-  uint32_t tile = 0;
-  if (L.lds_table + kWaves * per_block_bytes <= budget) tile = (budget - L.lds_table) / (kWaves * per_block_bytes);
-  if (tile > kMaxTile) tile = kMaxTile;
-  if (!lds) {
-    // a table read from L2 leaves the LDS to the tiles: keep them small enough
-    // for two workgroups per CU, twice the loads in flight
-    const uint32_t half = static_cast<uint32_t>(D.lds_per_block) / 2 - 1024;
-    const uint32_t t2 = half / (kWaves * per_block_bytes);
-    if (t2 >= 1 && t2 < tile) tile = t2;
+  L.wave_bytes = queue_bytes<Acc>();
+  L.tile = 0;
+  L.waves = 0;
+  uint32_t best = 0;
+  for (uint32_t w : kWaveChoices) {
+    const size_t bytes = L.lds_table + static_cast<size_t>(w) * L.wave_bytes;
+    if (!fits_lds(bytes)) continue;
+    int n = resident_groups(fn, w, bytes);
+    if (n < 0) n = 1;  // no answer: one workgroup, which the LDS allows
+    if (static_cast<uint32_t>(n) * w > best) {
+      best = static_cast<uint32_t>(n) * w;
+      L.waves = w;
+      *per_cu = static_cast<uint32_t>(n);
+      *lds_bytes = bytes;
+    }
   }
-  L.tile = tile;
-  L.wave_bytes = tile * per_block_bytes;
-  *lds_bytes = L.lds_table + static_cast<size_t>(kWaves) * L.wave_bytes;
+  if (best) L.tile = kMaxTile;
   return L;
 }
 
-uint64_t persistent_grid(size_t lds_bytes) {
-  const uint64_t per_cu = 2 * (lds_bytes + 1024) <= static_cast<uint64_t>(limits().lds_per_block) ? 2 : 1;
-  return static_cast<uint64_t>(limits().cu_count) * per_cu;
-}
-
-template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false>
+template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false, bool kTwo = false>
 hipError_t launch_one(Launch P, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&generate_kernel<Acc, kLds, kReduce, kGeneral, kDegree, kTwo>);
   size_t lds = 0;
-  P.L = layout_for<Acc>(P.I.n_buckets * (P.I.table_mask + 1), kLds, &lds);
+  uint32_t per_cu = 0;
+  P.L = layout_for<Acc>(fn, P.I.n_buckets * (P.I.table_mask + 1), kLds, &lds, &per_cu);
   if (P.L.tile == 0) return hipErrorInvalidValue;
   const uint64_t waves_needed = (P.I.n_blocks + P.L.tile - 1) / P.L.tile;
-  const uint64_t wgs_needed = (waves_needed + kWaves - 1) / kWaves;
-  uint64_t grid = persistent_grid(lds);
+  const uint64_t wgs_needed = (waves_needed + P.L.waves - 1) / P.L.waves;
+  uint64_t grid = static_cast<uint64_t>(limits().cu_count) * per_cu;
   if (grid > wgs_needed) grid = wgs_needed;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce, kGeneral, kDegree>), dim3(static_cast<uint32_t>(grid)),
-                     dim3(kGenThreads), lds, s, P);
+  hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce, kGeneral, kDegree, kTwo>), dim3(static_cast<uint32_t>(grid)),
+                     dim3(P.L.waves * 64), lds, s, P);
   return hipGetLastError();
 }
 
@@ -1114,20 +1066,33 @@ hipError_t dispatch(const GenerateArgs& a, hipStream_t s) {
     scramble_params(a.scramble_key, a.k, &P.I);
   }
   const bool wide = a.k > 32;
+  // two counter blocks in the first pass only where the kernel has the
+  // unrolled copy for it (plain stores); the reduction and the epilogue take
+  // one, which their pipelined path then serves
+  const bool two = !kReduce && a.epi == 0 && a.first_blocks == 2;
+  P.I.first_blocks = two ? 2u : 1u;
   auto gen = [&](const Launch& L) {
+    auto plain = [&](auto acc, auto lds) {
+      using A = decltype(acc);
+      constexpr bool kL = decltype(lds)::value;
+      return two ? launch_one<A, kL, false, false, false, true>(L, s) : launch_one<A, kL, false, false, false>(L, s);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
     if (!kReduce && a.kron_k > 2) {  // base-K digits; no epilogue, reduction or sets for these tables
-      if (a.id_bytes == 4)
-        return a.lds ? launch_one<KronAcc<uint32_t>, true, false, false>(L, s)
-                     : launch_one<KronAcc<uint32_t>, false, false, false>(L, s);
-      return a.lds ? launch_one<KronAcc<uint64_t>, true, false, false>(L, s)
-                   : launch_one<KronAcc<uint64_t>, false, false, false>(L, s);
+      if (a.id_bytes == 4) return a.lds ? plain(KronAcc<uint32_t>{}, T{}) : plain(KronAcc<uint32_t>{}, F{});
+      return a.lds ? plain(KronAcc<uint64_t>{}, T{}) : plain(KronAcc<uint64_t>{}, F{});
     }
     if (!kReduce && L.I.epi != 0) {
       if (a.lds) return wide ? launch_one<Acc64, true, false, true>(L, s) : launch_one<Acc32, true, false, true>(L, s);
       return wide ? launch_one<Acc64, false, false, true>(L, s) : launch_one<Acc32, false, false, true>(L, s);
     }
-    if (a.lds) return wide ? launch_one<Acc64, true, kReduce, false>(L, s) : launch_one<Acc32, true, kReduce, false>(L, s);
-    return wide ? launch_one<Acc64, false, kReduce, false>(L, s) : launch_one<Acc32, false, kReduce, false>(L, s);
+    if (!kReduce) {
+      if (a.lds) return wide ? plain(Acc64{}, T{}) : plain(Acc32{}, T{});
+      return wide ? plain(Acc64{}, F{}) : plain(Acc32{}, F{});
+    }
+    if (a.lds) return wide ? launch_one<Acc64, true, true, false>(L, s) : launch_one<Acc32, true, true, false>(L, s);
+    return wide ? launch_one<Acc64, false, true, false>(L, s) : launch_one<Acc32, false, true, false>(L, s);
   };
   if (!kReduce) return gen(P);
   // reduction: sub-chunks of at most bins_cap edges, each generated into the
@@ -1162,14 +1127,16 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   B.items = a.items;
   B.n_items = a.n_items;
   B.counter = a.counter;
+  const void* fn = reinterpret_cast<const void*>(&generate_batch_kernel<Acc, kLds, kDigest, kGeneral>);
   size_t lds = 0;
-  B.L = layout_for<Acc>(a.max_buckets, kLds, &lds);
+  uint32_t per_cu = 0;
+  B.L = layout_for<Acc>(fn, a.max_buckets, kLds, &lds, &per_cu);
   if (B.L.tile == 0) return hipErrorInvalidValue;
-  uint64_t grid = persistent_grid(lds);
+  uint64_t grid = static_cast<uint64_t>(limits().cu_count) * per_cu;
   if (grid > a.n_items) grid = a.n_items;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((generate_batch_kernel<Acc, kLds, kDigest, kGeneral>), dim3(static_cast<uint32_t>(grid)),
-                     dim3(kGenThreads), lds, s, B);
+                     dim3(B.L.waves * 64), lds, s, B);
   return hipGetLastError();
 }
 
@@ -1181,15 +1148,14 @@ hipError_t allow_full_lds(F* fn) {
 
 }  // namespace
 
-// Largest power-of-two table (in buckets) staged in LDS: it must leave room
-// for one tile block per wave of the widest (64-bit id) layout.
+// Largest power-of-two table (in buckets, at most 2^13) staged in LDS: it
+// must leave room for the queues of the fewest waves a workgroup takes, in
+// the widest (64-bit id) layout.
 uint32_t lds_table_limit() {
-  const DeviceLimits& D = limits();
-  const int64_t room = static_cast<int64_t>(D.lds_per_block) - 1024 -
-                       static_cast<int64_t>(kWaves) * (64 * sizeof(ulonglong2) + 64 * sizeof(uint16_t));
+  const size_t queues = static_cast<size_t>(kMinWaves) * queue_bytes<Acc64>();
   uint32_t nb = 1;
-  while (static_cast<int64_t>(2 * nb) * static_cast<int64_t>(sizeof(BucketRecord)) <= room && nb < (1u << 13)) nb <<= 1;
-  return static_cast<int64_t>(nb) * static_cast<int64_t>(sizeof(BucketRecord)) <= room ? nb : 0;
+  while (nb < (1u << 13) && fits_lds(2 * nb * sizeof(BucketRecord) + queues)) nb <<= 1;
+  return fits_lds(nb * sizeof(BucketRecord) + queues) ? nb : 0;
 }
 
 uint64_t reduce_partials_bytes() {
@@ -1238,7 +1204,8 @@ hipError_t launch_generate(const GenerateArgs& a, hipStream_t s) { return dispat
 
 hipError_t launch_generate_degrees(const GenerateArgs& a, hipStream_t s) {
   if (a.m == 0) return hipSuccess;
-  const Launch P = make_launch(a);
+  Launch P = make_launch(a);
+  P.I.first_blocks = 1;  // the counting kernel has no two-block unrolled copy
   if (a.k > 32)
     return a.lds ? launch_one<Acc64, true, false, false, true>(P, s) : launch_one<Acc64, false, false, false, true>(P, s);
   return a.lds ? launch_one<Acc32, true, false, false, true>(P, s) : launch_one<Acc32, false, false, false, true>(P, s);
@@ -1271,9 +1238,9 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s) {
 }
 
 uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds) {
-  size_t bytes = 0;
-  return wide ? layout_for<Acc64>(table_buckets, lds != 0, &bytes).tile
-              : layout_for<Acc32>(table_buckets, lds != 0, &bytes).tile;
+  const size_t table = lds ? static_cast<size_t>(table_buckets) * sizeof(BucketRecord) : 0;
+  const size_t queues = static_cast<size_t>(kMinWaves) * (wide ? queue_bytes<Acc64>() : queue_bytes<Acc32>());
+  return fits_lds(table + queues) ? kMaxTile : 0;
 }
 
 hipError_t prepare_kernels() {
@@ -1315,7 +1282,13 @@ hipError_t prepare_kernels() {
       allow_full_lds(&generate_batch_kernel<Acc64, false, true, true>),
       allow_full_lds(&hist_partial_kernel),
       allow_full_lds(&generate_kernel<KronAcc<uint32_t>, true, false, false>),
-      allow_full_lds(&generate_kernel<KronAcc<uint64_t>, true, false, false>)};
+      allow_full_lds(&generate_kernel<KronAcc<uint64_t>, true, false, false>),
+      allow_full_lds(&generate_kernel<Acc32, true, false, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc32, false, false, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, true, false, false, false, true>),
+      allow_full_lds(&generate_kernel<Acc64, false, false, false, false, true>),
+      allow_full_lds(&generate_kernel<KronAcc<uint32_t>, true, false, false, false, true>),
+      allow_full_lds(&generate_kernel<KronAcc<uint64_t>, true, false, false, false, true>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

@@ -256,12 +256,9 @@ void fill_info(rmat_info* I, int k, int path_mode, uint64_t table_bound, const S
 // drawn from the table's length law, sum to fewer than k letters).
 double p_second_block(const BuildStats& st, int k);
 // Counter blocks the first generation pass draws for every edge: 2 when most
-// edges need a second block and the tiles are shorter than 8 blocks (the
-// continuation pass then holds only the few edges that need more than eight
-// samples), else 1.  Full 8-block tiles keep one: their continuation pass
-// runs nearly full waves and the first pass's software pipeline stays as it
-// is (a 3 x 3 Kronecker table measured 1% slower with two).
-inline uint32_t first_blocks_for(double p_second, uint32_t tile) { return p_second >= 0.5 && tile < 8 ? 2u : 1u; }
+// edges need a second block (the queue of unfinished edges then holds only
+// those that need more than eight samples), else 1.
+inline uint32_t first_blocks_for(double p_second) { return p_second >= 0.5 ? 2u : 1u; }
 
 void clear_error();
 int check_device();

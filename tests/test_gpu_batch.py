@@ -82,10 +82,10 @@ def test_batch_equals_plain_and_oracle(R, work_blocks):
     _alloc(R, insts)
     with R.rmat_batch_create(insts, work_blocks) as b:
         info = R.rmat_batch_get_info(b)
-        # one launch per id width, table residency and tile length: 32-bit
-        # ids on LDS tables with 8- and 3-block tiles and on an L2 table,
-        # 64-bit ids on LDS tables with 7- and 1-block tiles and on an L2 table
-        assert info["n_instances"] == len(insts) and info["n_launches"] == 6
+        # one launch per id width and table residency: 32-bit ids on LDS
+        # tables and on an L2 table, 64-bit ids on LDS tables (up to 8192
+        # buckets) and on an L2 table
+        assert info["n_instances"] == len(insts) and info["n_launches"] == 4
         assert info["total_edges"] == sum(p["m"] for p in insts)
         R.rmat_batch_enqueue(b, torch.cuda.current_stream())
         R.rmat_batch_check(b)
@@ -173,10 +173,10 @@ def test_autotune_measured_choice(R):
             tb.close()
 
 
-def test_batch_l2_and_tile_groups(R):
+def test_batch_l2_and_lds_groups(R):
     """Instances on 4096-, 8192- and 2^15-bucket tables in one batch: one
-    launch per tile length and residency, every instance equal to its plain
-    launch."""
+    launch per table residency (the two LDS sizes share one), every instance
+    equal to its plain launch."""
     import torch
     insts = workloads.batch_instances(12, k_min=12, k_max=20)
     for j, p in enumerate(insts):
@@ -184,7 +184,7 @@ def test_batch_l2_and_tile_groups(R):
     _alloc(R, insts)
     with R.rmat_batch_create(insts, 64) as b:
         info = R.rmat_batch_get_info(b)
-        assert info["n_launches"] == 3 and info["max_buckets"] == 1 << 15
+        assert info["n_launches"] == 2 and info["max_buckets"] == 1 << 15
         R.rmat_batch_enqueue(b, torch.cuda.current_stream())
         R.rmat_batch_check(b)
         for i, p in enumerate(insts):
