@@ -47,8 +47,10 @@
  *   R9 randomness: Philox4x32-10 [Salmon, Moraes, Dror, Shaw, SC'11] with
  *      key (seed_lo, seed_hi) and counter (e_lo, e_hi, j, 0); sample s of
  *      edge e uses output word s mod 4 of counter j = s / 4.
- *  R10 a sample x picks bucket x >> (32 - b); with f = x mod C the item is
- *      the bucket's own item if f < T, else its alias.
+ *  R10 a sample x picks bucket (x >> 4) mod 2^b, the b bits above the
+ *      lowest four; the other 32 - b bits, in their order, form the uniform
+ *      f = (x >> (b + 4)) * 16 + (x mod 16) in [0, C), and the item is the
+ *      bucket's own item if f < T, else its alias.
  *  R11 the first (root-most) letter of the stream is the most significant
  *      bit of the k-bit row and column ids.
  *  R12 letters left over after the k-th are discarded (each edge has its own
@@ -469,8 +471,8 @@ static void sample_edge(const orc_table* t, uint64_t seed, uint64_t e,
 static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t seed, uint64_t e,
                            uint64_t* src, uint64_t* dst, uint32_t* n_samples) {
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  const int shift = 32 - t->bucket_bits;
-  const uint32_t fmask = (uint32_t)(t->capacity - 1);
+  const int b = t->bucket_bits;
+  const uint32_t bmask = (uint32_t)(t->n_buckets - 1);
   uint64_t row = 0, col = 0;
   int filled = 0;
   uint32_t s = 0, words[4] = {0, 0, 0, 0};
@@ -481,8 +483,8 @@ static void sample_letters(const orc_table* t, int k, uint32_t stream, uint64_t 
     }
     uint32_t x = words[s & 3u];
     ++s;
-    uint32_t bucket = x >> shift;
-    uint32_t f = x & fmask;
+    uint32_t bucket = (x >> 4) & bmask;
+    uint32_t f = (uint32_t)(((uint64_t)x >> (b + 4)) << 4) | (x & 15u);
     uint32_t item = (f < t->thr[bucket]) ? bucket : t->alias[bucket];
     int L = t->len[item];
     int take = (L < k - filled) ? L : (k - filled);

@@ -446,7 +446,7 @@ static int rmat_batch_create_body(const rmat_instance* inst, int n, uint32_t wor
     d.records = b->views[i].records;
     d.n_buckets = static_cast<uint32_t>(b->shape[i].n_buckets);
     d.table_mask = 0;
-    d.shift = 32u - static_cast<uint32_t>(b->shape[i].bucket_bits);
+    d.bmask = ((1u << b->shape[i].bucket_bits) - 1u) << 4;
     d.k = static_cast<uint32_t>(x.k);
     d.key0 = static_cast<uint32_t>(x.seed);
     d.key1 = static_cast<uint32_t>(x.seed >> 32);

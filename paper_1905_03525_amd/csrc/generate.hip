@@ -200,10 +200,10 @@ struct KronAcc {
 };
 
 // Up to four samples of one Philox block, stopping at k letters, on bucket
-// records already loaded.  A sample x picks bucket x >> (32 - b) and keeps
-// the bucket's own path when x < thr_abs (= bucket * C + T), else takes its
-// alias; each field is the low half-word for the own item, else the high
-// one.  kSure1: the second sample is always used (k > kMaxDepthCap letters
+// records already loaded.  A sample x keeps its bucket's own path when
+// x < thr_abs (its bits other than the bucket's, read in order, are below
+// the threshold T), else takes the alias; each field is the low half-word
+// for the own item, else the high one.  kSure1: the second sample is always used (k > kMaxDepthCap letters
 // cannot come from one path).
 template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
@@ -259,14 +259,32 @@ __device__ __forceinline__ void consume4_flat(uint32_t k, const uint32_t (&x)[4]
   }
 }
 
+typedef __attribute__((address_space(3))) const BucketRecord* LdsRecordPtr;
+
+// The record sample x selects in the table at byte offset toff of a set:
+// bucket (x >> 4) mod nb, whose offset within the table is x & bmask with
+// bmask = (nb - 1) << 4 (one AND-OR: toff is a multiple of nb * 16).  A set
+// staged in LDS starts at LDS address 0 (the generation kernels declare no
+// static LDS), so that offset is the read's whole address.
+template <bool kLds>
+__device__ __forceinline__ BucketRecord record_of(const BucketRecord* __restrict__ set, uint32_t toff, uint32_t bmask,
+                                                  uint32_t x) {
+  const uint32_t off = toff | (x & bmask);
+  if constexpr (kLds)  // an LDS pointer, read through the generic type (the loads stay LDS reads)
+    return *(const BucketRecord*)(LdsRecordPtr)static_cast<uintptr_t>(off);
+  else
+    return *reinterpret_cast<const BucketRecord*>(reinterpret_cast<const char*>(set) + off);
+}
+
 // Loads the four bucket records of one Philox block, then samples them.  All
 // four reads are issued before any is used, so they are in flight together.
-template <typename Acc, bool kSure1 = false>
-__device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k, uint32_t x0,
-                                        uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc, uint32_t& filled,
-                                        const KronPow* kpow) {
+template <typename Acc, bool kLds, bool kSure1 = false>
+__device__ __forceinline__ void sample4(const BucketRecord* __restrict__ set, uint32_t toff, uint32_t bmask, uint32_t k,
+                                        uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc,
+                                        uint32_t& filled, const KronPow* kpow) {
   const uint32_t x[4] = {x0, x1, x2, x3};
-  const BucketRecord r[4] = {tab[x0 >> shift], tab[x1 >> shift], tab[x2 >> shift], tab[x3 >> shift]};
+  const BucketRecord r[4] = {record_of<kLds>(set, toff, bmask, x0), record_of<kLds>(set, toff, bmask, x1),
+                             record_of<kLds>(set, toff, bmask, x2), record_of<kLds>(set, toff, bmask, x3)};
   // keep the reads ahead of the branches below (an operand-only asm, no code)
   __asm__ volatile("" ::"v"(r[1].thr_abs), "v"(r[1].rows), "v"(r[1].cols), "v"(r[1].lens), "v"(r[2].thr_abs),
                    "v"(r[2].rows), "v"(r[2].cols), "v"(r[2].lens), "v"(r[3].thr_abs), "v"(r[3].rows), "v"(r[3].cols),
@@ -275,18 +293,18 @@ __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ tab, ui
 }
 
 // The samples of one Philox block with each bucket record loaded only when
-// the edge still needs letters (same samples, same order as sample4).  For a
-// table read from L2, where the continuation of an edge usually needs one or
+// the edge still needs letters (same samples, same order as sample4), for a
+// table set in global memory.  For a table read from L2, where the continuation of an edge usually needs one or
 // two of the block's four samples, this saves the unused random reads.
 template <typename Acc>
-__device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ tab, uint32_t shift, uint32_t k,
-                                            uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc,
+__device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ set, uint32_t toff, uint32_t bmask,
+                                            uint32_t k, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc,
                                             uint32_t& filled, const KronPow* kpow) {
   const uint32_t x[4] = {x0, x1, x2, x3};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (filled >= k) break;
-    const BucketRecord q = tab[x[i] >> shift];
+    const BucketRecord q = record_of<false>(set, toff, bmask, x[i]);
     const bool own = x[i] < q.thr_abs;
     const uint32_t len = own ? (q.lens & 0xFFFFu) : (q.lens >> 16);
     acc.append(own ? (q.rows & 0xFFFFu) : (q.rows >> 16), own ? (q.cols & 0xFFFFu) : (q.cols >> 16), len, filled, k,
@@ -483,7 +501,9 @@ constexpr uint32_t queue_bytes() {
 // Each edge's first counter block is drawn in block order; an edge with k
 // letters is stored (or reduced) at once, from registers, and the others
 // join the wave's queue, which is finished 64 edges at a time (counter
-// blocks 1, 2, ...) and emptied at the end of the tile.
+// blocks 1, 2, ...) and emptied at the end of the tile.  kLazy: the table
+// set is read from global memory (L2), where a continued edge loads a
+// record only for a sample it uses; otherwise it sits at LDS address 0.
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
           bool kLazy = false, bool kTwo = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
@@ -495,8 +515,10 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t last = I.edge_begin + (I.m - 1);  // last edge, no overflow
   // edge e reads table e mod P; blocks start at multiples of 64 and P divides
-  // 64, so in the first pass that is the lane's table for the whole run
-  const BucketRecord* __restrict__ tab_lane = tab + (lane & I.table_mask) * I.n_buckets;
+  // 64, so in the first pass that is the lane's table for the whole run (at
+  // byte offset toff_lane of the set)
+  const uint32_t tbytes = I.n_buckets * static_cast<uint32_t>(sizeof(BucketRecord));
+  const uint32_t toff_lane = (lane & I.table_mask) * tbytes;
   Epilogue<Id> E;
   if (kGeneral) E = make_epilogue<Id>(I);
   const Id src_prefix = static_cast<Id>(kGeneral ? I.src_prefix : 0);
@@ -558,14 +580,14 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         uint32_t filled = entry & 63u;
         const uint64_t e = ((I.first_block + t0 + (slot >> 6) * stride) << 6) + (slot & 63u);
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
-        const BucketRecord* __restrict__ tab_e = tab + ((slot & 63u) & I.table_mask) * I.n_buckets;
+        const uint32_t toff_e = ((slot & 63u) & I.table_mask) * tbytes;
         for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
           if (kLazy)
-            sample_lazy(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+            sample_lazy(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
           else
-            sample4(tab_e, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+            sample4<Acc, !kLazy>(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
         }
         finish_edge(acc, e, [&](Id s, Id d) {
           static_cast<Id*>(I.out_src)[e - I.edge_begin] = s;
@@ -618,9 +640,9 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
                  y3 = I.ctr3;
         philox10(y0, y1, y2, y3, I.key0, I.key1);
         if (kLazy)
-          sample_lazy(tab_lane, I.shift, I.k, y0, y1, y2, y3, acc, filled, kpow);
+          sample_lazy(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
         else
-          sample4(tab_lane, I.shift, I.k, y0, y1, y2, y3, acc, filled, kpow);
+          sample4<Acc, !kLazy>(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
       }
     };
     auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole, auto sure, auto desc) {
@@ -630,7 +652,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       uint32_t x0, x1, x2, x3;
       philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1, x0, x1,
                      x2, x3);
-      sample4<Acc, decltype(sure)::value>(tab_lane, I.shift, I.k, x0, x1, x2, x3, acc, filled, kpow);
+      sample4<Acc, !kLazy, decltype(sure)::value>(tab, toff_lane, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
       second_block(base, acc, filled);
       settle(j, base, acc, filled, decltype(whole)::value || ((amask >> lane) & 1ull), j * step, desc);
     };
@@ -645,7 +667,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       philox10_first(static_cast<uint32_t>(base) + lane, static_cast<uint32_t>(base >> 32), I.ctr3, I.key0, I.key1,
                      x[0], x[1], x[2], x[3]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) r[i] = tab_lane[x[i] >> I.shift];
+      for (int i = 0; i < 4; ++i) r[i] = record_of<!kLazy>(tab, toff_lane, I.bmask, x[i]);
     };
     auto consume = [&](const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc, uint32_t& filled) {
       if constexpr (Acc::kKron)
@@ -720,21 +742,23 @@ __device__ __forceinline__ void stage_table(const BucketRecord* src_rec, uint32_
 // launch stores the plain ids and keeps none of their parameters live.
 template <typename Acc, bool kLds, bool kReduce, bool kGeneral, bool kDegree = false, bool kTwo = false>
 __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
+  // all LDS is dynamic: [table set | queues | misc], the set at address 0
   extern __shared__ __align__(16) unsigned char s_mem[];
-  __shared__ unsigned long long s_xor[kWaves];
+  unsigned char* misc = s_mem + P.L.lds_table + P.L.waves * P.L.wave_bytes;
+  unsigned long long* s_xor = reinterpret_cast<unsigned long long*>(misc);  // kWaves words
   using Packed = typename Acc::Packed;
   const KronPow* kpow = nullptr;
   if constexpr (Acc::kKron) {
-    __shared__ KronPow s_kpow;
+    KronPow* s_kpow = reinterpret_cast<KronPow*>(misc + kWaves * sizeof(unsigned long long));
     if (threadIdx.x == 0) {
       uint64_t x = 1;
       for (int i = 0; i < 16; ++i, x *= P.I.kron_k) {
-        s_kpow.pow[i] = x;
-        s_kpow.magic[i] = static_cast<uint32_t>((1ull << 32) / x + 1);  // used for 2 <= x < 2^15 only
+        s_kpow->pow[i] = x;
+        s_kpow->magic[i] = static_cast<uint32_t>((1ull << 32) / x + 1);  // used for 2 <= x < 2^15 only
       }
     }
     __syncthreads();
-    kpow = &s_kpow;
+    kpow = s_kpow;
   }
   const BucketRecord* tab = P.I.records;
   if (kLds) {
@@ -770,8 +794,9 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
 // item's blocks.
 template <typename Acc, bool kLds, bool kDigest, bool kGeneral>
 __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch B) {
+  // all LDS is dynamic: [table | queues | misc], the table at address 0
   extern __shared__ __align__(16) unsigned char s_mem[];
-  __shared__ uint32_t s_item;
+  uint32_t& s_item = *reinterpret_cast<uint32_t*>(s_mem + B.L.lds_table + B.L.waves * B.L.wave_bytes);
   using Packed = typename Acc::Packed;
   const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   Packed* qacc = reinterpret_cast<Packed*>(s_mem + B.L.lds_table + wave_in_wg * B.L.wave_bytes);
@@ -846,7 +871,11 @@ const DeviceLimits& limits() {
 constexpr uint32_t kWaveChoices[] = {16, 12, 8};
 constexpr uint32_t kMinWaves = 8;
 
-bool fits_lds(size_t bytes) { return bytes + 1024 <= static_cast<size_t>(limits().lds_per_block); }  // + static LDS
+// LDS bytes after the table and the queues: the reduction's per-wave words
+// and the base-K powers (or a batch's claimed item).
+constexpr size_t kMiscLds = kWaves * sizeof(unsigned long long) + sizeof(KronPow);
+
+bool fits_lds(size_t bytes) { return bytes + kMiscLds <= static_cast<size_t>(limits().lds_per_block); }
 
 // Workgroups of kernel fn resident per CU at `waves` waves and `bytes` of
 // dynamic LDS, from the runtime's occupancy calculator (cached; -1 if the
@@ -887,8 +916,8 @@ TileLayout layout_for(const void* fn, uint32_t buckets, bool lds, size_t* lds_by
   L.waves = 0;
   uint32_t best = 0;
   for (uint32_t w : kWaveChoices) {
-    const size_t bytes = L.lds_table + static_cast<size_t>(w) * L.wave_bytes;
-    if (!fits_lds(bytes)) continue;
+    const size_t bytes = L.lds_table + static_cast<size_t>(w) * L.wave_bytes + kMiscLds;
+    if (bytes > static_cast<size_t>(limits().lds_per_block)) continue;
     int n = resident_groups(fn, w, bytes);
     if (n < 0) n = 1;  // no answer: one workgroup, which the LDS allows
     if (static_cast<uint32_t>(n) * w > best) {
@@ -1034,7 +1063,7 @@ Launch make_launch(const GenerateArgs& a) {
   P.I.records = a.records;
   P.I.n_buckets = a.n_buckets;
   P.I.table_mask = a.n_tables > 1 ? a.n_tables - 1 : 0;
-  P.I.shift = 32u - static_cast<uint32_t>(a.bucket_bits);
+  P.I.bmask = ((1u << a.bucket_bits) - 1u) << 4;
   P.I.k = static_cast<uint32_t>(a.k);
   P.I.key0 = static_cast<uint32_t>(a.seed);
   P.I.key1 = static_cast<uint32_t>(a.seed >> 32);
@@ -1143,7 +1172,18 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
 template <typename F>
 hipError_t allow_full_lds(F* fn) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             limits().lds_per_block - 1024);
+                             limits().lds_per_block);
+}
+
+// A generation kernel: all of its LDS must be dynamic, so that a staged
+// table starts at LDS address 0 (its records are addressed by offset alone).
+template <typename F>
+hipError_t prepare_generation(F* fn) {
+  hipFuncAttributes attr;
+  hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(fn));
+  if (e != hipSuccess) return e;
+  if (attr.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+  return allow_full_lds(fn);
 }
 
 }  // namespace
@@ -1248,47 +1288,47 @@ hipError_t prepare_kernels() {
   if (done) return hipSuccess;
   hipError_t e = hipSuccess;
   const hipError_t r[] = {
-      allow_full_lds(&generate_kernel<Acc32, true, false, false>),
-      allow_full_lds(&generate_kernel<Acc32, false, false, false>),
-      allow_full_lds(&generate_kernel<Acc64, true, false, false>),
-      allow_full_lds(&generate_kernel<Acc64, false, false, false>),
-      allow_full_lds(&generate_kernel<Acc32, true, false, true>),
-      allow_full_lds(&generate_kernel<Acc32, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, true, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc32, true, true, false>),
-      allow_full_lds(&generate_kernel<Acc32, false, true, false>),
-      allow_full_lds(&generate_kernel<Acc64, true, true, false>),
-      allow_full_lds(&generate_kernel<Acc64, false, true, false>),
-      allow_full_lds(&generate_kernel<Acc32, true, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc32, false, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, true, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, false, false, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true, false, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, true, true, true>),
-      allow_full_lds(&generate_batch_kernel<Acc32, false, false, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, false, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc32, false, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc32, false, true, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true, false, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, true, true, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, false, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, false, true>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, true, false>),
-      allow_full_lds(&generate_batch_kernel<Acc64, false, true, true>),
+      prepare_generation(&generate_kernel<Acc32, true, false, false>),
+      prepare_generation(&generate_kernel<Acc32, false, false, false>),
+      prepare_generation(&generate_kernel<Acc64, true, false, false>),
+      prepare_generation(&generate_kernel<Acc64, false, false, false>),
+      prepare_generation(&generate_kernel<Acc32, true, false, true>),
+      prepare_generation(&generate_kernel<Acc32, false, false, true>),
+      prepare_generation(&generate_kernel<Acc64, true, false, true>),
+      prepare_generation(&generate_kernel<Acc64, false, false, true>),
+      prepare_generation(&generate_kernel<Acc32, true, true, false>),
+      prepare_generation(&generate_kernel<Acc32, false, true, false>),
+      prepare_generation(&generate_kernel<Acc64, true, true, false>),
+      prepare_generation(&generate_kernel<Acc64, false, true, false>),
+      prepare_generation(&generate_kernel<Acc32, true, false, false, true>),
+      prepare_generation(&generate_kernel<Acc32, false, false, false, true>),
+      prepare_generation(&generate_kernel<Acc64, true, false, false, true>),
+      prepare_generation(&generate_kernel<Acc64, false, false, false, true>),
+      prepare_generation(&generate_batch_kernel<Acc32, true, false, false>),
+      prepare_generation(&generate_batch_kernel<Acc32, true, false, true>),
+      prepare_generation(&generate_batch_kernel<Acc32, true, true, false>),
+      prepare_generation(&generate_batch_kernel<Acc32, true, true, true>),
+      prepare_generation(&generate_batch_kernel<Acc32, false, false, false>),
+      prepare_generation(&generate_batch_kernel<Acc32, false, false, true>),
+      prepare_generation(&generate_batch_kernel<Acc32, false, true, false>),
+      prepare_generation(&generate_batch_kernel<Acc32, false, true, true>),
+      prepare_generation(&generate_batch_kernel<Acc64, true, false, false>),
+      prepare_generation(&generate_batch_kernel<Acc64, true, false, true>),
+      prepare_generation(&generate_batch_kernel<Acc64, true, true, false>),
+      prepare_generation(&generate_batch_kernel<Acc64, true, true, true>),
+      prepare_generation(&generate_batch_kernel<Acc64, false, false, false>),
+      prepare_generation(&generate_batch_kernel<Acc64, false, false, true>),
+      prepare_generation(&generate_batch_kernel<Acc64, false, true, false>),
+      prepare_generation(&generate_batch_kernel<Acc64, false, true, true>),
       allow_full_lds(&hist_partial_kernel),
-      allow_full_lds(&generate_kernel<KronAcc<uint32_t>, true, false, false>),
-      allow_full_lds(&generate_kernel<KronAcc<uint64_t>, true, false, false>),
-      allow_full_lds(&generate_kernel<Acc32, true, false, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc32, false, false, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, true, false, false, false, true>),
-      allow_full_lds(&generate_kernel<Acc64, false, false, false, false, true>),
-      allow_full_lds(&generate_kernel<KronAcc<uint32_t>, true, false, false, false, true>),
-      allow_full_lds(&generate_kernel<KronAcc<uint64_t>, true, false, false, false, true>)};
+      prepare_generation(&generate_kernel<KronAcc<uint32_t>, true, false, false>),
+      prepare_generation(&generate_kernel<KronAcc<uint64_t>, true, false, false>),
+      prepare_generation(&generate_kernel<Acc32, true, false, false, false, true>),
+      prepare_generation(&generate_kernel<Acc32, false, false, false, false, true>),
+      prepare_generation(&generate_kernel<Acc64, true, false, false, false, true>),
+      prepare_generation(&generate_kernel<Acc64, false, false, false, false, true>),
+      prepare_generation(&generate_kernel<KronAcc<uint32_t>, true, false, false, false, true>),
+      prepare_generation(&generate_kernel<KronAcc<uint64_t>, true, false, false, false, true>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

@@ -485,7 +485,7 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
     I.records = V.records;
     I.n_buckets = static_cast<uint32_t>(info.n_buckets);
     I.table_mask = 0;
-    I.shift = 32u - static_cast<uint32_t>(info.bucket_bits);
+    I.bmask = ((1u << info.bucket_bits) - 1u) << 4;
     I.k = static_cast<uint32_t>(kk);
     I.key0 = static_cast<uint32_t>(seed);
     I.key1 = static_cast<uint32_t>(seed >> 32);

@@ -16,9 +16,14 @@ constexpr int kBuildThreads = 1024;    // one workgroup builds one table
 constexpr int kMaxClasses = 4096;      // letter-count classes of depth < 15: 3060
 constexpr uint64_t kMaxBound = 1ull << 24;
 
-// Hot-path bucket record, 16 bytes (one ds_read_b128):
-//   x  thr_abs: bucket i keeps its own item for x < i*C + T_i (a full bucket
-//      stores i*C and an alias equal to itself, so the test never matters)
+// Hot-path bucket record, 16 bytes (one ds_read_b128).  A sample x selects
+// bucket i = (x >> 4) mod nb, so its record sits at byte offset
+// x & ((nb - 1) << 4) of the table, and keeps the own item when the other
+// bits of x, read as f = (x >> (b + 4)) * 16 + (x mod 16), are below T_i:
+//   x  thr_abs: T_i spread around the bucket bits, (T_i & ~15) << b | i << 4
+//      | (T_i & 15), so that x < thr_abs exactly when f < T_i (the bucket
+//      bits of both are i); a full bucket stores i << 4 and an alias equal
+//      to itself, so the test never matters
 //   y  rows: own item's row value in bits 15..0, the alias item's in 31..16
 //   z  cols: the same for the column values
 //   w  lens: own length in bits 15..0, the alias's in 31..16
@@ -103,7 +108,7 @@ struct GenInst {
   const BucketRecord* records;  // table_mask + 1 tables of n_buckets records, back to back
   uint32_t n_buckets;
   uint32_t table_mask;          // edge e reads table e & table_mask (perturbed sets; 0 otherwise)
-  uint32_t shift;  // 32 - b
+  uint32_t bmask;               // (n_buckets - 1) << 4: a sample's record offset within its table
   uint32_t k;
   uint32_t key0, key1;
   uint64_t edge_begin, m;

@@ -479,7 +479,7 @@ int issue_round(rmat_server* s, bool* launched) {
     I.records = sl.view.records;
     I.n_buckets = static_cast<uint32_t>(q->shape.n_buckets);
     I.table_mask = 0;
-    I.shift = 32u - static_cast<uint32_t>(q->shape.bucket_bits);
+    I.bmask = ((1u << q->shape.bucket_bits) - 1u) << 4;
     I.k = static_cast<uint32_t>(q->r.k);
     I.key0 = static_cast<uint32_t>(q->r.seed);
     I.key1 = static_cast<uint32_t>(q->r.seed >> 32);

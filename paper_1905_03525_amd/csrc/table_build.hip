@@ -499,7 +499,9 @@ __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_
       const uint32_t a = J.alias[i];
       const uint32_t ls = J.item_len[i], la = J.item_len[a];
       BucketRecord r;
-      r.thr_abs = static_cast<uint32_t>(static_cast<uint64_t>(i) * C + (a == i ? 0u : J.thr[i]));
+      // T < C = 2^32 / nb when the alias differs, so (T & ~15) * nb < 2^32
+      const uint32_t T = J.thr[i];
+      r.thr_abs = a == i ? i << 4 : ((T & ~15u) * nb) | (i << 4) | (T & 15u);
       if (reverse) {
         r.rows = reversed_bits(ls, J.item_row[i]) | (reversed_bits(la, J.item_row[a]) << 16);
         r.cols = reversed_bits(ls, J.item_col[i]) | (reversed_bits(la, J.item_col[a]) << 16);

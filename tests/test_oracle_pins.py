@@ -270,8 +270,8 @@ def test_alias_sampling_law_is_exact():
     t = oracle.build_table(*_dirichlet(21), 8, 20, oracle.VARIABLE)
     x = np.arange(0, 2**32, 4099, dtype=np.uint64)  # a lattice of words ...
     b = t.bucket_bits
-    bucket = (x >> np.uint64(32 - b)).astype(np.int64)
-    f = (x & np.uint64(t.capacity - 1)).astype(np.int64)
+    bucket = ((x >> np.uint64(4)) & np.uint64(t.n_buckets - 1)).astype(np.int64)
+    f = (((x >> np.uint64(b + 4)) << np.uint64(4)) | (x & np.uint64(15))).astype(np.int64)
     item = np.where(f < t.thr[bucket], bucket, t.alias[bucket])
     freq = np.bincount(item, minlength=t.n_buckets) / len(x)
     # ... whose frequencies match w / 2^32 up to the lattice's resolution
@@ -293,8 +293,9 @@ def _strings_edge(t, seed, e):
             words = oracle.philox4x32_10([e & 0xFFFFFFFF, e >> 32, s // 4, 0], [seed & 0xFFFFFFFF, seed >> 32])
         x = int(words[s % 4])
         s += 1
-        bucket = x >> (32 - t.bucket_bits)
-        f = x % t.capacity
+        # bucket: the b bits above the lowest four; f: the other bits, in order
+        bucket = (x >> 4) % t.n_buckets
+        f = (x >> (t.bucket_bits + 4)) * 16 + x % 16
         item = bucket if f < int(t.thr[bucket]) else int(t.alias[bucket])
         for letter in rm.letters_of(int(t.code[item]), int(t.length[item])):
             rs += str(rm.LETTER_BITS[letter][0])
