@@ -293,10 +293,11 @@ __device__ __forceinline__ void sample4(const BucketRecord* __restrict__ set, ui
 }
 
 // The samples of one Philox block with each bucket record loaded only when
-// the edge still needs letters (same samples, same order as sample4), for a
-// table set in global memory.  For a table read from L2, where the continuation of an edge usually needs one or
-// two of the block's four samples, this saves the unused random reads.
-template <typename Acc>
+// the edge still needs letters (same samples, same order as sample4).  The
+// continuation of an edge usually needs one or two of a block's four
+// samples, so this saves the unused random reads: line fetches from L2 for a
+// table in global memory, LDS reads (and their energy) for one in LDS.
+template <typename Acc, bool kLds>
 __device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ set, uint32_t toff, uint32_t bmask,
                                             uint32_t k, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, Acc& acc,
                                             uint32_t& filled, const KronPow* kpow) {
@@ -304,7 +305,7 @@ __device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ set
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (filled >= k) break;
-    const BucketRecord q = record_of<false>(set, toff, bmask, x[i]);
+    const BucketRecord q = record_of<kLds>(set, toff, bmask, x[i]);
     const bool own = x[i] < q.thr_abs;
     const uint32_t len = own ? (q.lens & 0xFFFFu) : (q.lens >> 16);
     acc.append(own ? (q.rows & 0xFFFFu) : (q.rows >> 16), own ? (q.cols & 0xFFFFu) : (q.cols >> 16), len, filled, k,
@@ -502,8 +503,9 @@ constexpr uint32_t queue_bytes() {
 // letters is stored (or reduced) at once, from registers, and the others
 // join the wave's queue, which is finished 64 edges at a time (counter
 // blocks 1, 2, ...) and emptied at the end of the tile.  kLazy: the table
-// set is read from global memory (L2), where a continued edge loads a
-// record only for a sample it uses; otherwise it sits at LDS address 0.
+// set is read from global memory (L2), where the first pass's second block
+// also loads a record only for a sample it uses; otherwise the set sits at
+// LDS address 0.  Continuations load lazily in both.
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
           bool kLazy = false, bool kTwo = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
@@ -584,10 +586,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
-          if (kLazy)
-            sample_lazy(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
-          else
-            sample4<Acc, !kLazy>(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
+          sample_lazy<Acc, !kLazy>(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
         }
         finish_edge(acc, e, [&](Id s, Id d) {
           static_cast<Id*>(I.out_src)[e - I.edge_begin] = s;
@@ -640,7 +639,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
                  y3 = I.ctr3;
         philox10(y0, y1, y2, y3, I.key0, I.key1);
         if (kLazy)
-          sample_lazy(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
+          sample_lazy<Acc, false>(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
         else
           sample4<Acc, !kLazy>(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
       }
