@@ -44,6 +44,7 @@ CASES = [
     (G500, 22, 1 << 16, oracle.VARIABLE, 3, 2 ** 33 - 777, 1 << 20, 1),   # L2 table
     ((0.25, 0.25, 0.25, 0.25), 12, 1000, oracle.VARIABLE, 4, 63, 100_001, 2),
     (G500, 1, 100, oracle.VARIABLE, 5, 0, 5000, 1),
+    (G500, 20, 16, oracle.VARIABLE, 6, 3, 200_000, 2),   # most edges need a second counter block
 ]
 
 

@@ -217,6 +217,9 @@ REDUCE_CASES = [
     (SKEW, 64, 8192, oracle.VARIABLE, 5, 2**64 - 40_000, 40_000, 16),
     (G500, 26, 1 << 18, oracle.VARIABLE, 6, 1, 300_000, 15),     # L2 table, one LDS window
     (G500, 26, 4096, oracle.VARIABLE, 7, 2**28 - 1000, 3000, 16),  # across a sub-chunk boundary of a longer call
+    # most edges need a second counter block: the reduction keeps one block
+    # in its first pass, so its queue drains nearly every block
+    (G500, 26, 16, oracle.VARIABLE, 8, 5, 70_000, 12),
 ]
 
 
@@ -309,6 +312,7 @@ EPILOGUE_CASES = [
     (G500, 1, 5, oracle.VARIABLE, 5, 0, 1000, 3, 6),
     (_dirichlet(5), 48, 20_000, oracle.VARIABLE, 17, 10**12, 40_000, 2, 99),
     (G500, 28, 1 << 20, oracle.VARIABLE, 21, 0, 100_000, 3, 4),           # L2 table, 32-bit ids
+    (G500, 26, 16, oracle.VARIABLE, 22, 5, 70_000, 3, 8),                 # mostly two counter blocks, one drawn
 ]
 
 
