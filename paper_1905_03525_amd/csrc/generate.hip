@@ -133,6 +133,7 @@ struct Acc32 {
   using Packed = uint2;
   uint32_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
+  __device__ __forceinline__ void first(uint32_t rowv, uint32_t colv) { row = rowv; col = colv; }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t, uint32_t filled, uint32_t,
                                          const KronPow*) {
     row |= rowv << filled;
@@ -150,6 +151,7 @@ struct Acc64 {
   using Packed = ulonglong2;
   uint64_t row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
+  __device__ __forceinline__ void first(uint32_t rowv, uint32_t colv) { row = rowv; col = colv; }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t, uint32_t filled, uint32_t,
                                          const KronPow*) {
     row |= static_cast<uint64_t>(rowv) << filled;
@@ -175,6 +177,8 @@ struct KronAcc {
   using Packed = typename std::conditional<sizeof(Id) == 4, uint2, ulonglong2>::type;
   Id row, col;
   __device__ __forceinline__ void clear() { row = 0; col = 0; }
+  // an edge's first path when it is taken whole (k is above the longest path)
+  __device__ __forceinline__ void first(uint32_t rowv, uint32_t colv) { row = rowv; col = colv; }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t len, uint32_t filled, uint32_t k,
                                          const KronPow* kpow) {
     const uint32_t take = len < k - filled ? len : k - filled;
@@ -203,8 +207,9 @@ struct KronAcc {
 // records already loaded.  A sample x keeps its bucket's own path when
 // x < thr_abs (its bits other than the bucket's, read in order, are below
 // the threshold T), else takes the alias; each field is the low half-word
-// for the own item, else the high one.  kSure1: the second sample is always used (k > kMaxDepthCap letters
-// cannot come from one path).
+// for the own item, else the high one.  kSure1: an edge's first block
+// (filled = 0) with k > kMaxDepthCap, so the first path is taken whole and
+// the second sample is always used (k letters cannot come from one path).
 template <typename Acc, bool kSure1 = false>
 __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], const BucketRecord (&r)[4], Acc& acc,
                                          uint32_t& filled, const KronPow* kpow) {
@@ -215,7 +220,12 @@ __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], con
     acc.append(half(o, q.rows), half(o, q.cols), len, filled, k, kpow);
     filled += len;
   };
-  take(o0, r[0]);
+  if constexpr (kSure1) {  // the edge's first path: whole, no power of K or cut
+    acc.first(half(o0, r[0].rows), half(o0, r[0].cols));
+    filled = half(o0, r[0].lens);
+  } else {
+    take(o0, r[0]);
+  }
   if (kSure1 || filled < k) {
     take(o1, r[1]);
     if (filled < k) {
@@ -503,9 +513,9 @@ constexpr uint32_t queue_bytes() {
 // letters is stored (or reduced) at once, from registers, and the others
 // join the wave's queue, which is finished 64 edges at a time (counter
 // blocks 1, 2, ...) and emptied at the end of the tile.  kLazy: the table
-// set is read from global memory (L2), where the first pass's second block
-// also loads a record only for a sample it uses; otherwise the set sits at
-// LDS address 0.  Continuations load lazily in both.
+// set is read from global memory (L2); otherwise it sits at LDS address 0.
+// Every block after an edge's first (the first pass's second block, the
+// continuations) loads a record only for a sample the edge uses.
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
           bool kLazy = false, bool kTwo = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
@@ -638,10 +648,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         uint32_t y0 = static_cast<uint32_t>(base) + lane, y1 = static_cast<uint32_t>(base >> 32), y2 = 1u,
                  y3 = I.ctr3;
         philox10(y0, y1, y2, y3, I.key0, I.key1);
-        if (kLazy)
-          sample_lazy<Acc, false>(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
-        else
-          sample4<Acc, !kLazy>(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
+        sample_lazy<Acc, !kLazy>(tab, toff_lane, I.bmask, I.k, y0, y1, y2, y3, acc, filled, kpow);
       }
     };
     auto first_block = [&](uint32_t j, uint64_t base, uint64_t amask, auto whole, auto sure, auto desc) {
