@@ -31,12 +31,14 @@ WORKLOAD = dict(name="rmat_k26_ef16_var4096", a=0.57, b=0.19, c=0.19, d=0.05, k=
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_EDGE = 8  # two uint32 ids written per edge
 # integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one 32-bit op per lane per cycle)
-INT_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_CLOCK_GHZ = 2.4
+INT_PEAK_OPS = 256 * 4 * 16 * PEAK_CLOCK_GHZ * 1e9
 OPS_PER_PHILOX_BLOCK = 40  # 20 products 32x32->64 + 20 three-input XORs (10 rounds)
 OPS_PER_SAMPLE = 11        # shift, compare, 2 selects, row/col split (2), 2 shifts, 2 ORs, add
 OPS_EPILOGUE = 27          # mirror (compare + 2 selects) + per id 3 rounds of (multiply-add, mask, shift, xor)
 OPS_KRON_CUT = 2           # K x K: the last path's two digit values divided by K^i (one multiply-high each)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "generate_k26_ef16_traffic.txt")
+POWER_CLOCK_SUMMARY = os.path.join(ROOT, "profiles", "generate_k26_ef16_power_clock.txt")
 
 
 def samples_per_edge(table_export: dict, k: int):
@@ -527,6 +529,18 @@ def read_traffic(summary: str):
     return float(kv["generate_hbm_bytes"])
 
 
+def read_sustained_clock_ghz(summary: str):
+    """The mean XCD clock (GHz) that amd-smi sampled while the k = 26
+    generation ran back to back (the chip's power limit holds it below the
+    rated clock), or None if the summary is missing."""
+    if not os.path.exists(summary):
+        return None
+    for ln in open(summary):
+        if ln.startswith("mean_gfx_clock_MHz:"):
+            return float(ln.split(":", 1)[1].split()[0]) / 1e3
+    return None
+
+
 def summarize_main(argv) -> int:
     mode = argv[0] if argv else ""
     if mode == "trace" and len(argv) == 4:
@@ -791,6 +805,7 @@ def main():
     tb.close()
 
     traffic = read_traffic(TRAFFIC_SUMMARY)
+    clock_ghz = read_sustained_clock_ghz(POWER_CLOCK_SUMMARY)
     value = m * args.steps / wall
     ops_per_edge = eb * OPS_PER_PHILOX_BLOCK + en * OPS_PER_SAMPLE
     achieved_ops = ops_per_edge * m / avg_kern_s
@@ -823,7 +838,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": INT_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved_ops / INT_PEAK_OPS,
                      "ops_per_edge": ops_per_edge,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # the same peak at the clock the power limit leaves on this kernel
+                     "sustained_clock_ghz": clock_ghz,
+                     "frac_at_sustained_clock": (achieved_ops / (INT_PEAK_OPS * clock_ghz / PEAK_CLOCK_GHZ)
+                                                 if clock_ghz else None)},
     }
     print(f"k=26 steps done: {out['generate_kernel_ms']:.3f} ms per generation", file=sys.stderr, flush=True)
     # the measured store-only stream on this device: the achievable write
