@@ -144,7 +144,7 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
 def batched_vs_plain(R, reps: int = 3) -> dict:
     """The 512-instance workload: one hipGraph launch of the batch (all 512
     table builds and every instance's edges) against 512 plain
-    rmat_build_table + rmat_generate_async calls on one stream, both timed by
+    rmat_build_table_async + rmat_generate_async calls on one stream, both timed by
     the host clock from the first call to the final synchronisation.  The
     autotuned bounds are also compared, as graph launches, with 4096 and
     with 8192 for every instance."""
@@ -161,7 +161,8 @@ def batched_vs_plain(R, reps: int = 3) -> dict:
     def plain():
         tables = []
         for p in insts:
-            t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+            t = R.rmat_build_table_async(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"],
+                                         stream)
             R.rmat_generate_async(t, p["seed"], 0, p["m"], p["out_src"], p["out_dst"], stream)
             tables.append(t)
         torch.cuda.synchronize()
@@ -232,7 +233,7 @@ def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0
     through the request server (200 GB output arena, device table cache,
     continuous batching), outputs released as each request completes.  The
     same requests are then generated one after another by plain
-    rmat_build_table + rmat_generate_async calls.  pool > 0: parameters from
+    rmat_build_table_async + rmat_generate_async calls.  pool > 0: parameters from
     that many pre-drawn sets, so the table cache can hit."""
     import torch
     from paper_1905_03525_amd import workloads
@@ -268,7 +269,7 @@ def served_vs_plain(R, window_s: float, reading: str = "A", rate: float = 2000.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i, p in enumerate(reqs):
-        t = R.rmat_build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+        t = R.rmat_build_table_async(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"], stream)
         R.rmat_generate_async(t, p["seed"], 0, p["m"], src, dst, stream)
         torch.cuda.synchronize()
         t.close()
@@ -769,7 +770,9 @@ def main():
     dst = torch.empty(m, dtype=torch.int32, device="cuda")
 
     def step(events=None):
-        t = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+        # the table is built on the device on the same stream, then the edges
+        # generated from it: the host waits for neither
+        t = R.rmat_build_table_async(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE, stream)
         if events is not None:
             events[0].record(stream)
         R.rmat_generate_async(t, w["seed"], 0, m, src, dst, stream)

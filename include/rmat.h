@@ -106,6 +106,27 @@ int rmat_build_table(double a, double b, double c, double d, int k,
                      uint64_t table_bound, int path_mode, rmat_table_t* out);
 
 /*
+ * rmat_build_table without waiting: validates and sizes on the host (the
+ * same errors), allocates the table, enqueues its device build on `stream`
+ * (a hipStream_t; NULL = the null stream) and returns.  The build's working
+ * arrays belong to the table (device_bytes counts them, about 24 bytes per
+ * bucket beside the table's 36), so builds on different streams may overlap.
+ * Work on the table is ordered after the build: a generation call on any
+ * stream waits for it on the device (no host wait), and rmat_table_info,
+ * rmat_table_export and the partitioned calls wait for it on the host.  The
+ * table's shape fields are known at once; its length statistics (min_len,
+ * max_len, expected_len) once rmat_table_info has waited.  Until the build
+ * is known to be finished, a generation draws one counter block per edge in
+ * its first pass (the same edges as with two).  A build that fails on the
+ * device (RMAT_EINVAL for parameters inside the sum tolerance whose
+ * largest-remainder residual is out of range) leaves terminating records;
+ * the failure is returned by rmat_table_info and by every later call on the
+ * table except rmat_free_table.  rmat_free_table waits for a running build.
+ */
+int rmat_build_table_async(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                           void* stream, rmat_table_t* out);
+
+/*
  * Table of a K x K stochastic Kronecker initiator (Sec. 3 generalizations):
  * P holds K^2 probabilities, row-major (cell (i, j) = letter K i + j: row
  * digit i, column digit j), each >= 0, summing to 1 within 1e-9; 2 <= K <= 16;
@@ -151,7 +172,8 @@ int rmat_table_export_member(rmat_table_t t, int i, void* host_buf, size_t nbyte
  * make sure no generation that uses it is still running. */
 int rmat_free_table(rmat_table_t t);
 
-/* Fills *out with the table's shape and statistics (host only, no sync). */
+/* Fills *out with the table's shape and statistics (host only; waits for an
+ * asynchronous build first, and returns its failure). */
 int rmat_table_info(rmat_table_t t, rmat_info* out);
 
 /*

@@ -7,6 +7,7 @@ from .rmat import (RMAT_EDEVICE, RMAT_EINVAL, RMAT_ENOMEM, RMAT_ERANGE, RMAT_FIX
                    generate_edges, generate_partition, id_dtype, load, make_instances, make_request, rmat_batch_autotune,
                    rmat_batch_check, rmat_batch_create, rmat_batch_enqueue, rmat_batch_free, rmat_batch_get_info,
                    rmat_batch_launch_graph, rmat_batch_table_export, rmat_batch_table_info, rmat_build_table,
+                   rmat_build_table_async,
                    rmat_kron_build_table, rmat_build_perturbed_table, rmat_table_export_member,
                    rmat_free_table, rmat_generate, rmat_generate_async, rmat_generate_ex_async, rmat_generate_partition, rmat_generate_reduce_async, rmat_generate_reduce_noalloc_async,
                    rmat_generate_degrees_async, rmat_degree_distribution_async,

@@ -28,6 +28,12 @@ struct rmat_table {
   double q[4];                 // a, b, c, d as given
   std::vector<rmat::TableView> members;  // a perturbed set's tables (empty for one table)
   double p_second = 0.0;       // probability that an edge needs more than four samples
+  // an asynchronous build: until finalize_table() has waited for `built`
+  // and read the device statistics, info's min/max/expected length and
+  // p_second are unknown
+  bool pending = false;
+  int build_status = RMAT_OK;  // a failed asynchronous build, once known
+  hipEvent_t built = nullptr;
 };
 
 namespace rmat {
@@ -257,6 +263,42 @@ int adopt_table(const rmat_info& info, const double q[4], int kron_K, const Tabl
   return RMAT_OK;
 }
 
+// The statistics of an asynchronous build, once: waits for its event, takes
+// min/max/expected length and p_second, and records a failed build (whose
+// records are the terminating sentinels) as the table's status.
+int finalize_table(rmat_table* t) {
+  if (!t->pending) return t->build_status;
+  hipError_t e = hipEventSynchronize(t->built);
+  BuildStats st;
+  if (e == hipSuccess) e = hipMemcpy(&st, t->v.stats, sizeof(st), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "table build");
+  t->pending = false;
+  if (st.error != 0) {
+    t->build_status = st.error == kBuildResidual ? RMAT_EINVAL : RMAT_EDEVICE;
+    return set_error(t->build_status, "table build failed on the device (code %d)", st.error);
+  }
+  t->info.min_len = st.min_len;
+  t->info.max_len = st.max_len;
+  t->info.expected_len = static_cast<double>(st.sum_wl) / 4294967296.0;
+  t->p_second = p_second_block(st, static_cast<int>(t->info.k));
+  return RMAT_OK;
+}
+
+// Orders work on `stream` after a table's build: a finished asynchronous
+// build is finalized (no wait); one still running makes the stream wait for
+// its event.  Returns the table's status (a failed build is an error).
+int order_after_build(rmat_table* t, hipStream_t stream) {
+  if (t->pending) {
+    const hipError_t q = hipEventQuery(t->built);
+    if (q == hipSuccess) return finalize_table(t);
+    if (q != hipErrorNotReady) return hip_fail(q, "table build");
+    const hipError_t e = hipStreamWaitEvent(stream, t->built, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(table build)");
+    return RMAT_OK;
+  }
+  return t->build_status;
+}
+
 // SplitMix64 [Steele, Lea, Flood, OOPSLA'14]: state advanced by the golden
 // gamma, output mixed by two multiply-xorshift steps.
 uint64_t splitmix64(uint64_t& state) {
@@ -323,8 +365,12 @@ hipError_t build_scratch(int device, uint64_t bytes, void** out) {
 }
 }  // namespace
 
-static int rmat_build_table_body(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
-                                 rmat_table_t* out) {
+// A synchronous build waits for the device and reads the statistics at
+// once, using the per-device scratch buffer; an asynchronous one launches on
+// `stream` with working arrays of its own in the table's allocation (builds
+// on different streams may overlap), records an event and returns.
+static int build_table_common(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                              bool async, hipStream_t stream, rmat_table_t* out) {
   g_err[0] = '\0';
   if (!out) return set_error(RMAT_EINVAL, "out is NULL");
   *out = nullptr;
@@ -337,23 +383,54 @@ static int rmat_build_table_body(double a, double b, double c, double d, int k, 
   rmat_table* t = new (std::nothrow) rmat_table();
   if (!t) return set_error(RMAT_ENOMEM, "host allocation of the table handle failed");
   if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
-  const uint64_t tb = rmat::table_bytes(S);
-  hipError_t e = hipMalloc(&t->d_mem, tb);
-  if (e != hipSuccess) {
+  auto release = [t]() {
+    if (t->built) (void)hipEventDestroy(t->built);
+    if (t->d_mem) (void)hipFree(t->d_mem);
     delete t;
+  };
+  const uint64_t tb = rmat::table_bytes(S);
+  // an asynchronous build keeps its working arrays behind the table
+  const uint64_t scratch_off = align_up(tb, 256);
+  hipError_t e = hipMalloc(&t->d_mem, async ? scratch_off + rmat::scratch_bytes(S) : tb);
+  if (e != hipSuccess) {
+    t->d_mem = nullptr;
+    release();
     return rmat::hip_fail(e, "hipMalloc(table)");
   }
   t->v = rmat::place_table(static_cast<char*>(t->d_mem), S);
+  std::memcpy(t->q, q, sizeof(t->q));
+  if (async) {
+    e = hipEventCreateWithFlags(&t->built, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      t->built = nullptr;
+      release();
+      return rmat::hip_fail(e, "hipEventCreate(table build)");
+    }
+    rmat::BuildJob job;
+    rmat::fill_job(&job, q, k, path_mode, S, t->v, static_cast<char*>(t->d_mem) + scratch_off);
+    e = rmat::launch_table_build_one(job, stream);
+    if (e == hipSuccess) e = hipEventRecord(t->built, stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(stream);  // nothing of this build may still run when its memory goes
+      release();
+      return rmat::hip_fail(e, "table build launch");
+    }
+    // shape-derived fields now; the statistics when the build is finalized
+    const rmat::BuildStats none{};
+    rmat::fill_info(&t->info, k, path_mode, table_bound, S, none, scratch_off + rmat::scratch_bytes(S));
+    t->pending = true;
+    *out = t;
+    return RMAT_OK;
+  }
   rmat::BuildStats stats;
   {
     // the build's working arrays come from a per-device buffer kept between
-    // builds (builds are synchronous and serialised here)
+    // synchronous builds (serialised here)
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     void* scratch = nullptr;
     e = build_scratch(t->device, rmat::scratch_bytes(S), &scratch);
     if (e != hipSuccess) {
-      (void)hipFree(t->d_mem);
-      delete t;
+      release();
       return rmat::hip_fail(e, "hipMalloc(build scratch)");
     }
     rmat::BuildJob job;
@@ -363,27 +440,31 @@ static int rmat_build_table_body(double a, double b, double c, double d, int k, 
     if (e == hipSuccess) e = hipMemcpy(&stats, t->v.stats, sizeof(stats), hipMemcpyDeviceToHost);
   }
   if (e != hipSuccess) {
-    (void)hipFree(t->d_mem);
-    delete t;
+    release();
     return rmat::hip_fail(e, "table build");
   }
   if (stats.error != 0) {
-    (void)hipFree(t->d_mem);
-    delete t;
+    release();
     return set_error(stats.error == rmat::kBuildResidual ? RMAT_EINVAL : RMAT_EDEVICE,
                      "table build failed on the device (code %d)", stats.error);
   }
 
   rmat::fill_info(&t->info, k, path_mode, table_bound, S, stats, tb);
   t->p_second = rmat::p_second_block(stats, k);
-  std::memcpy(t->q, q, sizeof(t->q));
   *out = t;
   return RMAT_OK;
 }
 
 int rmat_build_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
                      rmat_table_t* out) {
-  RMAT_GUARD("rmat_build_table", rmat_build_table_body(a, b, c, d, k, table_bound, path_mode, out));
+  RMAT_GUARD("rmat_build_table",
+             build_table_common(a, b, c, d, k, table_bound, path_mode, false, nullptr, out));
+}
+
+int rmat_build_table_async(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
+                           void* stream, rmat_table_t* out) {
+  RMAT_GUARD("rmat_build_table_async", build_table_common(a, b, c, d, k, table_bound, path_mode, true,
+                                                          static_cast<hipStream_t>(stream), out));
 }
 
 static int rmat_build_perturbed_table_body(double a, double b, double c, double d, int k, uint64_t table_bound,
@@ -489,6 +570,7 @@ int rmat_build_perturbed_table(double a, double b, double c, double d, int k, ui
 int rmat_table_export_member(rmat_table_t t, int i, void* host_buf, size_t nbytes) {
   g_err[0] = '\0';
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (int rc = rmat::finalize_table(t)) return rc;
   if (i < 0 || static_cast<uint32_t>(i) >= t->info.n_tables)
     return set_error(RMAT_EINVAL, "member %d outside 0..%u", i, t->info.n_tables - 1);
   const rmat::TableView& V = t->members.empty() ? t->v : t->members[static_cast<size_t>(i)];
@@ -498,7 +580,10 @@ int rmat_table_export_member(rmat_table_t t, int i, void* host_buf, size_t nbyte
 int rmat_free_table(rmat_table_t t) {
   g_err[0] = '\0';
   if (!t) return RMAT_OK;
+  // an asynchronous build still running must end before its memory goes
+  if (t->built) (void)hipEventSynchronize(t->built);
   if (t->d_reduce) (void)hipFree(t->d_reduce);
+  if (t->built) (void)hipEventDestroy(t->built);
   hipError_t e = hipFree(t->d_mem);
   delete t;
   if (e != hipSuccess) return rmat::hip_fail(e, "hipFree(table)");
@@ -508,6 +593,8 @@ int rmat_free_table(rmat_table_t t) {
 int rmat_table_info(rmat_table_t t, rmat_info* out) {
   g_err[0] = '\0';
   if (!t || !out) return set_error(RMAT_EINVAL, "NULL table or info pointer");
+  const int rc = rmat::finalize_table(t);
+  if (rc) return rc;
   *out = t->info;
   return RMAT_OK;
 }
@@ -515,6 +602,8 @@ int rmat_table_info(rmat_table_t t, rmat_info* out) {
 int rmat_table_export(rmat_table_t t, void* host_buf, size_t nbytes) {
   g_err[0] = '\0';
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  const int rc = rmat::finalize_table(t);
+  if (rc) return rc;
   return rmat::export_table(t->v, t->info.n_buckets, host_buf, nbytes);
 }
 
@@ -522,6 +611,7 @@ static int generate_common(rmat_table_t t, uint64_t seed, uint64_t edge_begin, u
                            void* out_dst, void* stream, bool reduce, int hist_bits, void* d_hist, void* d_xor,
                            int flags = 0, uint64_t scramble_key = 0, bool static_workspace = false) {
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (int rc = rmat::order_after_build(t, static_cast<hipStream_t>(stream))) return rc;
   if (t->info.initiator_k > 2 && (reduce || flags))
     return set_error(RMAT_EINVAL, "a K x K Kronecker table supports plain generation only");
   if (flags & ~(RMAT_UNDIRECTED | RMAT_SCRAMBLE)) return set_error(RMAT_EINVAL, "unknown flags 0x%x", flags);
@@ -624,6 +714,7 @@ int rmat_generate_degrees_async(rmat_table_t t, uint64_t seed, uint64_t edge_beg
                                 void* stream) {
   g_err[0] = '\0';
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (int rc = rmat::order_after_build(t, static_cast<hipStream_t>(stream))) return rc;
   if (t->info.initiator_k > 2) return set_error(RMAT_EINVAL, "out-degrees are for R-MAT tables (K = 2)");
   if (m == 0) return RMAT_OK;
   if (edge_begin + (m - 1) < edge_begin) return set_error(RMAT_ERANGE, "edge_begin + m exceeds 2^64");

@@ -308,6 +308,7 @@ namespace rmat {
 const rmat_info* table_info_of(const rmat_table* t);
 const TableView* table_view_of(const rmat_table* t);
 const double* table_params_of(const rmat_table* t);
+int finalize_table(rmat_table* t);  // waits for an asynchronous build; its status
 }  // namespace rmat
 
 namespace {
@@ -346,6 +347,7 @@ static int rmat_partition_counts_body(rmat_table_t t, uint64_t seed, uint64_t m,
                                       uint32_t row_end, uint64_t* counts) {
   rmat::clear_error();
   if (!t || !counts) return set_error(RMAT_EINVAL, "NULL table or counts");
+  if (int rc0 = rmat::finalize_table(t)) return rc0;
   const rmat_info& info = *rmat::table_info_of(t);
   int rc = check_args(info, m, tile_bits, row_begin, row_end);
   if (rc) return rc;
@@ -388,6 +390,7 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
                                         uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out) {
   rmat::clear_error();
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
+  if (int rc0 = rmat::finalize_table(t)) return rc0;
   const rmat_info& info = *rmat::table_info_of(t);
   int rc = check_args(info, m, tile_bits, row_begin, row_end);
   if (rc) return rc;

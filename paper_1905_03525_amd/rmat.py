@@ -27,7 +27,7 @@ _STATUS = {RMAT_EINVAL: "RMAT_EINVAL", RMAT_ENOMEM: "RMAT_ENOMEM", RMAT_EDEVICE:
            RMAT_ERANGE: "RMAT_ERANGE"}
 
 # Every symbol include/rmat.h declares (checked by the CPU test suite).
-EXPORTED = ["rmat_build_table", "rmat_kron_build_table", "rmat_build_perturbed_table", "rmat_table_export_member", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
+EXPORTED = ["rmat_build_table", "rmat_build_table_async", "rmat_kron_build_table", "rmat_build_perturbed_table", "rmat_table_export_member", "rmat_free_table", "rmat_table_info", "rmat_table_export", "rmat_generate",
             "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async",
             "rmat_generate_reduce_noalloc_async", "rmat_generate_degrees_async",
             "rmat_degree_distribution_async", "rmat_batch_create", "rmat_batch_enqueue",
@@ -125,6 +125,7 @@ def load() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, c_int = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     L.rmat_build_table.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, ctypes.POINTER(vp)]
+    L.rmat_build_table_async.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, vp, ctypes.POINTER(vp)]
     L.rmat_free_table.argtypes = [vp]
     L.rmat_build_perturbed_table.argtypes = [ctypes.c_double] * 4 + [c_int, u64, c_int, c_int, ctypes.c_double, u64,
                                                                       ctypes.POINTER(vp)]
@@ -220,6 +221,14 @@ class Table:
 def rmat_build_table(a: float, b: float, c: float, d: float, k: int, table_bound: int, path_mode: int) -> Table:
     h = ctypes.c_void_p()
     _check(load().rmat_build_table(a, b, c, d, k, table_bound, path_mode, ctypes.byref(h)), "rmat_build_table")
+    return Table(h.value)
+
+
+def rmat_build_table_async(a: float, b: float, c: float, d: float, k: int, table_bound: int, path_mode: int,
+                           stream=None) -> Table:
+    h = ctypes.c_void_p()
+    _check(load().rmat_build_table_async(a, b, c, d, k, table_bound, path_mode, _stream(stream), ctypes.byref(h)),
+           "rmat_build_table_async")
     return Table(h.value)
 
 
