@@ -5,26 +5,31 @@
 // (Sec. 2: the max-priority queue that always expands the most probable path,
 // then a Walker alias table), reached by a data-parallel route:
 //
+//  0. All nodes with the same letter counts share one probability, so every
+//     probability the build needs is one of 3876 classes (depth <= 15),
+//     tabulated once in LDS with the sequential rounding of the definition.
 //  1. The queue expands nodes in a fixed total order (probability descending,
 //     then depth, then base-4 code), and a node never precedes its parent in
 //     that order, so the expanded set is exactly the first t nodes of the
-//     order.  All nodes with the same letter counts share one probability, so
-//     the t-th node is found from at most 3060 letter-count classes (depth
-//     < 15) sorted in LDS, plus a walk over the digits of the codes inside
-//     the last, partly expanded class group.  Expansion is then a test
+//     order.  The t-th node is found by a radix select over the classes'
+//     probability bits weighted by their node counts (stopping once the group
+//     left holds one probability), then a walk over the digits of the codes
+//     inside the last, partly expanded class group.  Expansion is then a test
 //     against that boundary node.  (Sec. 3, Parallelization, notes the same
 //     idea: expand every entry above a probability threshold.)
 //  2. The tree is expanded level by level with block-wide prefix sums;
 //     subtree leaf counts (bottom-up) and leaf offsets (top-down) place every
 //     leaf at its tree-order index without sorting.
 //  3. Weights p * 2^32 are rounded by largest remainders: floors, then a
-//     radix select of the residual's worth of largest fractional parts.
+//     radix select of the residual's worth of largest fractional parts (the
+//     keys in LDS for tables of up to 10240 items).
 //  4. The alias sweep (lights and heavies in index order, the current heavy
 //     paying for each light) is evaluated in closed form from two prefix
 //     sums: light i aliases the first heavy whose cumulative excess reaches
 //     the lights' cumulative deficit before i, and a heavy whose cumulative
 //     excess E falls short of the total deficit keeps C + E - D(i) where
 //     D(i) is the first cumulative deficit above E, aliasing the next heavy.
+//     The binary searches run over LDS for tables of up to 10240 buckets.
 //     Sec. 3 cites a parallel construction of the same kind [HubSan19].
 #include "rmat_internal.h"
 
@@ -77,6 +82,115 @@ __device__ uint64_t block_sum(uint64_t v, uint64_t* s_warp) {
   uint64_t total;
   block_exclusive_scan(v, s_warp, &total);
   return total;
+}
+
+// Exclusive prefix sum over the workgroup of values below 2^kBits: a wave
+// counts the values' bit planes with ballots (no shuffles), the waves' totals
+// pass through LDS (two barriers).  *total gets the sum of all values.
+template <int kBits>
+__device__ __forceinline__ uint32_t block_scan_small(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t s_tot[kWaves];
+  const int wave = threadIdx.x >> 6;
+  uint32_t below = 0, wave_sum = 0;
+#pragma unroll
+  for (int b = 0; b < kBits; ++b) {
+    const uint64_t m = __ballot((v >> b) & 1u);
+    below += __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)) << b;
+    wave_sum += static_cast<uint32_t>(__popcll(m)) << b;
+  }
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) s_tot[wave] = wave_sum;
+  __syncthreads();
+  // lane w < kWaves: the inclusive sum of the totals of waves 0..w
+  uint32_t incl = lane < kWaves ? s_tot[lane] : 0u;
+#pragma unroll
+  for (int d = 1; d < kWaves; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  __syncthreads();
+  *total = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), kWaves - 1));
+  const uint32_t base = wave > 0 ? static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), wave - 1)) : 0u;
+  return base + below;
+}
+
+// Whether the keys of a radix select's current group are all one value,
+// without atomics: each lane tracks the first group key it saw (rep) and
+// whether another differed; a wave writes one verdict (0: no keys, 1: all its
+// keys equal its rep, 2: mixed) and, after a barrier, every thread combines
+// the waves' verdicts.
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  return static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l))) |
+         (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v >> 32), l))) << 32);
+}
+
+__device__ __forceinline__ void vote_uniform(uint64_t rep, bool has, bool differ, uint64_t* s_rep,
+                                             uint32_t* s_state) {
+  const uint64_t hb = __ballot(has);
+  uint32_t state = 0;
+  uint64_t wrep = 0;
+  if (hb != 0) {
+    wrep = readlane_u64(rep, __builtin_ctzll(hb));
+    state = __ballot(differ || (has && rep != wrep)) != 0 ? 2u : 1u;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_state[threadIdx.x >> 6] = state;
+    s_rep[threadIdx.x >> 6] = wrep;
+  }
+}
+
+__device__ __forceinline__ bool group_uniform(const uint64_t* s_rep, const uint32_t* s_state, uint64_t* only) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t st = lane < kWaves ? s_state[lane] : 0u;
+  const uint64_t r = lane < kWaves ? s_rep[lane] : 0;
+  const uint64_t with = __ballot(st != 0);
+  if (with == 0) return false;
+  const uint64_t r0 = readlane_u64(r, __builtin_ctzll(with));
+  *only = r0;
+  return __ballot(st == 2 || (st == 1 && r != r0)) == 0;
+}
+
+// Two exclusive 64-bit prefix sums over the workgroup in one pass (two
+// barriers for both); *ta and *tb get the sums of all a and all b.
+__device__ void block_exclusive_scan2(uint64_t a, uint64_t b, uint64_t* pa, uint64_t* pb, uint64_t* ta,
+                                      uint64_t* tb) {
+  __shared__ uint64_t s_w2[2 * kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t x = a, y = b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t xu = shfl_up_u64(x, d), yu = shfl_up_u64(y, d);
+    if (lane >= d) {
+      x += xu;
+      y += yu;
+    }
+  }
+  if (lane == 63) {
+    s_w2[wave] = x;
+    s_w2[kWaves + wave] = y;
+  }
+  __syncthreads();
+  // lane w < kWaves: the inclusive sums of the totals of waves 0..w
+  uint64_t wx = lane < kWaves ? s_w2[lane] : 0, wy = lane < kWaves ? s_w2[kWaves + lane] : 0;
+#pragma unroll
+  for (int d = 1; d < kWaves; d <<= 1) {
+    const uint64_t xu = shfl_up_u64(wx, d), yu = shfl_up_u64(wy, d);
+    if (lane >= d) {
+      wx += xu;
+      wy += yu;
+    }
+  }
+  __syncthreads();
+  auto lane_u64 = [](uint64_t v, int l) {
+    return static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l))) |
+           (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v >> 32), l)))
+            << 32);
+  };
+  *ta = lane_u64(wx, kWaves - 1);
+  *tb = lane_u64(wy, kWaves - 1);
+  *pa = (wave > 0 ? lane_u64(wx, wave - 1) : 0) + x - a;
+  *pb = (wave > 0 ? lane_u64(wy, wave - 1) : 0) + y - b;
 }
 
 __device__ uint32_t block_min_max(uint32_t vmin, uint32_t vmax, uint32_t* s_u32, uint32_t* out_max) {
@@ -138,15 +252,33 @@ __device__ uint32_t wave_select_desc(const Count* hist, uint64_t* need) {
   return bin;
 }
 
-// Probability of a path from its letter counts: 1.0 times a (na times), then
-// b, c, d, rounding after every product.
-__device__ __forceinline__ double path_prob(const double q[4], int na, int nb, int nc, int nd) {
-  double p = 1.0;
-  for (int i = 0; i < na; ++i) p = __dmul_rn(p, q[0]);
-  for (int i = 0; i < nb; ++i) p = __dmul_rn(p, q[1]);
-  for (int i = 0; i < nc; ++i) p = __dmul_rn(p, q[2]);
-  for (int i = 0; i < nd; ++i) p = __dmul_rn(p, q[3]);
-  return p;
+// Path probabilities by letter-count class.  A path's probability is 1.0
+// times a (na times), then b, c, d, rounding after every product, so it
+// depends only on the class (na, nb, nc, nd); the build tabulates every class
+// of depth <= kMaxDepthCap once, in LDS.  Classes sit in rows, one row per
+// (na, nb, nc) with na + nb + nc <= 15 in lexicographic order, holding
+// nd = 0 .. 15 - na - nb - nc; rows[(na * 16 + nb) * 16 + nc] is the row's
+// first slot.  Along a row each entry is the previous one times d, which is
+// the same rounded product as the chain from 1.0.
+constexpr int kClassRows = 816;     // triples with na + nb + nc <= 15: C(18, 3)
+constexpr int kClassSlots = 3876;   // classes of depth <= 15: C(19, 4)
+static_assert(kClassSlots <= kMaxClasses, "class slots exceed the class arrays");
+static_assert(kMaxDepthCap == 15, "the class rows cover depths up to 15");
+
+__device__ __forceinline__ uint32_t class_slot(const uint16_t* rows, int na, int nb, int nc, int nd) {
+  return rows[(na * 16 + nb) * 16 + nc] + static_cast<uint32_t>(nd);
+}
+
+// Row bits (digit bit 1) and column bits (digit bit 0) of a code, root-most
+// digit most significant: the odd and the even bits of the code, each
+// compacted to consecutive positions.
+__device__ __forceinline__ uint32_t compact_even_bits(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+  x = (x | (x >> 4)) & 0x00FF00FFu;
+  x = (x | (x >> 8)) & 0x0000FFFFu;
+  return x;
 }
 
 // Letter counts of a base-4 code of `depth` digits (a=0, b=1, c=2, d=3).
@@ -159,17 +291,9 @@ __device__ __forceinline__ void letter_counts(uint32_t code, int depth, int n[4]
   n[0] = depth - n[1] - n[2] - n[3];
 }
 
-// Row bits (digit bit 1) and column bits (digit bit 0) of a code, root-most
-// digit most significant.
-__device__ __forceinline__ void split_code(uint32_t code, int depth, uint32_t* row, uint32_t* col) {
-  uint32_t r = 0, c = 0;
-  for (int pos = depth - 1; pos >= 0; --pos) {
-    uint32_t digit = (code >> (2 * pos)) & 3u;
-    r = (r << 1) | (digit >> 1);
-    c = (c << 1) | (digit & 1u);
-  }
-  *row = r;
-  *col = c;
+__device__ __forceinline__ void split_code(uint32_t code, uint32_t* row, uint32_t* col) {
+  *row = compact_even_bits(code >> 1);
+  *col = compact_even_bits(code);
 }
 
 // Binomial coefficient C(n, r), 0 <= n <= 17, computed directly (used once
@@ -199,6 +323,7 @@ __device__ __forceinline__ uint32_t pack_class(int na, int nb, int nc, int nd) {
 }
 __device__ __forceinline__ int class_n(uint32_t key, int x) { return (key >> (4 * x)) & 15; }
 __device__ __forceinline__ int class_depth(uint32_t key) { return key >> 16; }
+constexpr uint32_t kNoClass = 0xFFFF0000u;  // an unused class slot
 
 // Order of the priority queue: does (p1, D1) come strictly before (p2, D2)?
 __device__ __forceinline__ bool class_before(double p1, int d1, double p2, int d2) {
@@ -222,24 +347,6 @@ __device__ __forceinline__ bool node_expanded(const Boundary& B, int mode, int c
   return code <= B.code;
 }
 
-__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t n, uint64_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] <= v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
 // The len low bits of v in reverse order (the first letter of a path, its
 // most significant bit, goes to bit 0).
 __device__ __forceinline__ uint32_t reversed_bits(uint32_t len, uint32_t v) {
@@ -258,7 +365,8 @@ __device__ __forceinline__ uint64_t frac_key(double p, uint64_t* floor_out) {
 // per-node arrays are LDS for trees of up to kLdsNodes expanded nodes and the
 // job's global scratch beyond (one body, inlined for either address space).
 // Returns false on an internal error (*s_error set).
-__device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundary& B, const double q[4], int cap,
+__device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundary& B, const double* prod,
+                                                const uint16_t* rows, int cap,
                                                 uint32_t n, uint32_t* lvl_code, uint8_t* lvl_mask,
                                                 uint32_t* lvl_first, uint32_t* lvl_size, uint32_t* lvl_off,
                                                 uint64_t* s_warp, uint32_t* s_lvl_start, int* s_error) {
@@ -284,13 +392,13 @@ __device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundar
         letter_counts(code, D, cnt);
         for (int x = 0; x < 4; ++x) {
           cnt[x]++;
-          double p = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+          const double p = prod[class_slot(rows, cnt[0], cnt[1], cnt[2], cnt[3])];
           cnt[x]--;
           if (node_expanded(B, 1, cap, 0, p, D + 1, code * 4 + x)) mask |= 1u << x;
         }
       }
-      uint64_t total;
-      uint32_t pos = next + static_cast<uint32_t>(block_exclusive_scan(__popc(mask), s_warp, &total));
+      uint32_t total;
+      uint32_t pos = next + block_scan_small<3>(__popc(mask), &total);
       if (i < end) {
         lvl_mask[i] = static_cast<uint8_t>(mask);
         lvl_first[i] = pos;
@@ -301,7 +409,7 @@ __device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundar
             ++pos;
           }
       }
-      next += static_cast<uint32_t>(total);
+      next += total;
     }
     if (tid == 0) s_lvl_start[D + 2] = next;
     __syncthreads();
@@ -338,12 +446,12 @@ __device__ __forceinline__ bool variable_leaves(const BuildJob& J, const Boundar
           ++f;
         } else {
           uint32_t cc = code * 4 + x, r, c;
-          split_code(cc, L + 1, &r, &c);
+          split_code(cc, &r, &c);
           cnt[x]++;
           J.item_len[cur] = L + 1;
           J.item_row[cur] = r;
           J.item_col[cur] = c;
-          J.item_p[cur] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+          J.item_p[cur] = prod[class_slot(rows, cnt[0], cnt[1], cnt[2], cnt[3])];
           cnt[x]--;
           ++cur;
         }
@@ -365,6 +473,10 @@ struct BuildShared {
   uint64_t* sel_need;
   unsigned long long* len_mass;
   int* error;
+  uint64_t* area;       // LDS free from phase 3 on (or null): the items' keys, then the alias sums
+  uint32_t area_words;  // its size in 8-byte words
+  uint64_t* vote_rep;    // per wave: a key of the select's current group
+  uint32_t* vote_state;  // per wave: none, all equal to it, or mixed
 };
 
 __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_t n, uint32_t nb, uint64_t C,
@@ -375,10 +487,14 @@ __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_
   const bool reverse = J.kron_K <= 2;
   // ---- 3. weights by largest remainders -------------------------------------
   {
+    // the radix passes read every key once per pass: from LDS when the
+    // items fit the area, else recomputed from the items
+    uint64_t* const keys = n <= S.area_words ? S.area : nullptr;
     uint64_t part = 0;
     for (uint32_t j = tid; j < n; j += kBuildThreads) {
       uint64_t fl;
-      frac_key(J.item_p[j], &fl);
+      const uint64_t key = frac_key(J.item_p[j], &fl);
+      if (keys) keys[j] = key;
       part += fl;
     }
     const uint64_t sum = block_sum(part, S.warp);
@@ -397,11 +513,29 @@ __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_
         for (int i = tid; i < 256; i += kBuildThreads) S.hist[i] = 0;
         __syncthreads();
         const uint64_t prefix = *S.sel_prefix;
+        uint64_t rep = 0;
+        bool has = false, differ = false;
         for (uint32_t j = tid; j < n; j += kBuildThreads) {
-          uint64_t fl, key = frac_key(J.item_p[j], &fl);
-          if ((key & pmask) == prefix) atomicAdd(&S.hist[(key >> shift) & 255u], 1u);
+          uint64_t fl;
+          const uint64_t key = keys ? keys[j] : frac_key(J.item_p[j], &fl);
+          if ((key & pmask) == prefix) {
+            atomicAdd(&S.hist[(key >> shift) & 255u], 1u);
+            differ = differ || (has && key != rep);
+            if (!has) rep = key;
+            has = true;
+          }
         }
+        vote_uniform(rep, has, differ, S.vote_rep, S.vote_state);
         __syncthreads();
+        // every key left in the group is the same: it is the threshold, and
+        // *S.sel_need the number of its ties that round up
+        uint64_t only;
+        if (group_uniform(S.vote_rep, S.vote_state, &only)) {
+          __syncthreads();
+          if (tid == 0) *S.sel_prefix = only;
+          __syncthreads();
+          break;
+        }
         if (tid < 64) {
           uint64_t need = *S.sel_need;
           const uint32_t bin = wave_select_desc(S.hist, &need);
@@ -425,8 +559,8 @@ __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_
         key = frac_key(J.item_p[j], &fl);
         tie = (R > 0) && key == tau;
       }
-      uint64_t total;
-      uint64_t rank = tie_base + block_exclusive_scan(tie ? 1u : 0u, S.warp, &total);
+      uint32_t total;
+      const uint64_t rank = tie_base + block_scan_small<1>(tie ? 1u : 0u, &total);
       if (j < n) {
         bool up = (R > 0) && (key > tau || (tie && rank < take_ties));
         J.item_w[j] = fl + (up ? 1u : 0u);
@@ -440,24 +574,34 @@ __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_
 
   // ---- 4. alias table ----------------------------------------------------------
   {
+    // the lights' cumulative deficits by light rank and the heavies'
+    // cumulative excesses by heavy rank: in LDS when the table fits the area
+    // (lights from the bottom, heavies from the top), else in the job's arrays
+    uint64_t* const cum = nb <= S.area_words ? S.area : nullptr;
+    auto light_cum = [&](uint32_t li) { return cum ? cum[li] : J.light_cum[li]; };
+    auto heavy_cum = [&](uint32_t hi) { return cum ? cum[nb - 1 - hi] : J.heavy_cum[hi]; };
     uint64_t nl = 0, dsum = 0, esum = 0;
     for (uint32_t base = 0; base < nb; base += kBuildThreads) {
       const uint32_t j = base + tid;
       uint64_t w = 0;
       bool light = false, valid = j < nb;
       if (valid) { w = J.item_w[j]; light = w < C; }
-      uint64_t t_l, t_d, t_e;
-      uint64_t lrank = nl + block_exclusive_scan(valid && light ? 1u : 0u, S.warp, &t_l);
-      uint64_t dpre = dsum + block_exclusive_scan(valid && light ? C - w : 0u, S.warp, &t_d);
-      uint64_t epre = esum + block_exclusive_scan(valid && !light ? w - C : 0u, S.warp, &t_e);
+      uint32_t t_l;
+      uint64_t t_d, t_e, dpre, epre;
+      const uint64_t lrank = nl + block_scan_small<1>(valid && light ? 1u : 0u, &t_l);
+      block_exclusive_scan2(valid && light ? C - w : 0u, valid && !light ? w - C : 0u, &dpre, &epre, &t_d, &t_e);
+      dpre += dsum;
+      epre += esum;
       if (valid) {
         if (light) {
           J.light_idx[lrank] = j;
-          J.light_cum[lrank] = dpre + (C - w);
+          if (cum) cum[lrank] = dpre + (C - w);
+          else J.light_cum[lrank] = dpre + (C - w);
         } else {
           uint64_t hrank = j - lrank;
           J.heavy_idx[hrank] = j;
-          J.heavy_cum[hrank] = epre + (w - C);
+          if (cum) cum[nb - 1 - hrank] = epre + (w - C);
+          else J.heavy_cum[hrank] = epre + (w - C);
         }
       }
       nl += t_l; dsum += t_d; esum += t_e;
@@ -471,17 +615,27 @@ __device__ __forceinline__ bool weights_alias_records(const BuildJob& J, uint32_
     }
     for (uint32_t li = tid; li < n_light; li += kBuildThreads) {
       const uint32_t j = J.light_idx[li];
-      const uint64_t prev = li > 0 ? J.light_cum[li - 1] : 0;
-      const uint32_t h = lower_bound_u64(J.heavy_cum, n_heavy, prev);
+      const uint64_t prev = li > 0 ? light_cum(li - 1) : 0;
+      // the first heavy whose cumulative excess reaches prev
+      uint32_t lo = 0, up = n_heavy;
+      while (lo < up) {
+        const uint32_t mid = (lo + up) >> 1;
+        if (heavy_cum(mid) < prev) lo = mid + 1; else up = mid;
+      }
       J.thr[j] = static_cast<uint32_t>(J.item_w[j]);
-      J.alias[j] = J.heavy_idx[h < n_heavy ? h : n_heavy - 1];
+      J.alias[j] = J.heavy_idx[lo < n_heavy ? lo : n_heavy - 1];
     }
     for (uint32_t hi = tid; hi < n_heavy; hi += kBuildThreads) {
       const uint32_t j = J.heavy_idx[hi];
-      const uint64_t E = J.heavy_cum[hi];
+      const uint64_t E = heavy_cum(hi);
       if (E < dsum && hi + 1 < n_heavy) {
-        const uint32_t i = upper_bound_u64(J.light_cum, n_light, E);
-        J.thr[j] = static_cast<uint32_t>(C + E - J.light_cum[i < n_light ? i : n_light - 1]);
+        // the first light whose cumulative deficit exceeds E
+        uint32_t lo = 0, up = n_light;
+        while (lo < up) {
+          const uint32_t mid = (lo + up) >> 1;
+          if (light_cum(mid) <= E) lo = mid + 1; else up = mid;
+        }
+        J.thr[j] = static_cast<uint32_t>(C + E - light_cum(lo < n_light ? lo : n_light - 1));
         J.alias[j] = J.heavy_idx[hi + 1];
       } else {
         J.thr[j] = static_cast<uint32_t>(C);
@@ -808,14 +962,14 @@ __device__ bool kron_variable_leaves(const BuildJob& J, const KronCtx& X, const 
         child = (code[i] << X.dbits) | x;
         if (D + 1 < X.cap) pass = kron_expanded(B, X.cap, kron_prob(X, child, D + 1), D + 1, child);
       }
-      uint64_t total;
-      const uint32_t pos = next + static_cast<uint32_t>(block_exclusive_scan(pass ? 1u : 0u, s_warp, &total));
+      uint32_t total;
+      const uint32_t pos = next + block_scan_small<1>(pass ? 1u : 0u, &total);
       if (pr < pairs && x == 0) first[i] = pos;
       if (pass) {
         if (pos < J.n_expand) code[pos] = child;
         else *s_error = kBuildItemCount;
       }
-      next += static_cast<uint32_t>(total);
+      next += total;
     }
     if (tid == 0) s_lvl_start[D + 2] = next;
     __syncthreads();
@@ -880,6 +1034,8 @@ __global__ __launch_bounds__(kBuildThreads) void kron_table_build_kernel(BuildJo
   __shared__ unsigned long long s_len_mass[16];
   __shared__ uint32_t s_lvl_start[kKronMaxDigits + 2];
   __shared__ KronBoundary s_kb;
+  __shared__ uint64_t s_vote_rep[kWaves];
+  __shared__ uint32_t s_vote_state[kWaves];
 
   const uint32_t n = J.n_items;
   const uint32_t nb = static_cast<uint32_t>(J.n_buckets);
@@ -921,7 +1077,8 @@ __global__ __launch_bounds__(kBuildThreads) void kron_table_build_kernel(BuildJo
   }
   __syncthreads();
   {
-    const BuildShared S{s_warp, s_u32, s_hist, &s_sel_prefix, &s_sel_need, s_len_mass, &s_error};
+    const BuildShared S{s_warp,    s_u32,      s_hist,  &s_sel_prefix, &s_sel_need, s_len_mass,
+                        &s_error,  nullptr,    0u,      s_vote_rep,    s_vote_state};
     weights_alias_records(J, n, nb, C, S);
   }
 
@@ -934,10 +1091,17 @@ finish:
 __device__ __forceinline__ void build_table(const BuildJob& J) {
   const int tid = threadIdx.x;
 
-  // phase 1's class arrays, then phase 2's per-node arrays (small trees)
-  __shared__ __align__(16) unsigned char s_work[kMaxClasses * (sizeof(double) + sizeof(uint32_t))];
-  double* const s_cls_p = reinterpret_cast<double*>(s_work);
-  uint32_t* const s_cls_key = reinterpret_cast<uint32_t*>(s_work + kMaxClasses * sizeof(double));
+  // one area: phase 1's class keys, then phase 2's per-node arrays (small
+  // trees) in its first part, the class probabilities by slot behind them;
+  // from phase 3 on the whole area holds the items' keys, then alias sums
+  constexpr size_t kWorkBytes = kMaxClasses * (sizeof(double) + sizeof(uint32_t));
+  constexpr size_t kAreaBytes = kWorkBytes + kMaxClasses * sizeof(double);
+  __shared__ __align__(16) unsigned char s_area[kAreaBytes];
+  unsigned char* const s_work = s_area;
+  uint32_t* const s_cls_key = reinterpret_cast<uint32_t*>(s_work);
+  double* const s_cls_p = reinterpret_cast<double*>(s_area + kWorkBytes);
+  // the class slots' rows (phases 1 and 2)
+  __shared__ uint16_t s_rows[16 * 16 * 16];
   __shared__ uint64_t s_warp[kWaves];
   __shared__ uint32_t s_u32[2 * kWaves];
   __shared__ uint32_t s_hist[256];
@@ -949,6 +1113,8 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
   __shared__ uint64_t s_sel_prefix, s_sel_need;
   __shared__ uint32_t s_binom[kBinomN * kBinomN];
   __shared__ unsigned long long s_len_mass[16];
+  __shared__ uint64_t s_vote_rep[kWaves];
+  __shared__ uint32_t s_vote_state[kWaves];
 
   const double q[4] = {J.q[0], J.q[1], J.q[2], J.q[3]};
   const int cap = J.cap;
@@ -966,33 +1132,42 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
   __syncthreads();
   const uint32_t* bt = s_binom;
 
-  // ---- 1. boundary node (VARIABLE) ------------------------------------------
-  if (J.mode == 1) {
-    // letter-count classes of every depth < cap: depth D has C(D+3, 3) of them
-    // (cap <= 15: at most 3060 <= kMaxClasses)
-    int K = 0;
-    for (int D = 0; D < cap; ++D) K += static_cast<int>(bt[(D + 3) * kBinomN + 3]);
-    for (int i = tid; i < kMaxClasses; i += kBuildThreads) {
-      if (i < K) {
-        // decode class i: depth, then counts of a, b, c (d takes the rest)
-        int r = i, D = 0;
-        while (r >= static_cast<int>(bt[(D + 3) * kBinomN + 3])) { r -= static_cast<int>(bt[(D + 3) * kBinomN + 3]); ++D; }
-        int na = D;
-        while (r >= static_cast<int>(bt[(D - na + 2) * kBinomN + 2])) {
-          r -= static_cast<int>(bt[(D - na + 2) * kBinomN + 2]);
-          --na;
-        }
-        int nb_ = D - na;
-        while (r >= D - na - nb_ + 1) { r -= D - na - nb_ + 1; --nb_; }
-        const int nc = D - na - nb_ - r, nd = r;
-        s_cls_key[i] = pack_class(na, nb_, nc, nd);
-        s_cls_p[i] = path_prob(q, na, nb_, nc, nd);
-      } else {
-        s_cls_p[i] = -1.0;  // sentinel, sorts last
-        s_cls_key[i] = 0xFFFF0000u;
+  // ---- class probabilities ----------------------------------------------------
+  {
+    // thread t < kClassRows owns row t: (na, nb, nc) from t, the row's first
+    // slot from a scan of the row lengths
+    int na = 0, nb_ = 0, nc = 0, len = 0;
+    if (tid < kClassRows) {
+      int r = tid;
+      while (r >= (16 - na) * (17 - na) / 2) { r -= (16 - na) * (17 - na) / 2; ++na; }
+      while (r >= 16 - na - nb_) { r -= 16 - na - nb_; ++nb_; }
+      nc = r;
+      len = 16 - na - nb_ - nc;
+    }
+    uint64_t total;
+    const uint32_t first = static_cast<uint32_t>(block_exclusive_scan(static_cast<uint64_t>(len), s_warp, &total));
+    if (tid < kClassRows) {
+      s_rows[(na * 16 + nb_) * 16 + nc] = static_cast<uint16_t>(first);
+      double p = 1.0;
+      for (int i = 0; i < na; ++i) p = __dmul_rn(p, q[0]);
+      for (int i = 0; i < nb_; ++i) p = __dmul_rn(p, q[1]);
+      for (int i = 0; i < nc; ++i) p = __dmul_rn(p, q[2]);
+      for (int nd = 0; nd < len; ++nd) {
+        if (nd > 0) p = __dmul_rn(p, q[3]);
+        s_cls_p[first + nd] = p;
+        // phase 1 takes the classes of depth < cap
+        s_cls_key[first + nd] = na + nb_ + nc + nd < cap ? pack_class(na, nb_, nc, nd) : kNoClass;
       }
     }
+    for (int i = kClassSlots + tid; i < kMaxClasses; i += kBuildThreads) {
+      s_cls_p[i] = -1.0;
+      s_cls_key[i] = kNoClass;
+    }
     __syncthreads();
+  }
+
+  // ---- 1. boundary node (VARIABLE) ------------------------------------------
+  if (J.mode == 1) {
     // The boundary is node n_expand of the order (p descending, depth
     // ascending, code ascending).  Classes hold whole (p, depth) runs, so a
     // radix select over the bits of p (descending; a non-negative double's
@@ -1003,7 +1178,7 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
     for (int u = 0; u < kPer; ++u) {
       const int i = tid * kPer + u;
       const uint32_t key = s_cls_key[i];
-      cnt_local[u] = i < K ? multinomial(bt, class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3)) : 0;
+      cnt_local[u] = key != kNoClass ? multinomial(bt, class_n(key, 0), class_n(key, 1), class_n(key, 2), class_n(key, 3)) : 0;
       pb_local[u] = static_cast<uint64_t>(__double_as_longlong(s_cls_p[i]));
       sum_local += cnt_local[u];
     }
@@ -1015,10 +1190,24 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
       for (int shift = 56; shift >= 0; shift -= 8) {
         for (int i = tid; i < 256; i += kBuildThreads) s_hist64[i] = 0;
         __syncthreads();
+        uint64_t rep = 0;
+        bool has = false, differ = false;
         for (int u = 0; u < kPer; ++u)
-          if (cnt_local[u] != 0 && (pb_local[u] & pmask) == prefix)
+          if (cnt_local[u] != 0 && (pb_local[u] & pmask) == prefix) {
             atomicAdd(&s_hist64[(pb_local[u] >> shift) & 255u], static_cast<unsigned long long>(cnt_local[u]));
+            differ = differ || (has && pb_local[u] != rep);
+            if (!has) rep = pb_local[u];
+            has = true;
+          }
+        vote_uniform(rep, has, differ, s_vote_rep, s_vote_state);
         __syncthreads();
+        // every class left in the group has the same probability: that is
+        // the boundary's, and s_sel_need its rank among the group's nodes
+        uint64_t only;
+        if (group_uniform(s_vote_rep, s_vote_state, &only)) {
+          prefix = only;
+          break;
+        }
         if (tid < 64) {
           uint64_t need = s_sel_need;
           const uint32_t bin = wave_select_desc(s_hist64, &need);
@@ -1058,38 +1247,51 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
       }
       __syncthreads();
     }
-    if (tid == 0 && s_error == 0) {
+    if (tid < 64 && s_error == 0) {
       if (all) {
-        s_bnd.all = 1;
+        if (tid == 0) s_bnd.all = 1;
       } else {
+        // digit by digit, the letter whose completions (summed over the
+        // run's classes) hold the rank: lane L counts letter L & 3 over the
+        // classes g = L >> 2, L >> 2 + 16, ...
         uint64_t r = s_sel_need - 1;  // rank of the last expanded node in its run
         const int n_group = static_cast<int>(s_u32[0]);
         const int D = static_cast<int>(s_u32[1]);
+        const int x = tid & 3;
         int used[4] = {0, 0, 0, 0};
         uint32_t code = 0;
         for (int pos = 0; pos < D; ++pos) {
-          int chosen = 3;
-          for (int x = 0; x < 4; ++x) {
-            uint64_t cnt = 0;
-            for (int g = 0; g < n_group; ++g) {
-              uint32_t key = s_cls_key[s_group[g]];
-              int rem[4];
-              bool ok = true;
-              for (int y = 0; y < 4; ++y) {
-                rem[y] = class_n(key, y) - used[y] - (y == x ? 1 : 0);
-                ok = ok && rem[y] >= 0;
-              }
-              if (ok) cnt += multinomial(bt, rem[0], rem[1], rem[2], rem[3]);
+          uint64_t cnt = 0;
+          for (int g = tid >> 2; g < n_group; g += 16) {
+            const uint32_t key = s_cls_key[s_group[g]];
+            int rem[4];
+            bool ok = true;
+            for (int y = 0; y < 4; ++y) {
+              rem[y] = class_n(key, y) - used[y] - (y == x ? 1 : 0);
+              ok = ok && rem[y] >= 0;
             }
-            if (r < cnt) { chosen = x; break; }
-            r -= cnt;
+            if (ok) cnt += multinomial(bt, rem[0], rem[1], rem[2], rem[3]);
+          }
+          for (int d = 4; d < 64; d <<= 1) cnt += shfl_xor_u64(cnt, d);  // lanes of one letter
+          int chosen = 3;
+          for (int y = 0; y < 4; ++y) {
+            const uint64_t c = static_cast<uint64_t>(static_cast<uint32_t>(__shfl(static_cast<uint32_t>(cnt), y, 64))) |
+                               (static_cast<uint64_t>(static_cast<uint32_t>(__shfl(static_cast<uint32_t>(cnt >> 32), y, 64)))
+                                << 32);
+            if (r < c) {
+              chosen = y;
+              break;
+            }
+            r -= c;
           }
           used[chosen]++;
           code = code * 4 + chosen;
         }
-        s_bnd.p = __longlong_as_double(static_cast<long long>(prefix));
-        s_bnd.depth = D;
-        s_bnd.code = code;
+        if (tid == 0) {
+          s_bnd.p = __longlong_as_double(static_cast<long long>(prefix));
+          s_bnd.depth = D;
+          s_bnd.code = code;
+        }
       }
     }
     __syncthreads();
@@ -1104,11 +1306,11 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
       int cnt[4];
       letter_counts(j, ell, cnt);
       uint32_t r, c;
-      split_code(j, ell, &r, &c);
+      split_code(j, &r, &c);
       J.item_len[j] = ell;
       J.item_row[j] = r;
       J.item_col[j] = c;
-      J.item_p[j] = path_prob(q, cnt[0], cnt[1], cnt[2], cnt[3]);
+      J.item_p[j] = s_cls_p[class_slot(s_rows, cnt[0], cnt[1], cnt[2], cnt[3])];
     }
   } else {
     bool ok;
@@ -1118,9 +1320,9 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
       uint32_t* size = first + kLdsNodes;
       uint32_t* off = size + kLdsNodes;
       uint8_t* mask = reinterpret_cast<uint8_t*>(off + kLdsNodes);
-      ok = variable_leaves(J, B, q, cap, n, code, mask, first, size, off, s_warp, s_lvl_start, &s_error);
+      ok = variable_leaves(J, B, s_cls_p, s_rows, cap, n, code, mask, first, size, off, s_warp, s_lvl_start, &s_error);
     } else {
-      ok = variable_leaves(J, B, q, cap, n, J.lvl_code, J.lvl_mask, J.lvl_first, J.lvl_size, J.lvl_off, s_warp,
+      ok = variable_leaves(J, B, s_cls_p, s_rows, cap, n, J.lvl_code, J.lvl_mask, J.lvl_first, J.lvl_size, J.lvl_off, s_warp,
                            s_lvl_start, &s_error);
     }
     if (!ok) goto finish;
@@ -1131,7 +1333,9 @@ __device__ __forceinline__ void build_table(const BuildJob& J) {
   __syncthreads();
 
   {
-    const BuildShared S{s_warp, s_u32, s_hist, &s_sel_prefix, &s_sel_need, s_len_mass, &s_error};
+    const BuildShared S{s_warp,  s_u32,       s_hist,   &s_sel_prefix,
+                        &s_sel_need, s_len_mass, &s_error, reinterpret_cast<uint64_t*>(s_area),
+                        static_cast<uint32_t>(kAreaBytes / sizeof(uint64_t)), s_vote_rep, s_vote_state};
     weights_alias_records(J, n, nb, C, S);
   }
 
