@@ -265,3 +265,36 @@ def test_served_failed_build_completes_with_einval(R):
         R.rmat_server_drain(s)
         (c,) = R.rmat_server_poll(s)
         assert c["ticket"] == t and c["status"] == R.RMAT_EINVAL and c["table_hit"] == 0
+
+
+def test_served_defaults_stream_digests_match_oracle(R):
+    """The server at its defaults, the configuration of the benchmark's served
+    stream (200e9-byte arena, 256 active requests, 1024 table slots, rounds of
+    2^24 blocks, quanta of 2^21 blocks): a Poisson stream of served-workload
+    requests (Dirichlet parameters, table bound 4096, edge factor 8 or 16; k
+    log-uniform in [12, 18] so that the oracle checks them in seconds)
+    arriving over 0.05 s, plus one request of 2^27 + 4097 edges that takes
+    two quanta and runs beside the others; every request's digest equals the
+    oracle's."""
+    reqs = workloads.served_requests(rate=2000.0, duration=0.05, arrival_seed=11, k_min=12, k_max=18)
+    n_stream = len(reqs)
+    assert n_stream > 50
+    q = (0.45, 0.22, 0.22, 0.11)
+    reqs.insert(n_stream // 2, dict(id=n_stream, t_arrival=reqs[n_stream // 2]["t_arrival"], a=q[0], b=q[1], c=q[2],
+                                    d=q[3], k=30, path_mode=R.RMAT_VARIABLE, table_bound=4096, seed=77,
+                                    edge_begin=123, m=(1 << 27) + 4097))
+    for p in reqs:
+        p["flags"] = R.RMAT_REQ_DIGEST | R.RMAT_REQ_DISCARD
+    import torch
+    torch.cuda.empty_cache()  # the default arena takes 200e9 of the 288 GB
+    with R.rmat_server_create() as s:
+        out = R.rmat_server_run_trace(s, reqs, [p["t_arrival"] for p in reqs])
+        st = R.rmat_server_get_stats(s)
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert R.rmat_server_get_stats(s)["arena_bytes"] == 0
+    assert st["rounds"] >= 2  # the large request spans two quanta
+    for i, (p, c) in enumerate(zip(reqs, out)):
+        assert c["status"] == 0, f"request {i}: status {c['status']}"
+        o = oracle.build_table(p["a"], p["b"], p["c"], p["d"], p["k"], p["table_bound"], p["path_mode"])
+        _, ox = oracle.generate_reduce(o, p["seed"], p["edge_begin"], p["m"], 0, threads=16)
+        assert c["digest"] == ox, f"request {i} (k={p['k']}, m={p['m']}): digest vs oracle"
