@@ -329,6 +329,18 @@ int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bi
 int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
                             uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out);
 
+/*
+ * As rmat_generate_partition, enqueued on `stream` (a hipStream_t; NULL: the
+ * null stream): the call returns once the tile list is copied and the launch
+ * enqueued, and the outputs are written when the stream reaches it, so the
+ * host can count the next row range meanwhile (Sec. 3: the ranges need no
+ * communication).  The table and the outputs must stay alive until then.
+ * Each device keeps a ring of four list buffers: a fifth call in flight waits
+ * for the oldest launch.  Errors as for rmat_generate_partition.
+ */
+int rmat_generate_partition_async(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                                  uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent instances (each its own a..d, k, table, seed,
  * edge range and outputs) built and generated together.  The method is the

@@ -9,7 +9,7 @@ from .rmat import (RMAT_EDEVICE, RMAT_EINVAL, RMAT_ENOMEM, RMAT_ERANGE, RMAT_FIX
                    rmat_batch_launch_graph, rmat_batch_table_export, rmat_batch_table_info, rmat_build_table,
                    rmat_build_table_async,
                    rmat_kron_build_table, rmat_build_perturbed_table, rmat_table_export_member,
-                   rmat_free_table, rmat_generate, rmat_generate_async, rmat_generate_ex_async, rmat_generate_partition, rmat_generate_reduce_async, rmat_generate_reduce_noalloc_async,
+                   rmat_free_table, rmat_generate, rmat_generate_async, rmat_generate_ex_async, rmat_generate_partition, rmat_generate_partition_async, rmat_generate_reduce_async, rmat_generate_reduce_noalloc_async,
                    rmat_generate_degrees_async, rmat_degree_distribution_async,
                    rmat_last_error, rmat_partition_counts, rmat_server_clock, rmat_server_create, rmat_server_drain, rmat_server_free,
                    rmat_server_get_stats, rmat_server_poll, rmat_server_release, rmat_server_run_trace,

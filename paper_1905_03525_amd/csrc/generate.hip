@@ -351,6 +351,14 @@ struct BatchLaunch {
   TileLayout L;
 };
 
+struct TilesLaunch {
+  const Inst* insts;
+  const uint64_t* cum;  // cum[i]: cost of the instances before i (blocks + inst_cost each)
+  uint32_t n_inst;
+  uint32_t inst_cost;   // an instance's fixed cost, in blocks
+  TileLayout L;
+};
+
 // A wave-uniform value held in a vector register: the epilogue's parameters
 // stay out of the scalar registers, which the tile loop needs.
 __device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
@@ -517,7 +525,7 @@ constexpr uint32_t queue_bytes() {
 // Every block after an edge's first (the first pass's second block, the
 // continuations) loads a record only for a sample the edge uses.
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
-          bool kLazy = false, bool kTwo = false>
+          bool kLazy = false, bool kTwo = false, bool kPrefix = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* qacc, uint16_t* qent, uint32_t hist_shift,
@@ -533,8 +541,9 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   const uint32_t toff_lane = (lane & I.table_mask) * tbytes;
   Epilogue<Id> E;
   if (kGeneral) E = make_epilogue<Id>(I);
-  const Id src_prefix = static_cast<Id>(kGeneral ? I.src_prefix : 0);
-  const Id dst_prefix = static_cast<Id>(kGeneral ? I.dst_prefix : 0);
+  // kPrefix: id prefixes without the epilogue (the tiles of a partitioned graph)
+  const Id src_prefix = static_cast<Id>(kGeneral || kPrefix ? I.src_prefix : 0);
+  const Id dst_prefix = static_cast<Id>(kGeneral || kPrefix ? I.dst_prefix : 0);
 
   // the ids of a finished edge e: reduced, counted, or handed to put(s, d)
   auto finish_edge = [&](const Acc& acc, uint64_t e, auto put) {
@@ -547,7 +556,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     } else {
       Id s = static_cast<Id>(acc.src(I.k));
       Id d = static_cast<Id>(acc.dst(I.k));
-      if (kGeneral) {  // tiles of a partitioned graph carry id prefixes
+      if (kGeneral || kPrefix) {  // tiles of a partitioned graph carry id prefixes
         s |= src_prefix;
         d |= dst_prefix;
       }
@@ -848,6 +857,58 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
       const uint64_t x = wave_xor(xsum);
       if ((threadIdx.x & 63) == 0 && x != 0) atomicXor(I.digest, x);
     }
+  }
+}
+
+// The tiles of a partitioned graph: instances on one table (staged once per
+// workgroup) laid out in list order on one line of cost, each instance a
+// fixed cost (its setup, its partial tiles and drains, in blocks) followed by
+// its blocks; the grid's waves share the line in equal contiguous parts.  A
+// wave finds the instance holding the start of its part with a 64-way search
+// (three rounds for 2^18 instances) and runs every instance whose blocks meet
+// its part over those blocks; no work is claimed and no workgroup waits
+// after the staging, and a run of tiny tiles weighs as much as its cost.
+template <typename Acc, bool kLds>
+__global__ __launch_bounds__(kGenThreads) void generate_tiles_kernel(TilesLaunch P) {
+  extern __shared__ __align__(16) unsigned char s_mem[];
+  using Packed = typename Acc::Packed;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave_in_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Packed* qacc = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
+  uint16_t* qent = reinterpret_cast<uint16_t*>(qacc + kQueueCap);
+  if (kLds) {
+    stage_table(P.insts[0].records, P.insts[0].n_buckets, s_mem);
+    __syncthreads();
+  }
+  // this wave's part [lo, hi) of the line
+  const uint64_t total = P.cum[P.n_inst];
+  const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * P.L.waves;
+  const uint64_t w = static_cast<uint64_t>(blockIdx.x) * P.L.waves + wave_in_wg;
+  const uint64_t q = total / n_waves, r = total % n_waves;
+  const uint64_t lo = q * w + (w < r ? w : r), hi = lo + q + (w < r ? 1 : 0);
+  if (lo >= hi) return;
+  // the instance holding position lo: cum[a] <= lo < cum[b] narrows to b = a + 1
+  uint32_t a = 0, b = P.n_inst;
+  while (b - a > 1) {
+    const uint32_t step = (b - a + 63) / 64;
+    const uint32_t idx = a + lane * step;
+    const uint64_t below = __ballot(idx < b && P.cum[idx] <= lo);  // a prefix of the lanes, lane 0 in it
+    const uint32_t last = 63u - static_cast<uint32_t>(__builtin_clzll(below));
+    a += last * step;
+    b = a + step < b ? a + step : b;
+  }
+  uint64_t xsum = 0;
+  for (uint32_t i = a; i < P.n_inst; ++i) {
+    if (P.cum[i] >= hi) break;
+    // the instance's blocks sit at [c0, c1) on the line, after its fixed cost
+    const uint64_t c0 = P.cum[i] + P.inst_cost, c1 = P.cum[i + 1];
+    const uint64_t end = hi < c1 ? hi : c1;
+    if (end <= c0) continue;  // the part ends inside the fixed cost: the next wave runs it
+    const uint64_t b0 = lo > c0 ? lo - c0 : 0, b1 = end - c0;
+    const Inst I = P.insts[i];  // a copy: the loop keeps the fields in registers
+    const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
+    run_blocks<Acc, false, false, false, false, !kLds, false, true>(I, tab, P.L, b0, b1, 1, qacc, qent, 0, nullptr,
+                                                                    xsum);
   }
 }
 
@@ -1175,6 +1236,28 @@ hipError_t launch_batch(const BatchArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename Acc, bool kLds>
+hipError_t launch_tiles(const TilesArgs& a, hipStream_t s) {
+  TilesLaunch P;
+  P.insts = a.insts;
+  P.cum = a.cum_cost;
+  P.n_inst = a.n_inst;
+  P.inst_cost = a.inst_cost;
+  const void* fn = reinterpret_cast<const void*>(&generate_tiles_kernel<Acc, kLds>);
+  size_t lds = 0;
+  uint32_t per_cu = 0;
+  P.L = layout_for<Acc>(fn, a.n_buckets, kLds, &lds, &per_cu);
+  if (P.L.tile == 0) return hipErrorInvalidValue;
+  // every resident wave, fewer when there are fewer blocks than waves
+  uint64_t grid = static_cast<uint64_t>(limits().cu_count) * per_cu;
+  const uint64_t wgs_needed = (a.total_blocks + P.L.waves - 1) / P.L.waves;
+  if (grid > wgs_needed) grid = wgs_needed;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((generate_tiles_kernel<Acc, kLds>), dim3(static_cast<uint32_t>(grid)), dim3(P.L.waves * 64),
+                     lds, s, P);
+  return hipGetLastError();
+}
+
 template <typename F>
 hipError_t allow_full_lds(F* fn) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1283,6 +1366,12 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s) {
   return a.general ? pick(std::false_type{}, std::true_type{}) : pick(std::false_type{}, std::false_type{});
 }
 
+hipError_t launch_generate_tiles(const TilesArgs& a, hipStream_t s) {
+  if (a.n_inst == 0 || a.total_blocks == 0) return hipSuccess;
+  if (a.wide) return a.lds ? launch_tiles<Acc64, true>(a, s) : launch_tiles<Acc64, false>(a, s);
+  return a.lds ? launch_tiles<Acc32, true>(a, s) : launch_tiles<Acc32, false>(a, s);
+}
+
 uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds) {
   const size_t table = lds ? static_cast<size_t>(table_buckets) * sizeof(BucketRecord) : 0;
   const size_t queues = static_cast<size_t>(kMinWaves) * (wide ? queue_bytes<Acc64>() : queue_bytes<Acc32>());
@@ -1334,7 +1423,11 @@ hipError_t prepare_kernels() {
       prepare_generation(&generate_kernel<Acc64, true, false, false, false, true>),
       prepare_generation(&generate_kernel<Acc64, false, false, false, false, true>),
       prepare_generation(&generate_kernel<KronAcc<uint32_t>, true, false, false, false, true>),
-      prepare_generation(&generate_kernel<KronAcc<uint64_t>, true, false, false, false, true>)};
+      prepare_generation(&generate_kernel<KronAcc<uint64_t>, true, false, false, false, true>),
+      prepare_generation(&generate_tiles_kernel<Acc32, true>),
+      prepare_generation(&generate_tiles_kernel<Acc32, false>),
+      prepare_generation(&generate_tiles_kernel<Acc64, true>),
+      prepare_generation(&generate_tiles_kernel<Acc64, false>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   if (e == hipSuccess) done = true;

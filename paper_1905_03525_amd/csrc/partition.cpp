@@ -327,12 +327,22 @@ struct CountCache {
 };
 CountCache g_count_cache;
 
-// Per-device buffers (device and pinned host) for a generation's instance
-// and work lists, grown on demand and kept until the process ends.
-struct Lists {
+// Per-device rings of buffers (device and pinned host) for a generation's
+// instance list and running costs, grown on demand and kept until the
+// process ends.  A call takes the next buffer of its device's ring and waits
+// first for the launch that used it last, so that up to kListRing
+// asynchronous calls per device can be in flight.
+constexpr int kListRing = 4;
+struct ListBuf {
   void* dev = nullptr;   // device copy
   void* host = nullptr;  // pinned staging
   uint64_t bytes = 0;
+  hipEvent_t done = nullptr;  // recorded after the launch that used the buffer last
+  bool pending = false;
+};
+struct Lists {
+  ListBuf buf[kListRing];
+  int next = 0;
 };
 std::mutex g_lists_mu;
 std::map<int, Lists> g_lists;
@@ -387,7 +397,8 @@ int rmat_partition_counts(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bi
 }
 
 static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
-                                        uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out) {
+                                        uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out,
+                                        hipStream_t stream, bool sync) {
   rmat::clear_error();
   if (!t) return set_error(RMAT_EINVAL, "NULL table");
   if (int rc0 = rmat::finalize_table(t)) return rc0;
@@ -408,77 +419,56 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
   if ((reinterpret_cast<uintptr_t>(out_src) | reinterpret_cast<uintptr_t>(out_dst)) % idb)
     return set_error(RMAT_EINVAL, "output pointers must be %u-byte aligned", (unsigned)idb);
   // one instance per non-empty tile, outputs back to back in row-major
-  // order.  A tile of more than kSmallTile blocks is cut into work items of
-  // up to work_blocks blocks that a workgroup's waves share; the smaller tiles
-  // follow the others in the instance list and are packed, in row-major
-  // order, into items of up to kPackInsts instances (kPackBlocks blocks), one
-  // wave per instance.  The lists are sized in a first pass and written
-  // straight into pinned memory in a second.
+  // order, and the running cost before each (kInstCost blocks per instance
+  // for its setup, partial tiles and drains, plus its blocks): the generation
+  // launch cuts that line into one equal part per wave, so that a run of
+  // tiny tiles is not one wave's alone.  Both arrays are written straight
+  // into pinned memory and sent in one copy.
+  constexpr uint32_t kInstCost = 4;
   const rmat::TableView& V = *rmat::table_view_of(t);
   const int kk = info.k - tile_bits;
-  const uint64_t work_blocks = 2048;
-  constexpr uint64_t kSmallTile = 8;
-  constexpr uint32_t kPackInsts = 256;
-  constexpr uint64_t kPackBlocks = 1024;
-  // a small tile of nb blocks opens a new pack when the current one is full
-  auto opens_pack = [&](uint32_t pack_n, uint64_t pack_blocks, uint64_t nb) {
-    return pack_n == 0 || pack_n == kPackInsts || pack_blocks + nb > kPackBlocks;
-  };
-  uint64_t n_big = 0, n_small = 0, n_big_items = 0, n_packs = 0;
-  {
-    uint32_t pack_n = 0;
-    uint64_t pack_blocks = 0;
-    for (uint64_t i = 0; i < n_tiles; ++i) {
-      if (counts[i] == 0) continue;
-      const uint64_t nb = (counts[i] + 63) / 64;
-      if (nb > kSmallTile) {
-        ++n_big;
-        n_big_items += (nb + work_blocks - 1) / work_blocks;
-        continue;
-      }
-      ++n_small;
-      if (opens_pack(pack_n, pack_blocks, nb)) {
-        ++n_packs;
-        pack_n = 0;
-        pack_blocks = 0;
-      }
-      ++pack_n;
-      pack_blocks += nb;
-    }
-  }
-  const uint64_t n_items = n_big_items + n_packs;
-  const uint64_t inst_bytes = ((n_big + n_small) * sizeof(rmat::GenInst) + 255) / 256 * 256;
-  const uint64_t item_bytes = (n_items * sizeof(rmat::GenWorkItem) + 255) / 256 * 256;
-  const uint64_t bytes = inst_bytes + item_bytes + 256;
-  // [instances | work items | zeroed work counter] in pinned host memory, sent
-  // in one copy to a device buffer; both are kept between calls (calls are
-  // synchronous and serialised here)
+  uint64_t n_inst = 0;
+  for (uint64_t i = 0; i < n_tiles; ++i) n_inst += counts[i] != 0;
+  const uint64_t inst_bytes = (n_inst * sizeof(rmat::GenInst) + 255) / 256 * 256;
+  const uint64_t bytes = inst_bytes + (n_inst + 1) * sizeof(uint64_t);
+  // the next buffer of the device's ring, once its last launch is done
   std::lock_guard<std::mutex> lock(g_lists_mu);
   int device = 0;
   hipError_t e = hipGetDevice(&device);
   if (e != hipSuccess) return rmat::hip_fail(e, "hipGetDevice");
-  Lists& L = g_lists[device];
+  Lists& ring = g_lists[device];
+  ListBuf& L = ring.buf[ring.next];
+  ring.next = (ring.next + 1) % kListRing;
+  if (L.pending) {
+    e = hipEventSynchronize(L.done);
+    if (e != hipSuccess) return rmat::hip_fail(e, "waiting for an earlier partitioned generation");
+    L.pending = false;
+  }
+  if (!L.done) {
+    e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      L.done = nullptr;
+      return rmat::hip_fail(e, "hipEventCreateWithFlags");
+    }
+  }
   if (L.bytes < bytes) {
     if (L.dev) (void)hipFree(L.dev);
     if (L.host) (void)hipHostFree(L.host);
-    L = Lists{};
+    L.dev = L.host = nullptr;
+    L.bytes = 0;
     e = hipMalloc(&L.dev, bytes);
     if (e == hipSuccess) e = hipHostMalloc(&L.host, bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
       if (L.dev) (void)hipFree(L.dev);
-      L = Lists{};
+      L.dev = L.host = nullptr;
       return rmat::hip_fail(e, "allocation of the partition lists");
     }
     L.bytes = bytes;
   }
   char* host = static_cast<char*>(L.host);
   auto* h_inst = reinterpret_cast<rmat::GenInst*>(host);
-  auto* h_item = reinterpret_cast<rmat::GenWorkItem*>(host + inst_bytes);
-  uint64_t next_big = 0, next_small = n_big, next_big_item = 0, next_pack = n_big_items;
-  uint32_t pack_n = 0;
-  uint64_t pack_blocks = 0;
-  uint64_t off = 0;
-  const char* overrun = "partition lists: filling outgrew the sizing pass";
+  auto* h_cum = reinterpret_cast<uint64_t*>(host + inst_bytes);
+  uint64_t ii = 0, off = 0, blocks = 0, cost = 0;
   for (uint64_t i = 0; i < n_tiles; ++i) {
     const uint64_t n = counts[i];
     if (n == 0) continue;
@@ -505,58 +495,29 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
     I.dst_prefix = static_cast<uint64_t>(c) << kk;
     I.epi = 0;
     off += n;
-    if (I.n_blocks > kSmallTile) {
-      if (next_big >= n_big) return set_error(RMAT_EDEVICE, "%s", overrun);
-      const uint64_t ii = next_big++;
-      h_inst[ii] = I;
-      for (uint64_t f = 0; f < I.n_blocks; f += work_blocks) {
-        if (next_big_item >= n_big_items) return set_error(RMAT_EDEVICE, "%s", overrun);
-        rmat::GenWorkItem w;
-        w.inst = static_cast<uint32_t>(ii);
-        w.first = f;
-        w.n_blocks = static_cast<uint32_t>(I.n_blocks - f < work_blocks ? I.n_blocks - f : work_blocks);
-        h_item[next_big_item++] = w;
-      }
-      continue;
-    }
-    if (next_small >= n_big + n_small) return set_error(RMAT_EDEVICE, "%s", overrun);
-    const uint64_t ii = next_small++;
-    h_inst[ii] = I;
-    if (opens_pack(pack_n, pack_blocks, I.n_blocks)) {
-      if (next_pack >= n_items) return set_error(RMAT_EDEVICE, "%s", overrun);
-      rmat::GenWorkItem w;  // a pack of one instance is an ordinary item over it
-      w.inst = static_cast<uint32_t>(ii);
-      w.first = 0;
-      w.n_blocks = 0;
-      w.n_inst = 0;
-      h_item[next_pack++] = w;
-      pack_n = 0;
-      pack_blocks = 0;
-    }
-    rmat::GenWorkItem& w = h_item[next_pack - 1];
-    w.n_inst = ++pack_n;
-    pack_blocks += I.n_blocks;
-    w.n_blocks = static_cast<uint32_t>(pack_blocks);
+    h_cum[ii] = cost;
+    cost += kInstCost + I.n_blocks;
+    blocks += I.n_blocks;
+    h_inst[ii++] = I;
   }
-  if (next_big != n_big || next_small != n_big + n_small || next_big_item != n_big_items || next_pack != n_items)
-    return set_error(RMAT_EDEVICE, "partition lists: sizing and filling disagree");
-  std::memset(host + inst_bytes + item_bytes, 0, 256);
+  h_cum[n_inst] = cost;
   char* base = static_cast<char*>(L.dev);
-  e = hipMemcpy(base, host, bytes, hipMemcpyHostToDevice);
+  e = hipMemcpyAsync(base, host, bytes, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) {
-    rmat::BatchArgs a;
+    rmat::TilesArgs a;
     a.insts = reinterpret_cast<const rmat::GenInst*>(base);
-    a.items = reinterpret_cast<const rmat::GenWorkItem*>(base + inst_bytes);
-    a.n_items = static_cast<uint32_t>(n_items);
-    a.counter = reinterpret_cast<unsigned int*>(base + inst_bytes + item_bytes);
-    a.max_buckets = static_cast<uint32_t>(info.n_buckets);
+    a.cum_cost = reinterpret_cast<const uint64_t*>(base + inst_bytes);
+    a.n_inst = static_cast<uint32_t>(n_inst);
+    a.inst_cost = kInstCost;
+    a.total_blocks = blocks;
+    a.n_buckets = static_cast<uint32_t>(info.n_buckets);
     a.wide = info.k > 32;
     a.lds = info.lds_resident != 0;
-    a.digest = 0;
-    a.general = 1;  // tiles carry id prefixes
-    e = rmat::launch_generate_batch(a, nullptr);
+    e = rmat::launch_generate_tiles(a, stream);
   }
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipEventRecord(L.done, stream);
+  if (e == hipSuccess) L.pending = true;
+  if (e == hipSuccess && sync) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return rmat::hip_fail(e, "partitioned generation");
   return RMAT_OK;
 }
@@ -564,7 +525,14 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
 int rmat_generate_partition(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
                             uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out) {
   RMAT_GUARD("rmat_generate_partition", rmat_generate_partition_body(t, seed, m, tile_bits, row_begin, row_end,
-                                                                     out_src, out_dst, n_out));
+                                                                     out_src, out_dst, n_out, nullptr, true));
+}
+
+int rmat_generate_partition_async(rmat_table_t t, uint64_t seed, uint64_t m, int tile_bits, uint32_t row_begin,
+                                  uint32_t row_end, void* out_src, void* out_dst, uint64_t n_out, void* stream) {
+  RMAT_GUARD("rmat_generate_partition_async",
+             rmat_generate_partition_body(t, seed, m, tile_bits, row_begin, row_end, out_src, out_dst, n_out,
+                                          static_cast<hipStream_t>(stream), false));
 }
 
 }  // extern "C"

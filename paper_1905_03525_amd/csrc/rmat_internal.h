@@ -166,6 +166,23 @@ struct BatchArgs {
 
 hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t s);
 
+// The tiles of a partitioned graph: instances on one table, laid out in list
+// order on a line of cost (inst_cost, then its blocks, per instance) that is
+// cut into one equal contiguous part per wave of the launch.
+struct TilesArgs {
+  const GenInst* insts;      // device array of n_inst instances (one table, each with blocks)
+  const uint64_t* cum_cost;  // device array of n_inst + 1: sum over the instances before i of
+                             // inst_cost + n_blocks
+  uint32_t n_inst;
+  uint32_t inst_cost;        // an instance's fixed cost, in blocks
+  uint64_t total_blocks;     // blocks of all instances
+  uint32_t n_buckets;        // the table's buckets (LDS staging size)
+  int wide;                  // k > 32 (64-bit ids)
+  int lds;                   // table staged in LDS
+};
+
+hipError_t launch_generate_tiles(const TilesArgs& a, hipStream_t s);
+
 // Blocks per tile the generation kernels use for a table of this size.
 uint32_t tile_blocks(uint32_t table_buckets, int wide, int lds);
 

@@ -31,7 +31,7 @@ EXPORTED = ["rmat_build_table", "rmat_build_table_async", "rmat_kron_build_table
             "rmat_generate_async", "rmat_generate_ex_async", "rmat_generate_reduce_async",
             "rmat_generate_reduce_noalloc_async", "rmat_generate_degrees_async",
             "rmat_degree_distribution_async", "rmat_batch_create", "rmat_batch_enqueue",
-            "rmat_partition_counts", "rmat_generate_partition", "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
+            "rmat_partition_counts", "rmat_generate_partition", "rmat_generate_partition_async", "rmat_batch_launch_graph", "rmat_batch_check", "rmat_batch_table_info", "rmat_batch_table_export", "rmat_batch_get_info",
             "rmat_batch_free", "rmat_batch_autotune", "rmat_server_create", "rmat_server_submit",
             "rmat_server_step", "rmat_server_drain", "rmat_server_poll", "rmat_server_release",
             "rmat_server_run_trace", "rmat_server_get_stats", "rmat_server_clock", "rmat_server_free",
@@ -143,6 +143,8 @@ def load() -> ctypes.CDLL:
     L.rmat_degree_distribution_async.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
     L.rmat_partition_counts.argtypes = [vp, u64, u64, c_int, ctypes.c_uint32, ctypes.c_uint32, vp]
     L.rmat_generate_partition.argtypes = [vp, u64, u64, c_int, ctypes.c_uint32, ctypes.c_uint32, vp, vp, u64]
+    L.rmat_generate_partition_async.argtypes = [vp, u64, u64, c_int, ctypes.c_uint32, ctypes.c_uint32, vp, vp, u64,
+                                                vp]
     L.rmat_batch_create.argtypes = [ctypes.POINTER(rmat_instance), c_int, ctypes.c_uint32, ctypes.POINTER(vp)]
     L.rmat_batch_enqueue.argtypes = [vp, vp]
     L.rmat_batch_launch_graph.argtypes = [vp, vp]
@@ -314,6 +316,13 @@ def rmat_generate_partition(t: Table, seed: int, m: int, tile_bits: int, row_beg
                             out_dst, n_out: int):
     _check(load().rmat_generate_partition(t.handle, seed, m, tile_bits, row_begin, row_end, _ptr(out_src),
                                           _ptr(out_dst), n_out), "rmat_generate_partition")
+
+
+def rmat_generate_partition_async(t: Table, seed: int, m: int, tile_bits: int, row_begin: int, row_end: int,
+                                  out_src, out_dst, n_out: int, stream=None):
+    _check(load().rmat_generate_partition_async(t.handle, seed, m, tile_bits, row_begin, row_end, _ptr(out_src),
+                                                _ptr(out_dst), n_out, _stream(stream)),
+           "rmat_generate_partition_async")
 
 
 def generate_partition(t: Table, seed: int, m: int, tile_bits: int, row_begin: int = 0, row_end: int | None = None,

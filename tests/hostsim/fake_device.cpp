@@ -219,6 +219,60 @@ hipError_t launch_generate_batch(const BatchArgs& a, hipStream_t) {
   return hipSuccess;
 }
 
+// The partitioned tiles' launch: the list must hold one table, instances with
+// blocks and their running costs; then the waves' parts of the cost line are
+// cut and searched exactly as generate_tiles_kernel does, for several grid
+// sizes, and every block of every instance must fall in exactly one part.
+hipError_t launch_generate_tiles(const TilesArgs& a, hipStream_t) {
+  ++g_launches;
+  if (a.n_inst == 0 || a.total_blocks == 0) return hipSuccess;
+  const uint64_t* cum = a.cum_cost;
+  uint64_t blocks = 0;
+  if (cum[0] != 0) fail("running costs: start");
+  for (uint32_t i = 0; i < a.n_inst; ++i) {
+    const GenInst& I = a.insts[i];
+    if (I.n_blocks == 0 || cum[i + 1] - cum[i] != a.inst_cost + I.n_blocks) fail("running costs");
+    if (I.records != a.insts[0].records || I.n_buckets != a.n_buckets) fail("tiles on different tables");
+    if (g_whole_cover ? (I.k > 32 && !a.wide) : ((I.k > 32) != (a.wide != 0))) fail("id width of the launch");
+    if ((I.n_buckets <= lds_table_limit()) != (a.lds != 0)) fail("table residency of the launch");
+    blocks += I.n_blocks;
+  }
+  if (blocks != a.total_blocks) fail("total blocks");
+  std::vector<std::vector<uint8_t>> seen(a.n_inst);
+  const uint64_t total = cum[a.n_inst];
+  for (uint64_t n_waves : {uint64_t{1}, uint64_t{7}, uint64_t{6144}, total + 5}) {
+    for (uint32_t i = 0; i < a.n_inst; ++i) seen[i].assign(a.insts[i].n_blocks, 0);
+    for (uint64_t w = 0; w < n_waves; ++w) {
+      const uint64_t q = total / n_waves, r = total % n_waves;
+      const uint64_t lo = q * w + (w < r ? w : r), hi = lo + q + (w < r ? 1 : 0);
+      if (lo >= hi) continue;
+      uint32_t lo_i = 0, hi_i = a.n_inst;  // the kernel's 64-way search, lane by lane
+      while (hi_i - lo_i > 1) {
+        const uint32_t step = (hi_i - lo_i + 63) / 64;
+        uint32_t last = 64;
+        for (uint32_t lane = 0; lane < 64; ++lane) {
+          const uint32_t idx = lo_i + lane * step;
+          if (idx < hi_i && cum[idx] <= lo) last = lane;
+          else if (last == 64) fail("search: lane 0 below the range");
+        }
+        lo_i += last * step;
+        hi_i = lo_i + step < hi_i ? lo_i + step : hi_i;
+      }
+      if (!(cum[lo_i] <= lo && lo < cum[lo_i + 1])) fail("search: wrong instance");
+      for (uint32_t i = lo_i; i < a.n_inst && cum[i] < hi; ++i) {
+        const uint64_t c0 = cum[i] + a.inst_cost, end = hi < cum[i + 1] ? hi : cum[i + 1];
+        if (end <= c0) continue;
+        for (uint64_t b = lo > c0 ? lo - c0 : 0; b < end - c0; ++b) ++seen[i][b];
+      }
+    }
+    for (const auto& v : seen)
+      for (uint8_t c : v)
+        if (c != 1) fail("a block of the tiles not in exactly one wave's part");
+  }
+  if (g_whole_cover) g_cover_insts = a.n_inst;
+  return hipSuccess;
+}
+
 hipError_t launch_generate(const GenerateArgs&, hipStream_t) { return hipSuccess; }
 hipError_t launch_generate_reduce(const GenerateArgs&, hipStream_t) { return hipSuccess; }
 hipError_t launch_generate_degrees(const GenerateArgs&, hipStream_t) { return hipSuccess; }

@@ -100,3 +100,35 @@ def test_counts_of_another_table_are_not_reused(R):
     assert np.array_equal(R.to_numpy_ids(src, k), os_) and np.array_equal(R.to_numpy_ids(dst, k), od)
     a.close()
     b.close()
+
+
+def test_async_row_ranges_in_flight_equal_oracle(R):
+    """Six row ranges enqueued back to back on one stream by the asynchronous
+    entry point (each counted on the host while the previous ones run; six
+    calls in flight wrap the ring of four list buffers), synchronised once at
+    the end: every range equals the oracle's tiles, and together they hold
+    the whole graph."""
+    import torch
+    k, tb, m, seed = 22, 6, 1 << 22, 11
+    t = R.rmat_build_table(*G500, k, 4096, R.RMAT_VARIABLE)
+    o = oracle.build_table(*G500, k, 4096, oracle.VARIABLE)
+    ranges = [(0, 5), (5, 6), (6, 20), (20, 21), (21, 40), (40, 64)]
+    stream = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(stream):
+        for r0, r1 in ranges:
+            n = int(R.rmat_partition_counts(t, seed, m, tb, r0, r1).sum())
+            src = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+            dst = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+            R.rmat_generate_partition_async(t, seed, m, tb, r0, r1, src, dst, n, stream)
+            outs.append((n, src, dst))
+    stream.synchronize()
+    total = 0
+    for (r0, r1), (n, src, dst) in zip(ranges, outs):
+        oc, os_, od = oracle.generate_partition(o, seed, m, tb, r0, r1)
+        assert int(oc.sum()) == n
+        assert np.array_equal(R.to_numpy_ids(src[:n], k), os_), f"rows {r0}..{r1}: src"
+        assert np.array_equal(R.to_numpy_ids(dst[:n], k), od), f"rows {r0}..{r1}: dst"
+        total += n
+    assert total == m
+    t.close()

@@ -34,6 +34,8 @@ def lib(tmp_path_factory):
     L.rmat_partition_counts.argtypes = [vp, u64, u64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, vp]
     L.rmat_free_table.argtypes = [vp]
     L.rmat_generate_partition.argtypes = [vp, u64, u64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, vp, vp, u64]
+    L.rmat_generate_partition_async.argtypes = [vp, u64, u64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, vp, vp,
+                                                u64, vp]
     L.sim_whole_cover.argtypes = [ctypes.c_int]
     L.sim_cover_insts.restype = u64
     L.rmat_last_error.restype = ctypes.c_char_p
@@ -83,9 +85,10 @@ LIST_CASES = [
 
 @pytest.mark.parametrize("q,k,bound,seed,m,tb,rows", LIST_CASES)
 def test_generation_lists_cover_every_tile_once(lib, q, k, bound, seed, m, tb, rows):
-    """The work lists of a partitioned generation (through the fake device):
-    every block of every non-empty tile in exactly one work item, packed
-    items on one table with their block counts, one instance per tile."""
+    """The tile list of a partitioned generation (through the fake device):
+    one instance per non-empty tile, all on one table, with running block
+    counts; the waves' parts, cut and searched as the kernel does for several
+    grid sizes, hold every block of every tile exactly once."""
     r0, r1 = rows if rows else (0, 1 << tb)
     h = ctypes.c_void_p()
     assert lib.rmat_build_table(*q, k, bound, 1, ctypes.byref(h)) == 0, lib.rmat_last_error()
@@ -99,6 +102,30 @@ def test_generation_lists_cover_every_tile_once(lib, q, k, bound, seed, m, tb, r
         assert rc == 0, lib.rmat_last_error()
         assert lib.sim_failed() == 0
         assert lib.sim_cover_insts() == int((counts > 0).sum())
+    finally:
+        lib.sim_whole_cover(0)
+        lib.rmat_free_table(h)
+
+
+def test_async_calls_wrap_the_list_ring(lib):
+    """Asynchronous partitioned generations through the fake device: seven
+    calls in a row (the ring holds four list buffers, so the later ones wait
+    for earlier launches and reuse their buffers, grown when a range has more
+    tiles), every tile list covered exactly once."""
+    q, k, tb, m, seed = (0.57, 0.19, 0.19, 0.05), 20, 6, 1 << 20, 4
+    h = ctypes.c_void_p()
+    assert lib.rmat_build_table(*q, k, 4096, 1, ctypes.byref(h)) == 0, lib.rmat_last_error()
+    out = np.zeros(2, np.uint64)
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    lib.sim_whole_cover(1)
+    try:
+        for r0, r1 in [(0, 2), (2, 3), (3, 30), (30, 31), (31, 33), (33, 64), (0, 64)]:
+            counts = np.zeros((r1 - r0, 1 << tb), np.uint64)
+            assert lib.rmat_partition_counts(h, seed, m, tb, r0, r1, counts.ctypes.data_as(ctypes.c_void_p)) == 0
+            rc = lib.rmat_generate_partition_async(h, seed, m, tb, r0, r1, p, p, int(counts.sum()), None)
+            assert rc == 0, lib.rmat_last_error()
+            assert lib.sim_failed() == 0
+            assert lib.sim_cover_insts() == int((counts > 0).sum())
     finally:
         lib.sim_whole_cover(0)
         lib.rmat_free_table(h)
