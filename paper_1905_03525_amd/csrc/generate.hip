@@ -271,6 +271,24 @@ __device__ __forceinline__ void consume4_flat(uint32_t k, const uint32_t (&x)[4]
 
 typedef __attribute__((address_space(3))) const BucketRecord* LdsRecordPtr;
 
+// A wave-uniform record of a list that no launch writes (instances, work
+// items, running costs), read through the constant address space: the
+// compiler may then load it with scalar loads into scalar registers, where a
+// plain load, which a store of the same kernel might alias, goes through the
+// vector unit and holds the whole record in vector registers.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  typedef __attribute__((address_space(4))) const uint32_t* ConstWordPtr;
+  const ConstWordPtr w = (ConstWordPtr)reinterpret_cast<uintptr_t>(p);
+  uint32_t words[sizeof(T) / 4];
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) words[i] = w[i];
+  T r;
+  __builtin_memcpy(&r, words, sizeof(T));
+  return r;
+}
+
 // The record sample x selects in the table at byte offset toff of a set:
 // bucket (x >> 4) mod nb, whose offset within the table is x & bmask with
 // bmask = (nb - 1) << 4 (one AND-OR: toff is a multiple of nb * 16).  A set
@@ -824,8 +842,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
     const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();  // everyone has read s_item (and finished the previous item)
     if (item >= B.n_items) break;
-    const GenWorkItem W = B.items[item];
-    const Inst I = B.insts[W.inst];
+    const GenWorkItem W = load_uniform(B.items + item);
+    const Inst I = load_uniform(B.insts + W.inst);
     const uint32_t buckets = I.n_buckets * (I.table_mask + 1);
     if (kLds && (I.records != cur || buckets != cur_buckets)) {
       stage_table(I.records, buckets, s_mem);
@@ -837,7 +855,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_batch_kernel(BatchLaunch
       // a run of small instances on this table: each wave takes whole
       // instances (no workgroup step between them)
       for (uint32_t j = wave_in_wg; j < W.n_inst; j += B.L.waves) {
-        const Inst Ij = B.insts[W.inst + j];
+        const Inst Ij = load_uniform(B.insts + W.inst + j);
         const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : Ij.records;
         uint64_t xsum = 0;
         run_blocks<Acc, false, kDigest, kGeneral, false, !kLds>(Ij, tab, B.L, 0, Ij.n_blocks, 1, qacc, qent, 0,
@@ -897,15 +915,18 @@ __global__ __launch_bounds__(kGenThreads) void generate_tiles_kernel(TilesLaunch
     a += last * step;
     b = a + step < b ? a + step : b;
   }
+  // the same in every lane: instances load through the scalar unit
+  a = __builtin_amdgcn_readfirstlane(a);
   uint64_t xsum = 0;
   for (uint32_t i = a; i < P.n_inst; ++i) {
-    if (P.cum[i] >= hi) break;
+    const uint64_t ci = load_uniform(P.cum + i);
+    if (ci >= hi) break;
     // the instance's blocks sit at [c0, c1) on the line, after its fixed cost
-    const uint64_t c0 = P.cum[i] + P.inst_cost, c1 = P.cum[i + 1];
+    const uint64_t c0 = ci + P.inst_cost, c1 = load_uniform(P.cum + i + 1);
     const uint64_t end = hi < c1 ? hi : c1;
     if (end <= c0) continue;  // the part ends inside the fixed cost: the next wave runs it
     const uint64_t b0 = lo > c0 ? lo - c0 : 0, b1 = end - c0;
-    const Inst I = P.insts[i];  // a copy: the loop keeps the fields in registers
+    const Inst I = load_uniform(P.insts + i);
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
     run_blocks<Acc, false, false, false, false, !kLds, false, true>(I, tab, P.L, b0, b1, 1, qacc, qent, 0, nullptr,
                                                                     xsum);
