@@ -503,6 +503,7 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
   h_cum[n_inst] = cost;
   char* base = static_cast<char*>(L.dev);
   e = hipMemcpyAsync(base, host, bytes, hipMemcpyHostToDevice, stream);
+  const bool copying = e == hipSuccess;  // the buffer is in use from here on, whatever follows
   if (e == hipSuccess) {
     rmat::TilesArgs a;
     a.insts = reinterpret_cast<const rmat::GenInst*>(base);
@@ -515,8 +516,15 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
     a.lds = info.lds_resident != 0;
     e = rmat::launch_generate_tiles(a, stream);
   }
-  if (e == hipSuccess) e = hipEventRecord(L.done, stream);
-  if (e == hipSuccess) L.pending = true;
+  if (copying) {  // the next user of this buffer waits for the copy (and the launch, if any)
+    const hipError_t r = hipEventRecord(L.done, stream);
+    if (r == hipSuccess) {
+      L.pending = true;
+    } else {  // no event to wait for: let the copy finish before the buffer can be reused
+      (void)hipStreamSynchronize(stream);
+      if (e == hipSuccess) e = r;
+    }
+  }
   if (e == hipSuccess && sync) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return rmat::hip_fail(e, "partitioned generation");
   return RMAT_OK;
