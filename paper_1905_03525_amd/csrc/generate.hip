@@ -608,7 +608,13 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     const uint32_t step = static_cast<uint32_t>(stride) * 64u * static_cast<uint32_t>(sizeof(Id));
 
     // the queued edges [q0, q0 + cnt), one per lane, finished from counter
-    // block 1 (2 when the first pass drew two) and stored
+    // block 1 (2 when the first pass drew two) and stored.  A queued edge is
+    // the tile's first edge plus j * stride * 64 + lane: every launch keeps
+    // stride (its waves) below 2^16, so that offset is one 24-bit
+    // multiply-add, and the stores go through the tile's buffer descriptors
+    // at it.
+    const uint64_t tile_e0 = (I.first_block + t0) << 6;
+    const uint32_t stride64 = static_cast<uint32_t>(stride) << 6;
     auto drain = [&](uint32_t q0, uint32_t cnt) {
       wave_lds_fence();
       if (lane < cnt) {
@@ -617,17 +623,19 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         acc.unpack(qacc[q0 + lane]);
         const uint32_t slot = entry >> 6;
         uint32_t filled = entry & 63u;
-        const uint64_t e = ((I.first_block + t0 + (slot >> 6) * stride) << 6) + (slot & 63u);
+        const uint32_t lane_e = slot & 63u;
+        const uint32_t off = __umul24(slot >> 6, stride64) + lane_e;
+        const uint64_t e = tile_e0 + off;
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
-        const uint32_t toff_e = ((slot & 63u) & I.table_mask) * tbytes;
+        const uint32_t toff_e = __umul24(lane_e & I.table_mask, tbytes);  // tbytes <= 2^20
         for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);
           sample_lazy<Acc, !kLazy>(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
         }
         finish_edge(acc, e, [&](Id s, Id d) {
-          static_cast<Id*>(I.out_src)[e - I.edge_begin] = s;
-          static_cast<Id*>(I.out_dst)[e - I.edge_begin] = d;
+          store_at(rs, off, 0u, s);
+          store_at(rd, off, 0u, d);
         });
       }
       wave_lds_fence();
@@ -1031,6 +1039,7 @@ hipError_t launch_one(Launch P, hipStream_t s) {
   uint64_t grid = static_cast<uint64_t>(limits().cu_count) * per_cu;
   if (grid > wgs_needed) grid = wgs_needed;
   if (grid < 1) grid = 1;
+  if (grid * P.L.waves >= (1u << 16)) return hipErrorInvalidValue;  // the queue's 24-bit offsets
   hipLaunchKernelGGL((generate_kernel<Acc, kLds, kReduce, kGeneral, kDegree, kTwo>), dim3(static_cast<uint32_t>(grid)),
                      dim3(P.L.waves * 64), lds, s, P);
   return hipGetLastError();
