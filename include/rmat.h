@@ -441,9 +441,14 @@ int rmat_batch_free(rmat_batch_t b);
  * exact expected Philox blocks and samples per edge (Sec. 2: a longer
  * expected path means fewer samples per edge), and the model's cost of an
  * instance is m x (40 x blocks + 11 x samples) integer ops at the measured
- * rate of the candidate's launch class (table residency; one
- * 2^24-edge batch per class, measured once per process), plus the time to
- * stage an LDS table once per work item.  When every tuned instance has its
+ * rate of the candidate's launch class (each LDS table size, whose bytes set
+ * how many workgroups a CU holds, and tables read from L2; one-instance
+ * batches per class, measured once per process), plus the time to stage an
+ * LDS table once per work item.  The LDS tables of a batch run in one launch
+ * laid out for the largest, so the model tries each largest LDS size: every
+ * instance takes its cheapest candidate no larger (at that size's rate) or
+ * read from L2, and the size with the least total wins.  When every tuned
+ * instance has its
  * outputs, the model's bounds are then timed on the batch itself against
  * 4096 and against 8192 for all (a single size replaces the model's bounds
  * only if it is faster by more than 1%), and the work-item size (the

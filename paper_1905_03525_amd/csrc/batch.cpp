@@ -200,13 +200,15 @@ constexpr double kResidentWorkgroups = 256.0;
 constexpr int kMinBoundLog2 = 8, kMaxBoundLog2 = 16;
 
 // Measured device time per (edge x integer op) of the batch generation
-// kernel, one figure per launch class (table residency):
+// kernel, one figure per launch class: each LDS table size (its bytes set
+// how many workgroups a CU holds beside it) and one for tables read from L2;
 // one-instance batches of 2^25 and 2^27 edges at k = 26 (a = .57, b = c =
 // .19, d = .05) on a table of the class's size, best of three runs each;
 // the slope between the two leaves out the table build and the launches.
 // Measured once per process and class.
 struct ClassRate {
   bool lds;
+  uint32_t n_buckets;  // LDS classes: the table's buckets (0 for the L2 class)
   double ns_per_op;
 };
 std::vector<ClassRate> g_rates;
@@ -288,15 +290,16 @@ int measure_class(uint64_t bound, double* ns_per_op) {
 // The rate of the launch class of a table of nb buckets (32-bit ids).
 int class_rate(uint32_t nb, double* ns_per_op) {
   const bool lds = nb <= rmat::lds_table_limit();
+  const uint32_t key = lds ? nb : 0u;
   for (const ClassRate& c : g_rates)
-    if (c.lds == lds) {
+    if (c.lds == lds && c.n_buckets == key) {
       *ns_per_op = c.ns_per_op;
       return RMAT_OK;
     }
   double ns = 0.0;
   int rc = measure_class(nb, &ns);
   if (rc) return rc;
-  g_rates.push_back(ClassRate{lds, ns});
+  g_rates.push_back(ClassRate{lds, key, ns});
   *ns_per_op = ns;
   return RMAT_OK;
 }
@@ -631,22 +634,62 @@ static int rmat_batch_autotune_body(rmat_instance* inst, int n, rmat_autotune_re
     free_tables(&T);
     if (e != hipSuccess) return rmat::hip_fail(e, "autotune candidate tables");
     // the model: exact ops per edge of each candidate (its length law) at
-    // the measured rate of its launch class, plus table staging
-    std::vector<double> best(n, 1e300);
-    for (size_t c = 0; c < cand.size(); ++c) {
-      if (st[c].error != 0) continue;
-      const int i = who[c];
-      double rate = 0.0;
-      if ((rc = class_rate(static_cast<uint32_t>(shapes[c].n_buckets), &rate))) return rc;
+    // the measured rate of its launch class, plus table staging.  The LDS
+    // tables of a batch share one launch laid out for the largest of them,
+    // so they all run at that table's rate: for each largest LDS size M,
+    // every instance takes its cheapest candidate among the LDS tables of at
+    // most M buckets (at M's rate) and the tables read from L2 (at theirs),
+    // and the M with the least total cost wins (M = 0: L2 tables only).
+    auto is_lds = [&](size_t c) { return shapes[c].n_buckets <= rmat::lds_table_limit(); };
+    auto cost_at = [&](size_t c, double rate) {
       const double gen = static_cast<double>(cand[c].m) * rate * laws_ops(st[c].len_mass, cand[c].k);
       const double items = std::ceil(static_cast<double>((cand[c].m + 63) / 64) / work_blocks);
-      const bool lds = shapes[c].n_buckets <= rmat::lds_table_limit();
       const double stage_one =
-          lds ? kStageLatencyNs + static_cast<double>(shapes[c].n_buckets) * 16.0 / kStageBytesPerNs : 0.0;
-      const double cost = gen + items * stage_one / kResidentWorkgroups;
-      if (cost < best[i]) {
-        best[i] = cost;
-        model[i] = cand[c].table_bound;
+          is_lds(c) ? kStageLatencyNs + static_cast<double>(shapes[c].n_buckets) * 16.0 / kStageBytesPerNs : 0.0;
+      return gen + items * stage_one / kResidentWorkgroups;
+    };
+    std::vector<uint32_t> sizes{0u};  // the largest LDS sizes to try
+    double l2_rate = 0.0;
+    bool have_l2 = false;
+    for (size_t c = 0; c < cand.size(); ++c) {
+      if (st[c].error != 0) continue;
+      const uint32_t nb = static_cast<uint32_t>(shapes[c].n_buckets);
+      if (!is_lds(c)) {
+        if (!have_l2 && (rc = class_rate(nb, &l2_rate))) return rc;
+        have_l2 = true;
+      } else if (std::find(sizes.begin(), sizes.end(), nb) == sizes.end()) {
+        sizes.push_back(nb);
+      }
+    }
+    std::vector<double> best(n, 1e300);
+    double best_total = 1e300;
+    for (uint32_t M : sizes) {
+      double rate_m = 0.0;
+      if (M != 0 && (rc = class_rate(M, &rate_m))) return rc;
+      std::vector<double> cost_i(n, 1e300);
+      std::vector<uint64_t> pick_i(n, 0);
+      for (size_t c = 0; c < cand.size(); ++c) {
+        if (st[c].error != 0) continue;
+        const bool lds = is_lds(c);
+        if (lds && shapes[c].n_buckets > M) continue;
+        const double cost = cost_at(c, lds ? rate_m : l2_rate);
+        const int i = who[c];
+        if (cost < cost_i[i]) {
+          cost_i[i] = cost;
+          pick_i[i] = cand[c].table_bound;
+        }
+      }
+      double total = 0.0;
+      bool every = true;
+      for (int i = 0; i < n; ++i)
+        if (inst[i].table_bound == 0) {
+          every = every && pick_i[i] != 0;
+          total += cost_i[i];
+        }
+      if (every && total < best_total) {
+        best_total = total;
+        best = cost_i;
+        model = pick_i;
       }
     }
     for (int i = 0; i < n; ++i)
