@@ -162,7 +162,10 @@ int rmat_kron_build_table(const double* P, int K, int k, uint64_t table_bound, i
  * n_tables = P; rmat_table_export exports member 0 and
  * rmat_table_export_member member i.  rmat_generate(_async),
  * rmat_generate_ex_async and rmat_generate_reduce_async accept the set.
- * Errors: as rmat_build_table; RMAT_EINVAL for n_tables or epsilon.
+ * With P > 1 each member has at most 2^19 buckets (the set is addressed by
+ * 32-bit offsets and a member's offset is a 24-bit product).  Errors: as
+ * rmat_build_table; RMAT_EINVAL for n_tables, epsilon or a member table
+ * above 2^19 buckets.
  */
 int rmat_build_perturbed_table(double a, double b, double c, double d, int k, uint64_t table_bound, int path_mode,
                                int n_tables, double epsilon, uint64_t perturb_seed, rmat_table_t* out);

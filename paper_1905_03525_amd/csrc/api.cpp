@@ -494,6 +494,11 @@ static int rmat_build_perturbed_table_body(double a, double b, double c, double 
     rmat::Shape Si;
     if ((rc = rmat::validate_and_size(&qs[4 * i], k, table_bound, path_mode, &Si))) return rc;
   }
+  // a set's members are addressed by 32-bit byte offsets, and the queue's
+  // continuation takes a member's offset with a 24-bit multiply
+  if (n_tables > 1 && S.n_buckets * sizeof(rmat::BucketRecord) >= (1ull << 24))
+    return set_error(RMAT_EINVAL, "a set of %d tables takes tables of at most 2^19 buckets, not %llu", n_tables,
+                     (unsigned long long)S.n_buckets);
   if ((rc = rmat::check_device())) return rc;
   const uint64_t nb = S.n_buckets;
   const uint64_t tb = rmat::table_bytes(S);

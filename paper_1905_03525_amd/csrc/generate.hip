@@ -627,7 +627,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
         const uint32_t off = __umul24(slot >> 6, stride64) + lane_e;
         const uint64_t e = tile_e0 + off;
         const uint32_t e_lo = static_cast<uint32_t>(e), e_hi = static_cast<uint32_t>(e >> 32);
-        const uint32_t toff_e = __umul24(lane_e & I.table_mask, tbytes);  // tbytes <= 2^20
+        const uint32_t toff_e = __umul24(lane_e & I.table_mask, tbytes);  // a set member: tbytes < 2^24
         for (uint32_t jj = I.first_blocks == 2 ? 2u : 1u; filled < I.k && jj < kMaxBlocksPerEdge; ++jj) {
           uint32_t x0 = e_lo, x1 = e_hi, x2 = jj, x3 = I.ctr3;
           philox10(x0, x1, x2, x3, I.key0, I.key1);

@@ -124,3 +124,13 @@ def test_server_null_handles_and_config_checks():
         with pytest.raises(R.RmatError) as ei:
             R.rmat_server_create(**bad)
         assert ei.value.status == R.RMAT_EINVAL
+
+
+def test_perturbed_set_member_size_rejected_on_host():
+    """A perturbed set of more than one table takes member tables of at most
+    2^19 buckets (a member's byte offset is a 24-bit product); the check
+    runs on the host, before any device call."""
+    with pytest.raises(R.RmatError) as ei:
+        R.rmat_build_perturbed_table(0.57, 0.19, 0.19, 0.05, 30, 1 << 20, R.RMAT_VARIABLE, 2, 0.1, 7)
+    assert ei.value.status == R.RMAT_EINVAL
+    assert "2^19" in R.rmat_last_error()
