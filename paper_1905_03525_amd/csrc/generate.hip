@@ -116,10 +116,13 @@ __device__ __forceinline__ uint64_t mad_u64_u32(uint32_t x, uint32_t m, uint64_t
 // (i <= 15) and magic[i] = floor(2^32 / K^i) + 1, with which the high word of
 // x * magic[i] is floor(x / K^i) for every x < 2^16 when 2 <= K^i <= 2^16
 // (the error x * (magic[i] - 2^32 / K^i) / 2^32 < 2^-16 <= 1 / K^i cannot
-// carry the quotient past the next integer).
+// carry the quotient past the next integer).  rcp[i] is the double one unit
+// in the last place above the rounded 1 / K^i, so 1 / K^i <= rcp[i] <=
+// (1 / K^i)(1 + 2^-51).
 struct KronPow {
   uint64_t pow[16];
   uint32_t magic[16];
+  double rcp[16];
 };
 
 // Row/column accumulators, filled from bit 0 up: a path of L letters,
@@ -139,6 +142,7 @@ struct Acc32 {
     row |= rowv << filled;
     col |= colv << filled;
   }
+  __device__ __forceinline__ void trim(uint32_t, uint32_t, const KronPow*) {}
   __device__ __forceinline__ uint32_t src(uint32_t k) const { return __builtin_bitreverse32(row) >> (32 - k); }
   __device__ __forceinline__ uint32_t dst(uint32_t k) const { return __builtin_bitreverse32(col) >> (32 - k); }
   __device__ __forceinline__ Packed pack() const { return make_uint2(row, col); }
@@ -157,6 +161,7 @@ struct Acc64 {
     row |= static_cast<uint64_t>(rowv) << filled;
     col |= static_cast<uint64_t>(colv) << filled;
   }
+  __device__ __forceinline__ void trim(uint32_t, uint32_t, const KronPow*) {}
   __device__ __forceinline__ uint64_t src(uint32_t k) const { return __builtin_bitreverse64(row) >> (64 - k); }
   __device__ __forceinline__ uint64_t dst(uint32_t k) const { return __builtin_bitreverse64(col) >> (64 - k); }
   __device__ __forceinline__ Packed pack() const { return make_ulonglong2(row, col); }
@@ -165,43 +170,96 @@ struct Acc64 {
 
 // Base-K accumulators for K x K initiators: a path of L digit pairs holds
 // its row and column digits as base-K numbers (root-most digit most
-// significant); the first min(L, k - filled) digits are appended by
-// id = id * K^take + value / K^(L - take).  Path values are below 2^15 and
+// significant), and the id is the first k digits of the edge's paths.
+// 64-bit ids append the first min(L, k - filled) digits of each path by
+// id = id * K^take + value / K^(L - take); path values are below 2^15 and
 // the divisor K^(L - take) is at least K, so the quotient is a multiply-high
-// by KronPow::magic.  Ids stay below K^k, so 32-bit ids (K^k <= 2^32) take
-// one 32 x 32 + 32 multiply-add each (its low word, exact).
+// by KronPow::magic.  32-bit ids (K^k <= 2^32) append every path whole, with
+// one 32 x 32 + 32 multiply-add whose 64-bit result is exact: the value
+// before the last path is below K^(k-1) < 2^32, so the last one ends below
+// 2^32 * K^L <= 2^47, and trim() divides it once by K^(filled - k).  The
+// quotient q < 2^32 is the truncated double product value * rcp[filled - k]:
+// with value = q K^d + r, 0 <= r < K^d <= 2^15, the exact product lies in
+// [value / K^d, value / K^d + 2^-19), rounding moves it by at most 2^-22 and
+// not below an integer it is at or above, and value / K^d is an integer or
+// at least 2^-15 from both neighbours, so the truncation is q.
 template <typename IdT>
 struct KronAcc {
   static constexpr bool kKron = true;
+  static constexpr bool kNarrow = sizeof(IdT) == 4;
   using Id = IdT;
-  using Packed = typename std::conditional<sizeof(Id) == 4, uint2, ulonglong2>::type;
+  using Packed = typename std::conditional<kNarrow, uint2, ulonglong2>::type;
   Id row, col;
-  __device__ __forceinline__ void clear() { row = 0; col = 0; }
+  uint32_t row_hi, col_hi;  // 32-bit ids: bits 32 and up of the last path's product
+  __device__ __forceinline__ void clear() {
+    row = 0;
+    col = 0;
+    if constexpr (kNarrow) row_hi = col_hi = 0;
+  }
   // an edge's first path when it is taken whole (k is above the longest path)
-  __device__ __forceinline__ void first(uint32_t rowv, uint32_t colv) { row = rowv; col = colv; }
+  __device__ __forceinline__ void first(uint32_t rowv, uint32_t colv) {
+    row = rowv;
+    col = colv;
+    if constexpr (kNarrow) row_hi = col_hi = 0;
+  }
   __device__ __forceinline__ void append(uint32_t rowv, uint32_t colv, uint32_t len, uint32_t filled, uint32_t k,
                                          const KronPow* kpow) {
-    const uint32_t take = len < k - filled ? len : k - filled;
-    if (take < len) {  // the edge's last path, cut to the digits still needed
-      const uint32_t mg = kpow->magic[len - take];
-      rowv = static_cast<uint32_t>(mad_u64_u32(rowv, mg, 0) >> 32);
-      colv = static_cast<uint32_t>(mad_u64_u32(colv, mg, 0) >> 32);
-    }
-    if constexpr (sizeof(Id) == 4) {
-      const uint32_t mul = static_cast<uint32_t>(kpow->pow[take]);
-      row = static_cast<uint32_t>(mad_u64_u32(row, mul, rowv));
-      col = static_cast<uint32_t>(mad_u64_u32(col, mul, colv));
+    if constexpr (kNarrow) {
+      const uint32_t mul = static_cast<uint32_t>(kpow->pow[len]);
+      const uint64_t r = mad_u64_u32(row, mul, rowv), c = mad_u64_u32(col, mul, colv);
+      row = static_cast<uint32_t>(r);
+      row_hi = static_cast<uint32_t>(r >> 32);
+      col = static_cast<uint32_t>(c);
+      col_hi = static_cast<uint32_t>(c >> 32);
     } else {
+      const uint32_t take = len < k - filled ? len : k - filled;
+      if (take < len) {  // the edge's last path, cut to the digits still needed
+        const uint32_t mg = kpow->magic[len - take];
+        rowv = static_cast<uint32_t>(mad_u64_u32(rowv, mg, 0) >> 32);
+        colv = static_cast<uint32_t>(mad_u64_u32(colv, mg, 0) >> 32);
+      }
       const Id mul = static_cast<Id>(kpow->pow[take]);
       row = row * mul + rowv;
       col = col * mul + colv;
     }
   }
+  // 32-bit ids: the first k of `filled` digits (filled >= k; the index is
+  // masked only to keep the read inside the table)
+  __device__ __forceinline__ void trim(uint32_t filled, uint32_t k, const KronPow* kpow) {
+    if constexpr (kNarrow) {
+      const double r = kpow->rcp[(filled - k) & 15u];
+      row = static_cast<uint32_t>(fma(static_cast<double>(row_hi), 4294967296.0, static_cast<double>(row)) * r);
+      col = static_cast<uint32_t>(fma(static_cast<double>(col_hi), 4294967296.0, static_cast<double>(col)) * r);
+    }
+  }
   __device__ __forceinline__ Id src(uint32_t) const { return row; }
   __device__ __forceinline__ Id dst(uint32_t) const { return col; }
   __device__ __forceinline__ Packed pack() const { return Packed{row, col}; }
-  __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
+  // a queued edge is short of k digits, so its value is all in row and col
+  __device__ __forceinline__ void unpack(const Packed& p) {
+    row = p.x;
+    col = p.y;
+    if constexpr (kNarrow) row_hi = col_hi = 0;
+  }
 };
+
+// A record's own (low) or alias (high) half-words of its three fields.  For
+// 32-bit base-K ids, whose path values go straight into 64-bit addends, one
+// byte permute per field from a shared selector: there the compiler would
+// otherwise mask and shift each half before selecting.
+template <typename Acc>
+__device__ __forceinline__ void pick(bool own, const BucketRecord& q, uint32_t& len, uint32_t& rowv, uint32_t& colv) {
+  if constexpr (Acc::kKron && sizeof(typename Acc::Id) == 4) {
+    const uint32_t sel = own ? 0x0C0C0100u : 0x0C0C0302u;  // bytes 1:0 or 3:2, zero above
+    len = __builtin_amdgcn_perm(q.lens, q.lens, sel);
+    rowv = __builtin_amdgcn_perm(q.rows, q.rows, sel);
+    colv = __builtin_amdgcn_perm(q.cols, q.cols, sel);
+  } else {
+    len = own ? (q.lens & 0xFFFFu) : (q.lens >> 16);
+    rowv = own ? (q.rows & 0xFFFFu) : (q.rows >> 16);
+    colv = own ? (q.cols & 0xFFFFu) : (q.cols >> 16);
+  }
+}
 
 // Up to four samples of one Philox block, stopping at k letters, on bucket
 // records already loaded.  A sample x keeps its bucket's own path when
@@ -216,8 +274,9 @@ __device__ __forceinline__ void consume4(uint32_t k, const uint32_t (&x)[4], con
   auto half = [](bool own, uint32_t v) { return own ? (v & 0xFFFFu) : (v >> 16); };
   const bool o0 = x[0] < r[0].thr_abs, o1 = x[1] < r[1].thr_abs, o2 = x[2] < r[2].thr_abs, o3 = x[3] < r[3].thr_abs;
   auto take = [&](bool o, const BucketRecord& q) {
-    const uint32_t len = half(o, q.lens);
-    acc.append(half(o, q.rows), half(o, q.cols), len, filled, k, kpow);
+    uint32_t len, rowv, colv;
+    pick<Acc>(o, q, len, rowv, colv);
+    acc.append(rowv, colv, len, filled, k, kpow);
     filled += len;
   };
   if constexpr (kSure1) {  // the edge's first path: whole, no power of K or cut
@@ -334,10 +393,9 @@ __device__ __forceinline__ void sample_lazy(const BucketRecord* __restrict__ set
   for (int i = 0; i < 4; ++i) {
     if (filled >= k) break;
     const BucketRecord q = record_of<kLds>(set, toff, bmask, x[i]);
-    const bool own = x[i] < q.thr_abs;
-    const uint32_t len = own ? (q.lens & 0xFFFFu) : (q.lens >> 16);
-    acc.append(own ? (q.rows & 0xFFFFu) : (q.rows >> 16), own ? (q.cols & 0xFFFFu) : (q.cols >> 16), len, filled, k,
-               kpow);
+    uint32_t len, rowv, colv;
+    pick<Acc>(x[i] < q.thr_abs, q, len, rowv, colv);
+    acc.append(rowv, colv, len, filled, k, kpow);
     filled += len;
   }
 }
@@ -564,7 +622,8 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   const Id dst_prefix = static_cast<Id>(kGeneral || kPrefix ? I.dst_prefix : 0);
 
   // the ids of a finished edge e: reduced, counted, or handed to put(s, d)
-  auto finish_edge = [&](const Acc& acc, uint64_t e, auto put) {
+  auto finish_edge = [&](Acc acc, uint32_t filled, uint64_t e, auto put) {
+    acc.trim(filled, I.k, kpow);
     if (kReduce) {
       const uint64_t s = acc.src(I.k), d = acc.dst(I.k);
       bins[e - I.edge_begin] = static_cast<uint16_t>(hist_shift >= 64 ? 0 : (s >> hist_shift));
@@ -633,7 +692,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
           philox10(x0, x1, x2, x3, I.key0, I.key1);
           sample_lazy<Acc, !kLazy>(tab, toff_e, I.bmask, I.k, x0, x1, x2, x3, acc, filled, kpow);
         }
-        finish_edge(acc, e, [&](Id s, Id d) {
+        finish_edge(acc, filled, e, [&](Id s, Id d) {
           store_at(rs, off, 0u, s);
           store_at(rd, off, 0u, d);
         });
@@ -650,7 +709,7 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
       const bool need = active && filled < I.k;
       const uint64_t qmask = __ballot(need);
       if (active && !need) {
-        finish_edge(acc, base + lane, [&](Id s, Id d) {
+        finish_edge(acc, filled, base + lane, [&](Id s, Id d) {
           if constexpr (decltype(desc)::value) {
             store_at(rs, lane, soff, s);
             store_at(rd, lane, soff, d);
@@ -796,6 +855,7 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
       for (int i = 0; i < 16; ++i, x *= P.I.kron_k) {
         s_kpow->pow[i] = x;
         s_kpow->magic[i] = static_cast<uint32_t>((1ull << 32) / x + 1);  // used for 2 <= x < 2^15 only
+        s_kpow->rcp[i] = __longlong_as_double(__double_as_longlong(1.0 / static_cast<double>(x)) + 1);
       }
     }
     __syncthreads();
