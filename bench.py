@@ -35,7 +35,7 @@ PEAK_CLOCK_GHZ = 2.4
 INT_PEAK_OPS = 256 * 4 * 16 * PEAK_CLOCK_GHZ * 1e9
 OPS_PER_PHILOX_BLOCK = 40  # 20 products 32x32->64 + 20 three-input XORs (10 rounds)
 OPS_PER_SAMPLE = 11        # shift, compare, 2 selects, row/col split (2), 2 shifts, 2 ORs, add
-OPS_EPILOGUE = 27          # mirror (compare + 2 selects) + per id 3 rounds of (multiply-add, mask, shift, xor)
+OPS_EPILOGUE = 21          # mirror (compare + 2 selects) + per id 3 rounds of (multiply-add, field extract, and-xor)
 OPS_KRON_CUT = 2           # K x K: the last path's two digit values divided by K^i (one multiply-high each)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "generate_k26_ef16_traffic.txt")
 POWER_CLOCK_SUMMARY = os.path.join(ROOT, "profiles", "generate_k26_ef16_power_clock.txt")

@@ -453,6 +453,7 @@ struct Epilogue {
   uint32_t flags;  // kEpiUndirected | kEpiScramble, wave-uniform
   Id mul[3], add[3], mask;
   uint32_t shift;
+  uint32_t width;  // k - shift: the bits a round's xor-shift brings down
 };
 
 template <typename Id>
@@ -465,17 +466,21 @@ __device__ __forceinline__ Epilogue<Id> make_epilogue(const Inst& I) {
   }
   E.mask = in_vgpr(static_cast<Id>(I.scr_mask));
   E.shift = in_vgpr(I.scr_shift);
+  E.width = in_vgpr(I.k - I.scr_shift);
   return E;
 }
 
 // The scramble bijection of [0, 2^k): three rounds of an affine map with an
 // odd multiplier followed by an xor-shift, each a bijection mod 2^k.  In
-// 32-bit arithmetic when the ids are (k <= 32: the low k bits agree).
+// 32-bit arithmetic when the ids are (k <= 32: the low k bits agree).  With
+// t the affine map's 32-bit result, the round's value y = t mod 2^k and
+// y >> shift is the bit field of t at [shift, k), so a round is the
+// multiply-add, one field extract and one three-input and/xor.
 __device__ __forceinline__ uint32_t scramble_id(uint32_t x, const Epilogue<uint32_t>& E) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    x = static_cast<uint32_t>(mad_u64_u32(x, E.mul[r], E.add[r])) & E.mask;
-    x ^= x >> E.shift;
+    const uint32_t t = static_cast<uint32_t>(mad_u64_u32(x, E.mul[r], E.add[r]));
+    x = (t & E.mask) ^ __builtin_amdgcn_ubfe(t, E.shift, E.width);
   }
   return x;
 }

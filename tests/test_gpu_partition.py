@@ -132,3 +132,40 @@ def test_async_row_ranges_in_flight_equal_oracle(R):
         total += n
     assert total == m
     t.close()
+
+
+def test_partitioned_workload_full_size_sampled(R):
+    """The benchmark's partitioned leg at full size: the k = 26 instance's
+    2^30 edges in 256 x 256 tiles, four asynchronous calls of 64 tile rows on
+    one stream, each counted on the host before it is enqueued.  Every tile
+    count equals the oracle's; the edges of tile rows 1, 63, 64 (the first row
+    of the second call), 127, 191 and 255 equal the oracle's tiles."""
+    import torch
+    import bench
+    w = bench.WORKLOAD
+    k, m, seed, tb = w["k"], w["m"], w["seed"], 8
+    t = R.rmat_build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], R.RMAT_VARIABLE)
+    o = oracle.build_table(w["a"], w["b"], w["c"], w["d"], k, w["table_bound"], oracle.VARIABLE)
+    src = torch.empty(m, dtype=torch.int32, device="cuda")
+    dst = torch.empty(m, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    counts, n_all = [], 0
+    for r0 in range(0, 256, 64):
+        c = R.rmat_partition_counts(t, seed, m, tb, r0, r0 + 64)
+        n = int(c.sum())
+        R.rmat_generate_partition_async(t, seed, m, tb, r0, r0 + 64, src[n_all:], dst[n_all:], n, stream)
+        counts.append(c)
+        n_all += n
+    torch.cuda.synchronize()
+    assert n_all == m
+    counts = np.concatenate(counts)
+    assert np.array_equal(counts, oracle.partition_counts(o, seed, m, tb))
+    row_off = np.concatenate([[0], np.cumsum(counts.sum(axis=1))]).astype(np.int64)
+    for r in (1, 63, 64, 127, 191, 255):
+        _, os_, od = oracle.generate_partition(o, seed, m, tb, r, r + 1)
+        a, b = int(row_off[r]), int(row_off[r + 1])
+        assert b - a == os_.size
+        assert np.array_equal(R.to_numpy_ids(src[a:b], k), os_), f"row {r}: src"
+        assert np.array_equal(R.to_numpy_ids(dst[a:b], k), od), f"row {r}: dst"
+    del src, dst
+    t.close()
