@@ -343,6 +343,7 @@ struct ListBuf {
 struct Lists {
   ListBuf buf[kListRing];
   int next = 0;
+  uint64_t largest = 0;  // the largest buffer of the ring so far
 };
 std::mutex g_lists_mu;
 std::map<int, Lists> g_lists;
@@ -452,18 +453,23 @@ static int rmat_generate_partition_body(rmat_table_t t, uint64_t seed, uint64_t 
     }
   }
   if (L.bytes < bytes) {
+    // grown to at least twice its size and to the ring's largest, so that
+    // calls of varying sizes rotating through the ring settle after a few
+    // reallocations (each one waits for the device)
+    const uint64_t cap = std::max(std::max(bytes, 2 * L.bytes), ring.largest);
     if (L.dev) (void)hipFree(L.dev);
     if (L.host) (void)hipHostFree(L.host);
     L.dev = L.host = nullptr;
     L.bytes = 0;
-    e = hipMalloc(&L.dev, bytes);
-    if (e == hipSuccess) e = hipHostMalloc(&L.host, bytes, hipHostMallocDefault);
+    e = hipMalloc(&L.dev, cap);
+    if (e == hipSuccess) e = hipHostMalloc(&L.host, cap, hipHostMallocDefault);
     if (e != hipSuccess) {
       if (L.dev) (void)hipFree(L.dev);
       L.dev = L.host = nullptr;
       return rmat::hip_fail(e, "allocation of the partition lists");
     }
-    L.bytes = bytes;
+    L.bytes = cap;
+    ring.largest = std::max(ring.largest, cap);
   }
   char* host = static_cast<char*>(L.host);
   auto* h_inst = reinterpret_cast<rmat::GenInst*>(host);
