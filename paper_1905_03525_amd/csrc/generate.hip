@@ -145,6 +145,9 @@ struct Acc32 {
   __device__ __forceinline__ void trim(uint32_t, uint32_t, const KronPow*) {}
   __device__ __forceinline__ uint32_t src(uint32_t k) const { return __builtin_bitreverse32(row) >> (32 - k); }
   __device__ __forceinline__ uint32_t dst(uint32_t k) const { return __builtin_bitreverse32(col) >> (32 - k); }
+  // the ids' letters first-most-significant, before the shift down to k bits
+  __device__ __forceinline__ uint32_t src_fill() const { return __builtin_bitreverse32(row); }
+  __device__ __forceinline__ uint32_t dst_fill() const { return __builtin_bitreverse32(col); }
   __device__ __forceinline__ Packed pack() const { return make_uint2(row, col); }
   __device__ __forceinline__ void unpack(const Packed& p) { row = p.x; col = p.y; }
 };
@@ -606,7 +609,7 @@ constexpr uint32_t queue_bytes() {
 // Every block after an edge's first (the first pass's second block, the
 // continuations) loads a record only for a sample the edge uses.
 template <typename Acc, bool kReduce, bool kDigest = false, bool kGeneral = true, bool kDegree = false,
-          bool kLazy = false, bool kTwo = false, bool kPrefix = false>
+          bool kLazy = false, bool kTwo = false, bool kPrefix = false, bool kFunnelIds = false>
 __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __restrict__ tab, const TileLayout& L,
                                            uint64_t wave_blk, uint64_t blk_end, uint64_t stride,
                                            typename Acc::Packed* qacc, uint16_t* qent, uint32_t hist_shift,
@@ -625,6 +628,14 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
   // kPrefix: id prefixes without the epilogue (the tiles of a partitioned graph)
   const Id src_prefix = static_cast<Id>(kGeneral || kPrefix ? I.src_prefix : 0);
   const Id dst_prefix = static_cast<Id>(kGeneral || kPrefix ? I.dst_prefix : 0);
+  // kFunnelIds, 32-bit bit-string ids: a prefix (zero below bit k) shifted
+  // down by k, so that one funnel shift of (prefix >> k : reversed fill) by
+  // 32 - k gives the prefixed id (one vector register more: the batch kernel,
+  // at the edge of a register step, keeps the shift and the OR)
+  constexpr bool kFunnel = kFunnelIds && (kGeneral || kPrefix) && std::is_same<Acc, Acc32>::value;
+  const uint32_t src_hi = kFunnel && I.k < 32 ? static_cast<uint32_t>(src_prefix) >> I.k : 0u;
+  const uint32_t dst_hi = kFunnel && I.k < 32 ? static_cast<uint32_t>(dst_prefix) >> I.k : 0u;
+  const uint32_t fshift = kFunnel ? in_vgpr(32u - I.k) : 0u;  // a vector operand: the funnel takes one scalar
 
   // the ids of a finished edge e: reduced, counted, or handed to put(s, d)
   auto finish_edge = [&](Acc acc, uint32_t filled, uint64_t e, auto put) {
@@ -636,11 +647,17 @@ __device__ __forceinline__ void run_blocks(const Inst& I, const BucketRecord* __
     } else if (kDegree) {  // one more edge out of its source
       atomicAdd(degree + acc.src(I.k), 1u);
     } else {
-      Id s = static_cast<Id>(acc.src(I.k));
-      Id d = static_cast<Id>(acc.dst(I.k));
-      if (kGeneral || kPrefix) {  // tiles of a partitioned graph carry id prefixes
-        s |= src_prefix;
-        d |= dst_prefix;
+      Id s, d;
+      if constexpr (kFunnel) {  // tiles of a partitioned graph carry id prefixes
+        s = __builtin_amdgcn_alignbit(src_hi, acc.src_fill(), fshift);
+        d = __builtin_amdgcn_alignbit(dst_hi, acc.dst_fill(), fshift);
+      } else {
+        s = static_cast<Id>(acc.src(I.k));
+        d = static_cast<Id>(acc.dst(I.k));
+        if (kGeneral || kPrefix) {
+          s |= src_prefix;
+          d |= dst_prefix;
+        }
       }
       epilogue<kGeneral>(E, s, d);
       put(s, d);
@@ -879,8 +896,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_kernel(Launch P) {
   Packed* qacc = reinterpret_cast<Packed*>(s_mem + P.L.lds_table + wave_in_wg * P.L.wave_bytes);
   uint16_t* qent = reinterpret_cast<uint16_t*>(qacc + kQueueCap);
   uint64_t xsum = 0;
-  run_blocks<Acc, kReduce, false, kGeneral, kDegree, !kLds, kTwo>(P.I, tab, P.L, wave, P.I.n_blocks, n_waves, qacc,
-                                                            qent, P.hist_shift, P.bins, xsum, kpow, P.degree);
+  run_blocks<Acc, kReduce, false, kGeneral, kDegree, !kLds, kTwo, false, true>(
+      P.I, tab, P.L, wave, P.I.n_blocks, n_waves, qacc, qent, P.hist_shift, P.bins, xsum, kpow, P.degree);
   if (kReduce) {
     const uint64_t x = wave_xor(xsum);
     if (lane == 0) s_xor[wave_in_wg] = x;
@@ -1001,8 +1018,8 @@ __global__ __launch_bounds__(kGenThreads) void generate_tiles_kernel(TilesLaunch
     const uint64_t b0 = lo > c0 ? lo - c0 : 0, b1 = end - c0;
     const Inst I = load_uniform(P.insts + i);
     const BucketRecord* tab = kLds ? reinterpret_cast<const BucketRecord*>(s_mem) : I.records;
-    run_blocks<Acc, false, false, false, false, !kLds, false, true>(I, tab, P.L, b0, b1, 1, qacc, qent, 0, nullptr,
-                                                                    xsum);
+    run_blocks<Acc, false, false, false, false, !kLds, false, true, true>(I, tab, P.L, b0, b1, 1, qacc, qent, 0,
+                                                                          nullptr, xsum);
   }
 }
 
