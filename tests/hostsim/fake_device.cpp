@@ -65,7 +65,11 @@ int sim_take_coverage(uint64_t seed, uint64_t m, int partial) {
 }
 }
 
+static uint64_t g_mallocs = 0;
+extern "C" uint64_t sim_mallocs() { return g_mallocs; }
+
 hipError_t hipMalloc(void** p, size_t n) {
+  ++g_mallocs;
   *p = std::aligned_alloc(256, (n + 255) / 256 * 256);
   return *p ? hipSuccess : hipErrorOutOfMemory;
 }

@@ -129,3 +129,36 @@ def test_async_calls_wrap_the_list_ring(lib):
     finally:
         lib.sim_whole_cover(0)
         lib.rmat_free_table(h)
+
+
+def test_list_ring_settles_for_calls_of_varying_sizes(lib):
+    """Calls of varying sizes rotating through the ring of four list buffers
+    (five row ranges per pass, so each pass puts them on other buffers): a
+    buffer that grows takes at least twice its size and the ring's largest,
+    so each buffer grows at most twice (its first size, then the largest
+    range's) and the ring stops allocating once every buffer has met it."""
+    # more non-empty tiles than any other test here lists, so that the ring
+    # grows whatever ran before in this process
+    q, k, tb, m, seed = (0.57, 0.19, 0.19, 0.05), 20, 8, 1 << 24, 5
+    lib.sim_mallocs.restype = ctypes.c_uint64
+    h = ctypes.c_void_p()
+    assert lib.rmat_build_table(*q, k, 4096, 1, ctypes.byref(h)) == 0, lib.rmat_last_error()
+    out = np.zeros(2, np.uint64)
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    ranges = [(0, 4), (4, 128), (128, 130), (130, 256), (0, 256)]
+    try:
+        per_pass = []
+        for _ in range(6):
+            before = lib.sim_mallocs()
+            for r0, r1 in ranges:
+                counts = np.zeros((r1 - r0, 1 << tb), np.uint64)
+                assert lib.rmat_partition_counts(h, seed, m, tb, r0, r1, counts.ctypes.data_as(ctypes.c_void_p)) == 0
+                rc = lib.rmat_generate_partition_async(h, seed, m, tb, r0, r1, p, p, int(counts.sum()), None)
+                assert rc == 0, lib.rmat_last_error()
+                assert lib.sim_failed() == 0
+            per_pass.append(lib.sim_mallocs() - before)
+        # a growth allocates the device buffer and its pinned twin
+        assert per_pass[0] > 0 and per_pass[-2:] == [0, 0], per_pass
+        assert sum(per_pass) <= 2 * 2 * 4, per_pass
+    finally:
+        lib.rmat_free_table(h)
